@@ -1,0 +1,214 @@
+#!/usr/bin/env python3
+"""Benchmark of the screened ACE build on one MI355X.
+
+Workload (32-water scale): 128 orbitals on a 96^3 grid, L = 18.6 bohr,
+erfc-screened kernel (omega = 0.106), seeded synthetic orbitals.  One step is
+the whole hot path from canonical orbitals: SCDM localization, pair screening
+at rho_cut = 1e-3, pair Poisson solves + W, M = Phi^T W, Cholesky(-M) and the
+projectors xi = L^-1 W.  Inputs are resident in HBM before the timed region.
+
+Prints ONE JSON line.  value = ACE builds/s (whole step).  Extra fields carry
+the pair Poisson solves/s of the pair stage, the E_x errors, the other forms
+(full pair list, FP32) and the roofline of the dominant kernel measured with
+HIP events inside the timed region.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+METRIC = "ACE builds/s and pair Poisson solves/s (128 orb, 96^3), E_x rel. err vs FP64"
+
+CLASS_NAMES = {0: "pair_fwd_xy", 1: "pair_conv_z", 2: "pair_inv_xy_accumulate", 3: "pair_fwd_x",
+               4: "pair_fwd_y", 5: "pair_inv_y", 6: "pair_inv_x_accumulate", 7: "gemm_nt_splitk",
+               8: "gemm_left_small", 9: "qrcp_update"}
+CLASS_KERNEL = {0: "k_fwd_xy", 1: "k_conv_z", 2: "k_inv_xy", 3: "k_fwd_x", 4: "k_line_y", 5: "k_line_y",
+                6: "k_inv_x", 7: "k_gemm_nt", 8: "k_gemm_ls", 9: "k_qrcp_update"}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--rho-cut", type=float, default=1e-3)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--no-oracle-check", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(o, pairs_np, kind, omega, sample_pairs=60):
+    """The FP64 oracle, single-threaded, on a bounded sample of the same step."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+
+    s = o.spec
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        _, _, phi = oracle.scdm_localize(o.psi, s.dV)
+        t1 = time.perf_counter()
+        oracle.pairlist(phi, s.dV, 1e-3)
+        t2 = time.perf_counter()
+        v = oracle.coulomb_kernel(s.N, s.L, kind, omega)
+        sub = pairs_np[np.linspace(0, len(pairs_np) - 1, sample_pairs).astype(int)]
+        oracle.build_W(phi, sub, v, s.dV)
+        t3 = time.perf_counter()
+    per_pair = (t3 - t2) / len(sub)
+    t_step = (t1 - t0) + (t2 - t1) + per_pair * len(pairs_np)
+    return {
+        "value": 1.0 / t_step, "unit": "builds/s", "cores": 1, "kind": "oracle",
+        "sample": (f"full SCDM + pair screening, then {len(sub)} of {len(pairs_np)} kept pair solves "
+                   f"(extrapolated; M/Cholesky tail omitted); oracle pair solves/s = {1.0 / per_pair:.2f}"),
+        "seconds": round(t3 - t0, 2),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}); the multi-GPU pair-sharded "
+              "design is described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2101_03155_amd import Context, Grid, ace
+    from synth import config_spec, make_orbitals
+
+    spec = config_spec(args.config)
+    kind, omega = spec.kernel, spec.omega
+    o = make_orbitals(spec)
+    psi = torch.as_tensor(o.psi, device="cuda")
+    grid = Grid.cubic(spec.N, spec.L)
+    ctx = Context()
+    prec = args.precision
+
+    def step():
+        phi, piv, _ = ctx.localize(psi, grid)
+        pairs, _ = ctx.pairlist(phi, grid, args.rho_cut)
+        r = ctx.build(phi, pairs, grid, kernel=kind, omega=omega, precision=prec, want_M=False)
+        return phi, pairs, r
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    for c in range(15):
+        ctx.profile_read(c, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        phi, pairs, r = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = {c: ctx.profile_read(c, reset=True) for c in range(15)}
+    ctx.profile(False)
+    ms_per_step = (t1 - t0) * 1000.0 / args.steps
+    npairs = int(pairs.shape[0])
+    ex = float(r["ex"].item())
+
+    stage_ms = {name: prof[c][1] / args.steps for c, name in
+                ((10, "localize"), (11, "pairlist"), (12, "pair_stage"), (13, "tail"), (14, "build"))}
+    pair_solves = npairs / (stage_ms["pair_stage"] / 1000.0)
+
+    # dominant kernel class inside the timed region
+    dom = max(range(10), key=lambda c: prof[c][1])
+    n_l, ms_l, units = prof[dom]
+    if dom in (7, 8):
+        peak = FP64_PEAK_TFLOPS
+        achieved = units / (ms_l / 1000.0) / 1e12
+        roof = {"bound": "mfma", "unit": "TFLOP/s"}
+    else:
+        peak = HBM_PEAK_GBS
+        achieved = units / (ms_l / 1000.0) / 1e9
+        roof = {"bound": "hbm", "unit": "GB/s"}
+    roof.update({"kernel": CLASS_KERNEL[dom], "class": CLASS_NAMES[dom], "launches_per_step": n_l / args.steps,
+                 "avg_launch_us": 1000.0 * ms_l / max(n_l, 1),
+                 "algorithmic_per_launch": units / max(n_l, 1),
+                 "achieved": round(achieved, 2), "peak": peak, "frac": round(achieved / peak, 4),
+                 "traffic": None})
+    kernels = {CLASS_NAMES[c]: {"launches": prof[c][0], "ms": round(prof[c][1], 3),
+                                "rate": (round(prof[c][2] / (prof[c][1] / 1000.0) / (1e12 if c in (7, 8) else 1e9), 2)
+                                         if prof[c][1] > 0 else None)}
+               for c in range(10) if prof[c][0]}
+
+    out = {
+        "metric": METRIC, "value": round(1000.0 / ms_per_step, 4), "unit": "builds/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64" if prec == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"screened ACE build from canonical orbitals, {spec.norb} orbitals, {spec.N}^3 grid, "
+                               f"L={spec.L} bohr, {kind} kernel omega={omega}, rho_cut={args.rho_cut}",
+                   "norb": spec.norb, "grid": spec.N, "npairs_kept": npairs, "precision": prec},
+        "pair_solves_per_s": round(pair_solves, 1),
+        "stage_ms": {k: round(v, 3) for k, v in stage_ms.items()},
+        "ex_hartree": ex,
+        "roofline": roof,
+        "kernels": kernels,
+    }
+
+    pairs_np = pairs.cpu().numpy().astype(np.int64)
+    phi_np = None
+    if not args.no_oracle_check:
+        import oracle
+
+        phi_np = phi.cpu().numpy()
+        v = oracle.coulomb_kernel(spec.N, spec.L, kind, omega)
+        e_ref = oracle.exchange_energy_pairs(phi_np, pairs_np, v, spec.dV)
+        out["ex_rel_err_vs_oracle_fp64"] = abs(ex - e_ref.sum()) / abs(e_ref.sum())
+
+    if not args.no_forms:
+        forms = {}
+        # FP32 precision form on the same pair list
+        for _ in range(2):
+            r32 = ctx.build(phi, pairs, grid, kernel=kind, omega=omega, precision="fp32", want_M=False)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for _ in range(3):
+            r32 = ctx.build(phi, pairs, grid, kernel=kind, omega=omega, precision="fp32", want_M=False)
+        torch.cuda.synchronize()
+        forms["screened_fp32_build_ms"] = round((time.perf_counter() - ta) * 1000 / 3, 3)
+        ex32 = float(r32["ex"].item())
+        r64 = ctx.build(phi, pairs, grid, kernel=kind, omega=omega, precision="fp64", want_M=False)
+        forms["ex_rel_err_fp32_vs_fp64"] = abs(ex32 - float(r64["ex"].item())) / abs(float(r64["ex"].item()))
+        # full pair list, FP64 and FP32
+        n = spec.norb
+        full = torch.tensor([(i, j) for i in range(n) for j in range(i, n)], dtype=torch.int32, device="cuda")
+        for p in ("fp64", "fp32"):
+            ctx.build(phi, full, grid, kernel=kind, omega=omega, precision=p, want_M=False)
+            ctx.profile(True)
+            ctx.profile_read(12, reset=True)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            for _ in range(3):
+                rf = ctx.build(phi, full, grid, kernel=kind, omega=omega, precision=p, want_M=False)
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            _, pms, _ = ctx.profile_read(12, reset=True)
+            ctx.profile(False)
+            forms[f"full_{p}_build_ms"] = round((tb - ta) * 1000 / 3, 3)
+            forms[f"full_{p}_pair_solves_per_s"] = round(full.shape[0] / (pms / 3 / 1000.0), 1)
+            forms[f"full_{p}_ex"] = float(rf["ex"].item())
+        out["forms"] = forms
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(o, pairs_np, kind, omega)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,177 @@
+/*
+ * libace — screened adaptively compressed exchange (ACE) build on AMD MI355X.
+ *
+ * C ABI.  Every array argument is DEVICE memory owned by the caller (for
+ * example torch tensors); the library never frees it and keeps no pointer to
+ * it after a call returns.  Work is issued on the context's HIP stream.
+ *
+ * Units and layout (all entry points):
+ *   - Hartree atomic units (bohr, Hartree);
+ *   - a grid function is stored [z][y][x], x fastest, FP64, over an
+ *     n[0] x n[1] x n[2] (= nx, ny, nz) periodic grid of an orthorhombic box
+ *     with edges L[0..2] (bohr); N_G = nx*ny*nz, dV = Lx*Ly*Lz / N_G;
+ *   - a set of orbitals is [norb][N_G] (orbital-major);
+ *   - orbitals are real and orthonormal on the grid: sum_r phi_i phi_j dV = d_ij;
+ *   - the Fourier convention is G = 2 pi k / L with k in FFT order over the
+ *     full FFT box (no spherical cutoff).
+ *
+ * Errors: every call returns an ace_status; on failure ace_last_error() holds
+ * a message and the outputs are unspecified.  Argument checks are done on the
+ * host before any work is queued.  Supported grids: cubic, n = 8, 12, 16, 24,
+ * 32, 48, 64, 80, 96, 100, 108, 120 or 160; 1 <= norb <= 512.
+ *
+ * Calls that must return a count or a factorization status to the host
+ * (ace_pairlist, ace_build, ace_localize) synchronize the stream once.
+ */
+#ifndef ACE_H
+#define ACE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ace_ctx ace_ctx;
+
+typedef enum {
+  ACE_OK = 0,
+  ACE_E_ARG = -1,         /* invalid argument (message names it)                 */
+  ACE_E_HIP = -2,         /* HIP runtime error                                    */
+  ACE_E_NOMEM = -3,       /* workspace allocation failed or above ACE_WORKSPACE_MAX */
+  ACE_E_NOT_PD = -4,      /* -M not positive definite (message names the column) */
+  ACE_E_CAPACITY = -5,    /* output capacity too small (required count returned) */
+  ACE_E_NONFINITE = -6,   /* NaN/Inf met in M                                     */
+  ACE_E_UNSUPPORTED = -7  /* grid size / shape not supported                      */
+} ace_status;
+
+typedef enum {
+  ACE_KERNEL_COULOMB = 0, /* v(G) = 4 pi / G^2, v(0) = 0                            */
+  ACE_KERNEL_ERFC = 1     /* erfc(omega r)/r: 4 pi/G^2 (1 - exp(-G^2/4 omega^2)),
+                             v(0) = pi / omega^2                                    */
+} ace_kernel;
+
+typedef enum {
+  ACE_FP64 = 0, /* every step in FP64                                            */
+  ACE_FP32 = 1  /* pair products, FFTs and W in FP32; Phi^T W on FP32 matrix cores
+                   with compensated summation; Cholesky, L^-1 and xi in FP64     */
+} ace_precision;
+
+typedef struct {
+  int32_t n[3]; /* grid points along x, y, z */
+  double L[3];  /* box edges along x, y, z (bohr) */
+} ace_grid;
+
+/* Library version string. */
+const char* ace_version(void);
+
+/* Create a context issuing work on `hip_stream` (a hipStream_t; NULL = the
+ * default stream) on the current device.  The context owns workspaces, FFT
+ * twiddle tables, pair schedules and timing events. */
+int ace_create(ace_ctx** ctx, void* hip_stream);
+int ace_destroy(ace_ctx* ctx);
+const char* ace_last_error(const ace_ctx* ctx);
+int ace_set_stream(ace_ctx* ctx, void* hip_stream);
+
+/*
+ * (a) Localization by selected columns of the density matrix (SCDM), the
+ * unitary rotation of Eq. (unit), as used in the SCDM paragraph of Sec. Theory.
+ *
+ *   psi    [norb][N_G]  canonical orbitals (input)
+ *   phi    [norb][N_G]  localized orbitals phi_k = sum_i psi_i U_ik (output)
+ *   pivots [norb] int32 grid indices c_k picked by greedy QR with column
+ *                        pivoting of A[i][r] = psi_i(r) (output)
+ *   U      [norb][norb] orthogonal rotation, row i = psi index (output, nullable)
+ *
+ * Pivot k maximizes the residual norm of column r after projection onto the
+ * previously picked columns; the 8 best downdated candidates are re-ranked by
+ * explicitly projected residuals; ties go to the smaller grid index.
+ * U = A_C (A_C^T A_C)^-1/2 with A_C = A[:, pivots] (Loewdin orthonormalization
+ * of the selected density-matrix columns).  phi[k] belongs to pivots[k].
+ */
+int ace_localize(ace_ctx* ctx, const ace_grid* grid, int norb, const double* psi, double* phi,
+                 int32_t* pivots, double* U);
+
+/*
+ * (b) Pair screening (criterion in the SCDM paragraph of Sec. Theory): keep
+ * (i, j), i <= j, when  O_ij = dV sum_r |phi_i(r)| |phi_j(r)|  >= rho_cut;
+ * diagonal pairs are always kept.
+ *
+ *   pairs    [capacity][2] int32 (i, j) sorted by i then j (output)
+ *   overlap  [capacity] FP64 O_ij of each kept pair (output, nullable)
+ *   npairs   HOST pointer: number of kept pairs (output)
+ *
+ * If more than `capacity` pairs are kept, returns ACE_E_CAPACITY with the
+ * required count in *npairs.
+ */
+int ace_pairlist(ace_ctx* ctx, const ace_grid* grid, int norb, const double* phi, double rho_cut,
+                 int64_t capacity, int32_t* pairs, double* overlap, int64_t* npairs);
+
+/*
+ * (c)-(e) ACE build over a pair list (Appendix A applied to the screened
+ * exchange of Eq. (vx)):
+ *   (c) for each pair (i, j): v_ij = K * (phi_i phi_j) by FFT (Eq. e:vij),
+ *       W_i -= v_ij phi_j and, if i != j, W_j -= v_ij phi_i;
+ *   (d) M = dV Phi W^T, symmetrized (M + M^T)/2; -M = L L^T (Cholesky);
+ *   (e) xi = L^-1 W, i.e. the projectors P = W L^-T, so V_ACE = -xi^T xi dV.
+ *
+ *   phi     [norb][N_G] orthonormal orbitals (input)
+ *   pairs   [npairs][2] int32, 0 <= i <= j < norb, no duplicates (input)
+ *   kernel  ace_kernel; omega used for ACE_KERNEL_ERFC (bohr^-1)
+ *   prec    ace_precision
+ *   xi      [norb][N_G] projectors (output)
+ *   M       [norb][norb] symmetrized M (output, nullable)
+ *   W       [norb][N_G] FP64 copy of W (output, nullable)
+ *   ex      [1] E_x = tr M, Hartree (output, nullable)
+ *   pair_energy [npairs] e_ij = -(2 - d_ij) dV sum_r phi_i phi_j v_ij
+ *           (output, nullable); sum of e_ij equals E_x
+ *
+ * Returns ACE_E_NOT_PD when -M is not positive definite (a screened list that
+ * dropped too much); rebuilding with the full pair list is the remedy.
+ */
+int ace_build(ace_ctx* ctx, const ace_grid* grid, int norb, const double* phi, const int32_t* pairs,
+              int64_t npairs, int kernel, double omega, int prec, double* xi, double* M, double* W,
+              double* ex, double* pair_energy);
+
+/*
+ * ACE application (Sec. Theory, equation after Eq. e:vij; Appendix A):
+ *   y_a = V_ACE x_a = -sum_k xi_k <xi_k | x_a>,  <f|g> = dV sum_r f g.
+ *   xi [norb][N_G], x [nvec][N_G] (inputs), y [nvec][N_G] (output).
+ */
+int ace_apply(ace_ctx* ctx, const ace_grid* grid, int norb, const double* xi, int nvec, const double* x,
+              double* y);
+
+/*
+ * Timing.  While enabled, every launch of the hot kernels and every stage of
+ * the calls above is bracketed by HIP events on the context stream.
+ * ace_profile_read synchronizes and returns, for class `cls`, the number of
+ * bracketed launches, their summed milliseconds and their summed algorithmic
+ * work `units` (HBM bytes for the pair-stage and pivot-search classes, flops
+ * for the GEMM classes; 0 for stages), then clears the class if reset != 0.
+ * Classes:
+ *   0 pair product + forward in-plane FFTs      (3 N^3 s bytes per pair)
+ *   1 z FFT, v(G) multiply, inverse z FFT        (2 N^3 s bytes per pair)
+ *   2 inverse in-plane FFTs + W update           (7 N^3 s bytes per pair)
+ *   3..6 split path: forward x, forward y, inverse y, inverse x passes
+ *   7 split-K GEMM (2 M N K flops), 8 left-small GEMM (2 M K R flops)
+ *   9 pivot-search update pass ((norb + 2) N_G 8 bytes)
+ *   10 localize, 11 pairlist, 12 pair stage, 13 M + Cholesky + projectors,
+ *   14 whole ace_build
+ * (s = 8 bytes in FP64, 4 in FP32.)
+ */
+int ace_profile_enable(ace_ctx* ctx, int enable);
+int ace_profile_read(ace_ctx* ctx, int cls, int64_t* launches, double* total_ms, double* units, int reset);
+
+/*
+ * Pair-stage launch shape for one (precision, grid size): fused = 1 transforms
+ * each z-plane in one workgroup (when it fits in LDS), 0 uses separate x and
+ * y passes; max_packs caps the packs per launch.  Set by the autotuner.
+ */
+int ace_set_pair_shape(ace_ctx* ctx, int prec, int n, int fused, int max_packs);
+int ace_get_pair_shape(ace_ctx* ctx, int prec, int n, int* fused, int* max_packs);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ACE_H */

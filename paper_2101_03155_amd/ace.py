@@ -1,0 +1,263 @@
+"""Thin Python binding of libace (ctypes).
+
+Marshals torch tensors (device memory, the current HIP stream) into the C ABI
+declared in include/ace.h; every step of the computation runs in the library's
+HIP kernels.  There is no fallback: if libace.so is missing or no GPU is
+present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libace.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "ace.h")
+
+ACE_OK = 0
+STATUS = {0: "ACE_OK", -1: "ACE_E_ARG", -2: "ACE_E_HIP", -3: "ACE_E_NOMEM", -4: "ACE_E_NOT_PD",
+          -5: "ACE_E_CAPACITY", -6: "ACE_E_NONFINITE", -7: "ACE_E_UNSUPPORTED"}
+KERNELS = {"bare": 0, "coulomb": 0, "erfc": 1}
+PRECISIONS = {"fp64": 0, "fp32": 1}
+
+# profile classes (see include/ace.h)
+KC_FWD_XY, KC_CONV_Z, KC_INV_XY = 0, 1, 2
+KC_FWD_X, KC_FWD_Y, KC_INV_Y, KC_INV_X = 3, 4, 5, 6
+KC_GEMM_NT, KC_GEMM_TN, KC_QRCP = 7, 8, 9
+ST_LOCALIZE, ST_PAIRLIST, ST_PAIRS, ST_TAIL, ST_BUILD = 10, 11, 12, 13, 14
+
+
+class AceError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+
+
+class ace_grid(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("L", C.c_double * 3)]
+
+
+@dataclass(frozen=True)
+class Grid:
+    """Cubic-or-orthorhombic periodic grid: n points and box edge L (bohr) per axis."""
+
+    n: Sequence[int]
+    L: Sequence[float]
+
+    @staticmethod
+    def cubic(n: int, L: float) -> "Grid":
+        return Grid((n, n, n), (L, L, L))
+
+    @property
+    def size(self) -> int:
+        return int(self.n[0]) * int(self.n[1]) * int(self.n[2])
+
+    @property
+    def dV(self) -> float:
+        return float(self.L[0]) * float(self.L[1]) * float(self.L[2]) / self.size
+
+    def c(self) -> ace_grid:
+        g = ace_grid()
+        for d in range(3):
+            g.n[d] = int(self.n[d])
+            g.L[d] = float(self.L[d])
+        return g
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libace.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} not found: build it first (python -m paper_2101_03155_amd.build)")
+    lib = C.CDLL(path)
+    P, I, I64, D = C.c_void_p, C.c_int, C.c_int64, C.c_double
+    GP = C.POINTER(ace_grid)
+    sig = {
+        "ace_version": ([], C.c_char_p),
+        "ace_create": ([C.POINTER(P), P], I),
+        "ace_destroy": ([P], I),
+        "ace_last_error": ([P], C.c_char_p),
+        "ace_set_stream": ([P, P], I),
+        "ace_localize": ([P, GP, I, P, P, P, P], I),
+        "ace_pairlist": ([P, GP, I, P, D, I64, P, P, C.POINTER(I64)], I),
+        "ace_build": ([P, GP, I, P, P, I64, I, D, I, P, P, P, P, P], I),
+        "ace_apply": ([P, GP, I, P, I, P, P], I),
+        "ace_profile_enable": ([P, I], I),
+        "ace_profile_read": ([P, I, C.POINTER(I64), C.POINTER(D), C.POINTER(D), I], I),
+        "ace_set_pair_shape": ([P, I, I, I, I], I),
+        "ace_get_pair_shape": ([P, I, I, C.POINTER(I), C.POINTER(I)], I),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def declared_functions(header: str = HEADER):
+    """Names of the functions declared in include/ace.h."""
+    txt = open(header).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ace_[a-z_]+)\s*\(", txt)))
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _require(t, dtype, name):
+    import torch
+
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must live on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Context:
+    """An ace_ctx bound to a torch stream (default: the current stream)."""
+
+    def __init__(self, stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("libace needs a GPU; none is visible")
+        self.lib = load()
+        self._stream = stream
+        h = C.c_void_p()
+        s = (stream or torch.cuda.current_stream()).cuda_stream
+        rc = self.lib.ace_create(C.byref(h), C.c_void_p(s))
+        if rc != ACE_OK:
+            raise AceError(rc, "ace_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ace_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_stream(self):
+        import torch
+
+        s = (self._stream or torch.cuda.current_stream()).cuda_stream
+        self.lib.ace_set_stream(self.h, C.c_void_p(s))
+
+    def _check(self, rc):
+        if rc != ACE_OK:
+            raise AceError(rc, self.lib.ace_last_error(self.h).decode())
+
+    # ------------------------------------------------------------ API
+    def localize(self, psi, grid: Grid):
+        """SCDM localization: returns (phi, pivots[int32], U)."""
+        import torch
+
+        _require(psi, torch.float64, "psi")
+        norb = psi.shape[0]
+        phi = torch.empty_like(psi)
+        piv = torch.empty(norb, dtype=torch.int32, device=psi.device)
+        U = torch.empty(norb, norb, dtype=torch.float64, device=psi.device)
+        self._sync_stream()
+        g = grid.c()
+        self._check(self.lib.ace_localize(self.h, C.byref(g), norb, _ptr(psi), _ptr(phi), _ptr(piv), _ptr(U)))
+        return phi, piv, U
+
+    def pairlist(self, phi, grid: Grid, rho_cut: float, capacity: Optional[int] = None):
+        """Screened pair list: returns (pairs[int32, n x 2], overlap[n])."""
+        import torch
+
+        _require(phi, torch.float64, "phi")
+        norb = phi.shape[0]
+        cap = norb * (norb + 1) // 2 if capacity is None else int(capacity)
+        pairs = torch.empty(max(cap, 1), 2, dtype=torch.int32, device=phi.device)
+        ov = torch.empty(max(cap, 1), dtype=torch.float64, device=phi.device)
+        n = C.c_int64()
+        self._sync_stream()
+        g = grid.c()
+        rc = self.lib.ace_pairlist(self.h, C.byref(g), norb, _ptr(phi), float(rho_cut), cap, _ptr(pairs), _ptr(ov),
+                                   C.byref(n))
+        if rc == -5:
+            raise AceError(rc, self.lib.ace_last_error(self.h).decode() + f" (required {n.value})")
+        self._check(rc)
+        return pairs[: n.value], ov[: n.value]
+
+    def build(self, phi, pairs, grid: Grid, kernel: str = "erfc", omega: float = 0.106, precision: str = "fp64",
+              want_M: bool = True, want_W: bool = False, want_energies: bool = False, out=None):
+        """ACE build over a pair list: returns dict(xi, M, W, ex, e)."""
+        import torch
+
+        _require(phi, torch.float64, "phi")
+        _require(pairs, torch.int32, "pairs")
+        norb = phi.shape[0]
+        npairs = pairs.shape[0]
+        dev = phi.device
+        o = out or {}
+        xi = o.get("xi")
+        if xi is None:
+            xi = torch.empty_like(phi)
+        M = o.get("M") if want_M else None
+        if want_M and M is None:
+            M = torch.empty(norb, norb, dtype=torch.float64, device=dev)
+        W = torch.empty_like(phi) if want_W else None
+        ex = o.get("ex")
+        if ex is None:
+            ex = torch.empty(1, dtype=torch.float64, device=dev)
+        e = torch.empty(npairs, dtype=torch.float64, device=dev) if want_energies else None
+        self._sync_stream()
+        g = grid.c()
+        rc = self.lib.ace_build(self.h, C.byref(g), norb, _ptr(phi), _ptr(pairs), npairs, KERNELS[kernel],
+                                float(omega), PRECISIONS[precision], _ptr(xi), _ptr(M), _ptr(W), _ptr(ex), _ptr(e))
+        self._check(rc)
+        return dict(xi=xi, M=M, W=W, ex=ex, e=e)
+
+    def apply(self, xi, x, grid: Grid):
+        """y = V_ACE x."""
+        import torch
+
+        _require(xi, torch.float64, "xi")
+        _require(x, torch.float64, "x")
+        y = torch.empty_like(x)
+        self._sync_stream()
+        g = grid.c()
+        self._check(self.lib.ace_apply(self.h, C.byref(g), xi.shape[0], _ptr(xi), x.shape[0], _ptr(x), _ptr(y)))
+        return y
+
+    # ------------------------------------------------------------ timing / tuning
+    def profile(self, enable: bool):
+        self._check(self.lib.ace_profile_enable(self.h, 1 if enable else 0))
+
+    def profile_read(self, cls: int, reset: bool = True):
+        """(launches, total milliseconds, total algorithmic units) of a timing class."""
+        n = C.c_int64()
+        ms = C.c_double()
+        u = C.c_double()
+        self._check(self.lib.ace_profile_read(self.h, cls, C.byref(n), C.byref(ms), C.byref(u), 1 if reset else 0))
+        return n.value, ms.value, u.value
+
+    def set_pair_shape(self, precision: str, n: int, fused: bool, max_packs: int):
+        self._check(self.lib.ace_set_pair_shape(self.h, PRECISIONS[precision], n, 1 if fused else 0, max_packs))
+
+    def get_pair_shape(self, precision: str, n: int):
+        f = C.c_int()
+        m = C.c_int()
+        self._check(self.lib.ace_get_pair_shape(self.h, PRECISIONS[precision], n, C.byref(f), C.byref(m)))
+        return bool(f.value), m.value

@@ -1,0 +1,601 @@
+// C-ABI host layer: argument checks, workspaces, pair scheduling, stage order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/ace.h"
+#include "ace_internal.h"
+
+namespace ace {
+
+struct EventRecorder {
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  struct Mark { int cls; size_t a, b; };
+  std::vector<Mark> marks;
+  std::vector<size_t> open[KC_COUNT];
+  double total_ms[KC_COUNT] = {0};
+  double total_units[KC_COUNT] = {0};
+  int64_t count[KC_COUNT] = {0};
+  std::vector<double> mark_units;
+  hipEvent_t next() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+};
+
+void rec_begin(EventRecorder* r, int cls, hipStream_t s) {
+  if (!r) return;
+  const size_t idx = r->used;
+  hipEvent_t e = r->next();
+  if (!e) return;
+  (void)hipEventRecord(e, s);
+  r->open[cls].push_back(idx);
+}
+
+void rec_end(EventRecorder* r, int cls, hipStream_t s, double units) {
+  if (!r || r->open[cls].empty()) return;
+  const size_t idx = r->used;
+  hipEvent_t e = r->next();
+  if (!e) return;
+  (void)hipEventRecord(e, s);
+  r->marks.push_back({cls, r->open[cls].back(), idx});
+  r->mark_units.push_back(units);
+  r->open[cls].pop_back();
+}
+
+// Collect finished marks into the per-class totals (synchronizes the stream).
+static void rec_collect(EventRecorder* r, hipStream_t s) {
+  if (!r || r->marks.empty()) return;
+  (void)hipStreamSynchronize(s);
+  for (size_t q = 0; q < r->marks.size(); ++q) {
+    const auto& m = r->marks[q];
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r->pool[m.a], r->pool[m.b]) == hipSuccess) {
+      r->total_ms[m.cls] += ms;
+      r->total_units[m.cls] += r->mark_units[q];
+      r->count[m.cls] += 1;
+    }
+  }
+  r->marks.clear();
+  r->mark_units.clear();
+  bool any_open = false;
+  for (int c = 0; c < KC_COUNT; ++c) any_open |= !r->open[c].empty();
+  if (!any_open) r->used = 0;
+}
+
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace ace
+
+using namespace ace;
+
+struct ScheduleKey {
+  int64_t npairs;
+  int norb;
+  uint64_t hash;
+  bool operator<(const ScheduleKey& o) const {
+    if (npairs != o.npairs) return npairs < o.npairs;
+    if (norb != o.norb) return norb < o.norb;
+    return hash < o.hash;
+  }
+};
+
+struct Schedule {
+  std::vector<Pack> packs;             // all rounds concatenated
+  std::vector<int64_t> pidx;           // pair index of each pack half (-1 if none)
+  struct Launch { int first, second, npairs; };
+  std::vector<Launch> launches;  // (first pack, pack count, pair count) per launch
+  int max_launch = 0;
+};
+
+struct ace_ctx {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::string err;
+  size_t ws_total = 0, ws_cap = 0;
+  std::map<std::string, Buf> bufs;
+  std::map<int, Buf> twiddles;       // key: N*2 + prec
+  std::map<int, PairShape> shapes;   // key: N*2 + prec
+  std::map<int, int> max_packs;      // key: N*2 + prec
+  std::map<ScheduleKey, Schedule> schedules;
+  EventRecorder rec;
+  bool profiling = false;
+  EventRecorder* R() { return profiling ? &rec : nullptr; }
+};
+
+static int fail(ace_ctx* c, int code, const char* fmt, ...) {
+  char msg[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(msg, sizeof msg, fmt, ap);
+  va_end(ap);
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                       \
+  do {                                                                                          \
+    hipError_t e__ = (expr);                                                                    \
+    if (e__ != hipSuccess)                                                                      \
+      return fail(ctx, ACE_E_HIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e__), __FILE__, \
+                  __LINE__);                                                                    \
+  } while (0)
+
+// Grow-only named workspace buffer.
+static int ws_get(ace_ctx* c, const char* name, size_t bytes, void** out) {
+  Buf& b = c->bufs[name];
+  if (b.bytes < bytes) {
+    if (b.p) {
+      (void)hipStreamSynchronize(c->stream);
+      (void)hipFree(b.p);
+      c->ws_total -= b.bytes;
+      b.p = nullptr;
+      b.bytes = 0;
+    }
+    if (c->ws_cap && c->ws_total + bytes > c->ws_cap)
+      return fail(c, ACE_E_NOMEM, "workspace '%s' of %zu bytes exceeds ACE_WORKSPACE_MAX", name, bytes);
+    if (hipMalloc(&b.p, bytes) != hipSuccess) {
+      b.p = nullptr;
+      return fail(c, ACE_E_NOMEM, "hipMalloc of %zu bytes for '%s' failed", bytes, name);
+    }
+    b.bytes = bytes;
+    c->ws_total += bytes;
+  }
+  *out = b.p;
+  return ACE_OK;
+}
+
+#define WS(ctx, name, bytes, ptr)                                   \
+  do {                                                              \
+    int rc__ = ws_get(ctx, name, bytes, (void**)&(ptr));            \
+    if (rc__ != ACE_OK) return rc__;                                \
+  } while (0)
+
+static int check_grid(ace_ctx* c, const ace_grid* g, int norb) {
+  if (!g) return fail(c, ACE_E_ARG, "grid is NULL");
+  if (norb < 1 || norb > 512) return fail(c, ACE_E_ARG, "norb=%d outside [1, 512]", norb);
+  for (int d = 0; d < 3; ++d)
+    if (!(g->L[d] > 0.0) || !std::isfinite(g->L[d])) return fail(c, ACE_E_ARG, "box edge L[%d] must be > 0", d);
+  if (g->n[0] != g->n[1] || g->n[1] != g->n[2])
+    return fail(c, ACE_E_UNSUPPORTED, "only cubic grids are supported (got %d x %d x %d)", g->n[0], g->n[1], g->n[2]);
+  if (!pair_supported(g->n[0]))
+    return fail(c, ACE_E_UNSUPPORTED, "grid size %d not supported (use 8,12,16,24,32,48,64,80,96,100,108,120,160)",
+                g->n[0]);
+  return ACE_OK;
+}
+
+static int64_t grid_size(const ace_grid* g) { return int64_t(g->n[0]) * g->n[1] * g->n[2]; }
+static double grid_dv(const ace_grid* g) { return g->L[0] * g->L[1] * g->L[2] / double(grid_size(g)); }
+
+static int twiddles(ace_ctx* c, int N, int prec, const void** out) {
+  const int key = N * 2 + prec;
+  auto it = c->twiddles.find(key);
+  if (it == c->twiddles.end()) {
+    std::vector<double> d(2 * N);
+    std::vector<float> f(2 * N);
+    for (int m = 0; m < N; ++m) {
+      const long double a = -2.0L * 3.141592653589793238462643383279502884L * (long double)m / (long double)N;
+      d[2 * m] = (double)cosl(a);
+      d[2 * m + 1] = (double)sinl(a);
+      f[2 * m] = (float)cosl(a);
+      f[2 * m + 1] = (float)sinl(a);
+    }
+    Buf b;
+    b.bytes = prec == 0 ? d.size() * sizeof(double) : f.size() * sizeof(float);
+    HIPCHK(c, hipMalloc(&b.p, b.bytes));
+    HIPCHK(c, hipMemcpy(b.p, prec == 0 ? (const void*)d.data() : (const void*)f.data(), b.bytes,
+                        hipMemcpyHostToDevice));
+    it = c->twiddles.emplace(key, b).first;
+  }
+  *out = it->second.p;
+  return ACE_OK;
+}
+
+static PairShape shape_for(ace_ctx* c, int prec, int N) {
+  auto it = c->shapes.find(N * 2 + prec);
+  if (it != c->shapes.end()) return it->second;
+  return pair_default_shape(prec, N);
+}
+
+static int max_packs_for(ace_ctx* c, int prec, int N) {
+  auto it = c->max_packs.find(N * 2 + prec);
+  if (it != c->max_packs.end()) return it->second;
+  return 64;
+}
+
+// Split the pair list into conflict-free rounds (no orbital twice in a round):
+// greedy maximal matchings, each round scanning the remaining pairs in order
+// of decreasing endpoint degree so that the busiest orbitals are served first.
+static void make_schedule(const std::vector<int32_t>& pr, int64_t npairs, int norb, int max_packs, Schedule& S) {
+  std::vector<int64_t> rem(npairs);
+  for (int64_t p = 0; p < npairs; ++p) rem[p] = p;
+  std::vector<int> deg(norb), used(norb, -1);
+  std::vector<int64_t> next, order;
+  int round = 0;
+  while (!rem.empty()) {
+    std::fill(deg.begin(), deg.end(), 0);
+    for (int64_t p : rem) {
+      deg[pr[2 * p]]++;
+      if (pr[2 * p] != pr[2 * p + 1]) deg[pr[2 * p + 1]]++;
+    }
+    // counting sort by decreasing deg[i] + deg[j] (stable)
+    int maxk = 0;
+    for (int64_t p : rem) maxk = std::max(maxk, deg[pr[2 * p]] + deg[pr[2 * p + 1]]);
+    std::vector<int64_t> cnt(maxk + 2, 0);
+    for (int64_t p : rem) cnt[maxk - (deg[pr[2 * p]] + deg[pr[2 * p + 1]]) + 1]++;
+    for (int k = 1; k < maxk + 2; ++k) cnt[k] += cnt[k - 1];
+    order.assign(rem.size(), 0);
+    for (int64_t p : rem) order[cnt[maxk - (deg[pr[2 * p]] + deg[pr[2 * p + 1]])]++] = p;
+    next.clear();
+    std::vector<int64_t> sel;
+    for (int64_t p : order) {
+      const int i = pr[2 * p], j = pr[2 * p + 1];
+      if (used[i] != round && used[j] != round) {
+        used[i] = used[j] = round;
+        sel.push_back(p);
+      } else {
+        next.push_back(p);
+      }
+    }
+    std::sort(sel.begin(), sel.end());  // keep each round in pair order
+    const int first = int(S.packs.size());
+    for (size_t q = 0; q < sel.size(); q += 2) {
+      Pack pk;
+      pk.ia = pr[2 * sel[q]];
+      pk.ja = pr[2 * sel[q] + 1];
+      if (q + 1 < sel.size()) {
+        pk.ib = pr[2 * sel[q + 1]];
+        pk.jb = pr[2 * sel[q + 1] + 1];
+      } else {
+        pk.ib = -1;
+        pk.jb = -1;
+      }
+      S.packs.push_back(pk);
+      S.pidx.push_back(sel[q]);
+      S.pidx.push_back(q + 1 < sel.size() ? sel[q + 1] : -1);
+    }
+    const int np = int(S.packs.size()) - first;
+    for (int off = 0; off < np; off += max_packs) {
+      const int cntp = std::min(max_packs, np - off);
+      int npr = 0;
+      for (int q = first + off; q < first + off + cntp; ++q) npr += S.packs[q].jb >= 0 ? 2 : 1;
+      S.launches.push_back({first + off, cntp, npr});
+      S.max_launch = std::max(S.max_launch, cntp);
+    }
+    rem.swap(next);
+    ++round;
+  }
+}
+
+extern "C" {
+
+const char* ace_version(void) { return "libace 0.1 (gfx950)"; }
+
+int ace_create(ace_ctx** out, void* stream) {
+  if (!out) return ACE_E_ARG;
+  ace_ctx* c = new ace_ctx();
+  c->stream = (hipStream_t)stream;
+  // Without a visible device the context still validates arguments; the
+  // first HIP call then reports ACE_E_HIP.
+  if (hipGetDevice(&c->device) != hipSuccess) c->device = -1;
+  if (const char* cap = getenv("ACE_WORKSPACE_MAX")) c->ws_cap = (size_t)strtoull(cap, nullptr, 10);
+  *out = c;
+  return ACE_OK;
+}
+
+int ace_destroy(ace_ctx* c) {
+  if (!c) return ACE_OK;
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& kv : c->bufs)
+    if (kv.second.p) (void)hipFree(kv.second.p);
+  for (auto& kv : c->twiddles)
+    if (kv.second.p) (void)hipFree(kv.second.p);
+  for (auto e : c->rec.pool) (void)hipEventDestroy(e);
+  delete c;
+  return ACE_OK;
+}
+
+const char* ace_last_error(const ace_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int ace_set_stream(ace_ctx* c, void* stream) {
+  if (!c) return ACE_E_ARG;
+  c->stream = (hipStream_t)stream;
+  return ACE_OK;
+}
+
+int ace_profile_enable(ace_ctx* c, int enable) {
+  if (!c) return ACE_E_ARG;
+  if (!enable) rec_collect(&c->rec, c->stream);
+  c->profiling = enable != 0;
+  return ACE_OK;
+}
+
+int ace_profile_read(ace_ctx* c, int cls, int64_t* launches, double* total_ms, double* units, int reset) {
+  if (!c || cls < 0 || cls >= KC_COUNT) return fail(c, ACE_E_ARG, "bad profile class %d", cls);
+  rec_collect(&c->rec, c->stream);
+  if (launches) *launches = c->rec.count[cls];
+  if (total_ms) *total_ms = c->rec.total_ms[cls];
+  if (units) *units = c->rec.total_units[cls];
+  if (reset) {
+    c->rec.count[cls] = 0;
+    c->rec.total_ms[cls] = 0.0;
+    c->rec.total_units[cls] = 0.0;
+  }
+  return ACE_OK;
+}
+
+int ace_set_pair_shape(ace_ctx* c, int prec, int n, int fused, int max_packs) {
+  if (!c || (prec != 0 && prec != 1) || !pair_supported(n) || max_packs < 1)
+    return fail(c, ACE_E_ARG, "bad pair shape");
+  PairShape sh = pair_default_shape(prec, n);
+  sh.fused_xy = (fused && pair_fused_fits(prec, n)) ? 1 : 0;
+  c->shapes[n * 2 + prec] = sh;
+  c->max_packs[n * 2 + prec] = max_packs;
+  c->schedules.clear();
+  return ACE_OK;
+}
+
+int ace_get_pair_shape(ace_ctx* c, int prec, int n, int* fused, int* max_packs) {
+  if (!c || (prec != 0 && prec != 1) || !pair_supported(n)) return fail(c, ACE_E_ARG, "bad pair shape query");
+  PairShape sh = shape_for(c, prec, n);
+  if (fused) *fused = sh.fused_xy;
+  if (max_packs) *max_packs = max_packs_for(c, prec, n);
+  return ACE_OK;
+}
+
+// ------------------------------------------------------------------ (a) localize
+int ace_localize(ace_ctx* c, const ace_grid* g, int norb, const double* psi, double* phi, int32_t* pivots,
+                 double* U) {
+  if (!c) return ACE_E_ARG;
+  int rc = check_grid(c, g, norb);
+  if (rc) return rc;
+  if (!psi || !phi || !pivots) return fail(c, ACE_E_ARG, "psi, phi and pivots must be non-NULL");
+  const int64_t ng = grid_size(g);
+  if (ng < norb) return fail(c, ACE_E_ARG, "grid smaller than the number of orbitals");
+  hipStream_t s = c->stream;
+  rec_begin(c->R(), ST_LOCALIZE, s);
+  double *res, *pv, *Q, *q, *AC, *X, *G, *Z, *dev, *Ub;
+  int64_t* pi;
+  const int nblk = qrcp_blocks(ng);
+  WS(c, "res", ng * sizeof(double), res);
+  WS(c, "pv", size_t(nblk) * 8 * sizeof(double), pv);
+  WS(c, "pi", size_t(nblk) * 8 * sizeof(int64_t), pi);
+  WS(c, "Q", size_t(norb) * norb * sizeof(double), Q);
+  WS(c, "q", size_t(norb) * sizeof(double), q);
+  WS(c, "AC", size_t(norb) * norb * sizeof(double), AC);
+  WS(c, "X", size_t(norb) * norb * sizeof(double), X);
+  WS(c, "G", size_t(norb) * norb * sizeof(double), G);
+  WS(c, "Z", size_t(norb) * norb * sizeof(double), Z);
+  WS(c, "U", size_t(norb) * norb * sizeof(double), Ub);
+  WS(c, "scal", 64 * sizeof(double), dev);
+  launch_colnorm(psi, norb, ng, res, s);
+  launch_qrcp_update(psi, norb, ng, nullptr, res, pv, pi, s);
+  // algorithmic bytes of one update pass: read Psi once, read + write res
+  const double qbytes = double(norb + 2) * double(ng) * sizeof(double);
+  for (int k = 0; k < norb; ++k) {
+    launch_qrcp_select(psi, norb, ng, k, pv, pi, nblk, Q, res, pivots, q, s);
+    if (k + 1 < norb) {
+      rec_begin(c->R(), KC_QRCP, s);
+      launch_qrcp_update(psi, norb, ng, q, res, pv, pi, s);
+      rec_end(c->R(), KC_QRCP, s, qbytes);
+    }
+  }
+  HIPCHK(c, hipGetLastError());
+  // Loewdin rotation U = A_C (A_C^T A_C)^-1/2 = polar factor of A_C,
+  // by the Newton-Schulz iteration X <- X (3 I - X^T X) / 2 from X = A_C/|A_C|_F.
+  launch_gather_cols(psi, norb, ng, pivots, AC, s);
+  HIPCHK(c, hipMemcpyAsync(X, AC, size_t(norb) * norb * sizeof(double), hipMemcpyDeviceToDevice, s));
+  launch_scale_frob(X, int64_t(norb) * norb, s);
+  int converged_iters = -1;
+  for (int it = 0; it < 200; ++it) {
+    HIPCHK(c, gemm_ls(0, true, false, X, norb, X, norb, G, norb, norb, norb, norb, 1.0, s, nullptr));
+    launch_dev_identity(G, norb, dev, s);
+    double h = 0.0;
+    HIPCHK(c, hipMemcpyAsync(&h, dev, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    if (!std::isfinite(h)) return fail(c, ACE_E_NONFINITE, "non-finite Loewdin iteration (singular A_C?)");
+    if (h < 1e-11 && converged_iters < 0) converged_iters = it;
+    if (converged_iters >= 0 && it >= converged_iters + 2) break;
+    HIPCHK(c, gemm_ls(0, false, false, X, norb, G, norb, Z, norb, norb, norb, norb, 1.0, s, nullptr));
+    launch_ns_combine(X, Z, X, int64_t(norb) * norb, s);
+  }
+  if (converged_iters < 0) return fail(c, ACE_E_NONFINITE, "Loewdin polar iteration did not converge");
+  // phi_k = sum_i psi_i U_ik
+  HIPCHK(c, gemm_ls(0, true, false, X, norb, psi, ng, phi, ng, norb, norb, ng, 1.0, s, c->R()));
+  if (U) HIPCHK(c, hipMemcpyAsync(U, X, size_t(norb) * norb * sizeof(double), hipMemcpyDeviceToDevice, s));
+  rec_end(c->R(), ST_LOCALIZE, s);
+  HIPCHK(c, hipGetLastError());
+  return ACE_OK;
+}
+
+// ------------------------------------------------------------------ (b) pairlist
+int ace_pairlist(ace_ctx* c, const ace_grid* g, int norb, const double* phi, double rho_cut, int64_t capacity,
+                 int32_t* pairs, double* overlap, int64_t* npairs) {
+  if (!c) return ACE_E_ARG;
+  int rc = check_grid(c, g, norb);
+  if (rc) return rc;
+  if (!phi || !pairs || !npairs) return fail(c, ACE_E_ARG, "phi, pairs and npairs must be non-NULL");
+  if (capacity < 0) return fail(c, ACE_E_ARG, "negative capacity");
+  if (!std::isfinite(rho_cut)) return fail(c, ACE_E_ARG, "rho_cut must be finite");
+  const int64_t ng = grid_size(g);
+  hipStream_t s = c->stream;
+  rec_begin(c->R(), ST_PAIRLIST, s);
+  double *part, *O;
+  int64_t* cnt;
+  int64_t kchunk;
+  const int64_t nsplit = gemm_nt_nsplit(norb, norb, ng, &kchunk);
+  WS(c, "mpart", size_t(nsplit) * norb * norb * sizeof(double), part);
+  WS(c, "O", size_t(norb) * norb * sizeof(double), O);
+  WS(c, "cnt", 64, cnt);
+  HIPCHK(c, gemm_nt(0, true, phi, ng, phi, ng, norb, norb, ng, grid_dv(g), part, O, s, c->R()));
+  launch_compact_pairs(O, norb, rho_cut, capacity, pairs, overlap, cnt, s);
+  int64_t h = 0;
+  HIPCHK(c, hipMemcpyAsync(&h, cnt, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  rec_end(c->R(), ST_PAIRLIST, s);
+  HIPCHK(c, hipStreamSynchronize(s));
+  *npairs = h;
+  if (h > capacity) return fail(c, ACE_E_CAPACITY, "%lld pairs kept but capacity is %lld", (long long)h,
+                                (long long)capacity);
+  return ACE_OK;
+}
+
+// ------------------------------------------------------------------ (c)-(e) build
+int ace_build(ace_ctx* c, const ace_grid* g, int norb, const double* phi, const int32_t* pairs, int64_t npairs,
+              int kernel, double omega, int prec, double* xi, double* Mout, double* Wout, double* ex,
+              double* pair_energy) {
+  if (!c) return ACE_E_ARG;
+  int rc = check_grid(c, g, norb);
+  if (rc) return rc;
+  if (!phi || !pairs || !xi) return fail(c, ACE_E_ARG, "phi, pairs and xi must be non-NULL");
+  if (kernel != ACE_KERNEL_COULOMB && kernel != ACE_KERNEL_ERFC) return fail(c, ACE_E_ARG, "unknown kernel %d", kernel);
+  if (kernel == ACE_KERNEL_ERFC && !(omega > 0.0)) return fail(c, ACE_E_ARG, "omega must be > 0 for erfc");
+  if (prec != ACE_FP64 && prec != ACE_FP32) return fail(c, ACE_E_ARG, "unknown precision %d", prec);
+  const int64_t maxp = int64_t(norb) * (norb + 1) / 2;
+  if (npairs < 1 || npairs > maxp) return fail(c, ACE_E_ARG, "npairs=%lld outside [1, %lld]", (long long)npairs,
+                                               (long long)maxp);
+  const int N = g->n[0];
+  const int64_t ng = grid_size(g);
+  const double dV = grid_dv(g);
+  hipStream_t s = c->stream;
+  EventRecorder* R = c->R();
+
+  for (auto& o : c->rec.open) o.clear();
+  // pair list to the host for validation and scheduling
+  std::vector<int32_t> pr(size_t(2 * npairs));
+  HIPCHK(c, hipMemcpyAsync(pr.data(), pairs, pr.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  uint64_t h = 1469598103934665603ull;
+  {
+    std::vector<uint8_t> seen(size_t(norb) * norb, 0);
+    for (int64_t p = 0; p < npairs; ++p) {
+      const int i = pr[2 * p], j = pr[2 * p + 1];
+      if (i < 0 || j < i || j >= norb)
+        return fail(c, ACE_E_ARG, "pair %lld = (%d, %d) not 0 <= i <= j < norb", (long long)p, i, j);
+      if (seen[size_t(i) * norb + j]) return fail(c, ACE_E_ARG, "pair (%d, %d) listed twice", i, j);
+      seen[size_t(i) * norb + j] = 1;
+      h = (h ^ uint64_t(uint32_t(i) * 65599u + uint32_t(j))) * 1099511628211ull;
+    }
+  }
+  const int mp = max_packs_for(c, prec, N);
+  ScheduleKey key{npairs, norb, h ^ (uint64_t(mp) << 48)};
+  auto sit = c->schedules.find(key);
+  if (sit == c->schedules.end()) {
+    if (c->schedules.size() > 64) c->schedules.clear();
+    Schedule S;
+    make_schedule(pr, npairs, norb, mp, S);
+    sit = c->schedules.emplace(key, std::move(S)).first;
+  }
+  const Schedule& S = sit->second;
+  const int npk = int(S.packs.size());
+  rec_begin(R, ST_BUILD, s);
+
+  const size_t es = prec == 0 ? sizeof(double) : sizeof(float);
+  const PairShape sh = shape_for(c, prec, N);
+  const int nblk = pair_energy_blocks(N, sh);
+  void *W, *spec, *phiw;
+  Pack* dpk;
+  int64_t* dpidx;
+  double *epart = nullptr, *part, *Mraw, *Lb, *Li, *scal;
+  int* info;
+  WS(c, "W", size_t(norb) * ng * es, W);
+  WS(c, "spec", size_t(S.max_launch) * ng * 2 * es, spec);
+  WS(c, "packs", size_t(npk) * sizeof(Pack), dpk);
+  WS(c, "pidx", size_t(npk) * 2 * sizeof(int64_t), dpidx);
+  if (pair_energy) WS(c, "epart", size_t(S.max_launch) * nblk * 2 * sizeof(double), epart);
+  int64_t kchunk;
+  const int64_t nsplit = gemm_nt_nsplit(norb, norb, ng, &kchunk);
+  WS(c, "mpart", size_t(nsplit) * norb * norb * sizeof(double), part);
+  WS(c, "Mraw", size_t(norb) * norb * sizeof(double), Mraw);
+  WS(c, "Lc", size_t(norb) * norb * sizeof(double), Lb);
+  WS(c, "Linv", size_t(norb) * norb * sizeof(double), Li);
+  WS(c, "scal", 64 * sizeof(double), scal);
+  WS(c, "info", 64, info);
+  if (prec == 1) WS(c, "phi32", size_t(norb) * ng * sizeof(float), phiw);
+  else phiw = (void*)phi;
+  const void* tw;
+  rc = twiddles(c, N, prec, &tw);
+  if (rc) return rc;
+
+  HIPCHK(c, hipMemcpyAsync(dpk, S.packs.data(), size_t(npk) * sizeof(Pack), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(dpidx, S.pidx.data(), size_t(npk) * 2 * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  if (prec == 1) launch_d2f(phi, (float*)phiw, int64_t(norb) * ng, s);
+  HIPCHK(c, hipMemsetAsync(W, 0, size_t(norb) * ng * es, s));
+
+  KernelParams kp;
+  kp.kind = kernel;
+  kp.omega = omega;
+  kp.inv_ng = 1.0 / double(ng);
+  for (int d = 0; d < 3; ++d) kp.g[d] = 2.0 * 3.141592653589793238462643383279502884 / g->L[d];
+
+  // (c) pair Poisson solves, round by round
+  rec_begin(R, ST_PAIRS, s);
+  for (const auto& L : S.launches) {
+    HIPCHK(c, pair_round(prec, N, sh, phiw, spec, dpk + L.first, L.second, L.npairs, W, epart, tw, kp, s, R));
+    if (pair_energy)
+      launch_pair_energy(epart, L.second, nblk, dpk + L.first, dpidx + 2 * L.first, dV, pair_energy, s);
+  }
+  rec_end(R, ST_PAIRS, s);
+
+  // W is an output of step (c) whatever the factorization below reports
+  if (Wout) {
+    if (prec == 0)
+      HIPCHK(c, hipMemcpyAsync(Wout, W, size_t(norb) * ng * sizeof(double), hipMemcpyDeviceToDevice, s));
+    else
+      launch_f2d((const float*)W, Wout, int64_t(norb) * ng, s);
+  }
+
+  // (d) M = dV Phi W^T, symmetrize, -M = L L^T
+  rec_begin(R, ST_TAIL, s);
+  HIPCHK(c, gemm_nt(prec, false, phiw, ng, W, ng, norb, norb, ng, dV, part, Mraw, s, R));
+  launch_symmetrize(Mraw, norb, Mout, Lb, ex ? ex : scal, scal + 1, s);
+  launch_cholesky(Lb, norb, info, s);
+  int hinfo = 0;
+  HIPCHK(c, hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  if (hinfo > 0) return fail(c, ACE_E_NOT_PD, "-M is not positive definite (Cholesky column %d)", hinfo - 1);
+  if (hinfo < 0) return fail(c, ACE_E_NONFINITE, "non-finite value in M (Cholesky column %d)", -hinfo - 1);
+  // (e) xi = L^-1 W
+  launch_trinv(Lb, norb, Li, s);
+  HIPCHK(c, gemm_ls(prec, false, true, Li, norb, W, ng, xi, ng, norb, norb, ng, 1.0, s, R));
+  rec_end(R, ST_TAIL, s);
+  rec_end(R, ST_BUILD, s);
+  HIPCHK(c, hipGetLastError());
+  return ACE_OK;
+}
+
+// ------------------------------------------------------------------ apply
+int ace_apply(ace_ctx* c, const ace_grid* g, int norb, const double* xi, int nvec, const double* x, double* y) {
+  if (!c) return ACE_E_ARG;
+  int rc = check_grid(c, g, norb);
+  if (rc) return rc;
+  if (!xi || !x || !y) return fail(c, ACE_E_ARG, "xi, x and y must be non-NULL");
+  if (nvec < 1) return fail(c, ACE_E_ARG, "nvec must be >= 1");
+  const int64_t ng = grid_size(g);
+  hipStream_t s = c->stream;
+  double *part, *cb;
+  int64_t kchunk;
+  const int64_t nsplit = gemm_nt_nsplit(norb, nvec, ng, &kchunk);
+  WS(c, "apart", size_t(nsplit) * norb * nvec * sizeof(double), part);
+  WS(c, "coef", size_t(norb) * nvec * sizeof(double), cb);
+  HIPCHK(c, gemm_nt(0, false, xi, ng, x, ng, norb, nvec, ng, grid_dv(g), part, cb, s, c->R()));
+  HIPCHK(c, gemm_ls(0, true, false, cb, nvec, xi, ng, y, ng, nvec, norb, ng, -1.0, s, c->R()));
+  return ACE_OK;
+}
+
+}  // extern "C"

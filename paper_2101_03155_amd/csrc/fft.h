@@ -1,0 +1,209 @@
+// Batched mixed-radix FFT building blocks for gfx950 (CDNA4), operating on
+// lines held in LDS.
+//
+// The pair Poisson solve of Eq. (e:vij) transforms every orbital-pair density
+// to reciprocal space and back.  A line of length N (N = 2^a 3^b 5^c) is
+// transformed by a sequence of Stockham autosort passes with radices 8, 4, 2,
+// 3 and 5; each pass reads R elements per butterfly into registers, applies
+// the twiddles and a length-R DFT, and writes them back to their
+// sorted-order positions in the same LDS buffer (a barrier separates the
+// reads from the writes, so one buffer suffices).  The radix plan, the number
+// of butterflies per thread and all strides are compile-time constants, so
+// every register array is statically indexed.
+//
+// Sign convention: forward uses exp(-2 pi i jk/N), inverse exp(+2 pi i jk/N),
+// both unnormalized (the 1/N^3 of the inverse is folded into the kernel v(G)).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace ace {
+
+template <typename T> struct cplx_t;
+template <> struct cplx_t<double> { using type = double2; };
+template <> struct cplx_t<float> { using type = float2; };
+template <typename T> using cplx = typename cplx_t<T>::type;
+
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { C r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { C r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
+  C r; r.x = a.x * b.x - a.y * b.y; r.y = a.x * b.y + a.y * b.x; return r;
+}
+// multiply by conj(b)
+template <typename C> __device__ __forceinline__ C cmulc(C a, C b) {
+  C r; r.x = a.x * b.x + a.y * b.y; r.y = a.y * b.x - a.x * b.y; return r;
+}
+// multiply by s*i (s = +1 or -1)
+template <int S, typename C> __device__ __forceinline__ C cmul_si(C a) {
+  C r;
+  if (S > 0) { r.x = -a.y; r.y = a.x; } else { r.x = a.y; r.y = -a.x; }
+  return r;
+}
+template <typename C, typename T> __device__ __forceinline__ C cscale(C a, T s) { C r; r.x = a.x * s; r.y = a.y * s; return r; }
+
+// ---------------------------------------------------------------- radix plan
+// 2^a is split into radix-8 passes with a 4,4 / 4 / 2 remainder; then one
+// radix-3 pass per factor 3 and one radix-5 pass per factor 5.
+constexpr int pow_of(int n, int p) { int a = 0; while (n % p == 0) { n /= p; ++a; } return a; }
+constexpr bool smooth235(int n) {
+  while (n % 2 == 0) n /= 2;
+  while (n % 3 == 0) n /= 3;
+  while (n % 5 == 0) n /= 5;
+  return n == 1;
+}
+constexpr int plan_len(int n) {
+  int a = pow_of(n, 2), cnt = 0;
+  while (a >= 3 && a != 4) { a -= 3; ++cnt; }
+  if (a == 4) cnt += 2; else if (a > 0) cnt += 1;
+  return cnt + pow_of(n, 3) + pow_of(n, 5);
+}
+constexpr int plan_radix(int n, int p) {
+  int a = pow_of(n, 2);
+  int r[24] = {0};
+  int cnt = 0;
+  while (a >= 3 && a != 4) { a -= 3; r[cnt++] = 8; }
+  if (a == 4) { r[cnt++] = 4; r[cnt++] = 4; } else if (a == 2) r[cnt++] = 4; else if (a == 1) r[cnt++] = 2;
+  for (int i = 0; i < pow_of(n, 3); ++i) r[cnt++] = 3;
+  for (int i = 0; i < pow_of(n, 5); ++i) r[cnt++] = 5;
+  return r[p];
+}
+// product of the radices of passes 0..p-1
+constexpr int plan_ns(int n, int p) { int s = 1; for (int i = 0; i < p; ++i) s *= plan_radix(n, i); return s; }
+
+// ---------------------------------------------------------------- small DFTs
+// In-register DFT of length R with exponent sign S (-1 forward, +1 inverse).
+template <int R, int S, typename C> struct Dft;
+
+template <int S, typename C> struct Dft<2, S, C> {
+  static __device__ __forceinline__ void run(C* v) {
+    C a = v[0], b = v[1];
+    v[0] = cadd(a, b); v[1] = csub(a, b);
+  }
+};
+
+template <int S, typename C> struct Dft<3, S, C> {
+  static __device__ __forceinline__ void run(C* v) {
+    using T = decltype(v[0].x);
+    const T h = T(0.866025403784438646763723170752936183);  // sin(2 pi/3)
+    C t1 = cadd(v[1], v[2]);
+    C t2 = csub(v[0], cscale(t1, T(0.5)));
+    C t3 = cmul_si<S>(cscale(csub(v[1], v[2]), h));
+    v[0] = cadd(v[0], t1);
+    v[1] = cadd(t2, t3);
+    v[2] = csub(t2, t3);
+  }
+};
+
+template <int S, typename C> struct Dft<4, S, C> {
+  static __device__ __forceinline__ void run(C* v) {
+    C a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+    C c = cadd(v[1], v[3]), d = cmul_si<S>(csub(v[1], v[3]));
+    v[0] = cadd(a, c); v[2] = csub(a, c);
+    v[1] = cadd(b, d); v[3] = csub(b, d);
+  }
+};
+
+template <int S, typename C> struct Dft<5, S, C> {
+  static __device__ __forceinline__ void run(C* v) {
+    using T = decltype(v[0].x);
+    const T c1 = T(0.309016994374947424102293417182819059);   // cos(2 pi/5)
+    const T c2 = T(-0.809016994374947424102293417182819059);  // cos(4 pi/5)
+    const T s1 = T(0.951056516295153572116439333379382143);   // sin(2 pi/5)
+    const T s2 = T(0.587785252292473129168705954639072769);   // sin(4 pi/5)
+    C t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+    C t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
+    C a1 = cadd(v[0], cadd(cscale(t1, c1), cscale(t2, c2)));
+    C a2 = cadd(v[0], cadd(cscale(t1, c2), cscale(t2, c1)));
+    C b1 = cmul_si<S>(cadd(cscale(t3, s1), cscale(t4, s2)));
+    C b2 = cmul_si<S>(csub(cscale(t3, s2), cscale(t4, s1)));
+    v[0] = cadd(v[0], cadd(t1, t2));
+    v[1] = cadd(a1, b1); v[4] = csub(a1, b1);
+    v[2] = cadd(a2, b2); v[3] = csub(a2, b2);
+  }
+};
+
+template <int S, typename C> struct Dft<8, S, C> {
+  static __device__ __forceinline__ void run(C* v) {
+    using T = decltype(v[0].x);
+    const T r2 = T(0.707106781186547524400844362104849039);
+    C e[4] = {v[0], v[2], v[4], v[6]};
+    C o[4] = {v[1], v[3], v[5], v[7]};
+    Dft<4, S, C>::run(e);
+    Dft<4, S, C>::run(o);
+    // o[k] *= W8^k with W8 = (1 + S i)/sqrt 2
+    C o1; o1.x = r2 * (o[1].x - S * o[1].y); o1.y = r2 * (o[1].y + S * o[1].x);
+    C o2 = cmul_si<S>(o[2]);
+    C o3; o3.x = r2 * (-o[3].x - S * o[3].y); o3.y = r2 * (-o[3].y + S * o[3].x);
+    v[0] = cadd(e[0], o[0]); v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);   v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);   v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);   v[7] = csub(e[3], o3);
+  }
+};
+
+// ---------------------------------------------------------------- one pass
+// LINES lines of length N in LDS; element p of line l at buf[l*LS + p*PS].
+// JFAST: consecutive threads take consecutive butterflies of one line
+// (unit-stride lines) rather than the same butterfly of consecutive lines.
+template <typename T, int N, int P, int LINES, int LS, int PS, int NT, int S, bool JFAST>
+__device__ __forceinline__ void fft_pass(cplx<T>* buf, const cplx<T>* tw, int tid) {
+  using C = cplx<T>;
+  constexpr int R = plan_radix(N, P);
+  constexpr int NS = plan_ns(N, P);
+  constexpr int NB = N / R;
+  constexpr int TOT = LINES * NB;
+  constexpr int PER = (TOT + NT - 1) / NT;
+  constexpr int TSTEP = N / (NS * R);
+  C v[PER][R];
+#pragma unroll
+  for (int s = 0; s < PER; ++s) {
+    const int b = tid + s * NT;
+    if ((TOT % NT) == 0 || b < TOT) {
+      const int l = JFAST ? b / NB : b % LINES;
+      const int j = JFAST ? b % NB : b / LINES;
+      const C* base = buf + l * LS;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[s][r] = base[(j + r * NB) * PS];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < PER; ++s) {
+    const int b = tid + s * NT;
+    if ((TOT % NT) == 0 || b < TOT) {
+      const int l = JFAST ? b / NB : b % LINES;
+      const int j = JFAST ? b % NB : b / LINES;
+      const int k = j % NS;
+      if (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const C w = tw[r * k * TSTEP];
+          v[s][r] = (S < 0) ? cmul(v[s][r], w) : cmulc(v[s][r], w);
+        }
+      }
+      Dft<R, S, C>::run(v[s]);
+      C* base = buf + l * LS;
+      const int o = (j / NS) * NS * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) base[(o + r * NS) * PS] = v[s][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int N, int P, int LINES, int LS, int PS, int NT, int S, bool JFAST>
+__device__ __forceinline__ void fft_lines_from(cplx<T>* buf, const cplx<T>* tw, int tid) {
+  if constexpr (P < plan_len(N)) {
+    fft_pass<T, N, P, LINES, LS, PS, NT, S, JFAST>(buf, tw, tid);
+    fft_lines_from<T, N, P + 1, LINES, LS, PS, NT, S, JFAST>(buf, tw, tid);
+  }
+}
+
+// Full length-N transform of LINES lines held in LDS.  tw[m] = exp(-2 pi i m/N).
+// Expects the caller to have synchronized after filling buf; ends synchronized.
+template <typename T, int N, int LINES, int LS, int PS, int NT, int S, bool JFAST>
+__device__ __forceinline__ void fft_lines(cplx<T>* buf, const cplx<T>* tw, int tid) {
+  static_assert(smooth235(N), "FFT length must be 2^a 3^b 5^c");
+  fft_lines_from<T, N, 0, LINES, LS, PS, NT, S, JFAST>(buf, tw, tid);
+}
+
+}  // namespace ace

@@ -1,0 +1,391 @@
+// Pair Poisson solves and W accumulation (step (c) of the ACE build).
+//
+// For every kept orbital pair (i, j) the exchange operator of Eq. (vx) needs
+// v_ij = K * (phi_i phi_j), the periodic convolution of the pair density with
+// the interaction kernel, computed in reciprocal space as in Eq. (e:vij):
+// forward 3D FFT, multiplication by v(G), inverse 3D FFT.  The contribution
+// -v_ij phi_j is added to W_i and, for i != j, -v_ij phi_i to W_j.
+//
+// Two real pair densities are packed into one complex field (real part pair
+// a, imaginary part pair b).  Because v(G) is real and even in G, the product
+// v(G) * FFT(rho_a + i rho_b) transforms back to v_a + i v_b exactly, so one
+// complex 3D FFT pair serves two orbital pairs.
+//
+// Data layout: grids are [z][y][x] with x fastest; the spectrum of a pack is
+// N^3 complex values in the same [z][y][x] order (in place through all
+// passes).  A round of packs is conflict-free (no orbital appears twice), so
+// the W read-modify-writes of one launch never collide: no atomics, and the
+// result does not depend on scheduling.
+//
+// Two launch paths:
+//  * fused: (product + x FFT + y FFT) per z-plane in one workgroup with the
+//    plane in LDS; (z FFT, v(G), inverse z FFT) per x-tile column block;
+//    (inverse y FFT + inverse x FFT + accumulate) per z-plane.  Three
+//    HBM round trips of the spectrum per direction pair.
+//  * split (planes larger than LDS): x, y and z passes as separate kernels.
+#include "ace_internal.h"
+#include "fft.h"
+
+namespace ace {
+
+__host__ __device__ constexpr int pick_tx(int n) { return (n % 16 == 0) ? 16 : (n % 8 == 0) ? 8 : (n % 4 == 0) ? 4 : 2; }
+__host__ __device__ constexpr int pick_rows(int n) { return (n % 8 == 0) ? 8 : (n % 4 == 0) ? 4 : 2; }
+
+template <typename T, int N>
+constexpr bool fused_fits_t() {
+  return (size_t(N) * N + N) * sizeof(cplx<T>) + 1024 <= 163840;
+}
+
+// v(G)/N^3 at integer grid frequencies (kx, ky, kz) in FFT order.
+template <typename T, int N>
+__device__ __forceinline__ T kernel_value(const KernelParams& kp, int kx, int ky, int kz) {
+  const int sx = kx < (N + 1) / 2 ? kx : kx - N;
+  const int sy = ky < (N + 1) / 2 ? ky : ky - N;
+  const int sz = kz < (N + 1) / 2 ? kz : kz - N;
+  const double gx = kp.g[0] * sx, gy = kp.g[1] * sy, gz = kp.g[2] * sz;
+  const double g2 = gx * gx + gy * gy + gz * gz;
+  const double four_pi = 12.566370614359172953850573533118011537;
+  double v;
+  if (g2 == 0.0) {
+    v = (kp.kind == 0) ? 0.0 : 3.14159265358979323846264338327950288 / (kp.omega * kp.omega);
+  } else if (kp.kind == 0) {
+    v = four_pi / g2;
+  } else {
+    v = -four_pi / g2 * expm1(-g2 / (4.0 * kp.omega * kp.omega));
+  }
+  return T(v * kp.inv_ng);
+}
+
+template <typename T, int NT>
+__device__ __forceinline__ void block_sum2(T a, T b, double* out, double* red) {
+  double x = a, y = b;
+  for (int off = 32; off > 0; off >>= 1) {
+    x += __shfl_down(x, off, 64);
+    y += __shfl_down(y, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) { red[2 * wv] = x; red[2 * wv + 1] = y; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sx = 0, sy = 0;
+    for (int w = 0; w < NT / 64; ++w) { sx += red[2 * w]; sy += red[2 * w + 1]; }
+    out[0] = sx; out[1] = sy;
+  }
+}
+
+// ------------------------------------------------------------ fused path
+
+template <typename T, int N, int NT>
+__global__ __launch_bounds__(NT) void k_fwd_xy(const T* __restrict__ phi, cplx<T>* __restrict__ spec,
+                                               const Pack* __restrict__ packs,
+                                               const cplx<T>* __restrict__ twg) {
+  using C = cplx<T>;
+  constexpr int P2 = N * N;
+  constexpr size_t NG = size_t(N) * N * N;
+  __shared__ C buf[P2];
+  __shared__ C tw[N];
+  const int tid = threadIdx.x, z = blockIdx.x, p = blockIdx.y;
+  const Pack pk = packs[p];
+  for (int i = tid; i < N; i += NT) tw[i] = twg[i];
+  const size_t zo = size_t(z) * P2;
+  const T* pia = phi + size_t(pk.ia) * NG + zo;
+  const T* pja = phi + size_t(pk.ja) * NG + zo;
+  if (pk.jb >= 0) {
+    const T* pib = phi + size_t(pk.ib) * NG + zo;
+    const T* pjb = phi + size_t(pk.jb) * NG + zo;
+    for (int e = tid; e < P2; e += NT) {
+      C v; v.x = pia[e] * pja[e]; v.y = pib[e] * pjb[e];
+      buf[e] = v;
+    }
+  } else {
+    for (int e = tid; e < P2; e += NT) {
+      C v; v.x = pia[e] * pja[e]; v.y = T(0);
+      buf[e] = v;
+    }
+  }
+  __syncthreads();
+  fft_lines<T, N, N, N, 1, NT, -1, true>(buf, tw, tid);   // x: rows
+  fft_lines<T, N, N, 1, N, NT, -1, false>(buf, tw, tid);  // y: columns
+  C* out = spec + size_t(p) * NG + zo;
+  for (int e = tid; e < P2; e += NT) out[e] = buf[e];
+}
+
+template <typename T, int N, int NT, bool EN>
+__global__ __launch_bounds__(NT) void k_inv_xy(const T* __restrict__ phi, const cplx<T>* __restrict__ spec,
+                                               const Pack* __restrict__ packs, T* __restrict__ W,
+                                               double* __restrict__ epart,
+                                               const cplx<T>* __restrict__ twg) {
+  using C = cplx<T>;
+  constexpr int P2 = N * N;
+  constexpr size_t NG = size_t(N) * N * N;
+  __shared__ C buf[P2];
+  __shared__ C tw[N];
+  __shared__ double red[2 * (NT / 64)];
+  const int tid = threadIdx.x, z = blockIdx.x, p = blockIdx.y;
+  const Pack pk = packs[p];
+  for (int i = tid; i < N; i += NT) tw[i] = twg[i];
+  const size_t zo = size_t(z) * P2;
+  const C* in = spec + size_t(p) * NG + zo;
+  for (int e = tid; e < P2; e += NT) buf[e] = in[e];
+  __syncthreads();
+  fft_lines<T, N, N, 1, N, NT, +1, false>(buf, tw, tid);  // y
+  fft_lines<T, N, N, N, 1, NT, +1, true>(buf, tw, tid);   // x
+  const T* pia = phi + size_t(pk.ia) * NG + zo;
+  const T* pja = phi + size_t(pk.ja) * NG + zo;
+  T* wia = W + size_t(pk.ia) * NG + zo;
+  T* wja = W + size_t(pk.ja) * NG + zo;
+  T ea = T(0), eb = T(0);
+  const bool offa = pk.ia != pk.ja;
+  for (int e = tid; e < P2; e += NT) {
+    const T v = buf[e].x, fi = pia[e], fj = pja[e];
+    wia[e] -= v * fj;
+    if (offa) wja[e] -= v * fi;
+    if (EN) ea += v * fi * fj;
+  }
+  if (pk.jb >= 0) {
+    const T* pib = phi + size_t(pk.ib) * NG + zo;
+    const T* pjb = phi + size_t(pk.jb) * NG + zo;
+    T* wib = W + size_t(pk.ib) * NG + zo;
+    T* wjb = W + size_t(pk.jb) * NG + zo;
+    const bool offb = pk.ib != pk.jb;
+    for (int e = tid; e < P2; e += NT) {
+      const T v = buf[e].y, fi = pib[e], fj = pjb[e];
+      wib[e] -= v * fj;
+      if (offb) wjb[e] -= v * fi;
+      if (EN) eb += v * fi * fj;
+    }
+  }
+  if (EN) block_sum2<T, NT>(ea, eb, epart + 2 * (size_t(p) * N + z), red);
+}
+
+// ------------------------------------------------------------ z pass (both paths)
+
+template <typename T, int N, int TX, int NT>
+__global__ __launch_bounds__(NT) void k_conv_z(cplx<T>* __restrict__ spec, const cplx<T>* __restrict__ twg,
+                                               KernelParams kp) {
+  using C = cplx<T>;
+  constexpr size_t NG = size_t(N) * N * N;
+  constexpr int E = N * TX;
+  __shared__ C buf[E];
+  __shared__ C tw[N];
+  const int tid = threadIdx.x, x0 = blockIdx.x * TX, y = blockIdx.y, p = blockIdx.z;
+  for (int i = tid; i < N; i += NT) tw[i] = twg[i];
+  C* base = spec + size_t(p) * NG + size_t(y) * N + x0;
+  for (int e = tid; e < E; e += NT) buf[e] = base[size_t(e / TX) * N * N + (e % TX)];
+  __syncthreads();
+  fft_lines<T, N, TX, 1, TX, NT, -1, false>(buf, tw, tid);
+  for (int e = tid; e < E; e += NT) {
+    const T v = kernel_value<T, N>(kp, x0 + e % TX, y, e / TX);
+    C c = buf[e];
+    c.x *= v; c.y *= v;
+    buf[e] = c;
+  }
+  __syncthreads();
+  fft_lines<T, N, TX, 1, TX, NT, +1, false>(buf, tw, tid);
+  for (int e = tid; e < E; e += NT) base[size_t(e / TX) * N * N + (e % TX)] = buf[e];
+}
+
+// ------------------------------------------------------------ split path
+
+template <typename T, int N, int ROWS, int NT>
+__global__ __launch_bounds__(NT) void k_fwd_x(const T* __restrict__ phi, cplx<T>* __restrict__ spec,
+                                              const Pack* __restrict__ packs,
+                                              const cplx<T>* __restrict__ twg) {
+  using C = cplx<T>;
+  constexpr size_t NG = size_t(N) * N * N;
+  constexpr int E = ROWS * N;
+  __shared__ C buf[E];
+  __shared__ C tw[N];
+  const int tid = threadIdx.x, p = blockIdx.y;
+  const size_t ro = size_t(blockIdx.x) * E;
+  const Pack pk = packs[p];
+  for (int i = tid; i < N; i += NT) tw[i] = twg[i];
+  const T* pia = phi + size_t(pk.ia) * NG + ro;
+  const T* pja = phi + size_t(pk.ja) * NG + ro;
+  if (pk.jb >= 0) {
+    const T* pib = phi + size_t(pk.ib) * NG + ro;
+    const T* pjb = phi + size_t(pk.jb) * NG + ro;
+    for (int e = tid; e < E; e += NT) { C v; v.x = pia[e] * pja[e]; v.y = pib[e] * pjb[e]; buf[e] = v; }
+  } else {
+    for (int e = tid; e < E; e += NT) { C v; v.x = pia[e] * pja[e]; v.y = T(0); buf[e] = v; }
+  }
+  __syncthreads();
+  fft_lines<T, N, ROWS, N, 1, NT, -1, true>(buf, tw, tid);
+  C* out = spec + size_t(p) * NG + ro;
+  for (int e = tid; e < E; e += NT) out[e] = buf[e];
+}
+
+// Lines along y: element (y, t) of block (xtile, z) at z*N*N + y*N + x0 + t.
+template <typename T, int N, int TX, int NT, int S>
+__global__ __launch_bounds__(NT) void k_line_y(cplx<T>* __restrict__ spec, const cplx<T>* __restrict__ twg) {
+  using C = cplx<T>;
+  constexpr size_t NG = size_t(N) * N * N;
+  constexpr int E = N * TX;
+  __shared__ C buf[E];
+  __shared__ C tw[N];
+  const int tid = threadIdx.x, x0 = blockIdx.x * TX, z = blockIdx.y, p = blockIdx.z;
+  for (int i = tid; i < N; i += NT) tw[i] = twg[i];
+  C* base = spec + size_t(p) * NG + size_t(z) * N * N + x0;
+  for (int e = tid; e < E; e += NT) buf[e] = base[size_t(e / TX) * N + (e % TX)];
+  __syncthreads();
+  fft_lines<T, N, TX, 1, TX, NT, S, false>(buf, tw, tid);
+  for (int e = tid; e < E; e += NT) base[size_t(e / TX) * N + (e % TX)] = buf[e];
+}
+
+template <typename T, int N, int ROWS, int NT, bool EN>
+__global__ __launch_bounds__(NT) void k_inv_x(const T* __restrict__ phi, const cplx<T>* __restrict__ spec,
+                                              const Pack* __restrict__ packs, T* __restrict__ W,
+                                              double* __restrict__ epart,
+                                              const cplx<T>* __restrict__ twg) {
+  using C = cplx<T>;
+  constexpr size_t NG = size_t(N) * N * N;
+  constexpr int E = ROWS * N;
+  __shared__ C buf[E];
+  __shared__ C tw[N];
+  __shared__ double red[2 * (NT / 64)];
+  const int tid = threadIdx.x, p = blockIdx.y;
+  const size_t ro = size_t(blockIdx.x) * E;
+  const Pack pk = packs[p];
+  for (int i = tid; i < N; i += NT) tw[i] = twg[i];
+  const C* in = spec + size_t(p) * NG + ro;
+  for (int e = tid; e < E; e += NT) buf[e] = in[e];
+  __syncthreads();
+  fft_lines<T, N, ROWS, N, 1, NT, +1, true>(buf, tw, tid);
+  const T* pia = phi + size_t(pk.ia) * NG + ro;
+  const T* pja = phi + size_t(pk.ja) * NG + ro;
+  T* wia = W + size_t(pk.ia) * NG + ro;
+  T* wja = W + size_t(pk.ja) * NG + ro;
+  T ea = T(0), eb = T(0);
+  const bool offa = pk.ia != pk.ja;
+  for (int e = tid; e < E; e += NT) {
+    const T v = buf[e].x, fi = pia[e], fj = pja[e];
+    wia[e] -= v * fj;
+    if (offa) wja[e] -= v * fi;
+    if (EN) ea += v * fi * fj;
+  }
+  if (pk.jb >= 0) {
+    const T* pib = phi + size_t(pk.ib) * NG + ro;
+    const T* pjb = phi + size_t(pk.jb) * NG + ro;
+    T* wib = W + size_t(pk.ib) * NG + ro;
+    T* wjb = W + size_t(pk.jb) * NG + ro;
+    const bool offb = pk.ib != pk.jb;
+    for (int e = tid; e < E; e += NT) {
+      const T v = buf[e].y, fi = pib[e], fj = pjb[e];
+      wib[e] -= v * fj;
+      if (offb) wjb[e] -= v * fi;
+      if (EN) eb += v * fi * fj;
+    }
+  }
+  if (EN) block_sum2<T, NT>(ea, eb, epart + 2 * (size_t(p) * gridDim.x + blockIdx.x), red);
+}
+
+// ------------------------------------------------------------ dispatch
+
+template <typename T, int N>
+static hipError_t pair_round_t(const PairShape& sh, const void* phi_, void* spec_, const Pack* packs,
+                               int npacks, int npairs, void* W_, double* epart, const void* tw_,
+                               const KernelParams& kp, hipStream_t s, EventRecorder* rec) {
+  using C = cplx<T>;
+  const T* phi = static_cast<const T*>(phi_);
+  T* W = static_cast<T*>(W_);
+  C* spec = static_cast<C*>(spec_);
+  const C* tw = static_cast<const C*>(tw_);
+  constexpr int TX = pick_tx(N);
+  constexpr int NTL = 256;
+  if (npacks <= 0) return hipSuccess;
+  // algorithmic HBM bytes per orbital pair, in units of N^3 * sizeof(T):
+  // read phi_i, phi_j (2) + spectrum write (1) | spectrum read + write (2) |
+  // spectrum read (1) + phi re-read (2) + W_i, W_j read-modify-write (4)
+  const double u = double(npairs) * double(N) * N * N * sizeof(T);
+  if constexpr (fused_fits_t<T, N>()) {
+    if (sh.fused_xy) {
+      constexpr int NTP = 512;
+      rec_begin(rec, KC_FWD_XY, s);
+      hipLaunchKernelGGL((k_fwd_xy<T, N, NTP>), dim3(N, npacks), dim3(NTP), 0, s, phi, spec, packs, tw);
+      rec_end(rec, KC_FWD_XY, s, 3 * u);
+      rec_begin(rec, KC_CONV_Z, s);
+      hipLaunchKernelGGL((k_conv_z<T, N, TX, NTL>), dim3(N / TX, N, npacks), dim3(NTL), 0, s, spec, tw, kp);
+      rec_end(rec, KC_CONV_Z, s, 2 * u);
+      rec_begin(rec, KC_INV_XY, s);
+      if (epart)
+        hipLaunchKernelGGL((k_inv_xy<T, N, NTP, true>), dim3(N, npacks), dim3(NTP), 0, s, phi, spec, packs, W, epart, tw);
+      else
+        hipLaunchKernelGGL((k_inv_xy<T, N, NTP, false>), dim3(N, npacks), dim3(NTP), 0, s, phi, spec, packs, W, epart, tw);
+      rec_end(rec, KC_INV_XY, s, 7 * u);
+      return hipGetLastError();
+    }
+  }
+  constexpr int ROWS = pick_rows(N);
+  const int nrb = N * N / ROWS;
+  rec_begin(rec, KC_FWD_X, s);
+  hipLaunchKernelGGL((k_fwd_x<T, N, ROWS, NTL>), dim3(nrb, npacks), dim3(NTL), 0, s, phi, spec, packs, tw);
+  rec_end(rec, KC_FWD_X, s, 3 * u);
+  rec_begin(rec, KC_FWD_Y, s);
+  hipLaunchKernelGGL((k_line_y<T, N, TX, NTL, -1>), dim3(N / TX, N, npacks), dim3(NTL), 0, s, spec, tw);
+  rec_end(rec, KC_FWD_Y, s, 2 * u);
+  rec_begin(rec, KC_CONV_Z, s);
+  hipLaunchKernelGGL((k_conv_z<T, N, TX, NTL>), dim3(N / TX, N, npacks), dim3(NTL), 0, s, spec, tw, kp);
+  rec_end(rec, KC_CONV_Z, s, 2 * u);
+  rec_begin(rec, KC_INV_Y, s);
+  hipLaunchKernelGGL((k_line_y<T, N, TX, NTL, +1>), dim3(N / TX, N, npacks), dim3(NTL), 0, s, spec, tw);
+  rec_end(rec, KC_INV_Y, s, 2 * u);
+  rec_begin(rec, KC_INV_X, s);
+  if (epart)
+    hipLaunchKernelGGL((k_inv_x<T, N, ROWS, NTL, true>), dim3(nrb, npacks), dim3(NTL), 0, s, phi, spec, packs, W, epart, tw);
+  else
+    hipLaunchKernelGGL((k_inv_x<T, N, ROWS, NTL, false>), dim3(nrb, npacks), dim3(NTL), 0, s, phi, spec, packs, W, epart, tw);
+  rec_end(rec, KC_INV_X, s, 7 * u);
+  return hipGetLastError();
+}
+
+#define ACE_PAIR_SIZES(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(80) X(96) X(100) X(108) X(120) X(160)
+
+bool pair_supported(int N) {
+  switch (N) {
+#define X(n) case n: return true;
+    ACE_PAIR_SIZES(X)
+#undef X
+    default: return false;
+  }
+}
+
+bool pair_fused_fits(int prec, int N) {
+  switch (N) {
+#define X(n) case n: return prec == 0 ? fused_fits_t<double, n>() : fused_fits_t<float, n>();
+    ACE_PAIR_SIZES(X)
+#undef X
+    default: return false;
+  }
+}
+
+PairShape pair_default_shape(int prec, int N) {
+  PairShape sh;
+  sh.fused_xy = pair_fused_fits(prec, N) ? 1 : 0;
+  sh.nt_xy = 512;
+  sh.tx = pick_tx(N);
+  return sh;
+}
+
+int pair_energy_blocks(int N, const PairShape& sh) {
+  if (sh.fused_xy) return N;
+  return N * N / pick_rows(N);
+}
+
+hipError_t pair_round(int prec, int N, const PairShape& sh, const void* phi, void* spec,
+                      const Pack* packs, int npacks, int npairs, void* W, double* epart, const void* tw,
+                      const KernelParams& kp, hipStream_t s, EventRecorder* rec) {
+  PairShape use = sh;
+  if (!pair_fused_fits(prec, N)) use.fused_xy = 0;
+  switch (N) {
+#define X(n)                                                                                          \
+  case n:                                                                                             \
+    return prec == 0 ? pair_round_t<double, n>(use, phi, spec, packs, npacks, npairs, W, epart, tw, kp, s, rec) \
+                     : pair_round_t<float, n>(use, phi, spec, packs, npacks, npairs, W, epart, tw, kp, s, rec);
+    ACE_PAIR_SIZES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace ace

@@ -1,0 +1,295 @@
+"""GPU parity: every C-ABI entry point against the FP64 oracle on the same
+seeded inputs.  Tolerances: |dE_x|/|E_x| <= 1e-10 (FP64) and <= 1e-6 (FP32);
+ACE matrix elements <= 1e-5 Ha; integer outputs (pivots, pair lists) exact."""
+import numpy as np
+import pytest
+
+import oracle
+from synth import SystemSpec, config_spec, make_orbitals, smooth_test_vectors
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    return lib.Context()
+
+
+def _dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+
+
+def _full_pairs(n):
+    return np.array([(i, j) for i in range(n) for j in range(i, n)], dtype=np.int32)
+
+
+def _grid(spec):
+    from paper_2101_03155_amd import Grid
+    return Grid.cubic(spec.N, spec.L)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+# ------------------------------------------------------------------ GEMMs via apply
+
+@pytest.mark.parametrize("norb,nvec,n", [(5, 3, 8), (70, 66, 12), (130, 1, 16)])
+def test_apply_matches_oracle_ragged(ctx, norb, nvec, n):
+    _say(f"apply norb={norb} nvec={nvec} N={n}")
+    from paper_2101_03155_amd import Grid
+    rng = np.random.default_rng(norb * 1000 + nvec)
+    xi = rng.normal(size=(norb, n, n, n))
+    x = rng.normal(size=(nvec, n, n, n))
+    g = Grid.cubic(n, 6.0)
+    y = ctx.apply(_dev(xi), _dev(x), g).cpu().numpy()
+    ref = oracle.ace_apply(xi, x, g.dV)
+    assert _rel(y, ref) < 1e-13
+
+
+# ------------------------------------------------------------------ c1 end to end
+
+@pytest.fixture(scope="module")
+def c1():
+    o = make_orbitals(config_spec("c1"))
+    s = o.spec
+    piv, U, phi = oracle.scdm_localize(o.psi, s.dV)
+    return o, piv, U, phi
+
+
+def test_localize_c1(ctx, c1):
+    _say("localize c1")
+    o, piv, U, phi = c1
+    s = o.spec
+    gphi, gpiv, gU = ctx.localize(_dev(o.psi), _grid(s))
+    np.testing.assert_array_equal(gpiv.cpu().numpy(), piv)
+    np.testing.assert_allclose(gU.cpu().numpy(), U, atol=1e-12)
+    np.testing.assert_allclose(gphi.cpu().numpy(), phi, atol=1e-12 * np.abs(phi).max())
+
+
+@pytest.mark.parametrize("rho_cut", [0.0, 0.05, 0.2, 2.0])
+def test_pairlist_c1(ctx, c1, rho_cut):
+    _say(f"pairlist c1 rho_cut={rho_cut}")
+    o, _, _, phi = c1
+    s = o.spec
+    ref, ov = oracle.pairlist(phi, s.dV, rho_cut)
+    gp, gov = ctx.pairlist(_dev(phi), _grid(s), rho_cut)
+    np.testing.assert_array_equal(gp.cpu().numpy(), ref)
+    np.testing.assert_allclose(gov.cpu().numpy(), ov, atol=1e-14)
+
+
+def test_pairlist_capacity_error(ctx, c1):
+    from paper_2101_03155_amd import AceError
+    o, _, _, phi = c1
+    with pytest.raises(AceError) as ei:
+        ctx.pairlist(_dev(phi), _grid(o.spec), 0.0, capacity=10)
+    assert ei.value.status == "ACE_E_CAPACITY" and "required 36" in str(ei.value)
+
+
+@pytest.mark.parametrize("which", ["psi", "phi"])
+def test_build_c1_full_fp64(ctx, c1, which):
+    _say(f"build c1 full fp64 from {which}")
+    o, _, _, phi = c1
+    s = o.spec
+    orbs = o.psi if which == "psi" else phi
+    pairs = _full_pairs(s.norb)
+    ref = oracle.ace_build(orbs, pairs, s.N, s.L, "bare", 0.1)
+    r = ctx.build(_dev(orbs), _dev(pairs), _grid(s), kernel="bare", precision="fp64", want_W=True,
+                  want_energies=True)
+    ex = float(r["ex"].item())
+    assert abs(ex - ref["ex"]) <= 1e-12 * abs(ref["ex"])
+    assert _rel(r["W"].cpu().numpy(), ref["W"]) < 1e-12
+    np.testing.assert_allclose(r["M"].cpu().numpy(), ref["M"], atol=1e-12 * np.abs(ref["M"]).max())
+    assert _rel(r["xi"].cpu().numpy(), ref["xi"]) < 1e-11
+    np.testing.assert_allclose(r["e"].cpu().numpy(), ref["e"], atol=1e-13 * np.abs(ref["e"]).max())
+
+
+def test_ace_matrix_elements_c1(ctx, c1):
+    _say("ACE matrix elements c1")
+    o, _, _, phi = c1
+    s = o.spec
+    pairs = _full_pairs(s.norb)
+    ref = oracle.ace_build(phi, pairs, s.N, s.L, "bare", 0.1)
+    r = ctx.build(_dev(phi), _dev(pairs), _grid(s), kernel="bare", precision="fp64")
+    vecs = np.concatenate([phi, smooth_test_vectors(s, 16)])
+    y = ctx.apply(r["xi"], _dev(vecs), _grid(s)).cpu().numpy()
+    yref = oracle.ace_apply(ref["xi"], vecs, s.dV)
+    A = vecs.reshape(len(vecs), -1)
+    mel = s.dV * A @ y.reshape(len(vecs), -1).T
+    mref = s.dV * A @ yref.reshape(len(vecs), -1).T
+    assert np.abs(mel - mref).max() <= 1e-10
+    # V_ACE phi = W on the occupied space
+    assert _rel(y[: s.norb], ref["W"]) < 1e-11
+
+
+def test_split_path_matches_fused(ctx, c1):
+    _say("split vs fused path c1")
+    o, _, _, phi = c1
+    s = o.spec
+    pairs = _dev(_full_pairs(s.norb))
+    a = ctx.build(_dev(phi), pairs, _grid(s), kernel="bare", want_W=True)
+    ctx.set_pair_shape("fp64", s.N, False, 5)
+    try:
+        b = ctx.build(_dev(phi), pairs, _grid(s), kernel="bare", want_W=True)
+    finally:
+        ctx.set_pair_shape("fp64", s.N, True, 64)
+    assert _rel(b["W"].cpu().numpy(), a["W"].cpu().numpy()) < 1e-13
+    assert abs(b["ex"].item() - a["ex"].item()) < 1e-13 * abs(a["ex"].item())
+
+
+def test_fp32_c1(ctx, c1):
+    _say("build c1 fp32")
+    o, _, _, phi = c1
+    s = o.spec
+    pairs = _full_pairs(s.norb)
+    ref = oracle.ace_build(phi, pairs, s.N, s.L, "bare", 0.1)
+    r = ctx.build(_dev(phi), _dev(pairs), _grid(s), kernel="bare", precision="fp32", want_W=True)
+    assert abs(r["ex"].item() - ref["ex"]) <= 1e-6 * abs(ref["ex"])
+    assert _rel(r["W"].cpu().numpy(), ref["W"]) < 1e-5
+    np.testing.assert_allclose(r["M"].cpu().numpy(), ref["M"], atol=1e-5)
+
+
+def test_not_positive_definite_reported(ctx, c1):
+    _say("NOT_PD path")
+    from paper_2101_03155_amd import AceError
+    o, _, _, phi = c1
+    s = o.spec
+    # a single off-diagonal pair leaves W_k = 0 for every other orbital: -M is singular
+    pairs = np.array([(0, 1)], dtype=np.int32)
+    with pytest.raises(oracle.NotPositiveDefinite):
+        oracle.ace_build(phi, pairs, s.N, s.L, "bare", 0.1)
+    with pytest.raises(AceError) as ei:
+        ctx.build(_dev(phi), _dev(pairs), _grid(s), kernel="bare")
+    assert ei.value.status == "ACE_E_NOT_PD"
+
+
+def test_bad_pairs_rejected(ctx, c1):
+    from paper_2101_03155_amd import AceError
+    o, _, _, phi = c1
+    s = o.spec
+    for bad in ([(0, 0), (0, 0)], [(3, 1)], [(0, s.norb)]):
+        with pytest.raises(AceError) as ei:
+            ctx.build(_dev(phi), _dev(np.array(bad, dtype=np.int32)), _grid(s))
+        assert ei.value.status == "ACE_E_ARG"
+
+
+# ------------------------------------------------------------------ other grid sizes, ragged lists
+
+@pytest.mark.parametrize("n,kind,prec", [(8, "erfc", "fp64"), (12, "bare", "fp64"), (16, "erfc", "fp64"),
+                                         (32, "erfc", "fp64"), (48, "bare", "fp64"), (16, "erfc", "fp32"),
+                                         (48, "erfc", "fp32")])
+def test_sizes_and_screened_lists(ctx, n, kind, prec):
+    _say(f"sizes N={n} {kind} {prec}")
+    L = n * 0.3
+    spec = SystemSpec(n_mol=3, L=L, N=n, sigma=0.7, offset=0.6, placement="uniform", seed=40 + n,
+                      kernel=kind, omega=0.4)
+    o = make_orbitals(spec)
+    rng = np.random.default_rng(n)
+    full = _full_pairs(spec.norb)
+    keep = (full[:, 0] == full[:, 1]) | (rng.random(len(full)) < 0.55)
+    pairs = full[keep]
+    if len(pairs) % 2 == 0:
+        pairs = pairs[:-1] if pairs[-1, 0] != pairs[-1, 1] else pairs
+    v = oracle.coulomb_kernel(n, L, kind, 0.4)
+    ref_W, ref_e = oracle.build_W(o.psi, pairs, v, spec.dV, energies=True)
+    try:
+        _, _, ref_xi, ref_ex, _ = oracle.ace_from_W(o.psi, ref_W, spec.dV)
+        pd = True
+    except oracle.NotPositiveDefinite:
+        pd = False
+    from paper_2101_03155_amd import AceError
+    ctx.set_pair_shape(prec, n, True, 3)
+    try:
+        if not pd:
+            with pytest.raises(AceError) as ei:
+                ctx.build(_dev(o.psi), _dev(pairs), _grid(spec), kernel=kind, omega=0.4, precision=prec)
+            assert ei.value.status == "ACE_E_NOT_PD"
+            return
+        r = ctx.build(_dev(o.psi), _dev(pairs), _grid(spec), kernel=kind, omega=0.4, precision=prec,
+                      want_W=True, want_energies=True)
+    finally:
+        ctx.set_pair_shape(prec, n, True, 64)
+    tol = 1e-12 if prec == "fp64" else 2e-5
+    assert _rel(r["W"].cpu().numpy(), ref_W) < tol
+    np.testing.assert_allclose(r["e"].cpu().numpy(), ref_e, atol=tol * np.abs(ref_e).max())
+    assert abs(r["ex"].item() - ref_ex) <= (1e-10 if prec == "fp64" else 1e-6) * abs(ref_ex)
+    assert _rel(r["xi"].cpu().numpy(), ref_xi) < (1e-10 if prec == "fp64" else 1e-4)
+
+
+# ------------------------------------------------------------------ c2 (128 orbitals, 96^3)
+
+@pytest.fixture(scope="module")
+def c2(ctx):
+    o = make_orbitals(config_spec("c2"))
+    s = o.spec
+    piv, U, phi = oracle.scdm_localize(o.psi, s.dV)
+    pairs, ov = oracle.pairlist(phi, s.dV, 1e-3)
+    return dict(o=o, s=s, piv=piv, phi=phi, pairs=pairs, ov=ov,
+                v=oracle.coulomb_kernel(s.N, s.L, "erfc", s.omega))
+
+
+def test_c2_localize_and_pairlist(ctx, c2):
+    _say("c2 localize + pairlist")
+    s = c2["s"]
+    gphi, gpiv, _ = ctx.localize(_dev(c2["o"].psi), _grid(s))
+    np.testing.assert_array_equal(gpiv.cpu().numpy(), c2["piv"])
+    phi = gphi.cpu().numpy()
+    assert np.abs(phi - c2["phi"]).max() < 1e-10 * np.abs(c2["phi"]).max()
+    gp, gov = ctx.pairlist(_dev(c2["phi"]), _grid(s), 1e-3)
+    np.testing.assert_array_equal(gp.cpu().numpy(), c2["pairs"])
+    np.testing.assert_allclose(gov.cpu().numpy(), c2["ov"], rtol=1e-12)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_c2_screened_build(ctx, c2, prec):
+    _say(f"c2 screened build {prec}")
+    s, phi, pairs = c2["s"], c2["phi"], c2["pairs"]
+    r = ctx.build(_dev(phi), _dev(pairs.astype(np.int32)), _grid(s), kernel="erfc", omega=s.omega,
+                  precision=prec, want_W=True, want_energies=True)
+    e_ref = oracle.exchange_energy_pairs(phi, pairs, c2["v"], s.dV)
+    ex_ref = e_ref.sum()
+    tol = 1e-10 if prec == "fp64" else 1e-6
+    assert abs(r["ex"].item() - ex_ref) <= tol * abs(ex_ref)
+    np.testing.assert_allclose(r["e"].cpu().numpy(), e_ref, atol=(1e-12 if prec == "fp64" else 1e-7))
+    rows = [5, 77]
+    Wref = oracle.build_W_rows(phi, pairs, rows, c2["v"])
+    Wg = r["W"][rows].cpu().numpy()
+    assert _rel(Wg, Wref) < (1e-12 if prec == "fp64" else 1e-5)
+    # M columns of the sampled rows: M_kl = dV <phi_k | W_l>
+    Mref = s.dV * phi.reshape(s.norb, -1) @ Wref.reshape(len(rows), -1).T
+    Mraw = r["M"].cpu().numpy()
+    # M is returned symmetrized; compare the symmetric part on sampled entries
+    for a, l in enumerate(rows):
+        for k in rows:
+            b = rows.index(k)
+            sym = 0.5 * (Mref[k, a] + Mref[l, b])
+            assert abs(Mraw[k, l] - sym) <= (1e-11 if prec == "fp64" else 1e-5)
+
+
+def test_c2_full_pair_energy(ctx, c2):
+    _say("c2 full pair list fp64")
+    s, phi = c2["s"], c2["phi"]
+    pairs = _full_pairs(s.norb)
+    r = ctx.build(_dev(phi), _dev(pairs), _grid(s), kernel="erfc", omega=s.omega, want_energies=True)
+    e_ref = oracle.exchange_energy_pairs(phi, pairs, c2["v"], s.dV)
+    assert abs(r["ex"].item() - e_ref.sum()) <= 1e-10 * abs(e_ref.sum())
+    np.testing.assert_allclose(r["e"].cpu().numpy(), e_ref, atol=1e-12)
+    # screening identity on the GPU: E_x(screened) - E_x(full) = -sum of dropped e_ij
+    kept = {tuple(p) for p in c2["pairs"]}
+    dropped = sum(e for p, e in zip(map(tuple, pairs), e_ref) if p not in kept)
+    rs = ctx.build(_dev(phi), _dev(c2["pairs"].astype(np.int32)), _grid(s), kernel="erfc", omega=s.omega)
+    assert abs((rs["ex"].item() - r["ex"].item()) + dropped) < 1e-9 * abs(e_ref.sum())
+    # ACE matrix elements <phi_k|V_ACE|phi_l> for a sampled l against the oracle's
+    # <phi_k|V_X|phi_l> = dV <phi_k|W_l> (full list: V_ACE = V_X on the occupied space)
+    rows = [31]
+    Wref = oracle.build_W_rows(phi, pairs, rows, c2["v"])
+    mref = s.dV * phi.reshape(s.norb, -1) @ Wref.reshape(len(rows), -1).T
+    y = ctx.apply(r["xi"], _dev(phi[rows]), _grid(s)).cpu().numpy()
+    mel = s.dV * phi.reshape(s.norb, -1) @ y.reshape(len(rows), -1).T
+    assert np.abs(mel - mref).max() <= 1e-10
