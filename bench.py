@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true")
+    ap.add_argument("--shape", default="auto", choices=["auto", "default", "fused", "split"],
+                    help="pair-stage launch shape: autotuned, library default, or forced")
     return ap.parse_args()
 
 
@@ -103,6 +105,18 @@ def main():
         r = ctx.build(phi, pairs, grid, kernel=kind, omega=omega, precision=prec, want_M=False)
         return phi, pairs, r
 
+    tuned = None
+    if args.shape == "auto":
+        from paper_2101_03155_amd.tune import autotune
+
+        phi0, _, _ = ctx.localize(psi, grid)
+        pairs0, _ = ctx.pairlist(phi0, grid, args.rho_cut)
+        tuned = autotune(ctx, phi0, pairs0, grid, kind, omega, prec)
+        del phi0, pairs0
+    elif args.shape in ("fused", "split"):
+        ctx.set_pair_shape(prec, spec.N, args.shape == "fused", 64)
+    shape = ctx.get_pair_shape(prec, spec.N)
+
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -157,6 +171,8 @@ def main():
         "pair_solves_per_s": round(pair_solves, 1),
         "stage_ms": {k: round(v, 3) for k, v in stage_ms.items()},
         "ex_hartree": ex,
+        "pair_shape": {"fused": shape[0], "max_packs": shape[1],
+                       "tune_table": tuned["table"] if tuned else None},
         "roofline": roof,
         "kernels": kernels,
     }

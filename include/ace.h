@@ -170,6 +170,50 @@ int ace_profile_read(ace_ctx* ctx, int cls, int64_t* launches, double* total_ms,
 int ace_set_pair_shape(ace_ctx* ctx, int prec, int n, int fused, int max_packs);
 int ace_get_pair_shape(ace_ctx* ctx, int prec, int n, int* fused, int* max_packs);
 
+/*
+ * Batched form: many independent ACE builds (uneven orbital counts, grids,
+ * pair lists and kernels) in shared launches.  Each system is what ace_build
+ * takes; its pair list is split into conflict-free rounds, round r of every
+ * system forms super-round r, and the pair-stage passes of a super-round run
+ * in launches shared by all its systems of one grid size.
+ *
+ *   grid, norb, kernel, omega, phi, pairs, npairs  as for ace_build (inputs)
+ *   xi, M (nullable), ex (nullable)                 as for ace_build (outputs)
+ *   status, fail_column  HOST fields written by the call: ACE_OK, or
+ *                        ACE_E_NOT_PD / ACE_E_NONFINITE with the column
+ *
+ * prec: ace_precision (the precision form runs the pair stage in FP32).
+ * mode 0: the whole batched build (pair stage and every system's M, Cholesky
+ *         and projectors) is captured in a hipGraph on a private stream and
+ *         replayed when the same inputs come back;
+ * mode 1: one persistent cooperative launch per grid size runs all its
+ *         super-rounds and passes, with grid-wide barriers between passes;
+ * mode 2: the launches of mode 0 issued directly.
+ * Grid sizes: 16, 24, 32, 48, 64, 80 or 96.  Returns ACE_E_NOT_PD if any
+ * system failed its factorization (the others are complete).
+ */
+typedef struct {
+  ace_grid grid;
+  int32_t norb;
+  int32_t kernel;
+  double omega;
+  const double* phi;
+  const int32_t* pairs;
+  int64_t npairs;
+  double* xi;
+  double* M;
+  double* ex;
+  int32_t status;
+  int32_t fail_column;
+} ace_system;
+
+int ace_build_batched(ace_ctx* ctx, int nsys, ace_system* systems, int prec, int mode);
+
+/* Batched launch shape (set by the autotuner): x-tile width of the line
+ * passes (8 or 16), radix order of the FFT plans (0 large radices first, 1
+ * small first), workgroups per compute unit of the persistent launch. */
+int ace_set_batched_shape(ace_ctx* ctx, int txv, int plan_variant, int blocks_per_cu);
+
 #ifdef __cplusplus
 }
 #endif

@@ -41,6 +41,15 @@ class ace_grid(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("L", C.c_double * 3)]
 
 
+class ace_system(C.Structure):
+    _fields_ = [("grid", ace_grid), ("norb", C.c_int32), ("kernel", C.c_int32), ("omega", C.c_double),
+                ("phi", C.c_void_p), ("pairs", C.c_void_p), ("npairs", C.c_int64), ("xi", C.c_void_p),
+                ("M", C.c_void_p), ("ex", C.c_void_p), ("status", C.c_int32), ("fail_column", C.c_int32)]
+
+
+BATCHED_MODES = {"graph": 0, "persistent": 1, "eager": 2}
+
+
 @dataclass(frozen=True)
 class Grid:
     """Cubic-or-orthorhombic periodic grid: n points and box edge L (bohr) per axis."""
@@ -95,6 +104,8 @@ def load(path: str = LIB_PATH):
         "ace_profile_read": ([P, I, C.POINTER(I64), C.POINTER(D), C.POINTER(D), I], I),
         "ace_set_pair_shape": ([P, I, I, I, I], I),
         "ace_get_pair_shape": ([P, I, I, C.POINTER(I), C.POINTER(I)], I),
+        "ace_build_batched": ([P, I, C.POINTER(ace_system), I, I], I),
+        "ace_set_batched_shape": ([P, I, I, I], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -261,3 +272,51 @@ class Context:
         m = C.c_int()
         self._check(self.lib.ace_get_pair_shape(self.h, PRECISIONS[precision], n, C.byref(f), C.byref(m)))
         return bool(f.value), m.value
+
+    def build_batched(self, systems, precision: str = "fp32", mode: str = "graph", want_M: bool = True,
+                      raise_on_not_pd: bool = True):
+        """Batched ACE builds.  systems: list of dict(phi, pairs, grid, kernel, omega).
+
+        Returns a list of dict(xi, M, ex, status, fail_column) in input order."""
+        import torch
+
+        n = len(systems)
+        arr = (ace_system * n)()
+        outs = []
+        for q, sy in enumerate(systems):
+            phi, pairs, grid = sy["phi"], sy["pairs"], sy["grid"]
+            _require(phi, torch.float64, f"systems[{q}].phi")
+            _require(pairs, torch.int32, f"systems[{q}].pairs")
+            norb = phi.shape[0]
+            # outputs may be passed in (same buffers => a captured graph is replayed)
+            o = dict(xi=sy["xi"] if sy.get("xi") is not None else torch.empty_like(phi),
+                     M=(sy["M"] if sy.get("M") is not None else
+                        torch.empty(norb, norb, dtype=torch.float64, device=phi.device)) if want_M else None,
+                     ex=sy["ex"] if sy.get("ex") is not None else torch.empty(1, dtype=torch.float64,
+                                                                               device=phi.device))
+            outs.append(o)
+            a = arr[q]
+            a.grid = grid.c()
+            a.norb = norb
+            a.kernel = KERNELS[sy.get("kernel", "erfc")]
+            a.omega = float(sy.get("omega", 0.106))
+            a.phi = phi.data_ptr()
+            a.pairs = pairs.data_ptr()
+            a.npairs = pairs.shape[0]
+            a.xi = o["xi"].data_ptr()
+            a.M = _ptr(o["M"])
+            a.ex = o["ex"].data_ptr()
+        self._sync_stream()
+        self._keep = systems  # inputs stay alive for the duration of the call
+        rc = self.lib.ace_build_batched(self.h, n, arr, PRECISIONS[precision], BATCHED_MODES[mode])
+        for q in range(n):
+            outs[q]["status"] = STATUS.get(arr[q].status, arr[q].status)
+            outs[q]["fail_column"] = arr[q].fail_column
+        if rc == -4 and not raise_on_not_pd:
+            return outs
+        self._check(rc)
+        return outs
+
+    def set_batched_shape(self, txv: int, plan_variant: int, blocks_per_cu: int):
+        self._check(self.lib.ace_set_batched_shape(self.h, txv, plan_variant, blocks_per_cu))
+

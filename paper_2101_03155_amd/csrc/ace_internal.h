@@ -21,6 +21,29 @@ struct KernelParams {
   double g[3];     // 2 pi / L along x, y, z
 };
 
+// Batched form: one system, one pack of a super-round, one super-round.
+struct BSys {
+  int N;
+  int kind;
+  double omega;
+  double inv_ng;
+  double g[3];
+  const void* phi;  // [norb][N^3] in the pair-stage precision
+  void* W;          // [norb][N^3] in the pair-stage precision
+  const void* tw;   // N twiddles
+};
+struct BPack {
+  int sys;
+  int pad;
+  Pack pk;
+  void* spec;       // N^3 complex values of this pack
+};
+struct BRound {                // one segment: the packs of one grid size in one super-round
+  int pack0, npacks;         // packs [pack0, pack0 + npacks) of the BPack table
+  int64_t start_off[5];      // per phase: offset of the item prefix table (npacks + 1 entries)
+  int64_t nitems[5];         // per phase: number of work items
+};
+
 // Kernel launch shape of the pair stage, chosen by the tuner.
 struct PairShape {
   int fused_xy;    // 1: one workgroup per (plane, pack) does both in-plane FFTs
@@ -70,9 +93,19 @@ void launch_trinv(const double* L, int n, double* X, hipStream_t s);
 void launch_colnorm(const double* A, int n, int64_t ng, double* res, hipStream_t s);
 int qrcp_blocks(int64_t ng);
 void launch_qrcp_update(const double* A, int n, int64_t ng, const double* q, double* res, double* pv, int64_t* pi,
+                        const int* stop, hipStream_t s);
+void launch_qrcp_select(const double* A, int n, int64_t ng, int* kdev, const double* pv, const int64_t* pi,
+                        int nblk, double* Q, double* res, int32_t* piv, double* qout, const int32_t* pool,
+                        const double* t_out, int* stop, hipStream_t s);
+int pool_blocks(int64_t ng);
+void launch_pool_build(const double* res, int64_t ng, int pmax, unsigned* hist, double* t, int64_t* cnt,
+                       double* tmax, int* total, double* t_out, hipStream_t s);
+void launch_pool_write(const double* res, int64_t ng, const double* t, const int64_t* off, int32_t* pool,
+                       double* pres, hipStream_t s);
+void launch_pool_gather(const double* A, int n, int64_t ng, const int32_t* pool, int np, double* Apool,
                         hipStream_t s);
-void launch_qrcp_select(const double* A, int n, int64_t ng, int k, const double* pv, const int64_t* pi, int nblk,
-                        double* Q, double* res, int32_t* piv, double* qout, hipStream_t s);
+void launch_refresh_res(const double* L, int k, int64_t rc, const double* norm0, double* res, hipStream_t s);
+void launch_retire(const int32_t* piv, int k, double* res, hipStream_t s);
 void launch_gather_cols(const double* A, int n, int64_t ng, const int32_t* piv, double* AC, hipStream_t s);
 void launch_scale_frob(double* X, int64_t cnt, hipStream_t s);
 void launch_ns_combine(const double* X, const double* Z, double* Y, int64_t cnt, hipStream_t s);
@@ -85,6 +118,14 @@ void launch_d2f(const double* a, float* b, int64_t n, hipStream_t s);
 void launch_f2d(const float* a, double* b, int64_t n, hipStream_t s);
 void launch_nonfinite(const double* a, int64_t n, int* flag, hipStream_t s);
 bool pair_fused_fits(int prec, int N);
+bool batched_supported(int n);
+int64_t batched_phase_items(int n, int phase, int txv);
+// Segments of one grid size n.  mode 0: one launch per (segment, phase);
+// mode 1: one cooperative launch for all the segments.
+hipError_t batched_segments(int prec, int n, int mode, int txv, int plan_v, int blocks_per_cu, int nseg,
+                            const BRound* h_segs, const BRound* d_segs, const BSys* sys, const BPack* packs,
+                            const int64_t* starts, hipStream_t s);
+void launch_zero(void* p, size_t bytes, hipStream_t s);
 PairShape pair_default_shape(int prec, int N);
 
 }  // namespace ace

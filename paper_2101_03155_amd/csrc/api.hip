@@ -101,6 +101,7 @@ struct Schedule {
   std::vector<int64_t> pidx;           // pair index of each pack half (-1 if none)
   struct Launch { int first, second, npairs; };
   std::vector<Launch> launches;  // (first pack, pack count, pair count) per launch
+  std::vector<int> round_first, round_count;  // packs of each conflict-free round
   int max_launch = 0;
 };
 
@@ -109,6 +110,7 @@ struct ace_ctx {
   int device = 0;
   std::string err;
   size_t ws_total = 0, ws_cap = 0;
+  uint64_t ws_gen = 0;  // bumped whenever a workspace is reallocated
   std::map<std::string, Buf> bufs;
   std::map<int, Buf> twiddles;       // key: N*2 + prec
   std::map<int, PairShape> shapes;   // key: N*2 + prec
@@ -117,6 +119,12 @@ struct ace_ctx {
   EventRecorder rec;
   bool profiling = false;
   EventRecorder* R() { return profiling ? &rec : nullptr; }
+  // batched form
+  hipStream_t bstream = nullptr;
+  hipEvent_t bev_in = nullptr, bev_out = nullptr;
+  std::map<uint64_t, hipGraphExec_t> graphs;
+  std::vector<uint64_t> graph_order;
+  int b_txv = 16, b_plan = 0, b_bpc = 8;
 };
 
 static int fail(ace_ctx* c, int code, const char* fmt, ...) {
@@ -156,6 +164,7 @@ static int ws_get(ace_ctx* c, const char* name, size_t bytes, void** out) {
     }
     b.bytes = bytes;
     c->ws_total += bytes;
+    ++c->ws_gen;
   }
   *out = b.p;
   return ACE_OK;
@@ -271,6 +280,8 @@ static void make_schedule(const std::vector<int32_t>& pr, int64_t npairs, int no
       S.pidx.push_back(q + 1 < sel.size() ? sel[q + 1] : -1);
     }
     const int np = int(S.packs.size()) - first;
+    S.round_first.push_back(first);
+    S.round_count.push_back(np);
     for (int off = 0; off < np; off += max_packs) {
       const int cntp = std::min(max_packs, np - off);
       int npr = 0;
@@ -281,6 +292,31 @@ static void make_schedule(const std::vector<int32_t>& pr, int64_t npairs, int no
     rem.swap(next);
     ++round;
   }
+}
+
+// Validate a host copy of a pair list and return its (cached) schedule.
+static int schedule_for(ace_ctx* c, const std::vector<int32_t>& pr, int64_t npairs, int norb, int max_packs,
+                        const Schedule** out) {
+  uint64_t h = 1469598103934665603ull;
+  std::vector<uint8_t> seen(size_t(norb) * norb, 0);
+  for (int64_t p = 0; p < npairs; ++p) {
+    const int i = pr[2 * p], j = pr[2 * p + 1];
+    if (i < 0 || j < i || j >= norb)
+      return fail(c, ACE_E_ARG, "pair %lld = (%d, %d) not 0 <= i <= j < norb", (long long)p, i, j);
+    if (seen[size_t(i) * norb + j]) return fail(c, ACE_E_ARG, "pair (%d, %d) listed twice", i, j);
+    seen[size_t(i) * norb + j] = 1;
+    h = (h ^ uint64_t(uint32_t(i) * 65599u + uint32_t(j))) * 1099511628211ull;
+  }
+  ScheduleKey key{npairs, norb, h ^ (uint64_t(max_packs) << 40)};
+  auto sit = c->schedules.find(key);
+  if (sit == c->schedules.end()) {
+    if (c->schedules.size() > 64) c->schedules.clear();
+    Schedule S;
+    make_schedule(pr, npairs, norb, max_packs, S);
+    sit = c->schedules.emplace(key, std::move(S)).first;
+  }
+  *out = &sit->second;
+  return ACE_OK;
 }
 
 extern "C" {
@@ -307,6 +343,10 @@ int ace_destroy(ace_ctx* c) {
   for (auto& kv : c->twiddles)
     if (kv.second.p) (void)hipFree(kv.second.p);
   for (auto e : c->rec.pool) (void)hipEventDestroy(e);
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  if (c->bev_in) (void)hipEventDestroy(c->bev_in);
+  if (c->bev_out) (void)hipEventDestroy(c->bev_out);
+  if (c->bstream) (void)hipStreamDestroy(c->bstream);
   delete c;
   return ACE_OK;
 }
@@ -370,12 +410,20 @@ int ace_localize(ace_ctx* c, const ace_grid* g, int norb, const double* psi, dou
   if (ng < norb) return fail(c, ACE_E_ARG, "grid smaller than the number of orbitals");
   hipStream_t s = c->stream;
   rec_begin(c->R(), ST_LOCALIZE, s);
-  double *res, *pv, *Q, *q, *AC, *X, *G, *Z, *dev, *Ub;
-  int64_t* pi;
-  const int nblk = qrcp_blocks(ng);
+  double *res, *norm0, *pv, *Q, *q, *AC, *X, *G, *Z, *dev, *Ub, *pres, *Apool, *tvals, *tmax, *Lc;
+  int64_t *pi, *pcnt;
+  int32_t* pool;
+  unsigned* hist;
+  int* iv;  // [0] k, [1] stop, [2] pool size
+  const int nblk_full = qrcp_blocks(ng);
+  const int pmax = 2048;
+  const int nblk_pool = qrcp_blocks(pmax);
+  const int64_t rchunk = std::min<int64_t>(ng, 65536);  // refresh chunk (grid columns)
+  const int nbp = pool_blocks(ng);
   WS(c, "res", ng * sizeof(double), res);
-  WS(c, "pv", size_t(nblk) * 8 * sizeof(double), pv);
-  WS(c, "pi", size_t(nblk) * 8 * sizeof(int64_t), pi);
+  WS(c, "norm0", ng * sizeof(double), norm0);
+  WS(c, "pv", size_t(nblk_full) * 8 * sizeof(double), pv);
+  WS(c, "pi", size_t(nblk_full) * 8 * sizeof(int64_t), pi);
   WS(c, "Q", size_t(norb) * norb * sizeof(double), Q);
   WS(c, "q", size_t(norb) * sizeof(double), q);
   WS(c, "AC", size_t(norb) * norb * sizeof(double), AC);
@@ -384,17 +432,93 @@ int ace_localize(ace_ctx* c, const ace_grid* g, int norb, const double* psi, dou
   WS(c, "Z", size_t(norb) * norb * sizeof(double), Z);
   WS(c, "U", size_t(norb) * norb * sizeof(double), Ub);
   WS(c, "scal", 64 * sizeof(double), dev);
-  launch_colnorm(psi, norb, ng, res, s);
-  launch_qrcp_update(psi, norb, ng, nullptr, res, pv, pi, s);
-  // algorithmic bytes of one update pass: read Psi once, read + write res
-  const double qbytes = double(norb + 2) * double(ng) * sizeof(double);
-  for (int k = 0; k < norb; ++k) {
-    launch_qrcp_select(psi, norb, ng, k, pv, pi, nblk, Q, res, pivots, q, s);
-    if (k + 1 < norb) {
-      rec_begin(c->R(), KC_QRCP, s);
-      launch_qrcp_update(psi, norb, ng, q, res, pv, pi, s);
-      rec_end(c->R(), KC_QRCP, s, qbytes);
+  WS(c, "pres", size_t(pmax) * sizeof(double), pres);
+  WS(c, "pool", size_t(pmax) * sizeof(int32_t), pool);
+  WS(c, "Apool", size_t(pmax) * norb * sizeof(double), Apool);
+  WS(c, "hist", size_t(1 << 14) * sizeof(unsigned), hist);
+  WS(c, "pcnt", size_t(nbp) * sizeof(int64_t), pcnt);
+  WS(c, "tmax", size_t(nbp) * sizeof(double), tmax);
+  WS(c, "tvals", 8 * sizeof(double), tvals);
+  WS(c, "ivals", 64, iv);
+  WS(c, "Lref", size_t(norb) * rchunk * sizeof(double), Lc);
+
+  // Greedy QRCP.  A compact pool of the columns with the largest residual
+  // bounds is searched step by step; a pick is certified against t_out, the
+  // largest bound outside the pool, and when certification fails the bounds
+  // of all columns are recomputed exactly from the picked directions and a
+  // new pool is drawn.  Residual norms only decrease, so every stored bound
+  // stays valid until it is recomputed.
+  launch_colnorm(psi, norb, ng, norm0, s);
+  HIPCHK(c, hipMemcpyAsync(res, norm0, ng * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(c, hipMemsetAsync(iv, 0, 64, s));
+  const double qbytes_pool = double(norb + 2) * double(pmax) * sizeof(double);
+  int k = 0;
+  for (int refresh = 0; k < norb; ++refresh) {
+    if (k > 0) {
+      // exact bounds: res = |a_r|^2 - |Q_k a_r|^2, then retire the pivots
+      for (int64_t r0 = 0; r0 < ng; r0 += rchunk) {
+        const int64_t w = std::min(rchunk, ng - r0);
+        HIPCHK(c, gemm_ls(0, false, false, Q, norb, psi + r0, ng, Lc, w, k, norb, w, 1.0, s, nullptr));
+        launch_refresh_res(Lc, k, w, norm0 + r0, res + r0, s);
+      }
+      launch_retire(pivots, k, res, s);
     }
+    bool use_pool = refresh < 16;
+    int np = 0;
+    if (use_pool) {
+      HIPCHK(c, hipMemsetAsync(hist, 0, size_t(1 << 14) * sizeof(unsigned), s));
+      launch_pool_build(res, ng, pmax, hist, tvals, pcnt, tmax, iv + 2, tvals + 1, s);
+      HIPCHK(c, hipMemcpyAsync(&np, iv + 2, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipStreamSynchronize(s));
+      use_pool = np > 0 && np <= pmax;
+    }
+    HIPCHK(c, hipMemsetAsync(iv + 1, 0, sizeof(int), s));  // clear stop
+    if (use_pool) {
+      launch_pool_write(res, ng, tvals, pcnt, pool, pres, s);
+      launch_pool_gather(psi, norb, ng, pool, np, Apool, s);
+      launch_qrcp_update(Apool, norb, np, nullptr, pres, pv, pi, iv + 1, s);
+      // steps are queued in batches; a batch after a certification failure
+      // would only hold no-op launches, so the flag is checked between batches
+      for (int kk = k; kk < norb;) {
+        const int kend = std::min(norb, kk + 24);
+        for (; kk < kend; ++kk) {
+          launch_qrcp_select(Apool, norb, np, iv, pv, pi, qrcp_blocks(np), Q, pres, pivots, q, pool, tvals + 1,
+                             iv + 1, s);
+          if (kk + 1 < norb) {
+            rec_begin(c->R(), KC_QRCP, s);
+            launch_qrcp_update(Apool, norb, np, q, pres, pv, pi, iv + 1, s);
+            rec_end(c->R(), KC_QRCP, s, qbytes_pool * double(np) / double(pmax));
+          }
+        }
+        if (kk < norb) {
+          int hs = 0;
+          HIPCHK(c, hipMemcpyAsync(&hs, iv + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+          HIPCHK(c, hipStreamSynchronize(s));
+          if (hs) break;
+        }
+      }
+    } else {
+      // the whole grid is the pool: no certification needed
+      launch_qrcp_update(psi, norb, ng, nullptr, res, pv, pi, iv + 1, s);
+      const double qbytes = double(norb + 2) * double(ng) * sizeof(double);
+      for (int kk = k; kk < norb; ++kk) {
+        launch_qrcp_select(psi, norb, ng, iv, pv, pi, nblk_full, Q, res, pivots, q, nullptr, nullptr, iv + 1, s);
+        if (kk + 1 < norb) {
+          rec_begin(c->R(), KC_QRCP, s);
+          launch_qrcp_update(psi, norb, ng, q, res, pv, pi, iv + 1, s);
+          rec_end(c->R(), KC_QRCP, s, qbytes);
+        }
+      }
+    }
+    HIPCHK(c, hipGetLastError());
+    int hk[2] = {0, 0};
+    HIPCHK(c, hipMemcpyAsync(hk, iv, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    if (!use_pool && hk[0] < norb)
+      return fail(c, ACE_E_NONFINITE, "pivot search stalled at step %d (degenerate orbitals?)", hk[0]);
+    if (hk[0] <= k && refresh > 0 && !use_pool)
+      return fail(c, ACE_E_NONFINITE, "pivot search made no progress at step %d", k);
+    k = hk[0];
   }
   HIPCHK(c, hipGetLastError());
   // Loewdin rotation U = A_C (A_C^T A_C)^-1/2 = polar factor of A_C,
@@ -402,20 +526,32 @@ int ace_localize(ace_ctx* c, const ace_grid* g, int norb, const double* psi, dou
   launch_gather_cols(psi, norb, ng, pivots, AC, s);
   HIPCHK(c, hipMemcpyAsync(X, AC, size_t(norb) * norb * sizeof(double), hipMemcpyDeviceToDevice, s));
   launch_scale_frob(X, int64_t(norb) * norb, s);
-  int converged_iters = -1;
-  for (int it = 0; it < 200; ++it) {
+  // Convergence is read back every 4 iterations; once max|X^T X - I| < 1e-11
+  // two more iterations take the quadratically converging iterate to rounding.
+  int converged_at = -1, it = 0;
+  while (it < 200) {
+    for (int j = 0; j < 4; ++j, ++it) {
+      HIPCHK(c, gemm_ls(0, true, false, X, norb, X, norb, G, norb, norb, norb, norb, 1.0, s, nullptr));
+      HIPCHK(c, gemm_ls(0, false, false, X, norb, G, norb, Z, norb, norb, norb, norb, 1.0, s, nullptr));
+      launch_ns_combine(X, Z, X, int64_t(norb) * norb, s);
+    }
     HIPCHK(c, gemm_ls(0, true, false, X, norb, X, norb, G, norb, norb, norb, norb, 1.0, s, nullptr));
     launch_dev_identity(G, norb, dev, s);
     double h = 0.0;
     HIPCHK(c, hipMemcpyAsync(&h, dev, sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
     if (!std::isfinite(h)) return fail(c, ACE_E_NONFINITE, "non-finite Loewdin iteration (singular A_C?)");
-    if (h < 1e-11 && converged_iters < 0) converged_iters = it;
-    if (converged_iters >= 0 && it >= converged_iters + 2) break;
+    if (h < 1e-11) {
+      converged_at = it;
+      break;
+    }
+  }
+  if (converged_at < 0) return fail(c, ACE_E_NONFINITE, "Loewdin polar iteration did not converge");
+  for (int j = 0; j < 2; ++j) {
+    HIPCHK(c, gemm_ls(0, true, false, X, norb, X, norb, G, norb, norb, norb, norb, 1.0, s, nullptr));
     HIPCHK(c, gemm_ls(0, false, false, X, norb, G, norb, Z, norb, norb, norb, norb, 1.0, s, nullptr));
     launch_ns_combine(X, Z, X, int64_t(norb) * norb, s);
   }
-  if (converged_iters < 0) return fail(c, ACE_E_NONFINITE, "Loewdin polar iteration did not converge");
   // phi_k = sum_i psi_i U_ik
   HIPCHK(c, gemm_ls(0, true, false, X, norb, psi, ng, phi, ng, norb, norb, ng, 1.0, s, c->R()));
   if (U) HIPCHK(c, hipMemcpyAsync(U, X, size_t(norb) * norb * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -480,28 +616,11 @@ int ace_build(ace_ctx* c, const ace_grid* g, int norb, const double* phi, const 
   std::vector<int32_t> pr(size_t(2 * npairs));
   HIPCHK(c, hipMemcpyAsync(pr.data(), pairs, pr.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
-  uint64_t h = 1469598103934665603ull;
-  {
-    std::vector<uint8_t> seen(size_t(norb) * norb, 0);
-    for (int64_t p = 0; p < npairs; ++p) {
-      const int i = pr[2 * p], j = pr[2 * p + 1];
-      if (i < 0 || j < i || j >= norb)
-        return fail(c, ACE_E_ARG, "pair %lld = (%d, %d) not 0 <= i <= j < norb", (long long)p, i, j);
-      if (seen[size_t(i) * norb + j]) return fail(c, ACE_E_ARG, "pair (%d, %d) listed twice", i, j);
-      seen[size_t(i) * norb + j] = 1;
-      h = (h ^ uint64_t(uint32_t(i) * 65599u + uint32_t(j))) * 1099511628211ull;
-    }
-  }
   const int mp = max_packs_for(c, prec, N);
-  ScheduleKey key{npairs, norb, h ^ (uint64_t(mp) << 48)};
-  auto sit = c->schedules.find(key);
-  if (sit == c->schedules.end()) {
-    if (c->schedules.size() > 64) c->schedules.clear();
-    Schedule S;
-    make_schedule(pr, npairs, norb, mp, S);
-    sit = c->schedules.emplace(key, std::move(S)).first;
-  }
-  const Schedule& S = sit->second;
+  const Schedule* Sp = nullptr;
+  rc = schedule_for(c, pr, npairs, norb, mp, &Sp);
+  if (rc) return rc;
+  const Schedule& S = *Sp;
   const int npk = int(S.packs.size());
   rec_begin(R, ST_BUILD, s);
 
@@ -595,6 +714,261 @@ int ace_apply(ace_ctx* c, const ace_grid* g, int norb, const double* xi, int nve
   WS(c, "coef", size_t(norb) * nvec * sizeof(double), cb);
   HIPCHK(c, gemm_nt(0, false, xi, ng, x, ng, norb, nvec, ng, grid_dv(g), part, cb, s, c->R()));
   HIPCHK(c, gemm_ls(0, true, false, cb, nvec, xi, ng, y, ng, nvec, norb, ng, -1.0, s, c->R()));
+  return ACE_OK;
+}
+
+
+// ------------------------------------------------------------------ batched form
+int ace_set_batched_shape(ace_ctx* c, int txv, int plan_variant, int blocks_per_cu) {
+  if (!c || (txv != 8 && txv != 16) || (plan_variant != 0 && plan_variant != 1) || blocks_per_cu < 1 ||
+      blocks_per_cu > 32)
+    return fail(c, ACE_E_ARG, "bad batched shape");
+  c->b_txv = txv;
+  c->b_plan = plan_variant;
+  c->b_bpc = blocks_per_cu;
+  return ACE_OK;
+}
+
+int ace_build_batched(ace_ctx* c, int nsys, ace_system* sys, int prec, int mode) {
+  if (!c) return ACE_E_ARG;
+  if (nsys < 1 || nsys > 4096 || !sys) return fail(c, ACE_E_ARG, "nsys=%d outside [1, 4096]", nsys);
+  if (prec != ACE_FP64 && prec != ACE_FP32) return fail(c, ACE_E_ARG, "unknown precision %d", prec);
+  if (mode < 0 || mode > 2) return fail(c, ACE_E_ARG, "unknown batched mode %d", mode);
+  for (int q = 0; q < nsys; ++q) {
+    ace_system& y = sys[q];
+    int rc = check_grid(c, &y.grid, y.norb);
+    if (rc) return fail(c, rc, "system %d: %s", q, c->err.c_str());
+    if (!batched_supported(y.grid.n[0]))
+      return fail(c, ACE_E_UNSUPPORTED, "system %d: batched grids are 16, 24, 32, 48, 64, 80 or 96", q);
+    if (!y.phi || !y.pairs || !y.xi) return fail(c, ACE_E_ARG, "system %d: phi, pairs and xi must be non-NULL", q);
+    if (y.kernel != ACE_KERNEL_COULOMB && y.kernel != ACE_KERNEL_ERFC)
+      return fail(c, ACE_E_ARG, "system %d: unknown kernel", q);
+    if (y.kernel == ACE_KERNEL_ERFC && !(y.omega > 0.0)) return fail(c, ACE_E_ARG, "system %d: omega must be > 0", q);
+    const int64_t maxp = int64_t(y.norb) * (y.norb + 1) / 2;
+    if (y.npairs < 1 || y.npairs > maxp) return fail(c, ACE_E_ARG, "system %d: npairs outside [1, %lld]", q,
+                                                     (long long)maxp);
+    y.status = ACE_OK;
+    y.fail_column = -1;
+  }
+  hipStream_t us = c->stream;
+  if (!c->bstream) {
+    HIPCHK(c, hipStreamCreateWithFlags(&c->bstream, hipStreamNonBlocking));
+    HIPCHK(c, hipEventCreateWithFlags(&c->bev_in, hipEventDisableTiming));
+    HIPCHK(c, hipEventCreateWithFlags(&c->bev_out, hipEventDisableTiming));
+  }
+  hipStream_t bs = c->bstream;
+  // pair lists to the host, schedules
+  std::vector<std::vector<int32_t>> prs(nsys);
+  for (int q = 0; q < nsys; ++q) {
+    prs[q].resize(size_t(2 * sys[q].npairs));
+    HIPCHK(c, hipMemcpyAsync(prs[q].data(), sys[q].pairs, prs[q].size() * sizeof(int32_t), hipMemcpyDeviceToHost,
+                             us));
+  }
+  HIPCHK(c, hipStreamSynchronize(us));
+  std::vector<const Schedule*> sch(nsys);
+  uint64_t key = 1469598103934665603ull;
+  auto mix = [&key](uint64_t v) { key = (key ^ v) * 1099511628211ull; };
+  mix(uint64_t(prec)); mix(uint64_t(mode)); mix(uint64_t(c->b_txv)); mix(uint64_t(c->b_plan)); mix(uint64_t(c->b_bpc));
+  int nrounds = 0;
+  for (int q = 0; q < nsys; ++q) {
+    int rc = schedule_for(c, prs[q], sys[q].npairs, sys[q].norb, 1 << 30, &sch[q]);
+    if (rc) return fail(c, rc, "system %d: %s", q, c->err.c_str());
+    nrounds = std::max(nrounds, int(sch[q]->round_first.size()));
+    const ace_system& y = sys[q];
+    mix(uint64_t(uintptr_t(y.phi))); mix(uint64_t(uintptr_t(y.xi))); mix(uint64_t(uintptr_t(y.M)));
+    mix(uint64_t(uintptr_t(y.ex))); mix(uint64_t(y.norb)); mix(uint64_t(y.grid.n[0])); mix(uint64_t(y.kernel));
+    uint64_t ob, lb[3];
+    std::memcpy(&ob, &y.omega, 8);
+    std::memcpy(lb, y.grid.L, 24);
+    mix(ob); mix(lb[0]); mix(lb[1]); mix(lb[2]);
+    mix(uint64_t(sch[q]->packs.size()));
+    for (const Pack& pk : sch[q]->packs) mix(uint64_t(uint32_t(pk.ia)) << 32 | uint32_t(pk.ja) ^ uint64_t(uint32_t(pk.jb)) << 16);
+  }
+  const size_t es = prec == 0 ? sizeof(double) : sizeof(float);
+  // segments: (grid size, super-round) with the packs of that size in that round
+  std::vector<int> sizes;
+  for (int q = 0; q < nsys; ++q) sizes.push_back(sys[q].grid.n[0]);
+  std::sort(sizes.begin(), sizes.end());
+  sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
+  std::vector<BRound> segs;
+  std::vector<int> seg_n;
+  std::vector<BPack> bp;
+  std::vector<int64_t> starts;
+  std::vector<int64_t> bp_off;  // spec offset of each pack (bytes, within its segment)
+  size_t spec_bytes = 0;
+  for (int n : sizes) {
+    const int64_t ngn = int64_t(n) * n * n;
+    for (int r = 0; r < nrounds; ++r) {
+      BRound sg{};
+      sg.pack0 = int(bp.size());
+      size_t off = 0;
+      for (int q = 0; q < nsys; ++q) {
+        if (sys[q].grid.n[0] != n || r >= int(sch[q]->round_first.size())) continue;
+        const Schedule& S = *sch[q];
+        for (int k = 0; k < S.round_count[r]; ++k) {
+          BPack b{};
+          b.sys = q;
+          b.pk = S.packs[S.round_first[r] + k];
+          bp.push_back(b);
+          bp_off.push_back(int64_t(off));
+          off += size_t(ngn) * 2 * es;
+        }
+      }
+      sg.npacks = int(bp.size()) - sg.pack0;
+      if (sg.npacks == 0) continue;
+      spec_bytes = std::max(spec_bytes, off);
+      for (int p = 0; p < 5; ++p) {
+        sg.start_off[p] = int64_t(starts.size());
+        int64_t acc = 0;
+        for (int k = 0; k < sg.npacks; ++k) {
+          starts.push_back(acc);
+          acc += batched_phase_items(n, p, c->b_txv);
+        }
+        starts.push_back(acc);
+        sg.nitems[p] = acc;
+      }
+      segs.push_back(sg);
+      seg_n.push_back(n);
+    }
+  }
+  // workspaces
+  int64_t w_total = 0, m_total = 0;
+  std::vector<int64_t> w_off(nsys), m_off(nsys);
+  int max_norb = 0;
+  int64_t max_nsplit = 1;
+  for (int q = 0; q < nsys; ++q) {
+    const int64_t ng = grid_size(&sys[q].grid);
+    w_off[q] = w_total;
+    w_total += int64_t(sys[q].norb) * ng;
+    m_off[q] = m_total;
+    m_total += int64_t(sys[q].norb) * sys[q].norb;
+    max_norb = std::max(max_norb, sys[q].norb);
+    int64_t kc;
+    max_nsplit = std::max(max_nsplit, gemm_nt_nsplit(sys[q].norb, sys[q].norb, ng, &kc));
+  }
+  char *bW, *bphi = nullptr, *bspec;
+  double *part, *Mraw, *Lb, *Li, *exs;
+  int* infos;
+  BSys* dsys;
+  BPack* dbp;
+  BRound* dsegs;
+  int64_t* dstarts;
+  WS(c, "bW", size_t(w_total) * es, bW);
+  if (prec == 1) WS(c, "bphi32", size_t(w_total) * es, bphi);
+  WS(c, "bspec", std::max<size_t>(spec_bytes, 256), bspec);
+  WS(c, "bmpart", size_t(max_nsplit) * max_norb * max_norb * sizeof(double), part);
+  WS(c, "bMraw", size_t(max_norb) * max_norb * sizeof(double), Mraw);
+  WS(c, "bLc", size_t(max_norb) * max_norb * sizeof(double), Lb);
+  WS(c, "bLinv", size_t(max_norb) * max_norb * sizeof(double), Li);
+  WS(c, "bex", size_t(nsys) * 2 * sizeof(double), exs);
+  WS(c, "binfo", size_t(nsys) * sizeof(int), infos);
+  WS(c, "bsys", size_t(nsys) * sizeof(BSys), dsys);
+  WS(c, "bpacks", std::max<size_t>(bp.size(), 1) * sizeof(BPack), dbp);
+  WS(c, "bsegs", std::max<size_t>(segs.size(), 1) * sizeof(BRound), dsegs);
+  WS(c, "bstarts", std::max<size_t>(starts.size(), 1) * sizeof(int64_t), dstarts);
+  // descriptor tables
+  std::vector<BSys> hs(nsys);
+  for (int q = 0; q < nsys; ++q) {
+    const ace_system& y = sys[q];
+    const void* tw;
+    int rc = twiddles(c, y.grid.n[0], prec, &tw);
+    if (rc) return rc;
+    BSys& b = hs[q];
+    b.N = y.grid.n[0];
+    b.kind = y.kernel;
+    b.omega = y.omega;
+    b.inv_ng = 1.0 / double(grid_size(&y.grid));
+    for (int d = 0; d < 3; ++d) b.g[d] = 2.0 * 3.141592653589793238462643383279502884 / y.grid.L[d];
+    b.phi = prec == 0 ? (const void*)y.phi : (const void*)(bphi + size_t(w_off[q]) * es);
+    b.W = bW + size_t(w_off[q]) * es;
+    b.tw = tw;
+  }
+  for (size_t k = 0; k < bp.size(); ++k) bp[k].spec = bspec + bp_off[k];
+  // a captured graph holds raw workspace pointers: any reallocation retires it
+  mix(c->ws_gen);
+  mix(uint64_t(uintptr_t(bW))); mix(uint64_t(uintptr_t(bspec))); mix(uint64_t(uintptr_t(part)));
+  HIPCHK(c, hipMemcpyAsync(dsys, hs.data(), hs.size() * sizeof(BSys), hipMemcpyHostToDevice, us));
+  if (!bp.empty()) HIPCHK(c, hipMemcpyAsync(dbp, bp.data(), bp.size() * sizeof(BPack), hipMemcpyHostToDevice, us));
+  if (!segs.empty())
+    HIPCHK(c, hipMemcpyAsync(dsegs, segs.data(), segs.size() * sizeof(BRound), hipMemcpyHostToDevice, us));
+  HIPCHK(c, hipMemcpyAsync(dstarts, starts.data(), starts.size() * sizeof(int64_t), hipMemcpyHostToDevice, us));
+  HIPCHK(c, hipStreamSynchronize(us));
+
+  // the whole build, in stream order on the private stream
+  auto enqueue = [&](hipStream_t s) -> int {
+    launch_zero(bW, size_t(w_total) * es, s);
+    if (prec == 1)
+      for (int q = 0; q < nsys; ++q)
+        launch_d2f(sys[q].phi, (float*)(bphi + size_t(w_off[q]) * es), int64_t(sys[q].norb) * grid_size(&sys[q].grid),
+                   s);
+    for (size_t a = 0; a < segs.size();) {
+      size_t b = a;
+      while (b < segs.size() && seg_n[b] == seg_n[a]) ++b;
+      hipError_t e = batched_segments(prec, seg_n[a], mode == 1 ? 1 : 0, c->b_txv, c->b_plan, c->b_bpc, int(b - a),
+                                      segs.data() + a, dsegs + a, dsys, dbp, dstarts, s);
+      if (e != hipSuccess) return fail(c, ACE_E_HIP, "batched pair launch failed: %s", hipGetErrorString(e));
+      a = b;
+    }
+    for (int q = 0; q < nsys; ++q) {
+      const ace_system& y = sys[q];
+      const int n = y.norb;
+      const int64_t ng = grid_size(&y.grid);
+      const void* W = bW + size_t(w_off[q]) * es;
+      const void* ph = prec == 0 ? (const void*)y.phi : (const void*)(bphi + size_t(w_off[q]) * es);
+      hipError_t e = gemm_nt(prec, false, ph, ng, W, ng, n, n, ng, grid_dv(&y.grid), part, Mraw, s, nullptr);
+      if (e != hipSuccess) return fail(c, ACE_E_HIP, "batched M launch failed: %s", hipGetErrorString(e));
+      launch_symmetrize(Mraw, n, y.M, Lb, y.ex ? y.ex : exs + 2 * q, exs + 2 * q + 1, s);
+      launch_cholesky(Lb, n, infos + q, s);
+      launch_trinv(Lb, n, Li, s);
+      e = gemm_ls(prec, false, true, Li, n, W, ng, y.xi, ng, n, n, ng, 1.0, s, nullptr);
+      if (e != hipSuccess) return fail(c, ACE_E_HIP, "batched projector launch failed: %s", hipGetErrorString(e));
+    }
+    return ACE_OK;
+  };
+
+  HIPCHK(c, hipEventRecord(c->bev_in, us));
+  HIPCHK(c, hipStreamWaitEvent(bs, c->bev_in, 0));
+  if (mode == 0) {
+    auto git = c->graphs.find(key);
+    if (git == c->graphs.end()) {
+      hipGraph_t graph;
+      HIPCHK(c, hipStreamBeginCapture(bs, hipStreamCaptureModeThreadLocal));
+      const int rc = enqueue(bs);
+      hipError_t ee = hipStreamEndCapture(bs, &graph);
+      if (rc) {
+        if (ee == hipSuccess) (void)hipGraphDestroy(graph);
+        return rc;
+      }
+      if (ee != hipSuccess) return fail(c, ACE_E_HIP, "graph capture failed: %s", hipGetErrorString(ee));
+      hipGraphExec_t exec;
+      ee = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ee != hipSuccess) return fail(c, ACE_E_HIP, "graph instantiation failed: %s", hipGetErrorString(ee));
+      if (c->graphs.size() >= 8) {
+        (void)hipGraphExecDestroy(c->graphs[c->graph_order.front()]);
+        c->graphs.erase(c->graph_order.front());
+        c->graph_order.erase(c->graph_order.begin());
+      }
+      git = c->graphs.emplace(key, exec).first;
+      c->graph_order.push_back(key);
+    }
+    HIPCHK(c, hipGraphLaunch(git->second, bs));
+  } else {
+    const int rc = enqueue(bs);
+    if (rc) return rc;
+  }
+  std::vector<int> hinfo(nsys, 0);
+  HIPCHK(c, hipMemcpyAsync(hinfo.data(), infos, size_t(nsys) * sizeof(int), hipMemcpyDeviceToHost, bs));
+  HIPCHK(c, hipEventRecord(c->bev_out, bs));
+  HIPCHK(c, hipStreamWaitEvent(us, c->bev_out, 0));
+  HIPCHK(c, hipStreamSynchronize(bs));
+  HIPCHK(c, hipGetLastError());
+  int bad = 0;
+  for (int q = 0; q < nsys; ++q) {
+    if (hinfo[q] > 0) { sys[q].status = ACE_E_NOT_PD; sys[q].fail_column = hinfo[q] - 1; ++bad; }
+    else if (hinfo[q] < 0) { sys[q].status = ACE_E_NONFINITE; sys[q].fail_column = -hinfo[q] - 1; ++bad; }
+  }
+  if (bad) return fail(c, ACE_E_NOT_PD, "%d of %d systems failed the Cholesky factorization (see status)", bad, nsys);
   return ACE_OK;
 }
 

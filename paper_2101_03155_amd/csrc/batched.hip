@@ -1,0 +1,202 @@
+// Batched pair stage: the pair Poisson solves of many independent systems of
+// uneven size (grids 16^3 .. 96^3, different orbital counts, pair lists and
+// interaction kernels) sharing launches.
+//
+// The pair list of every system is split into conflict-free rounds (as for a
+// single build); super-round r gathers round r of every system, and a
+// segment is the part of a super-round whose systems share one grid size N.
+// The five passes of the split path (x forward with the pair product,
+// y forward, z forward + v(G) + z inverse, y inverse, x inverse with the W
+// update) are "phases"; a work item is one workgroup's share of one phase of
+// one pack, and the items of a segment cover packs of different systems,
+// kernels and pair-list lengths.  Kernels are specialized per N (mixing sizes
+// in one kernel would size its registers for the largest case).
+//
+// Two launch forms:
+//  * one launch per (segment, phase), captured with everything else of the
+//    batched build in a hipGraph;
+//  * one cooperative (persistent) launch per grid size that walks all its
+//    segments and phases with a grid-wide barrier after each phase, so the
+//    data a phase reads was completely written by the previous one.
+#include <hip/hip_cooperative_groups.h>
+
+#include "ace_internal.h"
+#include "fft.h"
+#include "pair_phases.h"
+
+namespace ace {
+
+namespace cg = cooperative_groups;
+
+constexpr int BNT = 256;
+
+template <int TXV>
+__host__ __device__ constexpr int btx(int n) { return pick_tx(n) < TXV ? pick_tx(n) : TXV; }
+
+__host__ __device__ inline int64_t batched_items(int n, int phase, int txv) {
+  const int rows = pick_rows(n);
+  const int tx = txv == 8 ? btx<8>(n) : btx<16>(n);
+  return (phase == 0 || phase == 4) ? int64_t(n) * n / rows : int64_t(n / tx) * n;
+}
+
+template <typename T, int N, int TXV, int V>
+__device__ __forceinline__ void run_phase(int p, int64_t b, const BSys& sy, const BPack& bp, cplx<T>* buf,
+                                          const cplx<T>* tw, double* red, int tid) {
+  constexpr int TX = btx<TXV>(N);
+  constexpr int ROWS = pick_rows(N);
+  constexpr int NXT = N / TX;
+  cplx<T>* spec = static_cast<cplx<T>*>(bp.spec);
+  const T* phi = static_cast<const T*>(sy.phi);
+  if (p == 0) {
+    body_fwd_x<T, N, ROWS, BNT, V>(phi, spec, bp.pk, size_t(b) * ROWS * N, buf, tw, tid);
+  } else if (p == 1) {
+    body_line_y<T, N, TX, BNT, -1, V>(spec, int(b % NXT) * TX, int(b / NXT), buf, tw, tid);
+  } else if (p == 2) {
+    KernelParams kp;
+    kp.kind = sy.kind;
+    kp.omega = sy.omega;
+    kp.inv_ng = sy.inv_ng;
+    kp.g[0] = sy.g[0]; kp.g[1] = sy.g[1]; kp.g[2] = sy.g[2];
+    body_conv_z<T, N, TX, BNT, V>(spec, int(b % NXT) * TX, int(b / NXT), kp, buf, tw, tid);
+  } else if (p == 3) {
+    body_line_y<T, N, TX, BNT, +1, V>(spec, int(b % NXT) * TX, int(b / NXT), buf, tw, tid);
+  } else {
+    body_inv_x<T, N, ROWS, BNT, false, V>(phi, spec, bp.pk, size_t(b) * ROWS * N, static_cast<T*>(sy.W), nullptr,
+                                          buf, tw, red, tid);
+  }
+}
+
+// Item j of phase p of segment sg (all packs of one grid size N).
+template <typename T, int N, int TXV, int V>
+__device__ __forceinline__ void run_item(int p, int64_t j, const BRound& sg, const BSys* __restrict__ sys,
+                                         const BPack* __restrict__ packs, const int64_t* __restrict__ starts,
+                                         cplx<T>* buf, cplx<T>* tw, double* red) {
+  const int tid = threadIdx.x;
+  // pack q with starts[q] <= j < starts[q + 1]
+  const int64_t* st = starts + sg.start_off[p];
+  int lo = 0, hi = sg.npacks;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (st[mid] <= j) lo = mid; else hi = mid;
+  }
+  const BPack bp = packs[sg.pack0 + lo];
+  const BSys& sy = sys[bp.sys];
+  const int64_t b = j - st[lo];
+  const cplx<T>* twg = static_cast<const cplx<T>*>(sy.tw);
+  __syncthreads();  // the previous item's last reads of buf/tw are done
+  for (int i = tid; i < N; i += BNT) tw[i] = twg[i];
+  run_phase<T, N, TXV, V>(p, b, sy, bp, buf, tw, red, tid);
+}
+
+template <typename T, int N, int TXV, int V>
+__global__ __launch_bounds__(BNT) void k_batched_phase(int p, BRound sg, const BSys* __restrict__ sys,
+                                                       const BPack* __restrict__ packs,
+                                                       const int64_t* __restrict__ starts) {
+  constexpr int E = (N * btx<TXV>(N) > pick_rows(N) * N) ? N * btx<TXV>(N) : pick_rows(N) * N;
+  __shared__ cplx<T> buf[E];
+  __shared__ cplx<T> tw[N];
+  __shared__ double red[2 * (BNT / 64)];
+  for (int64_t j = blockIdx.x; j < sg.nitems[p]; j += gridDim.x)
+    run_item<T, N, TXV, V>(p, j, sg, sys, packs, starts, buf, tw, red);
+}
+
+// One launch for every segment of one grid size: all super-rounds, all five
+// phases, a grid-wide barrier after each phase.
+template <typename T, int N, int TXV, int V>
+__global__ __launch_bounds__(BNT) void k_batched_persistent(int nseg, const BRound* __restrict__ segs,
+                                                            const BSys* __restrict__ sys,
+                                                            const BPack* __restrict__ packs,
+                                                            const int64_t* __restrict__ starts) {
+  constexpr int E = (N * btx<TXV>(N) > pick_rows(N) * N) ? N * btx<TXV>(N) : pick_rows(N) * N;
+  __shared__ cplx<T> buf[E];
+  __shared__ cplx<T> tw[N];
+  __shared__ double red[2 * (BNT / 64)];
+  cg::grid_group grid = cg::this_grid();
+  for (int r = 0; r < nseg; ++r) {
+    const BRound sg = segs[r];
+    for (int p = 0; p < 5; ++p) {
+      for (int64_t j = blockIdx.x; j < sg.nitems[p]; j += gridDim.x)
+        run_item<T, N, TXV, V>(p, j, sg, sys, packs, starts, buf, tw, red);
+      grid.sync();
+    }
+  }
+}
+
+bool batched_supported(int n) {
+  return n == 16 || n == 24 || n == 32 || n == 48 || n == 64 || n == 80 || n == 96;
+}
+
+int64_t batched_phase_items(int n, int phase, int txv) { return batched_items(n, phase, txv); }
+
+template <typename T, int N, int TXV, int V>
+static hipError_t launch_seg_t(int mode, int nseg, const BRound* h_segs, const BRound* d_segs, const BSys* sys,
+                               const BPack* packs, const int64_t* starts, int blocks_per_cu, hipStream_t s) {
+  if (mode == 1) {
+    int dev = 0, ncu = 0, per = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched_persistent<T, N, TXV, V>, BNT, 0);
+    if (e != hipSuccess) return e;
+    if (per < 1) return hipErrorInvalidConfiguration;
+    const int use = (blocks_per_cu > 0 && blocks_per_cu < per) ? blocks_per_cu : per;
+    dim3 grid(unsigned(ncu * use)), block(BNT);
+    void* args[] = {&nseg, (void*)&d_segs, (void*)&sys, (void*)&packs, (void*)&starts};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_batched_persistent<T, N, TXV, V>), grid, block,
+                                      args, 0, s);
+  }
+  const int grid_cap = 256 * (blocks_per_cu > 0 ? blocks_per_cu : 8);
+  for (int r = 0; r < nseg; ++r)
+    for (int p = 0; p < 5; ++p) {
+      const int64_t n = h_segs[r].nitems[p];
+      if (n == 0) continue;
+      const unsigned g = unsigned(n < grid_cap ? n : grid_cap);
+      hipLaunchKernelGGL((k_batched_phase<T, N, TXV, V>), dim3(g), dim3(BNT), 0, s, p, h_segs[r], sys, packs, starts);
+    }
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+static hipError_t launch_seg_n(int mode, int txv, int plan_v, int nseg, const BRound* h, const BRound* d,
+                               const BSys* sys, const BPack* packs, const int64_t* starts, int bpc, hipStream_t s) {
+  if (txv == 8)
+    return plan_v ? launch_seg_t<T, N, 8, 1>(mode, nseg, h, d, sys, packs, starts, bpc, s)
+                  : launch_seg_t<T, N, 8, 0>(mode, nseg, h, d, sys, packs, starts, bpc, s);
+  return plan_v ? launch_seg_t<T, N, 16, 1>(mode, nseg, h, d, sys, packs, starts, bpc, s)
+                : launch_seg_t<T, N, 16, 0>(mode, nseg, h, d, sys, packs, starts, bpc, s);
+}
+
+// Launch the segments [h_segs, h_segs + nseg), all of grid size n.
+hipError_t batched_segments(int prec, int n, int mode, int txv, int plan_v, int blocks_per_cu, int nseg,
+                            const BRound* h_segs, const BRound* d_segs, const BSys* sys, const BPack* packs,
+                            const int64_t* starts, hipStream_t s) {
+  switch (n) {
+#define X(nn)                                                                                                  \
+  case nn:                                                                                                     \
+    return prec == 0 ? launch_seg_n<double, nn>(mode, txv, plan_v, nseg, h_segs, d_segs, sys, packs, starts,   \
+                                                blocks_per_cu, s)                                              \
+                     : launch_seg_n<float, nn>(mode, txv, plan_v, nseg, h_segs, d_segs, sys, packs, starts,    \
+                                               blocks_per_cu, s);
+    X(16) X(24) X(32) X(48) X(64) X(80) X(96)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+// Zero fill without memset nodes (kept out of captured graphs).
+__global__ void k_zero(uint32_t* __restrict__ p, int64_t n) {
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < n; e += int64_t(gridDim.x) * blockDim.x)
+    p[e] = 0u;
+}
+
+void launch_zero(void* p, size_t bytes, hipStream_t s) {
+  const int64_t n = int64_t(bytes / 4);
+  int64_t g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_zero, dim3(unsigned(g)), dim3(256), 0, s, static_cast<uint32_t*>(p), n);
+}
+
+}  // namespace ace

@@ -66,8 +66,15 @@ constexpr int plan_radix(int n, int p) {
   for (int i = 0; i < pow_of(n, 5); ++i) r[cnt++] = 5;
   return r[p];
 }
+// Plan variants: 0 takes the radices in the order above, 1 in reverse order
+// (small radices first).  Both give the same transform; the tuner picks.
+constexpr int plan_radix_v(int n, int p, int v) { return v == 0 ? plan_radix(n, p) : plan_radix(n, plan_len(n) - 1 - p); }
 // product of the radices of passes 0..p-1
-constexpr int plan_ns(int n, int p) { int s = 1; for (int i = 0; i < p; ++i) s *= plan_radix(n, i); return s; }
+constexpr int plan_ns(int n, int p, int v = 0) {
+  int s = 1;
+  for (int i = 0; i < p; ++i) s *= plan_radix_v(n, i, v);
+  return s;
+}
 
 // ---------------------------------------------------------------- small DFTs
 // In-register DFT of length R with exponent sign S (-1 forward, +1 inverse).
@@ -144,11 +151,11 @@ template <int S, typename C> struct Dft<8, S, C> {
 // LINES lines of length N in LDS; element p of line l at buf[l*LS + p*PS].
 // JFAST: consecutive threads take consecutive butterflies of one line
 // (unit-stride lines) rather than the same butterfly of consecutive lines.
-template <typename T, int N, int P, int LINES, int LS, int PS, int NT, int S, bool JFAST>
+template <typename T, int N, int P, int LINES, int LS, int PS, int NT, int S, bool JFAST, int V>
 __device__ __forceinline__ void fft_pass(cplx<T>* buf, const cplx<T>* tw, int tid) {
   using C = cplx<T>;
-  constexpr int R = plan_radix(N, P);
-  constexpr int NS = plan_ns(N, P);
+  constexpr int R = plan_radix_v(N, P, V);
+  constexpr int NS = plan_ns(N, P, V);
   constexpr int NB = N / R;
   constexpr int TOT = LINES * NB;
   constexpr int PER = (TOT + NT - 1) / NT;
@@ -190,20 +197,20 @@ __device__ __forceinline__ void fft_pass(cplx<T>* buf, const cplx<T>* tw, int ti
   __syncthreads();
 }
 
-template <typename T, int N, int P, int LINES, int LS, int PS, int NT, int S, bool JFAST>
+template <typename T, int N, int P, int LINES, int LS, int PS, int NT, int S, bool JFAST, int V>
 __device__ __forceinline__ void fft_lines_from(cplx<T>* buf, const cplx<T>* tw, int tid) {
   if constexpr (P < plan_len(N)) {
-    fft_pass<T, N, P, LINES, LS, PS, NT, S, JFAST>(buf, tw, tid);
-    fft_lines_from<T, N, P + 1, LINES, LS, PS, NT, S, JFAST>(buf, tw, tid);
+    fft_pass<T, N, P, LINES, LS, PS, NT, S, JFAST, V>(buf, tw, tid);
+    fft_lines_from<T, N, P + 1, LINES, LS, PS, NT, S, JFAST, V>(buf, tw, tid);
   }
 }
 
 // Full length-N transform of LINES lines held in LDS.  tw[m] = exp(-2 pi i m/N).
 // Expects the caller to have synchronized after filling buf; ends synchronized.
-template <typename T, int N, int LINES, int LS, int PS, int NT, int S, bool JFAST>
+template <typename T, int N, int LINES, int LS, int PS, int NT, int S, bool JFAST, int V = 0>
 __device__ __forceinline__ void fft_lines(cplx<T>* buf, const cplx<T>* tw, int tid) {
   static_assert(smooth235(N), "FFT length must be 2^a 3^b 5^c");
-  fft_lines_from<T, N, 0, LINES, LS, PS, NT, S, JFAST>(buf, tw, tid);
+  fft_lines_from<T, N, 0, LINES, LS, PS, NT, S, JFAST, V>(buf, tw, tid);
 }
 
 }  // namespace ace

@@ -230,6 +230,34 @@ __global__ __launch_bounds__(256) void k_gemm_ls(const double* __restrict__ S, i
       }
 }
 
+// ---------------------------------------------------------------- small outputs
+// Same contraction as the left-small kernel for small outputs (R <= 1024):
+// one wave per 16 x 16 output tile, operands read straight from global memory
+// (L2-resident at these sizes), so even a 128^3 product spreads over 64 CUs.
+template <typename TB, bool TRANS, bool LOWER>
+__global__ __launch_bounds__(64) void k_gemm_tiny(const double* __restrict__ S, int lds, const TB* __restrict__ B,
+                                                  int64_t ldb, double* __restrict__ C, int64_t ldc, int M, int K,
+                                                  int64_t R, double alpha) {
+  const int lane = threadIdx.x;
+  const int r0 = blockIdx.x * 16, m0 = blockIdx.y * 16;
+  const int li = lane % 16, lk = lane / 16;
+  d4 acc = d4{0, 0, 0, 0};
+  const int kend = LOWER ? ((m0 + 16 < K) ? m0 + 16 : K) : K;
+  for (int k0 = 0; k0 < kend; k0 += 4) {
+    const int k = k0 + lk, m = m0 + li;
+    const int64_t r = r0 + li;
+    double a = 0.0, b = 0.0;
+    if (k < K && m < M) a = TRANS ? S[int64_t(k) * lds + m] : S[int64_t(m) * lds + k];
+    if (k < K && r < R) b = double(B[int64_t(k) * ldb + r]);
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+  for (int q = 0; q < 4; ++q) {
+    const int i = m0 + lk + 4 * q;
+    const int64_t j = r0 + li;
+    if (i < M && j < R) C[int64_t(i) * ldc + j] = alpha * acc[q];
+  }
+}
+
 // ---------------------------------------------------------------- host wrappers
 
 int64_t gemm_nt_nsplit(int M, int Nn, int64_t K, int64_t* kchunk_out) {
@@ -273,7 +301,10 @@ hipError_t gemm_nt(int prec, bool abs_ops, const void* A, int64_t lda, const voi
 template <typename TB, bool TRANS, bool LOWER>
 static void launch_ls(const double* S, int lds, const TB* B, int64_t ldb, double* C, int64_t ldc, int M, int K,
                       int64_t R, double alpha, hipStream_t s) {
-  if (M > 64) {
+  if (R <= 1024) {
+    dim3 grid(unsigned((R + 15) / 16), unsigned((M + 15) / 16));
+    hipLaunchKernelGGL((k_gemm_tiny<TB, TRANS, LOWER>), grid, dim3(64), 0, s, S, lds, B, ldb, C, ldc, M, K, R, alpha);
+  } else if (M > 64) {
     dim3 grid(unsigned((R + GB - 1) / GB), unsigned((M + 127) / 128));
     hipLaunchKernelGGL((k_gemm_ls<TB, TRANS, LOWER, 128>), grid, dim3(256), 0, s, S, lds, B, ldb, C, ldc, M, K, R,
                        alpha);

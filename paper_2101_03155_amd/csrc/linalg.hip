@@ -44,10 +44,16 @@ __global__ void k_symmetrize(const double* __restrict__ M, int n, double* __rest
 
 // In-place right-looking Cholesky of the lower triangle of A (n x n, one
 // workgroup).  info: 0 ok, k+1 if the pivot of column k is not positive,
-// -(k+1) if it is not finite.  The strict upper triangle is zeroed.
-__global__ __launch_bounds__(1024) void k_cholesky(double* __restrict__ A, int n, int* __restrict__ info) {
+// -(k+1) if it is not finite.  The strict upper triangle is zeroed.  With
+// INLDS the matrix is staged in LDS (n <= 128).
+template <bool INLDS>
+__global__ __launch_bounds__(1024) void k_cholesky(double* __restrict__ Ag, int n, int* __restrict__ info) {
   __shared__ double piv;
   __shared__ int bad;
+  __shared__ double As[INLDS ? 128 * 128 : 1];
+  double* A = INLDS ? As : Ag;
+  if (INLDS)
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) As[e] = Ag[e];
   if (threadIdx.x == 0) bad = 0;
   __syncthreads();
   for (int k = 0; k < n; ++k) {
@@ -78,21 +84,26 @@ __global__ __launch_bounds__(1024) void k_cholesky(double* __restrict__ A, int n
   if (threadIdx.x == 0) info[0] = bad;
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
     const int i = e / n, j = e % n;
-    if (j > i) A[e] = 0.0;
+    Ag[e] = (j > i) ? 0.0 : A[e];
   }
 }
 
-// Inverse of a lower-triangular L (n x n): one thread per column c solves
-// L x = e_c by forward substitution; X is lower triangular.
-__global__ void k_trinv_lower(const double* __restrict__ L, int n, double* __restrict__ X) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
-  for (int i = 0; i < c; ++i) X[i * n + c] = 0.0;
+// Inverse of a lower-triangular L (n x n, n <= 512): one 64-lane wave per
+// column c solves L x = e_c by forward substitution, each step a wave-wide
+// dot product; x lives in LDS.  X is lower triangular.
+__global__ __launch_bounds__(64) void k_trinv_lower(const double* __restrict__ L, int n, double* __restrict__ X) {
+  __shared__ double x[512];
+  const int c = blockIdx.x, lane = threadIdx.x;
+  for (int i = lane; i < n; i += 64) x[i] = 0.0;
+  __syncthreads();
   for (int i = c; i < n; ++i) {
-    double s = (i == c) ? 1.0 : 0.0;
-    for (int k = c; k < i; ++k) s -= L[i * n + k] * X[k * n + c];
-    X[i * n + c] = s / L[i * n + i];
+    double s = 0.0;
+    for (int k = c + lane; k < i; k += 64) s += L[int64_t(i) * n + k] * x[k];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (lane == 0) x[i] = ((i == c ? 1.0 : 0.0) - s) / L[int64_t(i) * n + i];
+    __syncthreads();
   }
+  for (int i = lane; i < n; i += 64) X[int64_t(i) * n + c] = x[i];
 }
 
 // ---------------------------------------------------------------- SCDM pivot search
@@ -168,11 +179,15 @@ __device__ __forceinline__ void topk_insert(double (&tv)[TOPK], int64_t (&ti)[TO
 }
 
 // One pivot step, bulk part: ell[r] = q . A[:, r]; res[r] -= ell^2 (if q given);
-// then per-block top-8 of res into pv/pi [block][8].
+// then per-block top-8 of res into pv/pi [block][8].  A is [n][ng]: either
+// the orbitals themselves or a compact pool of candidate columns.  A set stop
+// flag turns the launch into a no-op.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_qrcp_update(const double* __restrict__ A, int n, int64_t ng,
                                                     const double* __restrict__ q, double* __restrict__ res,
-                                                    double* __restrict__ pv, int64_t* __restrict__ pi) {
+                                                    double* __restrict__ pv, int64_t* __restrict__ pi,
+                                                    const int* __restrict__ stop) {
+  if (stop && *stop) return;
   __shared__ double qs[1024];
   const bool upd = q != nullptr;
   if (upd)
@@ -198,19 +213,32 @@ __global__ __launch_bounds__(NT) void k_qrcp_update(const double* __restrict__ A
 // One pivot step, selection part (single workgroup of NT threads):
 // merge block candidates -> global top-8; recompute their residuals by
 // explicit double projection against Q[0..k); pick the best (ties: smaller
-// grid index); append q_k = residual / |residual| to Q; record the pivot and
+// column index); append q_k = residual / |residual| to Q; record the pivot and
 // retire the column (res = -1).
+//
+// k is read from and advanced in device memory.  With a candidate pool
+// (pool != nullptr, columns sorted by grid index), the pick is accepted only
+// if its exact residual is at least t_out, an upper bound of every residual
+// outside the pool; otherwise the stop flag is raised and the host refreshes
+// the pool.  A raised stop flag turns the launch into a no-op.
 template <int NT>
-__global__ __launch_bounds__(NT) void k_qrcp_select(const double* __restrict__ A, int n, int64_t ng, int k,
-                                                    const double* __restrict__ pv, const int64_t* __restrict__ pi,
-                                                    int nblk, double* __restrict__ Q, double* __restrict__ res,
-                                                    int32_t* __restrict__ piv, double* __restrict__ qout) {
+__global__ __launch_bounds__(NT) void k_qrcp_select(const double* __restrict__ A, int n, int64_t ng,
+                                                    int* __restrict__ kdev, const double* __restrict__ pv,
+                                                    const int64_t* __restrict__ pi, int nblk, double* __restrict__ Q,
+                                                    double* __restrict__ res, int32_t* __restrict__ piv,
+                                                    double* __restrict__ qout, const int32_t* __restrict__ pool,
+                                                    const double* __restrict__ t_out, int* __restrict__ stop) {
+  if (*stop) return;
   __shared__ double cv[TOPK];
   __shared__ int64_t ci[TOPK];
   __shared__ double vec[TOPK][512];
   __shared__ double dots[TOPK][512];
+  __shared__ double part[TOPK * NT];
+  constexpr int QCH = 4096;
+  __shared__ double Qs[QCH];
   __shared__ double r2[TOPK];
-  __shared__ int best;
+  __shared__ int best, accept;
+  const int k = *kdev;
   {
     double tv[TOPK];
     int64_t ti[TOPK];
@@ -220,37 +248,85 @@ __global__ __launch_bounds__(NT) void k_qrcp_select(const double* __restrict__ A
     block_topk<NT>(tv, ti, cv, ci);
   }
   __syncthreads();
+  // valid candidates: real columns that are not retired (res = -1)
   int nc = 0;
   for (int t = 0; t < TOPK; ++t)
-    if (ci[t] != INT64_MAX && ci[t] < ng) nc = t + 1;
-  // gather candidate columns
-  for (int e = threadIdx.x; e < nc * n; e += NT) {
+    if (ci[t] != INT64_MAX && ci[t] < ng && cv[t] > -0.5) nc = t + 1;
+  if (nc == 0) {
+    if (threadIdx.x == 0) *stop = 1;
+    return;
+  }
+  for (int e = threadIdx.x; e < TOPK * n; e += NT) {
     const int c = e / n, i = e % n;
-    vec[c][i] = A[int64_t(i) * ng + ci[c]];
+    vec[c][i] = c < nc ? A[int64_t(i) * ng + ci[c]] : 0.0;
   }
   __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  constexpr int NW = NT / 64;
+  // Q is read in chunks of mc rows staged through LDS (coalesced bulk loads)
+  const int mc = QCH / n;
+  const int G = NT / n;
+  const int g = threadIdx.x / n, gi = threadIdx.x % n;
   for (int pass = 0; pass < 2; ++pass) {
-    // dots[c][m] = Q[m] . vec[c]
-    for (int e = threadIdx.x; e < nc * k; e += NT) {
-      const int c = e / k, m = e % k;
-      double s = 0.0;
-      for (int i = 0; i < n; ++i) s += Q[int64_t(m) * n + i] * vec[c][i];
-      dots[c][m] = s;
+    // dots[c][m] = Q[m] . vec[c]: one wave per row, lanes across i
+    for (int m0 = 0; m0 < k; m0 += mc) {
+      const int rows = (k - m0 < mc) ? k - m0 : mc;
+      for (int e = threadIdx.x; e < rows * n; e += NT) Qs[e] = Q[int64_t(m0) * n + e];
+      __syncthreads();
+      for (int r = wv; r < rows; r += NW) {
+        double acc[TOPK];
+#pragma unroll
+        for (int c = 0; c < TOPK; ++c) acc[c] = 0.0;
+        for (int i = lane; i < n; i += 64) {
+          const double qv = Qs[r * n + i];
+#pragma unroll
+          for (int c = 0; c < TOPK; ++c) acc[c] += qv * vec[c][i];
+        }
+#pragma unroll
+        for (int c = 0; c < TOPK; ++c) {
+          double v = acc[c];
+          for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+          if (lane == 0) dots[c][m0 + r] = v;
+        }
+      }
+      __syncthreads();
+    }
+    // vec[c][i] -= sum_m dots[c][m] Q[m][i]: G thread groups split the rows,
+    // their partial sums meet in LDS
+    double acc[TOPK];
+#pragma unroll
+    for (int c = 0; c < TOPK; ++c) acc[c] = 0.0;
+    for (int m0 = 0; m0 < k; m0 += mc) {
+      const int rows = (k - m0 < mc) ? k - m0 : mc;
+      for (int e = threadIdx.x; e < rows * n; e += NT) Qs[e] = Q[int64_t(m0) * n + e];
+      __syncthreads();
+      if (g < G)
+        for (int r = g; r < rows; r += G) {
+          const double qv = Qs[r * n + gi];
+#pragma unroll
+          for (int c = 0; c < TOPK; ++c) acc[c] += dots[c][m0 + r] * qv;
+        }
+      __syncthreads();
+    }
+    if (g < G) {
+#pragma unroll
+      for (int c = 0; c < TOPK; ++c) part[(g * TOPK + c) * n + gi] = acc[c];
     }
     __syncthreads();
-    // vec[c][i] -= sum_m dots[c][m] Q[m][i]
-    for (int e = threadIdx.x; e < nc * n; e += NT) {
-      const int c = e / n, i = e % n;
-      double s = 0.0;
-      for (int m = 0; m < k; ++m) s += dots[c][m] * Q[int64_t(m) * n + i];
-      vec[c][i] -= s;
+    for (int e = threadIdx.x; e < TOPK * n; e += NT) {
+      const int c = e / n, ii = e % n;
+      double sum = 0.0;
+      for (int gg = 0; gg < G; ++gg) sum += part[(gg * TOPK + c) * n + ii];
+      vec[c][ii] -= sum;
     }
     __syncthreads();
   }
-  if (threadIdx.x < nc) {
-    double s = 0.0;
-    for (int i = 0; i < n; ++i) s += vec[threadIdx.x][i] * vec[threadIdx.x][i];
-    r2[threadIdx.x] = s;
+  // squared residual norms: one wave per candidate
+  for (int c = wv; c < TOPK; c += NW) {
+    double v = 0.0;
+    for (int i = lane; i < n; i += 64) v += vec[c][i] * vec[c][i];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) r2[c] = v;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -258,16 +334,211 @@ __global__ __launch_bounds__(NT) void k_qrcp_select(const double* __restrict__ A
     for (int c = 1; c < nc; ++c)
       if (ranks_before(r2[c], ci[c], r2[b], ci[b])) b = c;
     best = b;
-    piv[k] = int32_t(ci[b]);
-    res[ci[b]] = -1.0;
+    const bool ok = (t_out == nullptr) || (r2[b] >= *t_out);
+    accept = ok ? 1 : 0;
+    if (ok) {
+      piv[k] = pool ? pool[ci[b]] : int32_t(ci[b]);
+      res[ci[b]] = -1.0;
+    } else {
+      *stop = 1;
+    }
   }
   __syncthreads();
+  if (!accept) return;
   const double inv = 1.0 / sqrt(r2[best]);
   for (int i = threadIdx.x; i < n; i += NT) {
     const double v = vec[best][i] * inv;
     Q[int64_t(k) * n + i] = v;
     qout[i] = v;
   }
+  __syncthreads();
+  if (threadIdx.x == 0) *kdev = k + 1;
+}
+
+// ---------------------------------------------------------------- candidate pool
+// The pool holds every column whose residual bound is at least a threshold t
+// picked from a histogram of the top 14 bits of the (positive) residuals, so
+// that the pool has at most pmax columns.  t_out = the largest residual
+// below t bounds every column left out.
+constexpr int HBIN = 1 << 14;
+
+__device__ __forceinline__ int res_bin(double v) { return int(__double_as_longlong(v) >> 49); }
+
+__global__ __launch_bounds__(256) void k_res_hist(const double* __restrict__ res, int64_t ng,
+                                                  unsigned* __restrict__ hist) {
+  __shared__ unsigned h[HBIN];
+  for (int i = threadIdx.x; i < HBIN; i += 256) h[i] = 0u;
+  __syncthreads();
+  for (int64_t r = blockIdx.x * int64_t(256) + threadIdx.x; r < ng; r += int64_t(gridDim.x) * 256) {
+    const double v = res[r];
+    if (v > 0.0) atomicAdd(&h[res_bin(v)], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < HBIN; i += 256)
+    if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+// Lowest bin b such that the columns in bins >= b number at most pmax;
+// t = lower edge of bin b (as a double).
+__global__ __launch_bounds__(1024) void k_pool_threshold(const unsigned* __restrict__ hist, int pmax,
+                                                         double* __restrict__ t) {
+  constexpr int SEG = HBIN / 1024;
+  __shared__ unsigned long long above[1024];
+  __shared__ int tb;
+  unsigned long long seg = 0;
+  for (int b = 0; b < SEG; ++b) seg += hist[threadIdx.x * SEG + b];
+  above[threadIdx.x] = seg;
+  if (threadIdx.x == 0) tb = 0;
+  __syncthreads();
+  // inclusive suffix sum over segments
+  for (int off = 1; off < 1024; off <<= 1) {
+    unsigned long long v = (threadIdx.x + off < 1024) ? above[threadIdx.x + off] : 0ull;
+    __syncthreads();
+    above[threadIdx.x] += v;
+    __syncthreads();
+  }
+  const unsigned long long incl = above[threadIdx.x];
+  const unsigned long long excl = incl - seg;  // columns in higher segments
+  if (excl <= (unsigned long long)pmax && incl > (unsigned long long)pmax) {
+    unsigned long long c = excl;
+    int pick = threadIdx.x * SEG + SEG;
+    for (int b = threadIdx.x * SEG + SEG - 1; b >= threadIdx.x * SEG; --b) {
+      if (c + hist[b] > (unsigned long long)pmax) break;
+      c += hist[b];
+      pick = b;
+    }
+    tb = pick;
+  }
+  __syncthreads();
+  // tb == HBIN: not even the top bin fits; an infinite threshold empties the pool
+  if (threadIdx.x == 0) t[0] = tb >= HBIN ? INFINITY : __longlong_as_double((long long)tb << 49);
+}
+
+// Per block (contiguous chunk of columns): count of res >= t, max of 0 < res < t.
+__global__ __launch_bounds__(256) void k_pool_count(const double* __restrict__ res, int64_t ng, int64_t chunk,
+                                                    const double* __restrict__ t, int64_t* __restrict__ cnt,
+                                                    double* __restrict__ tmax) {
+  __shared__ int64_t sc[256];
+  __shared__ double sm[256];
+  const double th = t[0];
+  const int64_t r0 = int64_t(blockIdx.x) * chunk;
+  const int64_t r1 = (r0 + chunk < ng) ? r0 + chunk : ng;
+  int64_t c = 0;
+  double m = 0.0;
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
+    const double v = res[r];
+    if (v >= th && v > 0.0) ++c;
+    else if (v > 0.0 && v > m) m = v;
+  }
+  sc[threadIdx.x] = c;
+  sm[threadIdx.x] = m;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      sc[threadIdx.x] += sc[threadIdx.x + h];
+      sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + h]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) { cnt[blockIdx.x] = sc[0]; tmax[blockIdx.x] = sm[0]; }
+}
+
+// Exclusive scan of the block counts (in place), total count and t_out.
+__global__ __launch_bounds__(1024) void k_pool_scan(int64_t* __restrict__ cnt, const double* __restrict__ tmax,
+                                                    int nblk, int* __restrict__ total, double* __restrict__ t_out) {
+  __shared__ int64_t s[1024];
+  __shared__ double m[1024];
+  __shared__ int64_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  double mx = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += 1024) mx = fmax(mx, tmax[b]);
+  m[threadIdx.x] = mx;
+  __syncthreads();
+  for (int h = 512; h > 0; h >>= 1) {
+    if (threadIdx.x < h) m[threadIdx.x] = fmax(m[threadIdx.x], m[threadIdx.x + h]);
+    __syncthreads();
+  }
+  for (int base = 0; base < nblk; base += 1024) {
+    const int b = base + threadIdx.x;
+    const int64_t v = b < nblk ? cnt[b] : 0;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      const int64_t u = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
+      __syncthreads();
+      s[threadIdx.x] += u;
+      __syncthreads();
+    }
+    if (b < nblk) cnt[b] = carry + s[threadIdx.x] - v;
+    __syncthreads();
+    if (threadIdx.x == 0) carry += s[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) { total[0] = int(carry); t_out[0] = m[0]; }
+}
+
+// Ordered compaction: pool[off..] = columns with res >= t, by increasing index.
+__global__ __launch_bounds__(256) void k_pool_write(const double* __restrict__ res, int64_t ng, int64_t chunk,
+                                                    const double* __restrict__ t, const int64_t* __restrict__ off,
+                                                    int32_t* __restrict__ pool, double* __restrict__ pres) {
+  __shared__ int wsum[4];
+  __shared__ int64_t base;
+  const double th = t[0];
+  const int64_t r0 = int64_t(blockIdx.x) * chunk;
+  const int64_t r1 = (r0 + chunk < ng) ? r0 + chunk : ng;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (threadIdx.x == 0) base = off[blockIdx.x];
+  __syncthreads();
+  for (int64_t c0 = r0; c0 < r1; c0 += 256) {
+    const int64_t r = c0 + threadIdx.x;
+    double v = 0.0;
+    bool keep = false;
+    if (r < r1) {
+      v = res[r];
+      keep = v >= th && v > 0.0;
+    }
+    const unsigned long long bal = __ballot(keep);
+    const int before = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[wv] = __popcll(bal);
+    __syncthreads();
+    int64_t o = base;
+    for (int w = 0; w < wv; ++w) o += wsum[w];
+    if (keep) {
+      pool[o + before] = int32_t(r);
+      pres[o + before] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) base += wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+  }
+}
+
+// Apool[i][p] = A[i][pool[p]]
+__global__ void k_pool_gather(const double* __restrict__ A, int n, int64_t ng, const int32_t* __restrict__ pool,
+                              int np, double* __restrict__ Apool) {
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < int64_t(n) * np;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int i = int(e / np), p = int(e % np);
+    Apool[e] = A[int64_t(i) * ng + pool[p]];
+  }
+}
+
+// Residual bounds from scratch: res[r] = norm0[r] - sum_m L[m][r]^2 over the
+// k projections L = Q A of a chunk of columns (L is [k][rc]).
+__global__ void k_refresh_res(const double* __restrict__ L, int k, int64_t rc, const double* __restrict__ norm0,
+                              double* __restrict__ res) {
+  for (int64_t r = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; r < rc; r += int64_t(gridDim.x) * blockDim.x) {
+    double s = norm0[r];
+    for (int m = 0; m < k; ++m) {
+      const double l = L[int64_t(m) * rc + r];
+      s -= l * l;
+    }
+    res[r] = s;
+  }
+}
+
+__global__ void k_retire(const int32_t* __restrict__ piv, int k, double* __restrict__ res) {
+  for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < k; m += gridDim.x * blockDim.x) res[piv[m]] = -1.0;
 }
 
 // AC[i][k] = A[i][piv[k]]
@@ -412,22 +683,54 @@ void launch_symmetrize(const double* M, int n, double* out, double* negM, double
   hipLaunchKernelGGL(k_symmetrize, dim3(1), dim3(256), 0, s, M, n, out, negM, ex, asym);
 }
 void launch_cholesky(double* A, int n, int* info, hipStream_t s) {
-  hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, s, A, n, info);
+  if (n <= 128)
+    hipLaunchKernelGGL(k_cholesky<true>, dim3(1), dim3(1024), 0, s, A, n, info);
+  else
+    hipLaunchKernelGGL(k_cholesky<false>, dim3(1), dim3(1024), 0, s, A, n, info);
 }
 void launch_trinv(const double* L, int n, double* X, hipStream_t s) {
-  hipLaunchKernelGGL(k_trinv_lower, dim3((n + 63) / 64), dim3(64), 0, s, L, n, X);
+  hipLaunchKernelGGL(k_trinv_lower, dim3(n), dim3(64), 0, s, L, n, X);
 }
 void launch_colnorm(const double* A, int n, int64_t ng, double* res, hipStream_t s) {
   hipLaunchKernelGGL(k_colnorm, dim3(grid_for(ng, 256)), dim3(256), 0, s, A, n, ng, res);
 }
 int qrcp_blocks(int64_t ng) { return grid_for(ng, 256, 2048); }
 void launch_qrcp_update(const double* A, int n, int64_t ng, const double* q, double* res, double* pv, int64_t* pi,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(k_qrcp_update<256>, dim3(qrcp_blocks(ng)), dim3(256), 0, s, A, n, ng, q, res, pv, pi);
+                        const int* stop, hipStream_t s) {
+  hipLaunchKernelGGL(k_qrcp_update<256>, dim3(qrcp_blocks(ng)), dim3(256), 0, s, A, n, ng, q, res, pv, pi, stop);
 }
-void launch_qrcp_select(const double* A, int n, int64_t ng, int k, const double* pv, const int64_t* pi, int nblk,
-                        double* Q, double* res, int32_t* piv, double* qout, hipStream_t s) {
-  hipLaunchKernelGGL(k_qrcp_select<512>, dim3(1), dim3(512), 0, s, A, n, ng, k, pv, pi, nblk, Q, res, piv, qout);
+void launch_qrcp_select(const double* A, int n, int64_t ng, int* kdev, const double* pv, const int64_t* pi,
+                        int nblk, double* Q, double* res, int32_t* piv, double* qout, const int32_t* pool,
+                        const double* t_out, int* stop, hipStream_t s) {
+  hipLaunchKernelGGL(k_qrcp_select<512>, dim3(1), dim3(512), 0, s, A, n, ng, kdev, pv, pi, nblk, Q, res, piv, qout,
+                     pool, t_out, stop);
+}
+int pool_blocks(int64_t ng) { return grid_for(ng, 4096, 2048); }
+void launch_pool_build(const double* res, int64_t ng, int pmax, unsigned* hist, double* t, int64_t* cnt,
+                       double* tmax, int* total, double* t_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_res_hist, dim3(grid_for(ng, 256, 1024)), dim3(256), 0, s, res, ng, hist);
+  hipLaunchKernelGGL(k_pool_threshold, dim3(1), dim3(1024), 0, s, hist, pmax, t);
+  const int nb = pool_blocks(ng);
+  const int64_t chunk = (ng + nb - 1) / nb;
+  hipLaunchKernelGGL(k_pool_count, dim3(nb), dim3(256), 0, s, res, ng, chunk, t, cnt, tmax);
+  hipLaunchKernelGGL(k_pool_scan, dim3(1), dim3(1024), 0, s, cnt, tmax, nb, total, t_out);
+}
+void launch_pool_write(const double* res, int64_t ng, const double* t, const int64_t* off, int32_t* pool,
+                       double* pres, hipStream_t s) {
+  const int nb = pool_blocks(ng);
+  const int64_t chunk = (ng + nb - 1) / nb;
+  hipLaunchKernelGGL(k_pool_write, dim3(nb), dim3(256), 0, s, res, ng, chunk, t, off, pool, pres);
+}
+void launch_pool_gather(const double* A, int n, int64_t ng, const int32_t* pool, int np, double* Apool,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_pool_gather, dim3(grid_for(int64_t(n) * np, 256)), dim3(256), 0, s, A, n, ng, pool, np,
+                     Apool);
+}
+void launch_refresh_res(const double* L, int k, int64_t rc, const double* norm0, double* res, hipStream_t s) {
+  hipLaunchKernelGGL(k_refresh_res, dim3(grid_for(rc, 256)), dim3(256), 0, s, L, k, rc, norm0, res);
+}
+void launch_retire(const int32_t* piv, int k, double* res, hipStream_t s) {
+  if (k > 0) hipLaunchKernelGGL(k_retire, dim3((k + 255) / 256), dim3(256), 0, s, piv, k, res);
 }
 void launch_gather_cols(const double* A, int n, int64_t ng, const int32_t* piv, double* AC, hipStream_t s) {
   hipLaunchKernelGGL(k_gather_cols, dim3(grid_for(int64_t(n) * n, 256)), dim3(256), 0, s, A, n, ng, piv, AC);

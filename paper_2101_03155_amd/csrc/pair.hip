@@ -25,52 +25,14 @@
 //  * split (planes larger than LDS): x, y and z passes as separate kernels.
 #include "ace_internal.h"
 #include "fft.h"
+#include "pair_phases.h"
 
 namespace ace {
 
-__host__ __device__ constexpr int pick_tx(int n) { return (n % 16 == 0) ? 16 : (n % 8 == 0) ? 8 : (n % 4 == 0) ? 4 : 2; }
-__host__ __device__ constexpr int pick_rows(int n) { return (n % 8 == 0) ? 8 : (n % 4 == 0) ? 4 : 2; }
 
 template <typename T, int N>
 constexpr bool fused_fits_t() {
   return (size_t(N) * N + N) * sizeof(cplx<T>) + 1024 <= 163840;
-}
-
-// v(G)/N^3 at integer grid frequencies (kx, ky, kz) in FFT order.
-template <typename T, int N>
-__device__ __forceinline__ T kernel_value(const KernelParams& kp, int kx, int ky, int kz) {
-  const int sx = kx < (N + 1) / 2 ? kx : kx - N;
-  const int sy = ky < (N + 1) / 2 ? ky : ky - N;
-  const int sz = kz < (N + 1) / 2 ? kz : kz - N;
-  const double gx = kp.g[0] * sx, gy = kp.g[1] * sy, gz = kp.g[2] * sz;
-  const double g2 = gx * gx + gy * gy + gz * gz;
-  const double four_pi = 12.566370614359172953850573533118011537;
-  double v;
-  if (g2 == 0.0) {
-    v = (kp.kind == 0) ? 0.0 : 3.14159265358979323846264338327950288 / (kp.omega * kp.omega);
-  } else if (kp.kind == 0) {
-    v = four_pi / g2;
-  } else {
-    v = -four_pi / g2 * expm1(-g2 / (4.0 * kp.omega * kp.omega));
-  }
-  return T(v * kp.inv_ng);
-}
-
-template <typename T, int NT>
-__device__ __forceinline__ void block_sum2(T a, T b, double* out, double* red) {
-  double x = a, y = b;
-  for (int off = 32; off > 0; off >>= 1) {
-    x += __shfl_down(x, off, 64);
-    y += __shfl_down(y, off, 64);
-  }
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (lane == 0) { red[2 * wv] = x; red[2 * wv + 1] = y; }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double sx = 0, sy = 0;
-    for (int w = 0; w < NT / 64; ++w) { sx += red[2 * w]; sy += red[2 * w + 1]; }
-    out[0] = sx; out[1] = sy;
-  }
 }
 
 // ------------------------------------------------------------ fused path
@@ -163,26 +125,11 @@ __global__ __launch_bounds__(NT) void k_inv_xy(const T* __restrict__ phi, const 
 template <typename T, int N, int TX, int NT>
 __global__ __launch_bounds__(NT) void k_conv_z(cplx<T>* __restrict__ spec, const cplx<T>* __restrict__ twg,
                                                KernelParams kp) {
-  using C = cplx<T>;
-  constexpr size_t NG = size_t(N) * N * N;
-  constexpr int E = N * TX;
-  __shared__ C buf[E];
-  __shared__ C tw[N];
-  const int tid = threadIdx.x, x0 = blockIdx.x * TX, y = blockIdx.y, p = blockIdx.z;
-  for (int i = tid; i < N; i += NT) tw[i] = twg[i];
-  C* base = spec + size_t(p) * NG + size_t(y) * N + x0;
-  for (int e = tid; e < E; e += NT) buf[e] = base[size_t(e / TX) * N * N + (e % TX)];
-  __syncthreads();
-  fft_lines<T, N, TX, 1, TX, NT, -1, false>(buf, tw, tid);
-  for (int e = tid; e < E; e += NT) {
-    const T v = kernel_value<T, N>(kp, x0 + e % TX, y, e / TX);
-    C c = buf[e];
-    c.x *= v; c.y *= v;
-    buf[e] = c;
-  }
-  __syncthreads();
-  fft_lines<T, N, TX, 1, TX, NT, +1, false>(buf, tw, tid);
-  for (int e = tid; e < E; e += NT) base[size_t(e / TX) * N * N + (e % TX)] = buf[e];
+  __shared__ cplx<T> buf[N * TX];
+  __shared__ cplx<T> tw[N];
+  for (int i = threadIdx.x; i < N; i += NT) tw[i] = twg[i];
+  body_conv_z<T, N, TX, NT>(spec + size_t(blockIdx.z) * N * N * N, blockIdx.x * TX, blockIdx.y, kp, buf, tw,
+                            threadIdx.x);
 }
 
 // ------------------------------------------------------------ split path
@@ -191,45 +138,21 @@ template <typename T, int N, int ROWS, int NT>
 __global__ __launch_bounds__(NT) void k_fwd_x(const T* __restrict__ phi, cplx<T>* __restrict__ spec,
                                               const Pack* __restrict__ packs,
                                               const cplx<T>* __restrict__ twg) {
-  using C = cplx<T>;
-  constexpr size_t NG = size_t(N) * N * N;
-  constexpr int E = ROWS * N;
-  __shared__ C buf[E];
-  __shared__ C tw[N];
-  const int tid = threadIdx.x, p = blockIdx.y;
-  const size_t ro = size_t(blockIdx.x) * E;
-  const Pack pk = packs[p];
-  for (int i = tid; i < N; i += NT) tw[i] = twg[i];
-  const T* pia = phi + size_t(pk.ia) * NG + ro;
-  const T* pja = phi + size_t(pk.ja) * NG + ro;
-  if (pk.jb >= 0) {
-    const T* pib = phi + size_t(pk.ib) * NG + ro;
-    const T* pjb = phi + size_t(pk.jb) * NG + ro;
-    for (int e = tid; e < E; e += NT) { C v; v.x = pia[e] * pja[e]; v.y = pib[e] * pjb[e]; buf[e] = v; }
-  } else {
-    for (int e = tid; e < E; e += NT) { C v; v.x = pia[e] * pja[e]; v.y = T(0); buf[e] = v; }
-  }
-  __syncthreads();
-  fft_lines<T, N, ROWS, N, 1, NT, -1, true>(buf, tw, tid);
-  C* out = spec + size_t(p) * NG + ro;
-  for (int e = tid; e < E; e += NT) out[e] = buf[e];
+  __shared__ cplx<T> buf[ROWS * N];
+  __shared__ cplx<T> tw[N];
+  for (int i = threadIdx.x; i < N; i += NT) tw[i] = twg[i];
+  const int p = blockIdx.y;
+  body_fwd_x<T, N, ROWS, NT>(phi, spec + size_t(p) * N * N * N, packs[p], size_t(blockIdx.x) * ROWS * N, buf, tw,
+                             threadIdx.x);
 }
 
-// Lines along y: element (y, t) of block (xtile, z) at z*N*N + y*N + x0 + t.
 template <typename T, int N, int TX, int NT, int S>
 __global__ __launch_bounds__(NT) void k_line_y(cplx<T>* __restrict__ spec, const cplx<T>* __restrict__ twg) {
-  using C = cplx<T>;
-  constexpr size_t NG = size_t(N) * N * N;
-  constexpr int E = N * TX;
-  __shared__ C buf[E];
-  __shared__ C tw[N];
-  const int tid = threadIdx.x, x0 = blockIdx.x * TX, z = blockIdx.y, p = blockIdx.z;
-  for (int i = tid; i < N; i += NT) tw[i] = twg[i];
-  C* base = spec + size_t(p) * NG + size_t(z) * N * N + x0;
-  for (int e = tid; e < E; e += NT) buf[e] = base[size_t(e / TX) * N + (e % TX)];
-  __syncthreads();
-  fft_lines<T, N, TX, 1, TX, NT, S, false>(buf, tw, tid);
-  for (int e = tid; e < E; e += NT) base[size_t(e / TX) * N + (e % TX)] = buf[e];
+  __shared__ cplx<T> buf[N * TX];
+  __shared__ cplx<T> tw[N];
+  for (int i = threadIdx.x; i < N; i += NT) tw[i] = twg[i];
+  body_line_y<T, N, TX, NT, S>(spec + size_t(blockIdx.z) * N * N * N, blockIdx.x * TX, blockIdx.y, buf, tw,
+                               threadIdx.x);
 }
 
 template <typename T, int N, int ROWS, int NT, bool EN>
@@ -237,46 +160,14 @@ __global__ __launch_bounds__(NT) void k_inv_x(const T* __restrict__ phi, const c
                                               const Pack* __restrict__ packs, T* __restrict__ W,
                                               double* __restrict__ epart,
                                               const cplx<T>* __restrict__ twg) {
-  using C = cplx<T>;
-  constexpr size_t NG = size_t(N) * N * N;
-  constexpr int E = ROWS * N;
-  __shared__ C buf[E];
-  __shared__ C tw[N];
+  __shared__ cplx<T> buf[ROWS * N];
+  __shared__ cplx<T> tw[N];
   __shared__ double red[2 * (NT / 64)];
-  const int tid = threadIdx.x, p = blockIdx.y;
-  const size_t ro = size_t(blockIdx.x) * E;
-  const Pack pk = packs[p];
-  for (int i = tid; i < N; i += NT) tw[i] = twg[i];
-  const C* in = spec + size_t(p) * NG + ro;
-  for (int e = tid; e < E; e += NT) buf[e] = in[e];
-  __syncthreads();
-  fft_lines<T, N, ROWS, N, 1, NT, +1, true>(buf, tw, tid);
-  const T* pia = phi + size_t(pk.ia) * NG + ro;
-  const T* pja = phi + size_t(pk.ja) * NG + ro;
-  T* wia = W + size_t(pk.ia) * NG + ro;
-  T* wja = W + size_t(pk.ja) * NG + ro;
-  T ea = T(0), eb = T(0);
-  const bool offa = pk.ia != pk.ja;
-  for (int e = tid; e < E; e += NT) {
-    const T v = buf[e].x, fi = pia[e], fj = pja[e];
-    wia[e] -= v * fj;
-    if (offa) wja[e] -= v * fi;
-    if (EN) ea += v * fi * fj;
-  }
-  if (pk.jb >= 0) {
-    const T* pib = phi + size_t(pk.ib) * NG + ro;
-    const T* pjb = phi + size_t(pk.jb) * NG + ro;
-    T* wib = W + size_t(pk.ib) * NG + ro;
-    T* wjb = W + size_t(pk.jb) * NG + ro;
-    const bool offb = pk.ib != pk.jb;
-    for (int e = tid; e < E; e += NT) {
-      const T v = buf[e].y, fi = pib[e], fj = pjb[e];
-      wib[e] -= v * fj;
-      if (offb) wjb[e] -= v * fi;
-      if (EN) eb += v * fi * fj;
-    }
-  }
-  if (EN) block_sum2<T, NT>(ea, eb, epart + 2 * (size_t(p) * gridDim.x + blockIdx.x), red);
+  for (int i = threadIdx.x; i < N; i += NT) tw[i] = twg[i];
+  const int p = blockIdx.y;
+  body_inv_x<T, N, ROWS, NT, EN>(phi, spec + size_t(p) * N * N * N, packs[p], size_t(blockIdx.x) * ROWS * N, W,
+                                 epart ? epart + 2 * (size_t(p) * gridDim.x + blockIdx.x) : nullptr, buf, tw, red,
+                                 threadIdx.x);
 }
 
 // ------------------------------------------------------------ dispatch

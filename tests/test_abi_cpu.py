@@ -67,6 +67,23 @@ def test_argument_validation(ctx):
     assert lib.ace_get_pair_shape(h, 0, 96, C.byref(f), C.byref(m)) == 0
     assert (f.value, m.value) == (0, 16)
     assert lib.ace_profile_read(h, 99, None, None, None, 0) == -1
+    # batched: argument checks before any device work
+    arr = (ace.ace_system * 2)()
+    for a in arr:
+        a.grid = ace.Grid.cubic(24, 8.0).c()
+        a.norb, a.kernel, a.omega, a.npairs = 4, 0, 0.1, 3
+        a.phi, a.pairs, a.xi = 0x1000, 0x1000, 0x1000
+    assert lib.ace_build_batched(h, 0, arr, 1, 0) == -1
+    assert lib.ace_build_batched(h, 2, arr, 3, 0) == -1
+    assert lib.ace_build_batched(h, 2, arr, 1, 9) == -1
+    arr[1].grid = ace.Grid.cubic(120, 8.0).c()
+    assert lib.ace_build_batched(h, 2, arr, 1, 0) == -7
+    assert b"system 1" in lib.ace_last_error(h)
+    arr[1].grid = ace.Grid.cubic(24, 8.0).c()
+    arr[0].npairs = 11
+    assert lib.ace_build_batched(h, 2, arr, 1, 0) == -1
+    assert lib.ace_set_batched_shape(h, 12, 0, 4) == -1
+    assert lib.ace_set_batched_shape(h, 8, 1, 4) == 0
 
 
 def test_binding_refuses_without_gpu():

@@ -1,0 +1,199 @@
+"""GPU parity of the production forms against the FP64 oracle.
+
+Precision form (64 waters, 256 orbitals, 120^3): FP32 pair stage and FP32
+matrix-core M with compensated summation; E_x within 1e-6 relative of the FP64
+oracle, ACE matrix elements within 1e-5 Ha, W errors reported."""
+import numpy as np
+import pytest
+
+import oracle
+from synth import config_spec, make_orbitals, smooth_test_vectors
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+def _dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    return lib.Context()
+
+
+@pytest.fixture(scope="module")
+def c3(ctx):
+    from paper_2101_03155_amd import Grid
+    spec = config_spec("c3")
+    o = make_orbitals(spec, device="cuda")
+    grid = Grid.cubic(spec.N, spec.L)
+    phi, piv, _ = ctx.localize(o.psi, grid)
+    pairs, _ = ctx.pairlist(phi, grid, 1e-3)
+    del o
+    return dict(spec=spec, grid=grid, phi=phi, pairs=pairs)
+
+
+def test_c3_localized_orbitals_are_orthonormal(c3):
+    _say("c3 localize orthonormality")
+    s = c3["spec"]
+    P = c3["phi"].reshape(s.norb, -1)
+    S = (P @ P.T).cpu().numpy() * s.dV
+    assert np.abs(S - np.eye(s.norb)).max() < 1e-11
+
+
+def test_c3_precision_form(ctx, c3):
+    _say("c3 precision form fp32 vs fp64 oracle")
+    s, grid, phi, pairs = c3["spec"], c3["grid"], c3["phi"], c3["pairs"]
+    r64 = ctx.build(phi, pairs, grid, kernel="erfc", omega=s.omega, precision="fp64")
+    r32 = ctx.build(phi, pairs, grid, kernel="erfc", omega=s.omega, precision="fp32", want_W=True)
+    phi_np = phi.cpu().numpy()
+    pairs_np = pairs.cpu().numpy().astype(np.int64)
+    v = oracle.coulomb_kernel(s.N, s.L, "erfc", s.omega)
+    e_ref = oracle.exchange_energy_pairs(phi_np, pairs_np, v, s.dV)
+    ex_ref = float(e_ref.sum())
+    ex64, ex32 = r64["ex"].item(), r32["ex"].item()
+    print(f"E_x oracle {ex_ref:.12f} fp64 {ex64:.12f} fp32 {ex32:.12f}", flush=True)
+    assert abs(ex64 - ex_ref) <= 1e-10 * abs(ex_ref)
+    assert abs(ex32 - ex_ref) <= 1e-6 * abs(ex_ref)
+    # W on sampled orbitals against the oracle
+    rows = [3, 200]
+    Wref = oracle.build_W_rows(phi_np, pairs_np, rows, v)
+    w_err = _rel(r32["W"][rows].cpu().numpy(), Wref)
+    print(f"W rel err fp32 {w_err:.3e}", flush=True)
+    assert w_err < 1e-5
+    # ACE matrix elements over {phi_i} and 16 smooth test vectors
+    vecs = torch.cat([phi, _dev(smooth_test_vectors(s, 16))])
+    y64 = ctx.apply(r64["xi"], vecs, grid)
+    y32 = ctx.apply(r32["xi"], vecs, grid)
+    A = vecs.reshape(vecs.shape[0], -1)
+    m64 = (A @ y64.reshape(vecs.shape[0], -1).T).cpu().numpy() * s.dV
+    m32 = (A @ y32.reshape(vecs.shape[0], -1).T).cpu().numpy() * s.dV
+    # the FP64 build's matrix elements on the occupied space equal M (checked
+    # against the oracle at 32 waters); here the FP32 form is held to 1e-5 Ha
+    print(f"ACE matrix elements max |fp32 - fp64| {np.abs(m32 - m64).max():.3e} Ha", flush=True)
+    assert np.abs(m32 - m64).max() <= 1e-5
+
+
+# ------------------------------------------------------------------ batched form
+
+def _small_batch(ctx, n_sys=5):
+    """Uneven small systems: grids 16/24/32, 8-12 orbitals, mixed kernels,
+    screened SCDM pair lists."""
+    from paper_2101_03155_amd import Grid
+    from synth import SystemSpec
+    sizes = [16, 24, 32, 24, 16, 32, 16][:n_sys]
+    out = []
+    for q, n in enumerate(sizes):
+        spec = SystemSpec(n_mol=2 + q % 2, L=0.32 * n, N=n, sigma=0.75, offset=0.6, placement="uniform",
+                          seed=900 + q, kernel="erfc" if q % 2 else "bare", omega=0.5)
+        o = make_orbitals(spec)
+        g = Grid.cubic(n, spec.L)
+        phi, _, _ = ctx.localize(_dev(o.psi), g)
+        pairs, _ = ctx.pairlist(phi, g, 0.02)
+        out.append(dict(phi=phi, pairs=pairs, grid=g, kernel=spec.kernel, omega=spec.omega, spec=spec))
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batched_equals_single_builds_bitwise(ctx, prec):
+    _say(f"batched vs single bitwise {prec}")
+    systems = _small_batch(ctx)
+    ctx.set_batched_shape(16, 0, 8)
+    res = ctx.build_batched(systems, precision=prec, mode="graph")
+    for q, sy in enumerate(systems):
+        n = sy["grid"].n[0]
+        ctx.set_pair_shape(prec, n, False, 64)
+        try:
+            r = ctx.build(sy["phi"], sy["pairs"], sy["grid"], kernel=sy["kernel"], omega=sy["omega"], precision=prec)
+        finally:
+            ctx.set_pair_shape(prec, n, True, 64)
+        assert res[q]["status"] == "ACE_OK"
+        assert torch.equal(res[q]["ex"], r["ex"]), (q, res[q]["ex"].item(), r["ex"].item())
+        assert torch.equal(res[q]["M"], r["M"])
+        assert torch.equal(res[q]["xi"], r["xi"])
+
+
+def test_batched_graph_replays_and_modes(ctx):
+    _say("batched graph replays + persistent + eager")
+    systems = _small_batch(ctx, 7)
+    for sy in systems:  # fixed output buffers: repeated calls replay the captured graph
+        n = sy["phi"].shape[0]
+        sy["xi"] = torch.empty_like(sy["phi"])
+        sy["M"] = torch.empty(n, n, dtype=torch.float64, device="cuda")
+        sy["ex"] = torch.empty(1, dtype=torch.float64, device="cuda")
+    ctx.set_batched_shape(16, 0, 8)
+    first = ctx.build_batched(systems, precision="fp32", mode="graph")
+    ref = [(r["ex"].clone(), r["xi"].clone()) for r in first]
+    for rep in range(3):
+        # unrelated eager work between replays
+        x = torch.randn(1 << 20, device="cuda")
+        _ = (x * x).sum().item()
+        again = ctx.build_batched(systems, precision="fp32", mode="graph")
+        for q in range(len(systems)):
+            assert torch.equal(again[q]["ex"], ref[q][0]), (rep, q)
+            assert torch.equal(again[q]["xi"], ref[q][1]), (rep, q)
+    for mode in ("persistent", "eager"):
+        other = ctx.build_batched(systems, precision="fp32", mode=mode)
+        for q in range(len(systems)):
+            assert torch.equal(other[q]["ex"], ref[q][0]), (mode, q)
+            assert torch.equal(other[q]["xi"], ref[q][1]), (mode, q)
+    # tile and radix-order variants agree to rounding
+    for txv, plan in ((8, 0), (16, 1), (8, 1)):
+        ctx.set_batched_shape(txv, plan, 4)
+        alt = ctx.build_batched(systems, precision="fp32", mode="persistent")
+        for q in range(len(systems)):
+            assert abs(alt[q]["ex"].item() - ref[q][0].item()) <= 1e-6 * abs(ref[q][0].item())
+    ctx.set_batched_shape(16, 0, 8)
+
+
+def test_batched_fp64_matches_oracle(ctx):
+    _say("batched fp64 vs oracle")
+    systems = _small_batch(ctx)
+    res = ctx.build_batched(systems, precision="fp64", mode="graph")
+    for q, sy in enumerate(systems):
+        s = sy["spec"]
+        phi = sy["phi"].cpu().numpy()
+        pairs = sy["pairs"].cpu().numpy()
+        ref = oracle.ace_build(phi, pairs, s.N, s.L, s.kernel, s.omega)
+        assert abs(res[q]["ex"].item() - ref["ex"]) <= 1e-10 * abs(ref["ex"])
+        np.testing.assert_allclose(res[q]["M"].cpu().numpy(), ref["M"], atol=1e-11 * np.abs(ref["M"]).max())
+        assert _rel(res[q]["xi"].cpu().numpy(), ref["xi"]) < 1e-10
+
+
+def test_batched_c4_workload(ctx):
+    """16 systems of 8-64 molecules on 48^3-96^3 grids, FP32 pair stage."""
+    _say("batched c4 workload fp32")
+    from paper_2101_03155_amd import Grid
+    from synth import batched_specs
+    specs = batched_specs()
+    systems = []
+    for sp in specs:
+        o = make_orbitals(sp, device="cuda")
+        g = Grid.cubic(sp.N, sp.L)
+        phi, _, _ = ctx.localize(o.psi, g)
+        del o
+        pairs, _ = ctx.pairlist(phi, g, 1e-3)
+        systems.append(dict(phi=phi, pairs=pairs, grid=g, kernel=sp.kernel, omega=sp.omega, spec=sp))
+    res = ctx.build_batched(systems, precision="fp32", mode="graph")
+    for q, sy in enumerate(systems):
+        r64 = ctx.build(sy["phi"], sy["pairs"], sy["grid"], kernel=sy["kernel"], omega=sy["omega"], precision="fp64",
+                        want_M=False)
+        e64 = r64["ex"].item()
+        assert abs(res[q]["ex"].item() - e64) <= 1e-6 * abs(e64), q
+    # the two smallest systems against the oracle's pair energies
+    for q in sorted(range(len(specs)), key=lambda k: specs[k].norb)[:2]:
+        sy, sp = systems[q], specs[q]
+        phi = sy["phi"].cpu().numpy()
+        pairs = sy["pairs"].cpu().numpy().astype(np.int64)
+        e = oracle.exchange_energy_pairs(phi, pairs, oracle.coulomb_kernel(sp.N, sp.L, sp.kernel, sp.omega), sp.dV)
+        assert abs(res[q]["ex"].item() - e.sum()) <= 1e-6 * abs(e.sum()), q
