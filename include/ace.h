@@ -214,6 +214,77 @@ int ace_build_batched(ace_ctx* ctx, int nsys, ace_system* systems, int prec, int
  * small first), workgroups per compute unit of the persistent launch. */
 int ace_set_batched_shape(ace_ctx* ctx, int txv, int plan_variant, int blocks_per_cu);
 
+/*
+ * Learned pair screener (the learned replacement of the screening criterion
+ * of Sec. Theory).  It predicts log10 |e_ij| from five pair features and
+ * drops the pairs with the smallest predicted |e_ij| while their predicted
+ * sum stays within an E_x budget.
+ */
+
+/* Features of each pair, float32 [npairs][5]: minimum-image distance of the
+ * periodic centroids of |phi_i|^2 and |phi_j|^2 (bohr); the smaller and the
+ * larger spread sqrt(dV sum |phi|^2 |r - c|^2) (bohr); log10 of
+ * dV sum |phi_i||phi_j|; log10 of dV sum phi_i^2 phi_j^2.  pairs == NULL
+ * means every pair i <= j in row-major triangle order (npairs must then be
+ * norb(norb+1)/2).  Cubic boxes. */
+int ace_pair_features(ace_ctx* ctx, const ace_grid* grid, int norb, const double* phi, const int32_t* pairs,
+                      int64_t npairs, float* feats);
+
+/* Exact pair energies e_ij = -(2 - d_ij) dV sum_r phi_i phi_j v_ij (Eq. e:vij)
+ * of a pair list, without building W or the ACE operator: the training
+ * targets of the screener.  Arguments as for ace_build. */
+int ace_pair_energies(ace_ctx* ctx, const ace_grid* grid, int norb, const double* phi, const int32_t* pairs,
+                      int64_t npairs, int kernel, double omega, int prec, double* e);
+
+/* MLP model: float32 device array of ACE_MLP_NMODEL values: W1[64][5], b1[64],
+ * W2[64][64], b2[64], w3[64], b3 (ACE_MLP_NPARAM trainable values), then
+ * xmean[5], xstd[5], tmean, tstd, xmin[5], xmax[5].  Network: standardize,
+ * tanh(W1 x + b1), tanh(W2 h + b2), w3 . h + b3; prediction tmean + tstd *
+ * output (the target is log10 |e_ij|). */
+#define ACE_MLP_NPARAM 4609
+#define ACE_MLP_NMODEL 4631
+
+typedef struct {
+  float lr, beta1, beta2, eps; /* Adam */
+  int32_t batch;               /* minibatch size */
+  int32_t epochs;
+  int32_t step0;               /* Adam steps taken before this call */
+  uint64_t seed;               /* sample order */
+} ace_mlp_hparams;
+
+/* Glorot-uniform weights from a counter-based generator (splitmix64 of seed
+ * and index), zero biases, unit standardization. */
+int ace_mlp_init(ace_ctx* ctx, float* model, uint64_t seed);
+/* Standardization statistics and feature ranges of a training set
+ * x [n][5], t [n]. */
+int ace_mlp_fit_norm(ace_ctx* ctx, float* model, const float* x, const float* t, int64_t n);
+/* Predictions y [n] (log10 |e|); clamp != 0 clips the features to the
+ * training ranges first (as the screening does). */
+int ace_mlp_forward(ace_ctx* ctx, const float* model, const float* x, int64_t n, int clamp, float* y);
+/* Gradient grad [ACE_MLP_NPARAM] of the mean squared error of the
+ * standardized targets over all n samples, and the loss (nullable). */
+int ace_mlp_grad(ace_ctx* ctx, const float* model, const float* x, const float* t, int64_t n, float* grad,
+                 float* loss);
+/* Adam training: epochs over the samples in a seeded order, minibatches of
+ * hp->batch; adam_m, adam_v [ACE_MLP_NPARAM] persist between calls;
+ * loss_curve [epochs] (nullable) receives the sum of the minibatch losses of
+ * each epoch.  Deterministic for a given seed. */
+int ace_mlp_train(ace_ctx* ctx, float* model, float* adam_m, float* adam_v, const float* x, const float* t, int64_t n,
+                  const ace_mlp_hparams* hp, float* loss_curve);
+
+/* Learned screening: features and predictions for every pair i <= j, then
+ * off-diagonal pairs are dropped in ascending order of predicted |e_ij| while
+ * their predicted sum stays <= budget (Hartree); diagonal pairs are kept.
+ * If any off-diagonal pair lies outside the model's training range (widened
+ * by ood_tol times each span) on the interacting side (closer centroids,
+ * larger overlaps, unseen spreads), the overlap rule O_ij >= rho_cut_fallback
+ * is used instead and *used_fallback is set; pairs beyond the range on the far
+ * side are predicted with clipped features.  pairs [capacity][2] sorted by
+ * (i, j); *npairs (HOST) as for ace_pairlist. */
+int ace_screen_learned(ace_ctx* ctx, const ace_grid* grid, int norb, const double* phi, const float* model,
+                       double budget, double rho_cut_fallback, double ood_tol, int64_t capacity, int32_t* pairs,
+                       int64_t* npairs, int* used_fallback);
+
 #ifdef __cplusplus
 }
 #endif

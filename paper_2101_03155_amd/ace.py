@@ -49,6 +49,14 @@ class ace_system(C.Structure):
 
 BATCHED_MODES = {"graph": 0, "persistent": 1, "eager": 2}
 
+MLP_NPARAM = 4609
+MLP_NMODEL = 4631
+
+
+class ace_mlp_hparams(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("batch", C.c_int32), ("epochs", C.c_int32), ("step0", C.c_int32), ("seed", C.c_uint64)]
+
 
 @dataclass(frozen=True)
 class Grid:
@@ -106,6 +114,14 @@ def load(path: str = LIB_PATH):
         "ace_get_pair_shape": ([P, I, I, C.POINTER(I), C.POINTER(I)], I),
         "ace_build_batched": ([P, I, C.POINTER(ace_system), I, I], I),
         "ace_set_batched_shape": ([P, I, I, I], I),
+        "ace_pair_features": ([P, GP, I, P, P, I64, P], I),
+        "ace_pair_energies": ([P, GP, I, P, P, I64, I, D, I, P], I),
+        "ace_mlp_init": ([P, P, C.c_uint64], I),
+        "ace_mlp_fit_norm": ([P, P, P, P, I64], I),
+        "ace_mlp_forward": ([P, P, P, I64, I, P], I),
+        "ace_mlp_grad": ([P, P, P, P, I64, P, P], I),
+        "ace_mlp_train": ([P, P, P, P, P, P, I64, C.POINTER(ace_mlp_hparams), P], I),
+        "ace_screen_learned": ([P, GP, I, P, P, D, D, D, I64, P, C.POINTER(I64), C.POINTER(I)], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -319,4 +335,92 @@ class Context:
 
     def set_batched_shape(self, txv: int, plan_variant: int, blocks_per_cu: int):
         self._check(self.lib.ace_set_batched_shape(self.h, txv, plan_variant, blocks_per_cu))
+
+    # ------------------------------------------------------------ learned screener
+    def pair_features(self, phi, grid: Grid, pairs=None):
+        """float32 [npairs][5] features (every pair i <= j when pairs is None)."""
+        import torch
+
+        _require(phi, torch.float64, "phi")
+        norb = phi.shape[0]
+        n = norb * (norb + 1) // 2 if pairs is None else pairs.shape[0]
+        if pairs is not None:
+            _require(pairs, torch.int32, "pairs")
+        f = torch.empty(n, 5, dtype=torch.float32, device=phi.device)
+        self._sync_stream()
+        g = grid.c()
+        self._check(self.lib.ace_pair_features(self.h, C.byref(g), norb, _ptr(phi), _ptr(pairs), n, _ptr(f)))
+        return f
+
+    def pair_energies(self, phi, pairs, grid: Grid, kernel: str = "erfc", omega: float = 0.106,
+                      precision: str = "fp64"):
+        import torch
+
+        _require(phi, torch.float64, "phi")
+        _require(pairs, torch.int32, "pairs")
+        e = torch.empty(pairs.shape[0], dtype=torch.float64, device=phi.device)
+        self._sync_stream()
+        g = grid.c()
+        self._check(self.lib.ace_pair_energies(self.h, C.byref(g), phi.shape[0], _ptr(phi), _ptr(pairs),
+                                               pairs.shape[0], KERNELS[kernel], float(omega), PRECISIONS[precision],
+                                               _ptr(e)))
+        return e
+
+    def mlp_init(self, seed: int = 0):
+        import torch
+
+        m = torch.empty(MLP_NMODEL, dtype=torch.float32, device="cuda")
+        self._sync_stream()
+        self._check(self.lib.ace_mlp_init(self.h, _ptr(m), C.c_uint64(seed)))
+        return m
+
+    def mlp_fit_norm(self, model, x, t):
+        self._sync_stream()
+        self._check(self.lib.ace_mlp_fit_norm(self.h, _ptr(model), _ptr(x), _ptr(t), x.shape[0]))
+
+    def mlp_forward(self, model, x, clamp: bool = False):
+        import torch
+
+        y = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+        self._sync_stream()
+        self._check(self.lib.ace_mlp_forward(self.h, _ptr(model), _ptr(x), x.shape[0], 1 if clamp else 0, _ptr(y)))
+        return y
+
+    def mlp_grad(self, model, x, t):
+        import torch
+
+        g = torch.empty(MLP_NPARAM, dtype=torch.float32, device=x.device)
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        self._sync_stream()
+        self._check(self.lib.ace_mlp_grad(self.h, _ptr(model), _ptr(x), _ptr(t), x.shape[0], _ptr(g), _ptr(loss)))
+        return g, loss
+
+    def mlp_train(self, model, adam_m, adam_v, x, t, lr=1e-3, batch=4096, epochs=10, seed=0, step0=0,
+                  beta1=0.9, beta2=0.999, eps=1e-8):
+        import torch
+
+        hp = ace_mlp_hparams(lr, beta1, beta2, eps, batch, epochs, step0, seed)
+        curve = torch.empty(epochs, dtype=torch.float32, device=x.device)
+        self._sync_stream()
+        self._check(self.lib.ace_mlp_train(self.h, _ptr(model), _ptr(adam_m), _ptr(adam_v), _ptr(x), _ptr(t),
+                                           x.shape[0], C.byref(hp), _ptr(curve)))
+        return curve
+
+    def screen_learned(self, phi, grid: Grid, model, budget: float, rho_cut_fallback: float = 1e-3,
+                       ood_tol: float = 0.05):
+        """Learned pair list: returns (pairs[int32, n x 2], used_fallback)."""
+        import torch
+
+        _require(phi, torch.float64, "phi")
+        norb = phi.shape[0]
+        cap = norb * (norb + 1) // 2
+        pairs = torch.empty(cap, 2, dtype=torch.int32, device=phi.device)
+        n = C.c_int64()
+        fb = C.c_int()
+        self._sync_stream()
+        g = grid.c()
+        self._check(self.lib.ace_screen_learned(self.h, C.byref(g), norb, _ptr(phi), _ptr(model), float(budget),
+                                                float(rho_cut_fallback), float(ood_tol), cap, _ptr(pairs),
+                                                C.byref(n), C.byref(fb)))
+        return pairs[: n.value], bool(fb.value)
 

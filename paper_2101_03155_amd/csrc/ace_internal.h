@@ -80,7 +80,8 @@ int pair_energy_blocks(int N, const PairShape& sh);
 bool pair_supported(int N);
 
 // Dense kernels (gemm.hip, linalg.hip).
-hipError_t gemm_nt(int prec, bool abs_ops, const void* A, int64_t lda, const void* B, int64_t ldb, int M,
+// op: 0 A B^T, 1 |A| |B|^T, 2 (A.A)(B.B)^T  (FP64 only for op != 0)
+hipError_t gemm_nt(int prec, int op, const void* A, int64_t lda, const void* B, int64_t ldb, int M,
                    int Nn, int64_t K, double alpha, double* Cpart, double* C, hipStream_t s,
                    EventRecorder* rec);
 int64_t gemm_nt_nsplit(int M, int Nn, int64_t K, int64_t* kchunk_out);
@@ -126,6 +127,26 @@ hipError_t batched_segments(int prec, int n, int mode, int txv, int plan_v, int 
                             const BRound* h_segs, const BRound* d_segs, const BSys* sys, const BPack* packs,
                             const int64_t* starts, hipStream_t s);
 void launch_zero(void* p, size_t bytes, hipStream_t s);
+
+// Learned screener (screener.hip).
+void launch_marginals(const double* phi, int norb, int n, double* pz, double* py, double* px, hipStream_t s);
+void launch_centroids(const double* pz, const double* py, const double* px, int norb, int n, double L, double dV,
+                      double* cen, double* spr, hipStream_t s);
+void launch_pair_features(const int32_t* pairs, int64_t np, int norb, const double* cen, const double* spr,
+                          const double* O, const double* P, double L, float* f, hipStream_t s);
+void launch_mlp_init(float* m, uint64_t seed, hipStream_t s);
+int stats_blocks(int64_t n);
+void launch_mlp_stats(const float* x, const float* t, int64_t n, double* part, float* m, hipStream_t s);
+void launch_mlp_forward(const float* m, const float* x, int64_t n, int clamp, float* y, hipStream_t s);
+int mlp_grad_blocks(int bsz);
+void launch_mlp_grad_partial(const float* m, const float* x, const float* t, int64_t n, int64_t off, int64_t stride,
+                             int64_t b0, int bsz, float* gpart, float* lpart, hipStream_t s);
+void launch_mlp_reduce(const float* gpart, const float* lpart, int nb, float* grad, float* loss, hipStream_t s);
+void launch_mlp_adam(const float* gpart, const float* lpart, int nb, float* m, float* mom, float* vel, int step,
+                     float lr, float b1, float b2, float eps, float* loss_acc, hipStream_t s);
+void launch_select(const float* pred, const float* feats, int64_t np, int norb, const float* model, double budget,
+                   const double* O, double rho_cut, float ood_tol, int* ood, double* tau, uint8_t* keep, int64_t cap,
+                   int32_t* pairs, int64_t* count, hipStream_t s);
 PairShape pair_default_shape(int prec, int N);
 
 }  // namespace ace

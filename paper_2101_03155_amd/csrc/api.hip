@@ -579,7 +579,7 @@ int ace_pairlist(ace_ctx* c, const ace_grid* g, int norb, const double* phi, dou
   WS(c, "mpart", size_t(nsplit) * norb * norb * sizeof(double), part);
   WS(c, "O", size_t(norb) * norb * sizeof(double), O);
   WS(c, "cnt", 64, cnt);
-  HIPCHK(c, gemm_nt(0, true, phi, ng, phi, ng, norb, norb, ng, grid_dv(g), part, O, s, c->R()));
+  HIPCHK(c, gemm_nt(0, 1, phi, ng, phi, ng, norb, norb, ng, grid_dv(g), part, O, s, c->R()));
   launch_compact_pairs(O, norb, rho_cut, capacity, pairs, overlap, cnt, s);
   int64_t h = 0;
   HIPCHK(c, hipMemcpyAsync(&h, cnt, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -592,13 +592,31 @@ int ace_pairlist(ace_ctx* c, const ace_grid* g, int norb, const double* phi, dou
 }
 
 // ------------------------------------------------------------------ (c)-(e) build
+static int build_impl(ace_ctx* c, const ace_grid* g, int norb, const double* phi, const int32_t* pairs,
+                      int64_t npairs, int kernel, double omega, int prec, double* xi, double* Mout, double* Wout,
+                      double* ex, double* pair_energy);
+
 int ace_build(ace_ctx* c, const ace_grid* g, int norb, const double* phi, const int32_t* pairs, int64_t npairs,
               int kernel, double omega, int prec, double* xi, double* Mout, double* Wout, double* ex,
               double* pair_energy) {
   if (!c) return ACE_E_ARG;
+  if (!xi) return fail(c, ACE_E_ARG, "xi must be non-NULL");
+  return build_impl(c, g, norb, phi, pairs, npairs, kernel, omega, prec, xi, Mout, Wout, ex, pair_energy);
+}
+
+int ace_pair_energies(ace_ctx* c, const ace_grid* g, int norb, const double* phi, const int32_t* pairs,
+                      int64_t npairs, int kernel, double omega, int prec, double* e) {
+  if (!c) return ACE_E_ARG;
+  if (!e) return fail(c, ACE_E_ARG, "e must be non-NULL");
+  return build_impl(c, g, norb, phi, pairs, npairs, kernel, omega, prec, nullptr, nullptr, nullptr, nullptr, e);
+}
+
+static int build_impl(ace_ctx* c, const ace_grid* g, int norb, const double* phi, const int32_t* pairs,
+                      int64_t npairs, int kernel, double omega, int prec, double* xi, double* Mout, double* Wout,
+                      double* ex, double* pair_energy) {
   int rc = check_grid(c, g, norb);
   if (rc) return rc;
-  if (!phi || !pairs || !xi) return fail(c, ACE_E_ARG, "phi, pairs and xi must be non-NULL");
+  if (!phi || !pairs) return fail(c, ACE_E_ARG, "phi and pairs must be non-NULL");
   if (kernel != ACE_KERNEL_COULOMB && kernel != ACE_KERNEL_ERFC) return fail(c, ACE_E_ARG, "unknown kernel %d", kernel);
   if (kernel == ACE_KERNEL_ERFC && !(omega > 0.0)) return fail(c, ACE_E_ARG, "omega must be > 0 for erfc");
   if (prec != ACE_FP64 && prec != ACE_FP32) return fail(c, ACE_E_ARG, "unknown precision %d", prec);
@@ -632,7 +650,8 @@ int ace_build(ace_ctx* c, const ace_grid* g, int norb, const double* phi, const 
   int64_t* dpidx;
   double *epart = nullptr, *part, *Mraw, *Lb, *Li, *scal;
   int* info;
-  WS(c, "W", size_t(norb) * ng * es, W);
+  if (xi) WS(c, "W", size_t(norb) * ng * es, W);
+  else W = nullptr;
   WS(c, "spec", size_t(S.max_launch) * ng * 2 * es, spec);
   WS(c, "packs", size_t(npk) * sizeof(Pack), dpk);
   WS(c, "pidx", size_t(npk) * 2 * sizeof(int64_t), dpidx);
@@ -654,7 +673,7 @@ int ace_build(ace_ctx* c, const ace_grid* g, int norb, const double* phi, const 
   HIPCHK(c, hipMemcpyAsync(dpk, S.packs.data(), size_t(npk) * sizeof(Pack), hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(dpidx, S.pidx.data(), size_t(npk) * 2 * sizeof(int64_t), hipMemcpyHostToDevice, s));
   if (prec == 1) launch_d2f(phi, (float*)phiw, int64_t(norb) * ng, s);
-  HIPCHK(c, hipMemsetAsync(W, 0, size_t(norb) * ng * es, s));
+  if (W) HIPCHK(c, hipMemsetAsync(W, 0, size_t(norb) * ng * es, s));
 
   KernelParams kp;
   kp.kind = kernel;
@@ -670,6 +689,11 @@ int ace_build(ace_ctx* c, const ace_grid* g, int norb, const double* phi, const 
       launch_pair_energy(epart, L.second, nblk, dpk + L.first, dpidx + 2 * L.first, dV, pair_energy, s);
   }
   rec_end(R, ST_PAIRS, s);
+  if (!xi) {  // energies only
+    rec_end(R, ST_BUILD, s);
+    HIPCHK(c, hipGetLastError());
+    return ACE_OK;
+  }
 
   // W is an output of step (c) whatever the factorization below reports
   if (Wout) {
@@ -681,7 +705,7 @@ int ace_build(ace_ctx* c, const ace_grid* g, int norb, const double* phi, const 
 
   // (d) M = dV Phi W^T, symmetrize, -M = L L^T
   rec_begin(R, ST_TAIL, s);
-  HIPCHK(c, gemm_nt(prec, false, phiw, ng, W, ng, norb, norb, ng, dV, part, Mraw, s, R));
+  HIPCHK(c, gemm_nt(prec, 0, phiw, ng, W, ng, norb, norb, ng, dV, part, Mraw, s, R));
   launch_symmetrize(Mraw, norb, Mout, Lb, ex ? ex : scal, scal + 1, s);
   launch_cholesky(Lb, norb, info, s);
   int hinfo = 0;
@@ -712,7 +736,7 @@ int ace_apply(ace_ctx* c, const ace_grid* g, int norb, const double* xi, int nve
   const int64_t nsplit = gemm_nt_nsplit(norb, nvec, ng, &kchunk);
   WS(c, "apart", size_t(nsplit) * norb * nvec * sizeof(double), part);
   WS(c, "coef", size_t(norb) * nvec * sizeof(double), cb);
-  HIPCHK(c, gemm_nt(0, false, xi, ng, x, ng, norb, nvec, ng, grid_dv(g), part, cb, s, c->R()));
+  HIPCHK(c, gemm_nt(0, 0, xi, ng, x, ng, norb, nvec, ng, grid_dv(g), part, cb, s, c->R()));
   HIPCHK(c, gemm_ls(0, true, false, cb, nvec, xi, ng, y, ng, nvec, norb, ng, -1.0, s, c->R()));
   return ACE_OK;
 }
@@ -915,7 +939,7 @@ int ace_build_batched(ace_ctx* c, int nsys, ace_system* sys, int prec, int mode)
       const int64_t ng = grid_size(&y.grid);
       const void* W = bW + size_t(w_off[q]) * es;
       const void* ph = prec == 0 ? (const void*)y.phi : (const void*)(bphi + size_t(w_off[q]) * es);
-      hipError_t e = gemm_nt(prec, false, ph, ng, W, ng, n, n, ng, grid_dv(&y.grid), part, Mraw, s, nullptr);
+      hipError_t e = gemm_nt(prec, 0, ph, ng, W, ng, n, n, ng, grid_dv(&y.grid), part, Mraw, s, nullptr);
       if (e != hipSuccess) return fail(c, ACE_E_HIP, "batched M launch failed: %s", hipGetErrorString(e));
       launch_symmetrize(Mraw, n, y.M, Lb, y.ex ? y.ex : exs + 2 * q, exs + 2 * q + 1, s);
       launch_cholesky(Lb, n, infos + q, s);
@@ -969,6 +993,164 @@ int ace_build_batched(ace_ctx* c, int nsys, ace_system* sys, int prec, int mode)
     else if (hinfo[q] < 0) { sys[q].status = ACE_E_NONFINITE; sys[q].fail_column = -hinfo[q] - 1; ++bad; }
   }
   if (bad) return fail(c, ACE_E_NOT_PD, "%d of %d systems failed the Cholesky factorization (see status)", bad, nsys);
+  return ACE_OK;
+}
+
+
+// ------------------------------------------------------------------ learned screener
+static int features_impl(ace_ctx* c, const ace_grid* g, int norb, const double* phi, const int32_t* pairs,
+                         int64_t np, float* feats, double** O_out) {
+  const int n = g->n[0];
+  const int64_t ng = grid_size(g);
+  hipStream_t s = c->stream;
+  double *pz, *py, *px, *cen, *spr, *O, *P, *part;
+  int64_t kchunk;
+  const int64_t nsplit = gemm_nt_nsplit(norb, norb, ng, &kchunk);
+  WS(c, "f_pz", size_t(norb) * n * sizeof(double), pz);
+  WS(c, "f_py", size_t(norb) * n * n * sizeof(double), py);
+  WS(c, "f_px", size_t(norb) * n * n * sizeof(double), px);
+  WS(c, "f_cen", size_t(norb) * 3 * sizeof(double), cen);
+  WS(c, "f_spr", size_t(norb) * sizeof(double), spr);
+  WS(c, "O", size_t(norb) * norb * sizeof(double), O);
+  WS(c, "f_P", size_t(norb) * norb * sizeof(double), P);
+  WS(c, "mpart", size_t(nsplit) * norb * norb * sizeof(double), part);
+  launch_marginals(phi, norb, n, pz, py, px, s);
+  launch_centroids(pz, py, px, norb, n, g->L[0], grid_dv(g), cen, spr, s);
+  HIPCHK(c, gemm_nt(0, 1, phi, ng, phi, ng, norb, norb, ng, grid_dv(g), part, O, s, nullptr));
+  HIPCHK(c, gemm_nt(0, 2, phi, ng, phi, ng, norb, norb, ng, grid_dv(g), part, P, s, nullptr));
+  launch_pair_features(pairs, np, norb, cen, spr, O, P, g->L[0], feats, s);
+  HIPCHK(c, hipGetLastError());
+  if (O_out) *O_out = O;
+  return ACE_OK;
+}
+
+int ace_pair_features(ace_ctx* c, const ace_grid* g, int norb, const double* phi, const int32_t* pairs, int64_t npairs,
+                      float* feats) {
+  if (!c) return ACE_E_ARG;
+  int rc = check_grid(c, g, norb);
+  if (rc) return rc;
+  if (g->L[0] != g->L[1] || g->L[1] != g->L[2]) return fail(c, ACE_E_UNSUPPORTED, "features need a cubic box");
+  if (!phi || !feats) return fail(c, ACE_E_ARG, "phi and feats must be non-NULL");
+  const int64_t all = int64_t(norb) * (norb + 1) / 2;
+  if (pairs ? (npairs < 1 || npairs > all) : (npairs != all))
+    return fail(c, ACE_E_ARG, "npairs must be in [1, %lld] (or exactly %lld with pairs == NULL)", (long long)all,
+                (long long)all);
+  return features_impl(c, g, norb, phi, pairs, npairs, feats, nullptr);
+}
+
+int ace_mlp_init(ace_ctx* c, float* model, uint64_t seed) {
+  if (!c || !model) return fail(c, ACE_E_ARG, "model must be non-NULL");
+  launch_mlp_init(model, seed, c->stream);
+  HIPCHK(c, hipGetLastError());
+  return ACE_OK;
+}
+
+int ace_mlp_fit_norm(ace_ctx* c, float* model, const float* x, const float* t, int64_t n) {
+  if (!c || !model || !x || !t || n < 2) return fail(c, ACE_E_ARG, "model, x, t non-NULL and n >= 2 required");
+  double* part;
+  WS(c, "m_stats", size_t(stats_blocks(n)) * 22 * sizeof(double), part);
+  launch_mlp_stats(x, t, n, part, model, c->stream);
+  HIPCHK(c, hipGetLastError());
+  return ACE_OK;
+}
+
+int ace_mlp_forward(ace_ctx* c, const float* model, const float* x, int64_t n, int clamp, float* y) {
+  if (!c || !model || !x || !y || n < 1) return fail(c, ACE_E_ARG, "model, x, y non-NULL and n >= 1 required");
+  launch_mlp_forward(model, x, n, clamp, y, c->stream);
+  HIPCHK(c, hipGetLastError());
+  return ACE_OK;
+}
+
+int ace_mlp_grad(ace_ctx* c, const float* model, const float* x, const float* t, int64_t n, float* grad, float* loss) {
+  if (!c || !model || !x || !t || !grad || n < 1 || n > (1 << 30))
+    return fail(c, ACE_E_ARG, "model, x, t, grad non-NULL and 1 <= n <= 2^30 required");
+  const int nb = mlp_grad_blocks(int(n));
+  float *gp, *lp;
+  WS(c, "m_gpart", size_t(nb) * ACE_MLP_NPARAM * sizeof(float), gp);
+  WS(c, "m_lpart", size_t(nb) * sizeof(float), lp);
+  launch_mlp_grad_partial(model, x, t, n, 0, 1, 0, int(n), gp, lp, c->stream);
+  launch_mlp_reduce(gp, lp, nb, grad, loss, c->stream);
+  HIPCHK(c, hipGetLastError());
+  return ACE_OK;
+}
+
+static uint64_t mix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+int ace_mlp_train(ace_ctx* c, float* model, float* adam_m, float* adam_v, const float* x, const float* t, int64_t n,
+                  const ace_mlp_hparams* hp, float* loss_curve) {
+  if (!c || !model || !adam_m || !adam_v || !x || !t || !hp || n < 1)
+    return fail(c, ACE_E_ARG, "model, Adam state, x, t and hparams must be non-NULL, n >= 1");
+  if (hp->batch < 1 || hp->batch > (1 << 20) || hp->epochs < 1 || !(hp->lr > 0))
+    return fail(c, ACE_E_ARG, "batch in [1, 2^20], epochs >= 1 and lr > 0 required");
+  hipStream_t s = c->stream;
+  const int bsz_max = int(std::min<int64_t>(hp->batch, n));
+  const int nb = mlp_grad_blocks(bsz_max);
+  float *gp, *lp;
+  WS(c, "m_gpart", size_t(nb) * ACE_MLP_NPARAM * sizeof(float), gp);
+  WS(c, "m_lpart", size_t(nb) * sizeof(float), lp);
+  if (loss_curve) launch_zero(loss_curve, size_t(hp->epochs) * sizeof(float), s);
+  // a permutation of the samples per epoch: k -> (off + k * stride) mod n with gcd(stride, n) = 1
+  auto gcd = [](uint64_t a, uint64_t b) { while (b) { uint64_t r = a % b; a = b; b = r; } return a; };
+  uint64_t stride = (uint64_t(double(n) * 0.6180339887498949) | 1ull) % uint64_t(n);
+  if (stride == 0) stride = 1;
+  while (gcd(stride, uint64_t(n)) != 1) stride = (stride + 2) % uint64_t(n) ? (stride + 2) % uint64_t(n) : 1;
+  int step = hp->step0;
+  for (int e = 0; e < hp->epochs; ++e) {
+    const int64_t off = int64_t(mix64(hp->seed * 1000003ull + uint64_t(e)) % uint64_t(n));
+    for (int64_t b0 = 0; b0 < n; b0 += hp->batch) {
+      const int bsz = int(std::min<int64_t>(hp->batch, n - b0));
+      launch_mlp_grad_partial(model, x, t, n, off, int64_t(stride), b0, bsz, gp, lp, s);
+      launch_mlp_adam(gp, lp, mlp_grad_blocks(bsz), model, adam_m, adam_v, ++step, hp->lr, hp->beta1, hp->beta2,
+                      hp->eps, loss_curve ? loss_curve + e : nullptr, s);
+    }
+  }
+  HIPCHK(c, hipGetLastError());
+  return ACE_OK;
+}
+
+int ace_screen_learned(ace_ctx* c, const ace_grid* g, int norb, const double* phi, const float* model,
+                       double budget, double rho_cut_fallback, double ood_tol, int64_t capacity, int32_t* pairs,
+                       int64_t* npairs, int* used_fallback) {
+  if (!c) return ACE_E_ARG;
+  int rc = check_grid(c, g, norb);
+  if (rc) return rc;
+  if (g->L[0] != g->L[1] || g->L[1] != g->L[2]) return fail(c, ACE_E_UNSUPPORTED, "screening needs a cubic box");
+  if (!phi || !model || !pairs || !npairs) return fail(c, ACE_E_ARG, "phi, model, pairs and npairs must be non-NULL");
+  if (!(budget >= 0) || !std::isfinite(rho_cut_fallback) || !(ood_tol >= 0) || capacity < 0)
+    return fail(c, ACE_E_ARG, "budget >= 0, finite rho_cut, ood_tol >= 0 and capacity >= 0 required");
+  hipStream_t s = c->stream;
+  const int64_t np = int64_t(norb) * (norb + 1) / 2;
+  float *f, *pred;
+  uint8_t* keep;
+  double *tau, *O;
+  int* ood;
+  int64_t* cnt;
+  WS(c, "s_feats", size_t(np) * 5 * sizeof(float), f);
+  WS(c, "s_pred", size_t(np) * sizeof(float), pred);
+  WS(c, "s_keep", size_t(np), keep);
+  WS(c, "s_tau", 64, tau);
+  WS(c, "s_ood", 64, ood);
+  WS(c, "cnt", 64, cnt);
+  rc = features_impl(c, g, norb, phi, nullptr, np, f, &O);
+  if (rc) return rc;
+  launch_mlp_forward(model, f, np, 1, pred, s);
+  HIPCHK(c, hipMemsetAsync(ood, 0, sizeof(int), s));
+  launch_select(pred, f, np, norb, model, budget, O, rho_cut_fallback, float(ood_tol), ood, tau, keep, capacity, pairs,
+                cnt, s);
+  int64_t h = 0;
+  int hood = 0;
+  HIPCHK(c, hipMemcpyAsync(&h, cnt, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(&hood, ood, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  *npairs = h;
+  if (used_fallback) *used_fallback = hood > 0 ? 1 : 0;
+  if (h > capacity) return fail(c, ACE_E_CAPACITY, "%lld pairs kept but capacity is %lld", (long long)h,
+                                (long long)capacity);
   return ACE_OK;
 }
 

@@ -27,12 +27,13 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 constexpr int GB = 64;   // output tile edge
 constexpr int GK = 32;   // K step staged through LDS
 
-template <typename T>
-__device__ __forceinline__ T absif(T v, bool a) { return a ? (v < T(0) ? -v : v) : v; }
+// elementwise operand map of the split-K product: 0 identity, 1 |x|, 2 x^2
+template <int OP, typename T>
+__device__ __forceinline__ T opmap(T v) { return OP == 1 ? (v < T(0) ? -v : v) : OP == 2 ? v * v : v; }
 
 // ---------------------------------------------------------------- NT split-K, FP64
-// Cpart[split][m][n] = sum_{k in split} f(A[m][k]) f(B[n][k]), f = |.| if ABS.
-template <bool ABS>
+// Cpart[split][m][n] = sum_{k in split} f(A[m][k]) f(B[n][k]), f = opmap<OP>.
+template <int OP>
 __global__ __launch_bounds__(256) void k_gemm_nt_f64(const double* __restrict__ A, int64_t lda,
                                                      const double* __restrict__ B, int64_t ldb, int M,
                                                      int Nn, int64_t K, int64_t kchunk,
@@ -56,8 +57,8 @@ __global__ __launch_bounds__(256) void k_gemm_nt_f64(const double* __restrict__ 
       const int64_t k = k0 + c;
       double va = 0.0, vb = 0.0;
       if (k < ke) {
-        if (m0 + r < M) va = absif(A[int64_t(m0 + r) * lda + k], ABS);
-        if (n0 + r < Nn) vb = absif(B[int64_t(n0 + r) * ldb + k], ABS);
+        if (m0 + r < M) va = opmap<OP>(A[int64_t(m0 + r) * lda + k]);
+        if (n0 + r < Nn) vb = opmap<OP>(B[int64_t(n0 + r) * ldb + k]);
       }
       As[c][r] = va;
       Bs[c][r] = vb;
@@ -272,7 +273,7 @@ int64_t gemm_nt_nsplit(int M, int Nn, int64_t K, int64_t* kchunk_out) {
   return nsplit;
 }
 
-hipError_t gemm_nt(int prec, bool abs_ops, const void* A, int64_t lda, const void* B, int64_t ldb, int M,
+hipError_t gemm_nt(int prec, int op, const void* A, int64_t lda, const void* B, int64_t ldb, int M,
                    int Nn, int64_t K, double alpha, double* Cpart, double* C, hipStream_t s,
                    EventRecorder* rec) {
   int64_t kchunk;
@@ -280,11 +281,14 @@ hipError_t gemm_nt(int prec, bool abs_ops, const void* A, int64_t lda, const voi
   dim3 grid((Nn + GB - 1) / GB, (M + GB - 1) / GB, unsigned(nsplit));
   rec_begin(rec, KC_GEMM_NT, s);
   if (prec == 0) {
-    if (abs_ops)
-      hipLaunchKernelGGL(k_gemm_nt_f64<true>, grid, dim3(256), 0, s, (const double*)A, lda, (const double*)B,
+    if (op == 1)
+      hipLaunchKernelGGL(k_gemm_nt_f64<1>, grid, dim3(256), 0, s, (const double*)A, lda, (const double*)B,
+                         ldb, M, Nn, K, kchunk, Cpart);
+    else if (op == 2)
+      hipLaunchKernelGGL(k_gemm_nt_f64<2>, grid, dim3(256), 0, s, (const double*)A, lda, (const double*)B,
                          ldb, M, Nn, K, kchunk, Cpart);
     else
-      hipLaunchKernelGGL(k_gemm_nt_f64<false>, grid, dim3(256), 0, s, (const double*)A, lda, (const double*)B,
+      hipLaunchKernelGGL(k_gemm_nt_f64<0>, grid, dim3(256), 0, s, (const double*)A, lda, (const double*)B,
                          ldb, M, Nn, K, kchunk, Cpart);
   } else {
     hipLaunchKernelGGL(k_gemm_nt_f32c, grid, dim3(256), 0, s, (const float*)A, lda, (const float*)B, ldb, M, Nn,

@@ -92,32 +92,7 @@ __global__ __launch_bounds__(NT) void k_inv_xy(const T* __restrict__ phi, const 
   __syncthreads();
   fft_lines<T, N, N, 1, N, NT, +1, false>(buf, tw, tid);  // y
   fft_lines<T, N, N, N, 1, NT, +1, true>(buf, tw, tid);   // x
-  const T* pia = phi + size_t(pk.ia) * NG + zo;
-  const T* pja = phi + size_t(pk.ja) * NG + zo;
-  T* wia = W + size_t(pk.ia) * NG + zo;
-  T* wja = W + size_t(pk.ja) * NG + zo;
-  T ea = T(0), eb = T(0);
-  const bool offa = pk.ia != pk.ja;
-  for (int e = tid; e < P2; e += NT) {
-    const T v = buf[e].x, fi = pia[e], fj = pja[e];
-    wia[e] -= v * fj;
-    if (offa) wja[e] -= v * fi;
-    if (EN) ea += v * fi * fj;
-  }
-  if (pk.jb >= 0) {
-    const T* pib = phi + size_t(pk.ib) * NG + zo;
-    const T* pjb = phi + size_t(pk.jb) * NG + zo;
-    T* wib = W + size_t(pk.ib) * NG + zo;
-    T* wjb = W + size_t(pk.jb) * NG + zo;
-    const bool offb = pk.ib != pk.jb;
-    for (int e = tid; e < P2; e += NT) {
-      const T v = buf[e].y, fi = pib[e], fj = pjb[e];
-      wib[e] -= v * fj;
-      if (offb) wjb[e] -= v * fi;
-      if (EN) eb += v * fi * fj;
-    }
-  }
-  if (EN) block_sum2<T, NT>(ea, eb, epart + 2 * (size_t(p) * N + z), red);
+  accumulate_w<T, NT, EN>(phi, pk, NG, zo, P2, W, EN ? epart + 2 * (size_t(p) * N + z) : nullptr, buf, red, tid);
 }
 
 // ------------------------------------------------------------ z pass (both paths)

@@ -51,6 +51,48 @@ __device__ __forceinline__ void block_sum2(T a, T b, double* out, double* red) {
 }
 
 
+// W_i -= v phi_j and (i != j) W_j -= v phi_i for the E grid points starting
+// at ro, with v = Re (pair a) and Im (pair b) of buf; with W == nullptr only
+// the energy sums are formed.  Optional partial sums of v rho go to eslot.
+template <typename T, int NT, bool EN>
+__device__ __forceinline__ void accumulate_w(const T* __restrict__ phi, const Pack& pk, size_t NG, size_t ro, int E,
+                                             T* W, double* eslot, const cplx<T>* buf, double* red, int tid) {
+  const T* pia = phi + size_t(pk.ia) * NG + ro;
+  const T* pja = phi + size_t(pk.ja) * NG + ro;
+  T ea = T(0), eb = T(0);
+  const bool offa = pk.ia != pk.ja;
+  if (W) {
+    T* wia = W + size_t(pk.ia) * NG + ro;
+    T* wja = W + size_t(pk.ja) * NG + ro;
+    for (int e = tid; e < E; e += NT) {
+      const T v = buf[e].x, fi = pia[e], fj = pja[e];
+      wia[e] -= v * fj;
+      if (offa) wja[e] -= v * fi;
+      if (EN) ea += v * fi * fj;
+    }
+  } else if (EN) {
+    for (int e = tid; e < E; e += NT) ea += buf[e].x * pia[e] * pja[e];
+  }
+  if (pk.jb >= 0) {
+    const T* pib = phi + size_t(pk.ib) * NG + ro;
+    const T* pjb = phi + size_t(pk.jb) * NG + ro;
+    const bool offb = pk.ib != pk.jb;
+    if (W) {
+      T* wib = W + size_t(pk.ib) * NG + ro;
+      T* wjb = W + size_t(pk.jb) * NG + ro;
+      for (int e = tid; e < E; e += NT) {
+        const T v = buf[e].y, fi = pib[e], fj = pjb[e];
+        wib[e] -= v * fj;
+        if (offb) wjb[e] -= v * fi;
+        if (EN) eb += v * fi * fj;
+      }
+    } else if (EN) {
+      for (int e = tid; e < E; e += NT) eb += buf[e].y * pib[e] * pjb[e];
+    }
+  }
+  if (EN) block_sum2<T, NT>(ea, eb, eslot, red);
+}
+
 // x pass, forward: product of the pack's two pairs over ROWS rows starting at
 // linear offset ro, row FFTs, store.
 template <typename T, int N, int ROWS, int NT, int V = 0>
@@ -121,32 +163,7 @@ __device__ __forceinline__ void body_inv_x(const T* __restrict__ phi, const cplx
   for (int e = tid; e < E; e += NT) buf[e] = in[e];
   __syncthreads();
   fft_lines<T, N, ROWS, N, 1, NT, +1, true, V>(buf, tw, tid);
-  const T* pia = phi + size_t(pk.ia) * NG + ro;
-  const T* pja = phi + size_t(pk.ja) * NG + ro;
-  T* wia = W + size_t(pk.ia) * NG + ro;
-  T* wja = W + size_t(pk.ja) * NG + ro;
-  T ea = T(0), eb = T(0);
-  const bool offa = pk.ia != pk.ja;
-  for (int e = tid; e < E; e += NT) {
-    const T v = buf[e].x, fi = pia[e], fj = pja[e];
-    wia[e] -= v * fj;
-    if (offa) wja[e] -= v * fi;
-    if (EN) ea += v * fi * fj;
-  }
-  if (pk.jb >= 0) {
-    const T* pib = phi + size_t(pk.ib) * NG + ro;
-    const T* pjb = phi + size_t(pk.jb) * NG + ro;
-    T* wib = W + size_t(pk.ib) * NG + ro;
-    T* wjb = W + size_t(pk.jb) * NG + ro;
-    const bool offb = pk.ib != pk.jb;
-    for (int e = tid; e < E; e += NT) {
-      const T v = buf[e].y, fi = pib[e], fj = pjb[e];
-      wib[e] -= v * fj;
-      if (offb) wjb[e] -= v * fi;
-      if (EN) eb += v * fi * fj;
-    }
-  }
-  if (EN) block_sum2<T, NT>(ea, eb, eslot, red);
+  accumulate_w<T, NT, EN>(phi, pk, NG, ro, E, W, eslot, buf, red, tid);
 }
 
 }  // namespace ace

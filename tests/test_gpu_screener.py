@@ -1,0 +1,173 @@
+"""GPU parity of the learned pair screener against its FP64 oracle, and what the
+trained network gains over the overlap-threshold rule."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import screener_oracle as so
+from synth import SystemSpec, box_length_for, config_spec, make_orbitals
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+def _dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    return lib.Context()
+
+
+def test_features_match_oracle(ctx):
+    _say("screener features vs oracle")
+    from paper_2101_03155_amd import Grid
+    spec = SystemSpec(n_mol=4, L=12.0, N=32, sigma=0.8, offset=0.7, placement="uniform", seed=31)
+    o = make_orbitals(spec)
+    g = Grid.cubic(spec.N, spec.L)
+    phi, _, _ = ctx.localize(_dev(o.psi), g)
+    f = ctx.pair_features(phi, g).cpu().numpy()
+    iu, ju = np.triu_indices(spec.norb)
+    ref = so.pair_features(phi.cpu().numpy(), spec.L, np.stack([iu, ju], 1))
+    np.testing.assert_allclose(f[:, 0], ref[:, 0], atol=2e-5 * spec.L)
+    np.testing.assert_allclose(f[:, 1:3], ref[:, 1:3], rtol=2e-6)
+    np.testing.assert_allclose(f[:, 3:], ref[:, 3:], atol=2e-5)
+    sub = _dev(np.array([[0, 5], [3, 3], [2, 11]], dtype=np.int32))
+    fs = ctx.pair_features(phi, g, sub).cpu().numpy()
+    np.testing.assert_array_equal(fs, f[[5, np.flatnonzero((iu == 3) & (ju == 3))[0],
+                                         np.flatnonzero((iu == 2) & (ju == 11))[0]]])
+
+
+def test_pair_energies_match_oracle(ctx):
+    _say("energies-only pair stage vs oracle")
+    from paper_2101_03155_amd import Grid
+    o = make_orbitals(config_spec("c1"))
+    s = o.spec
+    pairs = np.array([(i, j) for i in range(s.norb) for j in range(i, s.norb) if (i + j) % 3], dtype=np.int32)
+    for prec, tol in (("fp64", 1e-12), ("fp32", 2e-6)):
+        e = ctx.pair_energies(_dev(o.psi), _dev(pairs), Grid.cubic(s.N, s.L), kernel="bare", precision=prec)
+        ref = oracle.exchange_energy_pairs(o.psi, pairs, oracle.coulomb_kernel(s.N, s.L, "bare"), s.dV)
+        np.testing.assert_allclose(e.cpu().numpy(), ref, atol=tol * np.abs(ref).max())
+
+
+def _model_arrays(model):
+    m = model.cpu().numpy().astype(np.float64)
+    p = m[:so.NPARAM]
+    o = so.NPARAM
+    xmean, xstd = m[o:o + 5], m[o + 5:o + 10]
+    tmean, tstd = m[o + 10], m[o + 11]
+    return p, xmean, xstd, tmean, tstd
+
+
+def test_mlp_forward_and_gradient_match_oracle(ctx):
+    _say("MLP forward + gradient vs FP64 oracle")
+    rng = np.random.default_rng(5)
+    n = 300  # several 64-sample chunks and a ragged tail
+    x = rng.normal(size=(n, 5)).astype(np.float32) * np.array([3, 0.5, 0.5, 2, 3], np.float32) + \
+        np.array([6, 1.2, 1.5, -3, -6], np.float32)
+    t = (rng.normal(size=n) * 2 - 5).astype(np.float32)
+    model = ctx.mlp_init(123)
+    xd, td = _dev(x), _dev(t)
+    ctx.mlp_fit_norm(model, xd, td)
+    p, xmean, xstd, tmean, tstd = _model_arrays(model)
+    np.testing.assert_allclose(xmean, x.astype(np.float64).mean(0), rtol=1e-5, atol=1e-5)
+    np.testing.assert_allclose(xstd, x.astype(np.float64).std(0), rtol=1e-4)
+    xs = (x - xmean) / xstd
+    ts = (t - tmean) / tstd
+    y = ctx.mlp_forward(model, xd).cpu().numpy()
+    out, _ = so.forward(p, xs)
+    np.testing.assert_allclose(y, tmean + tstd * out, rtol=1e-5, atol=1e-5)
+    g, loss = ctx.mlp_grad(model, xd, td)
+    lref, gref = so.loss_and_grad(p, xs, ts)
+    g = g.cpu().numpy().astype(np.float64)
+    assert abs(loss.item() - lref) <= 1e-5 * lref
+    assert np.linalg.norm(g - gref) <= 1e-4 * np.linalg.norm(gref)
+    assert np.abs(g - gref).max() <= 1e-4 * np.abs(gref).max()
+
+
+def test_adam_step_matches_oracle(ctx):
+    _say("Adam step vs oracle")
+    rng = np.random.default_rng(8)
+    n = 200
+    x = rng.normal(size=(n, 5)).astype(np.float32)
+    t = rng.normal(size=n).astype(np.float32)
+    model = ctx.mlp_init(9)
+    xd, td = _dev(x), _dev(t)
+    ctx.mlp_fit_norm(model, xd, td)
+    p0, xmean, xstd, tmean, tstd = _model_arrays(model)
+    _, g = so.loss_and_grad(p0, (x - xmean) / xstd, (t - tmean) / tstd)
+    m = torch.zeros(so.NPARAM, dtype=torch.float32, device="cuda")
+    v = torch.zeros_like(m)
+    ctx.mlp_train(model, m, v, xd, td, lr=1e-3, batch=n, epochs=1, seed=0)
+    p1 = _model_arrays(model)[0]
+    ref, _, _ = so.adam_step(p0, g, np.zeros_like(g), np.zeros_like(g), 1, lr=1e-3)
+    # first Adam step: every parameter moves by ~lr * sign(g)
+    np.testing.assert_allclose(p1, ref, atol=2e-6)
+
+
+def _small_specs(count, first_seed, lo=12, hi=20):
+    from synth.orbitals import batched_grid_for
+    out = []
+    for k in range(count):
+        seed = first_seed + k
+        n_mol = int(np.random.default_rng(seed + 17).integers(lo, hi + 1))
+        L = box_length_for(n_mol)
+        out.append(SystemSpec(n_mol=n_mol, L=L, N=batched_grid_for(L), sigma=1.0, offset=0.8, placement="lattice",
+                              jitter=0.5, seed=seed, kernel="erfc", omega=0.106))
+    return out
+
+
+def test_learned_screener_budget_and_gain(ctx):
+    _say("learned screener: train, calibrate, budget vs full build, gain vs threshold")
+    from paper_2101_03155_amd import Grid
+    from paper_2101_03155_amd.screener import LearnedScreener, training_set
+    data = training_set(ctx, _small_specs(12, 8000))
+    scr = LearnedScreener.train(ctx, data, epochs=24, batch=2048)
+    curve = scr.meta["loss_curve"]
+    print(f"loss {curve[0]:.4f} -> {curve[-1]:.4f} on {data.x.shape[0]} samples", flush=True)
+    assert curve[-1] < 0.2 * curve[0]
+    scr.calibrate(ctx, _small_specs(3, 8100))
+    spec = _small_specs(1, 8500, 24, 24)[0]
+    o = make_orbitals(spec, device="cuda")
+    g = Grid.cubic(spec.N, spec.L)
+    phi, _, _ = ctx.localize(o.psi, g)
+    del o
+    n = spec.norb
+    budget = 1e-5 * spec.n_mol
+    pairs_l, fb = scr.select(ctx, phi, g, spec.n_mol)
+    assert not fb
+    full = torch.as_tensor(np.array([(i, j) for i in range(n) for j in range(i, n)], dtype=np.int32), device="cuda")
+    e_full = ctx.pair_energies(phi, full, g, kernel="erfc", omega=spec.omega).cpu().numpy()
+    r_full = ctx.build(phi, full, g, kernel="erfc", omega=spec.omega, precision="fp64")
+    r_l = ctx.build(phi, pairs_l, g, kernel="erfc", omega=spec.omega, precision="fp64")
+    err_l = abs(r_l["ex"].item() - r_full["ex"].item())
+    print(f"learned: {pairs_l.shape[0]} of {full.shape[0]} pairs, |dE_x| = {err_l:.3e} Ha (budget {budget:.1e})",
+          flush=True)
+    assert err_l <= budget
+    # the method without the network: the overlap rule at rho_cut = 1e-3
+    pairs_t, _ = ctx.pairlist(phi, g, 1e-3)
+    r_t = ctx.build(phi, pairs_t, g, kernel="erfc", omega=spec.omega, precision="fp64")
+    err_t = abs(r_t["ex"].item() - r_full["ex"].item())
+    print(f"overlap rule 1e-3: {pairs_t.shape[0]} pairs, |dE_x| = {err_t:.3e} Ha", flush=True)
+    # gain: fewer pair solves than the fixed threshold while meeting the stated budget
+    assert pairs_l.shape[0] < pairs_t.shape[0]
+    # at equal pair count the learned order drops no more energy than the overlap order
+    fp = ctx.pair_features(phi, g).cpu().numpy()
+    iu, ju = np.triu_indices(n)
+    off = iu != ju
+    k_off = pairs_l.shape[0] - n
+    e_off = e_full[off]
+    err_overlap_order = abs(e_off[np.argsort(-fp[off, 3], kind="stable")[k_off:]].sum())
+    err_best_order = abs(e_off[np.argsort(-np.abs(e_off), kind="stable")[k_off:]].sum())
+    kept_l = {tuple(p) for p in pairs_l.cpu().numpy().tolist()}
+    err_l_sum = abs(sum(e for (i, j), e in zip(zip(iu, ju), e_full) if (i, j) not in kept_l))
+    print(f"dropped energy at {pairs_l.shape[0]} pairs: learned {err_l_sum:.3e}, overlap order "
+          f"{err_overlap_order:.3e}, exact-|e| order {err_best_order:.3e}", flush=True)
+    assert abs(err_l_sum - err_l) <= 1e-6 + 1e-3 * err_l
+    assert err_l_sum <= err_overlap_order * 1.05
