@@ -46,9 +46,65 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true")
-    ap.add_argument("--shape", default="auto", choices=["auto", "default", "fused", "split"],
-                    help="pair-stage launch shape: autotuned, library default, or forced")
+    ap.add_argument("--screener", default=os.path.join(ROOT, "paper_2101_03155_amd", "models",
+                                                       "screener_water_erfc.npz"))
+    ap.add_argument("--skip-forms", default="", help="comma list of precision,batched,learned")
+    ap.add_argument("--shape", default="split", choices=["auto", "default", "fused", "split"],
+                    help="pair-stage launch shape: autotuned, library default, or forced (default: split, the "
+                         "tuner's pick for this workload, fixed so that profiles and the bench line agree)")
+    ap.add_argument("--max-packs", type=int, default=16, help="packs per pair-stage launch for a forced shape")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 1 GiB three times (calibrates FETCH_SIZE / WRITE_SIZE counters) and exit")
     return ap.parse_args()
+
+
+# Files whose code defines the pair-stage kernels; counters are voided when they change.
+PAIR_SOURCES = ("paper_2101_03155_amd/csrc/pair.hip", "paper_2101_03155_amd/csrc/pair_phases.h",
+                "paper_2101_03155_amd/csrc/fft.h")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_pair_stage.md")
+
+
+def pair_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in PAIR_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, N, prec, units_per_launch):
+    """HBM bytes per launch from the committed counter summary: FETCH_SIZE and
+    WRITE_SIZE per dispatch, each scaled by what the counter reads for a plain
+    1 GiB copy, expressed per algorithmic byte and applied to this launch size.
+    None when no summary matches or the kernel source changed since."""
+    import re
+
+    if not os.path.exists(COUNTERS_FILE):
+        return None, "no counter summary"
+    m = re.search(r"```json\n(.*?)\n```", open(COUNTERS_FILE).read(), re.S)
+    if not m:
+        return None, "no counter summary"
+    rows = json.loads(m.group(1))
+    for r in rows:
+        if r["kernel"] == kernel and r["N"] == N and r["precision"] == prec:
+            if r["source_hash"] != pair_source_hash():
+                return None, "pair-stage sources changed since the counters were taken"
+            return r["traffic_per_algorithmic_byte"] * units_per_launch, "FETCH_SIZE x %.3g + WRITE_SIZE x %.3g" % (
+                r["fetch_scale"], r["write_scale"])
+    return None, "no counter row for this kernel"
+
+
+def copy_probe():
+    import torch
+
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": a.numel() * 8, "copies": 3, "source_hash": pair_source_hash()}), flush=True)
 
 
 def cpu_baseline(o, pairs_np, kind, omega, sample_pairs=60):
@@ -79,12 +135,149 @@ def cpu_baseline(o, pairs_np, kind, omega, sample_pairs=60):
     }
 
 
+def _timed(fn, reps=3, warm=True):
+    import torch
+
+    if warm:
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1000.0 / reps, out
+
+
+def form_precision(ctx, log):
+    """64 waters (256 orbitals, 120^3): FP32 pair stage vs the plain FP64 path."""
+    import torch
+
+    from paper_2101_03155_amd import Grid
+    from synth import config_spec, make_orbitals
+
+    spec = config_spec("c3")
+    o = make_orbitals(spec, device="cuda")
+    g = Grid.cubic(spec.N, spec.L)
+    phi, _, _ = ctx.localize(o.psi, g)
+    del o
+    torch.cuda.empty_cache()
+    pairs, _ = ctx.pairlist(phi, g, 1e-3)
+    n = spec.norb
+    full = torch.tensor([(i, j) for i in range(n) for j in range(i, n)], dtype=torch.int32, device="cuda")
+    out = {"workload": "64 waters: 256 orbitals, 120^3, L=23.4, erfc omega=0.106", "pairs_screened": int(pairs.shape[0]),
+           "pairs_full": int(full.shape[0])}
+    for name, pl in (("screened", pairs), ("full", full)):
+        reps = 3 if name == "screened" else 1
+        ms64, r64 = _timed(lambda: ctx.build(phi, pl, g, kernel="erfc", omega=spec.omega, precision="fp64",
+                                             want_M=False), reps)
+        ms32, r32 = _timed(lambda: ctx.build(phi, pl, g, kernel="erfc", omega=spec.omega, precision="fp32",
+                                             want_M=False), reps)
+        e64, e32 = r64["ex"].item(), r32["ex"].item()
+        out[name] = {"fp64_ms": round(ms64, 2), "fp32_ms": round(ms32, 2), "speedup_fp32": round(ms64 / ms32, 3),
+                     "fp64_pair_solves_per_s": round(pl.shape[0] / ms64 * 1000, 1),
+                     "fp32_pair_solves_per_s": round(pl.shape[0] / ms32 * 1000, 1),
+                     "ex_fp64": e64, "ex_rel_err_fp32_vs_fp64": abs(e32 - e64) / abs(e64)}
+        log(f"precision form {name}: {out[name]}")
+    return out
+
+
+def form_batched(ctx, log):
+    """16 uneven systems (8-64 molecules, 48^3-96^3), FP32 pair stage, one batched call."""
+    import torch
+
+    from paper_2101_03155_amd import Grid
+    from paper_2101_03155_amd.tune import autotune_batched
+    from synth import batched_specs, make_orbitals
+
+    specs = batched_specs()
+    systems = []
+    for sp in specs:
+        o = make_orbitals(sp, device="cuda")
+        g = Grid.cubic(sp.N, sp.L)
+        phi, _, _ = ctx.localize(o.psi, g)
+        del o
+        pairs, _ = ctx.pairlist(phi, g, 1e-3)
+        n = phi.shape[0]
+        systems.append(dict(phi=phi, pairs=pairs, grid=g, kernel=sp.kernel, omega=sp.omega,
+                            xi=torch.empty_like(phi), M=torch.empty(n, n, dtype=torch.float64, device="cuda"),
+                            ex=torch.empty(1, dtype=torch.float64, device="cuda")))
+    torch.cuda.empty_cache()
+    tuned = autotune_batched(ctx, systems, precision="fp32")
+    best = tuned["best"]
+    ms_b, res = _timed(lambda: ctx.build_batched(systems, precision="fp32", mode=best["mode"]), 3)
+    ms_seq32, _ = _timed(lambda: [ctx.build(sy["phi"], sy["pairs"], sy["grid"], kernel=sy["kernel"],
+                                            omega=sy["omega"], precision="fp32", want_M=False) for sy in systems], 1)
+    ms_seq64, r64 = _timed(lambda: [ctx.build(sy["phi"], sy["pairs"], sy["grid"], kernel=sy["kernel"],
+                                              omega=sy["omega"], precision="fp64", want_M=False) for sy in systems], 1)
+    errs = [abs(res[q]["ex"].item() - r64[q]["ex"].item()) / abs(r64[q]["ex"].item()) for q in range(len(systems))]
+    npairs = sum(int(sy["pairs"].shape[0]) for sy in systems)
+    out = {"workload": "16 systems, 8-64 molecules, 48^3-96^3, mixed bare/erfc, rho_cut=1e-3, FP32 pair stage",
+           "systems": [{"n_mol": sp.n_mol, "N": sp.N, "kernel": sp.kernel, "pairs": int(sy["pairs"].shape[0])}
+                       for sp, sy in zip(specs, systems)],
+           "pairs_total": npairs, "tuned": best, "tune_table": tuned["table"],
+           "batched_ms": round(ms_b, 2), "builds_per_s": round(len(systems) / ms_b * 1000, 2),
+           "pair_solves_per_s": round(npairs / ms_b * 1000, 1),
+           "sequential_fp32_ms": round(ms_seq32, 2), "sequential_fp64_ms": round(ms_seq64, 2),
+           "max_ex_rel_err_vs_fp64": max(errs)}
+    log(f"batched form: {out['batched_ms']} ms for 16 builds (sequential fp32 {out['sequential_fp32_ms']} ms)")
+    return out
+
+
+def form_learned(ctx, log, model_path):
+    """128 waters (512 orbitals, 160^3): learned vs threshold vs full-pair builds."""
+    import torch
+
+    from paper_2101_03155_amd import Grid
+    from paper_2101_03155_amd.screener import LearnedScreener
+    from synth import config_spec, make_orbitals
+
+    if not os.path.exists(model_path):
+        return {"skipped": f"no screener checkpoint at {model_path}"}
+    scr = LearnedScreener.load(model_path)
+    spec = config_spec("c5")
+    o = make_orbitals(spec, device="cuda")
+    g = Grid.cubic(spec.N, spec.L)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    phi, _, _ = ctx.localize(o.psi, g)
+    torch.cuda.synchronize()
+    ms_loc = (time.perf_counter() - t0) * 1000
+    del o
+    torch.cuda.empty_cache()
+    budget = 1e-5 * spec.n_mol
+    ms_sel, (pl, fb) = _timed(lambda: scr.select(ctx, phi, g, spec.n_mol), 2)
+    ms_thr_sel, (pt, _) = _timed(lambda: ctx.pairlist(phi, g, 1e-3), 2)
+    n = spec.norb
+    full = torch.tensor([(i, j) for i in range(n) for j in range(i, n)], dtype=torch.int32, device="cuda")
+    ms_full, rf = _timed(lambda: ctx.build(phi, full, g, kernel="erfc", omega=spec.omega, precision="fp64",
+                                           want_M=False), 1, warm=False)
+    ex_full = rf["ex"].item()
+    del rf
+    out = {"workload": "128 waters: 512 orbitals, 160^3, L=29.6, erfc omega=0.106", "budget_ha": budget,
+           "margin": scr.margin, "used_fallback": fb, "localize_ms": round(ms_loc, 1),
+           "full_fp64": {"pairs": int(full.shape[0]), "build_ms": round(ms_full, 1),
+                         "builds_per_s": round(1000 / ms_full, 4), "ex": ex_full},
+           "screener_train": {k: v for k, v in scr.meta.items() if k != "loss_curve"}}
+    for name, pl_, sel_ms in (("learned_fp32", pl, ms_sel), ("threshold_fp32", pt, ms_thr_sel)):
+        ms_b, r = _timed(lambda: ctx.build(phi, pl_, g, kernel="erfc", omega=spec.omega, precision="fp32",
+                                           want_M=False), 2)
+        err = abs(r["ex"].item() - ex_full)
+        out[name] = {"pairs": int(pl_.shape[0]), "select_ms": round(sel_ms, 2), "build_ms": round(ms_b, 1),
+                     "builds_per_s": round(1000 / (ms_b + sel_ms), 3), "ex": r["ex"].item(),
+                     "abs_err_vs_full_fp64": err, "within_budget": err <= budget}
+        log(f"learned form {name}: {out[name]}")
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}); the multi-GPU pair-sharded "
-              "design is described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}); the pair-sharded multi-GPU "
+              "form is a design only and is not built", file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
+        return
     import numpy as np
     import torch
 
@@ -114,7 +307,7 @@ def main():
         tuned = autotune(ctx, phi0, pairs0, grid, kind, omega, prec)
         del phi0, pairs0
     elif args.shape in ("fused", "split"):
-        ctx.set_pair_shape(prec, spec.N, args.shape == "fused", 64)
+        ctx.set_pair_shape(prec, spec.N, args.shape == "fused", args.max_packs)
     shape = ctx.get_pair_shape(prec, spec.N)
 
     for _ in range(args.warmup):
@@ -153,8 +346,11 @@ def main():
     roof.update({"kernel": CLASS_KERNEL[dom], "class": CLASS_NAMES[dom], "launches_per_step": n_l / args.steps,
                  "avg_launch_us": 1000.0 * ms_l / max(n_l, 1),
                  "algorithmic_per_launch": units / max(n_l, 1),
-                 "achieved": round(achieved, 2), "peak": peak, "frac": round(achieved / peak, 4),
-                 "traffic": None})
+                 "achieved": round(achieved, 2), "peak": peak, "frac": round(achieved / peak, 4)})
+    traffic, note = (measured_traffic(CLASS_KERNEL[dom], spec.N, prec, units / max(n_l, 1)) if dom < 7
+                     else (None, "not an HBM-bound class"))
+    roof["traffic"] = round(traffic) if traffic is not None else None
+    roof["traffic_note"] = note
     kernels = {CLASS_NAMES[c]: {"launches": prof[c][0], "ms": round(prof[c][1], 3),
                                 "rate": (round(prof[c][2] / (prof[c][1] / 1000.0) / (1e12 if c in (7, 8) else 1e9), 2)
                                          if prof[c][1] > 0 else None)}
@@ -188,20 +384,8 @@ def main():
         out["ex_rel_err_vs_oracle_fp64"] = abs(ex - e_ref.sum()) / abs(e_ref.sum())
 
     if not args.no_forms:
+        log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
         forms = {}
-        # FP32 precision form on the same pair list
-        for _ in range(2):
-            r32 = ctx.build(phi, pairs, grid, kernel=kind, omega=omega, precision="fp32", want_M=False)
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        for _ in range(3):
-            r32 = ctx.build(phi, pairs, grid, kernel=kind, omega=omega, precision="fp32", want_M=False)
-        torch.cuda.synchronize()
-        forms["screened_fp32_build_ms"] = round((time.perf_counter() - ta) * 1000 / 3, 3)
-        ex32 = float(r32["ex"].item())
-        r64 = ctx.build(phi, pairs, grid, kernel=kind, omega=omega, precision="fp64", want_M=False)
-        forms["ex_rel_err_fp32_vs_fp64"] = abs(ex32 - float(r64["ex"].item())) / abs(float(r64["ex"].item()))
-        # full pair list, FP64 and FP32
         n = spec.norb
         full = torch.tensor([(i, j) for i in range(n) for j in range(i, n)], dtype=torch.int32, device="cuda")
         for p in ("fp64", "fp32"):
@@ -216,9 +400,22 @@ def main():
             tb = time.perf_counter()
             _, pms, _ = ctx.profile_read(12, reset=True)
             ctx.profile(False)
-            forms[f"full_{p}_build_ms"] = round((tb - ta) * 1000 / 3, 3)
-            forms[f"full_{p}_pair_solves_per_s"] = round(full.shape[0] / (pms / 3 / 1000.0), 1)
-            forms[f"full_{p}_ex"] = float(rf["ex"].item())
+            forms[f"c2_full_{p}_build_ms"] = round((tb - ta) * 1000 / 3, 3)
+            forms[f"c2_full_{p}_pair_solves_per_s"] = round(full.shape[0] / (pms / 3 / 1000.0), 1)
+            forms[f"c2_full_{p}_ex"] = float(rf["ex"].item())
+        r32 = ctx.build(phi, pairs, grid, kernel=kind, omega=omega, precision="fp32", want_M=False)
+        forms["c2_screened_ex_rel_err_fp32_vs_fp64"] = abs(float(r32["ex"].item()) - ex) / abs(ex)
+        del full, rf, r32
+        torch.cuda.empty_cache()
+        for name, fn in (("precision", lambda: form_precision(ctx, log)), ("batched", lambda: form_batched(ctx, log)),
+                         ("learned", lambda: form_learned(ctx, log, args.screener))):
+            if name in args.skip_forms:
+                continue
+            try:
+                forms[name] = fn()
+            except Exception as e:  # a failing form is reported, not hidden
+                forms[name] = {"error": f"{type(e).__name__}: {e}"}
+            torch.cuda.empty_cache()
         out["forms"] = forms
 
     if not args.no_cpu_baseline:

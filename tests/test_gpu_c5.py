@@ -1,0 +1,105 @@
+"""Full-size checks at 128 waters (512 orbitals on 160^3), the workload of the
+learned-screen form.  The oracle cannot run a whole build at this size in a
+test, so it checks sampled pair energies one by one, and the rest is held to
+properties that hold at any size: orthonormality of the localized orbitals,
+invariance of the occupied projector at sampled grid points, the first SCDM
+pivot, and E_x = sum of the pair energies of the kept pairs (Sec. Theory,
+Appendix A)."""
+import numpy as np
+import pytest
+
+import oracle
+from synth import config_spec, make_orbitals
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    return lib.Context()
+
+
+@pytest.fixture(scope="module")
+def c5(ctx):
+    from paper_2101_03155_amd import Grid
+    _say("c5: generate 512 orbitals on 160^3 and localize")
+    spec = config_spec("c5")
+    o = make_orbitals(spec, device="cuda")
+    grid = Grid.cubic(spec.N, spec.L)
+    phi, piv, _ = ctx.localize(o.psi, grid)
+    psi = o.psi.reshape(spec.norb, -1)
+    rng = np.random.default_rng(55)
+    pts = torch.as_tensor(np.sort(rng.choice(spec.N ** 3, size=96, replace=False)), device="cuda")
+    first = int(torch.argmax((psi * psi).sum(0)).item())
+    psi_pts = psi[:, pts].clone()
+    del o, psi
+    torch.cuda.empty_cache()
+    pairs, _ = ctx.pairlist(phi, grid, 1e-3)
+    return dict(spec=spec, grid=grid, phi=phi, piv=piv, pts=pts, psi_pts=psi_pts, first=first, pairs=pairs)
+
+
+def test_c5_localize_invariants(c5):
+    _say("c5 localize: orthonormality, projector at sampled points, first pivot")
+    s, phi, piv = c5["spec"], c5["phi"], c5["piv"].cpu().numpy()
+    P = phi.reshape(s.norb, -1)
+    S = (P @ P.T).cpu().numpy() * s.dV
+    assert np.abs(S - np.eye(s.norb)).max() < 1e-11
+    a, b = P[:, c5["pts"]], c5["psi_pts"]
+    np.testing.assert_allclose((a.T @ a).cpu().numpy(), (b.T @ b).cpu().numpy(), atol=1e-12)
+    assert len(set(piv.tolist())) == s.norb
+    assert piv[0] == c5["first"]
+
+
+def _sample_pairs(spec, pairs_np):
+    rng = np.random.default_rng(5001)
+    n = spec.norb
+    diag = [(i, i) for i in rng.choice(n, 4, replace=False)]
+    off = pairs_np[pairs_np[:, 0] != pairs_np[:, 1]]
+    near = [tuple(p) for p in off[rng.choice(len(off), 12, replace=False)]]
+    far = []
+    kept = {tuple(p) for p in pairs_np.tolist()}
+    while len(far) < 8:
+        i, j = sorted(rng.choice(n, 2, replace=False).tolist())
+        if (i, j) not in kept:
+            far.append((i, j))
+    return np.array(diag + near + far, dtype=np.int32)
+
+
+def test_c5_sampled_pair_energies_match_oracle(ctx, c5):
+    _say("c5 sampled pair energies (diagonal, kept, dropped) vs oracle, fp64 and fp32")
+    s, grid, phi = c5["spec"], c5["grid"], c5["phi"]
+    pairs_np = c5["pairs"].cpu().numpy()
+    sample = _sample_pairs(s, pairs_np)
+    orbs = np.unique(sample)
+    local = np.searchsorted(orbs, sample)
+    phi_sub = phi[torch.as_tensor(orbs, device="cuda")].cpu().numpy()
+    v = oracle.coulomb_kernel(s.N, s.L, "erfc", s.omega)
+    ref = oracle.exchange_energy_pairs(phi_sub, local, v, s.dV)
+    dp = torch.as_tensor(sample, device="cuda")
+    e64 = ctx.pair_energies(phi, dp, grid, kernel="erfc", omega=s.omega, precision="fp64").cpu().numpy()
+    e32 = ctx.pair_energies(phi, dp, grid, kernel="erfc", omega=s.omega, precision="fp32").cpu().numpy()
+    scale = np.abs(ref).max()
+    print(f"max |e| {scale:.4e}, fp64 max err {np.abs(e64 - ref).max():.3e}, fp32 {np.abs(e32 - ref).max():.3e}",
+          flush=True)
+    np.testing.assert_allclose(e64, ref, rtol=1e-10, atol=1e-13 * scale)
+    np.testing.assert_allclose(e32, ref, rtol=1e-5, atol=1e-7 * scale)
+
+
+def test_c5_screened_build_energy_identity(ctx, c5):
+    _say("c5 screened build: E_x = sum of kept pair energies, fp64 and fp32")
+    s, grid, phi, pairs = c5["spec"], c5["grid"], c5["phi"], c5["pairs"]
+    e = ctx.pair_energies(phi, pairs, grid, kernel="erfc", omega=s.omega, precision="fp64")
+    esum = float(e.sum().item())
+    for prec, tol in (("fp64", 1e-10), ("fp32", 1e-6)):
+        r = ctx.build(phi, pairs, grid, kernel="erfc", omega=s.omega, precision=prec, want_M=False)
+        ex = r["ex"].item()
+        print(f"{prec}: {pairs.shape[0]} pairs, E_x {ex:.10f}, sum e_ij {esum:.10f}", flush=True)
+        assert abs(ex - esum) <= tol * abs(esum)
+        del r
+        torch.cuda.empty_cache()
