@@ -95,6 +95,13 @@ void launch_colnorm(const double* A, int n, int64_t ng, double* res, hipStream_t
 int qrcp_blocks(int64_t ng);
 void launch_qrcp_update(const double* A, int n, int64_t ng, const double* q, double* res, double* pv, int64_t* pi,
                         const int* stop, hipStream_t s);
+int qrcp_pool_blocks(int P);
+void launch_qrcp_update_r(double* R, int n, int P, const double* q, double* res, double* pv, int64_t* pi,
+                          const int* stop, hipStream_t s);
+void launch_qrcp_select_r(const double* R, int n, int P, int* kdev, const double* pv, const int64_t* pi,
+                          double* Q, double* res, int32_t* piv, double* qout, const int32_t* pool,
+                          const double* t_out, int* stop, hipStream_t s);
+void launch_add_inplace(double* a, const double* b, int64_t cnt, hipStream_t s);
 void launch_qrcp_select(const double* A, int n, int64_t ng, int* kdev, const double* pv, const int64_t* pi,
                         int nblk, double* Q, double* res, int32_t* piv, double* qout, const int32_t* pool,
                         const double* t_out, int* stop, hipStream_t s);

@@ -410,18 +410,17 @@ int ace_localize(ace_ctx* c, const ace_grid* g, int norb, const double* psi, dou
   if (ng < norb) return fail(c, ACE_E_ARG, "grid smaller than the number of orbitals");
   hipStream_t s = c->stream;
   rec_begin(c->R(), ST_LOCALIZE, s);
-  double *res, *norm0, *pv, *Q, *q, *AC, *X, *G, *Z, *dev, *Ub, *pres, *Apool, *tvals, *tmax, *Lc;
+  double *res, *pv, *Q, *q, *AC, *X, *G, *Z, *dev, *Ub, *pres, *Apool, *tvals, *tmax, *Lc;
   int64_t *pi, *pcnt;
   int32_t* pool;
   unsigned* hist;
   int* iv;  // [0] k, [1] stop, [2] pool size
   const int nblk_full = qrcp_blocks(ng);
-  const int pmax = 2048;
+  const int pmax = std::max(2048, 8 * norb);  // candidate pool size
   const int nblk_pool = qrcp_blocks(pmax);
   const int64_t rchunk = std::min<int64_t>(ng, 65536);  // refresh chunk (grid columns)
   const int nbp = pool_blocks(ng);
   WS(c, "res", ng * sizeof(double), res);
-  WS(c, "norm0", ng * sizeof(double), norm0);
   WS(c, "pv", size_t(nblk_full) * 8 * sizeof(double), pv);
   WS(c, "pi", size_t(nblk_full) * 8 * sizeof(int64_t), pi);
   WS(c, "Q", size_t(norb) * norb * sizeof(double), Q);
@@ -441,6 +440,8 @@ int ace_localize(ace_ctx* c, const ace_grid* g, int norb, const double* psi, dou
   WS(c, "tvals", 8 * sizeof(double), tvals);
   WS(c, "ivals", 64, iv);
   WS(c, "Lref", size_t(norb) * rchunk * sizeof(double), Lc);
+  double* Tpool;
+  WS(c, "Tpool", size_t(pmax) * norb * sizeof(double), Tpool);
 
   // Greedy QRCP.  A compact pool of the columns with the largest residual
   // bounds is searched step by step; a pick is certified against t_out, the
@@ -448,20 +449,23 @@ int ace_localize(ace_ctx* c, const ace_grid* g, int norb, const double* psi, dou
   // of all columns are recomputed exactly from the picked directions and a
   // new pool is drawn.  Residual norms only decrease, so every stored bound
   // stays valid until it is recomputed.
-  launch_colnorm(psi, norb, ng, norm0, s);
-  HIPCHK(c, hipMemcpyAsync(res, norm0, ng * sizeof(double), hipMemcpyDeviceToDevice, s));
+  launch_colnorm(psi, norb, ng, res, s);
   HIPCHK(c, hipMemsetAsync(iv, 0, 64, s));
-  const double qbytes_pool = double(norb + 2) * double(pmax) * sizeof(double);
-  int k = 0;
+  // algorithmic bytes of one pool step per pool column: R read and written, residual read and written
+  const double qbytes_pool = double(2 * norb + 2) * sizeof(double);
+  int k = 0, kref = 0;  // kref: directions already folded into res
   for (int refresh = 0; k < norb; ++refresh) {
-    if (k > 0) {
-      // exact bounds: res = |a_r|^2 - |Q_k a_r|^2, then retire the pivots
+    if (k > kref) {
+      // bounds: res = |a_r|^2 - |Q_k a_r|^2, downdated by the directions
+      // picked since the last refresh only; then retire the pivots
       for (int64_t r0 = 0; r0 < ng; r0 += rchunk) {
         const int64_t w = std::min(rchunk, ng - r0);
-        HIPCHK(c, gemm_ls(0, false, false, Q, norb, psi + r0, ng, Lc, w, k, norb, w, 1.0, s, nullptr));
-        launch_refresh_res(Lc, k, w, norm0 + r0, res + r0, s);
+        HIPCHK(c, gemm_ls(0, false, false, Q + size_t(kref) * norb, norb, psi + r0, ng, Lc, w, k - kref, norb, w, 1.0,
+                          s, nullptr));
+        launch_refresh_res(Lc, k - kref, w, res + r0, res + r0, s);
       }
       launch_retire(pivots, k, res, s);
+      kref = k;
     }
     bool use_pool = refresh < 16;
     int np = 0;
@@ -476,18 +480,25 @@ int ace_localize(ace_ctx* c, const ace_grid* g, int norb, const double* psi, dou
     if (use_pool) {
       launch_pool_write(res, ng, tvals, pcnt, pool, pres, s);
       launch_pool_gather(psi, norb, ng, pool, np, Apool, s);
-      launch_qrcp_update(Apool, norb, np, nullptr, pres, pv, pi, iv + 1, s);
+      // the pool holds explicit residual columns R = (I - Q^T Q) A_pool:
+      // project out the k directions already taken, twice for accuracy
+      if (k > 0)
+        for (int pass = 0; pass < 2; ++pass) {
+          HIPCHK(c, gemm_ls(0, false, false, Q, norb, Apool, np, Lc, np, k, norb, np, 1.0, s, nullptr));
+          HIPCHK(c, gemm_ls(0, true, false, Q, norb, Lc, np, Tpool, np, norb, k, np, -1.0, s, nullptr));
+          launch_add_inplace(Apool, Tpool, int64_t(norb) * np, s);
+        }
+      launch_qrcp_update_r(Apool, norb, np, nullptr, pres, pv, pi, iv + 1, s);
       // steps are queued in batches; a batch after a certification failure
       // would only hold no-op launches, so the flag is checked between batches
       for (int kk = k; kk < norb;) {
         const int kend = std::min(norb, kk + 24);
         for (; kk < kend; ++kk) {
-          launch_qrcp_select(Apool, norb, np, iv, pv, pi, qrcp_blocks(np), Q, pres, pivots, q, pool, tvals + 1,
-                             iv + 1, s);
+          launch_qrcp_select_r(Apool, norb, np, iv, pv, pi, Q, pres, pivots, q, pool, tvals + 1, iv + 1, s);
           if (kk + 1 < norb) {
             rec_begin(c->R(), KC_QRCP, s);
-            launch_qrcp_update(Apool, norb, np, q, pres, pv, pi, iv + 1, s);
-            rec_end(c->R(), KC_QRCP, s, qbytes_pool * double(np) / double(pmax));
+            launch_qrcp_update_r(Apool, norb, np, q, pres, pv, pi, iv + 1, s);
+            rec_end(c->R(), KC_QRCP, s, qbytes_pool * double(np));
           }
         }
         if (kk < norb) {

@@ -355,6 +355,171 @@ __global__ __launch_bounds__(NT) void k_qrcp_select(const double* __restrict__ A
   if (threadIdx.x == 0) *kdev = k + 1;
 }
 
+// ---------------------------------------------------------------- pool steps on explicit residuals
+// On a candidate pool the residual columns are kept explicitly,
+// R = (I - Q^T Q) A_pool ([n][P], row-major), so every step's norms are exact
+// and no re-ranking against Q is needed: with the new direction q,
+// l_c = q . R[:,c], R[:,c] -= q l_c, res_c = |R[:,c]|^2.
+
+// Best (value, index) of the block, ties to the smaller index; result in
+// out[0], idx_out[0] (shared) for every thread after the call.
+template <int NT>
+__device__ void block_top1(double v, int64_t idx, double* outv, int64_t* outi) {
+  __shared__ double sv[NT / 64];
+  __shared__ int64_t si[NT / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_down(v, off, 64);
+    const int64_t oi = __shfl_down(idx, off, 64);
+    if (ranks_before(ov, oi, v, idx)) { v = ov; idx = oi; }
+  }
+  if (lane == 0) { sv[wv] = v; si[wv] = idx; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double bv = sv[0];
+    int64_t bi = si[0];
+    for (int w = 1; w < NT / 64; ++w)
+      if (ranks_before(sv[w], si[w], bv, bi)) { bv = sv[w]; bi = si[w]; }
+    *outv = bv;
+    *outi = bi;
+  }
+  __syncthreads();
+}
+
+// One update of the pool residuals (q == nullptr: only the norms).  A block
+// covers 64 columns with NT/64 row groups; partial sums meet in LDS in a fixed
+// order.  Retired columns (res = -1) are skipped.  Writes the block's best
+// live column to pv[blockIdx.x], pi[blockIdx.x].
+template <int NT>
+__global__ __launch_bounds__(NT) void k_qrcp_update_r(double* __restrict__ R, int n, int P,
+                                                      const double* __restrict__ q, double* __restrict__ res,
+                                                      double* __restrict__ pv, int64_t* __restrict__ pi,
+                                                      const int* __restrict__ stop) {
+  if (*stop) return;
+  constexpr int CW = 64, RG = NT / CW;
+  __shared__ double qs[1024];
+  __shared__ double red[RG][CW];
+  __shared__ double bv;
+  __shared__ int64_t bi;
+  const int lane = threadIdx.x % CW, g = threadIdx.x / CW;
+  const int c = blockIdx.x * CW + lane;
+  const bool upd = q != nullptr;
+  if (upd)
+    for (int i = threadIdx.x; i < n; i += NT) qs[i] = q[i];
+  const bool live = c < P && res[c] > -0.5;
+  __syncthreads();
+  double l = 0.0;
+  if (upd) {
+    if (live)
+      for (int i = g; i < n; i += RG) l += qs[i] * R[int64_t(i) * P + c];
+    red[g][lane] = l;
+    __syncthreads();
+    l = 0.0;
+#pragma unroll
+    for (int h = 0; h < RG; ++h) l += red[h][lane];
+    __syncthreads();
+  }
+  double v = 0.0;
+  if (live)
+    for (int i = g; i < n; i += RG) {
+      double x = R[int64_t(i) * P + c];
+      if (upd) {
+        x -= qs[i] * l;
+        R[int64_t(i) * P + c] = x;
+      }
+      v += x * x;
+    }
+  red[g][lane] = v;
+  __syncthreads();
+  double cand = -INFINITY;
+  int64_t cidx = INT64_MAX;
+  if (g == 0) {
+    v = 0.0;
+#pragma unroll
+    for (int h = 0; h < RG; ++h) v += red[h][lane];
+    if (live) {
+      res[c] = v;
+      cand = v;
+      cidx = c;
+    }
+  }
+  block_top1<NT>(cand, cidx, &bv, &bi);
+  if (threadIdx.x == 0) {
+    pv[blockIdx.x] = bv;
+    pi[blockIdx.x] = bi;
+  }
+}
+
+// Selection on the pool (single workgroup): the best block candidate is the
+// best live column; its norm is recomputed, certified against t_out (an upper
+// bound of every residual outside the pool), and q_k = R[:,b] / |R[:,b]| is
+// appended to Q.  A failed certification or an exhausted pool raises the
+// stop flag, after which the queued steps are no-ops.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_qrcp_select_r(const double* __restrict__ R, int n, int P,
+                                                      int* __restrict__ kdev, const double* __restrict__ pv,
+                                                      const int64_t* __restrict__ pi, int nblk,
+                                                      double* __restrict__ Q, double* __restrict__ res,
+                                                      int32_t* __restrict__ piv, double* __restrict__ qout,
+                                                      const int32_t* __restrict__ pool,
+                                                      const double* __restrict__ t_out, int* __restrict__ stop) {
+  if (*stop) return;
+  __shared__ double bv;
+  __shared__ int64_t bi;
+  __shared__ double r2s[NT / 64];
+  __shared__ int accept;
+  const int k = *kdev;
+  {
+    double v = -INFINITY;
+    int64_t idx = INT64_MAX;
+    for (int e = threadIdx.x; e < nblk; e += NT)
+      if (ranks_before(pv[e], pi[e], v, idx)) { v = pv[e]; idx = pi[e]; }
+    block_top1<NT>(v, idx, &bv, &bi);
+  }
+  const int64_t b = bi;
+  if (b < 0 || b >= P) {
+    if (threadIdx.x == 0) *stop = 1;
+    return;
+  }
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += NT) {
+    const double x = R[int64_t(i) * P + b];
+    v += x * x;
+  }
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  if ((threadIdx.x & 63) == 0) r2s[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r2 = 0.0;
+    for (int w = 0; w < NT / 64; ++w) r2 += r2s[w];
+    r2s[0] = r2;
+    const bool ok = r2 > 0.0 && (t_out == nullptr || r2 >= *t_out);
+    accept = ok ? 1 : 0;
+    if (ok) {
+      piv[k] = pool[b];
+      res[b] = -1.0;
+    } else {
+      *stop = 1;
+    }
+  }
+  __syncthreads();
+  if (!accept) return;
+  const double inv = 1.0 / sqrt(r2s[0]);
+  for (int i = threadIdx.x; i < n; i += NT) {
+    const double x = R[int64_t(i) * P + b] * inv;
+    Q[int64_t(k) * n + i] = x;
+    qout[i] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *kdev = k + 1;
+}
+
+// a += b (elementwise)
+__global__ void k_add_inplace(double* __restrict__ a, const double* __restrict__ b, int64_t cnt) {
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < cnt; e += int64_t(gridDim.x) * blockDim.x)
+    a[e] += b[e];
+}
+
 // ---------------------------------------------------------------- candidate pool
 // The pool holds every column whose residual bound is at least a threshold t
 // picked from a histogram of the top 14 bits of the (positive) residuals, so
@@ -523,10 +688,10 @@ __global__ void k_pool_gather(const double* __restrict__ A, int n, int64_t ng, c
   }
 }
 
-// Residual bounds from scratch: res[r] = norm0[r] - sum_m L[m][r]^2 over the
-// k projections L = Q A of a chunk of columns (L is [k][rc]).
-__global__ void k_refresh_res(const double* __restrict__ L, int k, int64_t rc, const double* __restrict__ norm0,
-                              double* __restrict__ res) {
+// Residual bounds: res[r] = base[r] - sum_m L[m][r]^2 over the projections
+// L = Q A of a chunk of columns onto k directions (L is [k][rc]).  base may
+// be res itself (each element is read before it is written).
+__global__ void k_refresh_res(const double* __restrict__ L, int k, int64_t rc, const double* norm0, double* res) {
   for (int64_t r = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; r < rc; r += int64_t(gridDim.x) * blockDim.x) {
     double s = norm0[r];
     for (int m = 0; m < k; ++m) {
@@ -704,6 +869,20 @@ void launch_qrcp_select(const double* A, int n, int64_t ng, int* kdev, const dou
                         const double* t_out, int* stop, hipStream_t s) {
   hipLaunchKernelGGL(k_qrcp_select<512>, dim3(1), dim3(512), 0, s, A, n, ng, kdev, pv, pi, nblk, Q, res, piv, qout,
                      pool, t_out, stop);
+}
+int qrcp_pool_blocks(int P) { return (P + 63) / 64; }
+void launch_qrcp_update_r(double* R, int n, int P, const double* q, double* res, double* pv, int64_t* pi,
+                          const int* stop, hipStream_t s) {
+  hipLaunchKernelGGL(k_qrcp_update_r<256>, dim3(qrcp_pool_blocks(P)), dim3(256), 0, s, R, n, P, q, res, pv, pi, stop);
+}
+void launch_qrcp_select_r(const double* R, int n, int P, int* kdev, const double* pv, const int64_t* pi,
+                          double* Q, double* res, int32_t* piv, double* qout, const int32_t* pool,
+                          const double* t_out, int* stop, hipStream_t s) {
+  hipLaunchKernelGGL(k_qrcp_select_r<256>, dim3(1), dim3(256), 0, s, R, n, P, kdev, pv, pi, qrcp_pool_blocks(P), Q,
+                     res, piv, qout, pool, t_out, stop);
+}
+void launch_add_inplace(double* a, const double* b, int64_t cnt, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_inplace, dim3(grid_for(cnt, 256)), dim3(256), 0, s, a, b, cnt);
 }
 int pool_blocks(int64_t ng) { return grid_for(ng, 4096, 2048); }
 void launch_pool_build(const double* res, int64_t ng, int pmax, unsigned* hist, double* t, int64_t* cnt,
