@@ -49,10 +49,11 @@ def parse():
     ap.add_argument("--screener", default=os.path.join(ROOT, "paper_2101_03155_amd", "models",
                                                        "screener_water_erfc.npz"))
     ap.add_argument("--skip-forms", default="", help="comma list of precision,batched,learned")
-    ap.add_argument("--shape", default="split", choices=["auto", "default", "fused", "split"],
-                    help="pair-stage launch shape: autotuned, library default, or forced (default: split, the "
-                         "tuner's pick for this workload, fixed so that profiles and the bench line agree)")
-    ap.add_argument("--max-packs", type=int, default=16, help="packs per pair-stage launch for a forced shape")
+    ap.add_argument("--shape", default="r2c", choices=["auto", "default", "fused", "split", "r2c"],
+                    help="pair-stage launch shape: autotuned, library default, or forced (default: r2c with 32 "
+                         "packs per launch, the fastest measured for this workload, fixed so that profiles and "
+                         "the bench line agree)")
+    ap.add_argument("--max-packs", type=int, default=32, help="packs per pair-stage launch for a forced shape")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB three times (calibrates FETCH_SIZE / WRITE_SIZE counters) and exit")
     return ap.parse_args()
@@ -306,8 +307,8 @@ def main():
         pairs0, _ = ctx.pairlist(phi0, grid, args.rho_cut)
         tuned = autotune(ctx, phi0, pairs0, grid, kind, omega, prec)
         del phi0, pairs0
-    elif args.shape in ("fused", "split"):
-        ctx.set_pair_shape(prec, spec.N, args.shape == "fused", args.max_packs)
+    elif args.shape in ("fused", "split", "r2c"):
+        ctx.set_pair_shape(prec, spec.N, args.shape, args.max_packs)
     shape = ctx.get_pair_shape(prec, spec.N)
 
     for _ in range(args.warmup):
@@ -343,11 +344,12 @@ def main():
         peak = HBM_PEAK_GBS
         achieved = units / (ms_l / 1000.0) / 1e9
         roof = {"bound": "hbm", "unit": "GB/s"}
-    roof.update({"kernel": CLASS_KERNEL[dom], "class": CLASS_NAMES[dom], "launches_per_step": n_l / args.steps,
+    kname = CLASS_KERNEL[dom] + ("_r" if shape[0] == "r2c" and dom in (0, 1, 2) else "")
+    roof.update({"kernel": kname, "class": CLASS_NAMES[dom], "launches_per_step": n_l / args.steps,
                  "avg_launch_us": 1000.0 * ms_l / max(n_l, 1),
                  "algorithmic_per_launch": units / max(n_l, 1),
                  "achieved": round(achieved, 2), "peak": peak, "frac": round(achieved / peak, 4)})
-    traffic, note = (measured_traffic(CLASS_KERNEL[dom], spec.N, prec, units / max(n_l, 1)) if dom < 7
+    traffic, note = (measured_traffic(kname, spec.N, prec, units / max(n_l, 1)) if dom < 7
                      else (None, "not an HBM-bound class"))
     roof["traffic"] = round(traffic) if traffic is not None else None
     roof["traffic_note"] = note
@@ -367,7 +369,7 @@ def main():
         "pair_solves_per_s": round(pair_solves, 1),
         "stage_ms": {k: round(v, 3) for k, v in stage_ms.items()},
         "ex_hartree": ex,
-        "pair_shape": {"fused": shape[0], "max_packs": shape[1],
+        "pair_shape": {"path": shape[0], "max_packs": shape[1],
                        "tune_table": tuned["table"] if tuned else None},
         "roofline": roof,
         "kernels": kernels,

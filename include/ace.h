@@ -163,9 +163,16 @@ int ace_profile_enable(ace_ctx* ctx, int enable);
 int ace_profile_read(ace_ctx* ctx, int cls, int64_t* launches, double* total_ms, double* units, int reset);
 
 /*
- * Pair-stage launch shape for one (precision, grid size): fused = 1 transforms
- * each z-plane in one workgroup (when it fits in LDS), 0 uses separate x and
- * y passes; max_packs caps the packs per launch.  Set by the autotuner.
+ * Pair-stage launch shape for one (precision, grid size), set by the autotuner:
+ *   fused = 0  separate x, y and z passes over the complex field of a pack of
+ *              two pairs (16 N^3 s algorithmic bytes per pair);
+ *   fused = 1  one workgroup per (z-plane, pack) does both in-plane FFTs with
+ *              the plane in LDS (12 N^3 s per pair);
+ *   fused = 2  real-to-complex: one workgroup per (z-plane, pair) on the half
+ *              spectrum N x N x (N/2 + 1) (12 N^3 s per pair, half the LDS).
+ * A path whose plane does not fit in LDS for this size falls back to 0.
+ * max_packs (>= 1) caps the packs per launch.  Results agree between paths to
+ * rounding.
  */
 int ace_set_pair_shape(ace_ctx* ctx, int prec, int n, int fused, int max_packs);
 int ace_get_pair_shape(ace_ctx* ctx, int prec, int n, int* fused, int* max_packs);

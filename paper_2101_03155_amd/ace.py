@@ -22,6 +22,8 @@ STATUS = {0: "ACE_OK", -1: "ACE_E_ARG", -2: "ACE_E_HIP", -3: "ACE_E_NOMEM", -4: 
           -5: "ACE_E_CAPACITY", -6: "ACE_E_NONFINITE", -7: "ACE_E_UNSUPPORTED"}
 KERNELS = {"bare": 0, "coulomb": 0, "erfc": 1}
 PRECISIONS = {"fp64": 0, "fp32": 1}
+PAIR_PATHS = {"split": 0, "fused": 1, "r2c": 2}
+PAIR_PATH_NAMES = {v: k for k, v in PAIR_PATHS.items()}
 
 # profile classes (see include/ace.h)
 KC_FWD_XY, KC_CONV_Z, KC_INV_XY = 0, 1, 2
@@ -280,14 +282,18 @@ class Context:
         self._check(self.lib.ace_profile_read(self.h, cls, C.byref(n), C.byref(ms), C.byref(u), 1 if reset else 0))
         return n.value, ms.value, u.value
 
-    def set_pair_shape(self, precision: str, n: int, fused: bool, max_packs: int):
-        self._check(self.lib.ace_set_pair_shape(self.h, PRECISIONS[precision], n, 1 if fused else 0, max_packs))
+    def set_pair_shape(self, precision: str, n: int, path, max_packs: int):
+        """path: "split" (or False/0), "fused" (True/1) or "r2c" (2); a path that
+        does not fit the grid size falls back to the split passes."""
+        code = PAIR_PATHS[path] if isinstance(path, str) else int(path)
+        self._check(self.lib.ace_set_pair_shape(self.h, PRECISIONS[precision], n, code, max_packs))
 
     def get_pair_shape(self, precision: str, n: int):
+        """(path name, max_packs) in effect for this precision and grid size."""
         f = C.c_int()
         m = C.c_int()
         self._check(self.lib.ace_get_pair_shape(self.h, PRECISIONS[precision], n, C.byref(f), C.byref(m)))
-        return bool(f.value), m.value
+        return PAIR_PATH_NAMES[f.value], m.value
 
     def build_batched(self, systems, precision: str = "fp32", mode: str = "graph", want_M: bool = True,
                       raise_on_not_pd: bool = True):

@@ -46,7 +46,8 @@ struct BRound {                // one segment: the packs of one grid size in one
 
 // Kernel launch shape of the pair stage, chosen by the tuner.
 struct PairShape {
-  int fused_xy;    // 1: one workgroup per (plane, pack) does both in-plane FFTs
+  int fused_xy;    // 0: split passes; 1: one workgroup per (plane, pack) does both in-plane FFTs;
+                   // 2: real-to-complex, one workgroup per (plane, pair) on the half spectrum
   int nt_xy;       // threads of the in-plane kernels (fused path)
   int tx;          // x-tile of the strided line kernels
 };
@@ -78,6 +79,8 @@ hipError_t pair_round(int prec, int N, const PairShape& sh, const void* phi, voi
                       const void* tw, const KernelParams& kp, hipStream_t s, EventRecorder* rec);
 int pair_energy_blocks(int N, const PairShape& sh);
 bool pair_supported(int N);
+bool pair_r2c_fits(int prec, int N);
+size_t pair_spec_elems(int prec, int N, const PairShape& sh);
 
 // Dense kernels (gemm.hip, linalg.hip).
 // op: 0 A B^T, 1 |A| |B|^T, 2 (A.A)(B.B)^T  (FP64 only for op != 0)

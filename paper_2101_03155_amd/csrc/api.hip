@@ -384,7 +384,7 @@ int ace_set_pair_shape(ace_ctx* c, int prec, int n, int fused, int max_packs) {
   if (!c || (prec != 0 && prec != 1) || !pair_supported(n) || max_packs < 1)
     return fail(c, ACE_E_ARG, "bad pair shape");
   PairShape sh = pair_default_shape(prec, n);
-  sh.fused_xy = (fused && pair_fused_fits(prec, n)) ? 1 : 0;
+  sh.fused_xy = (fused == 2 && pair_r2c_fits(prec, n)) ? 2 : (fused && pair_fused_fits(prec, n)) ? 1 : 0;
   c->shapes[n * 2 + prec] = sh;
   c->max_packs[n * 2 + prec] = max_packs;
   c->schedules.clear();
@@ -421,8 +421,10 @@ int ace_localize(ace_ctx* c, const ace_grid* g, int norb, const double* psi, dou
   const int64_t rchunk = std::min<int64_t>(ng, 65536);  // refresh chunk (grid columns)
   const int nbp = pool_blocks(ng);
   WS(c, "res", ng * sizeof(double), res);
-  WS(c, "pv", size_t(nblk_full) * 8 * sizeof(double), pv);
-  WS(c, "pi", size_t(nblk_full) * 8 * sizeof(int64_t), pi);
+  // block candidates: 8 per block of the full sweep, 1 per block of the pool steps
+  const size_t ncand = std::max<size_t>(size_t(nblk_full) * 8, size_t(qrcp_pool_blocks(pmax)));
+  WS(c, "pv", ncand * sizeof(double), pv);
+  WS(c, "pi", ncand * sizeof(int64_t), pi);
   WS(c, "Q", size_t(norb) * norb * sizeof(double), Q);
   WS(c, "q", size_t(norb) * sizeof(double), q);
   WS(c, "AC", size_t(norb) * norb * sizeof(double), AC);
@@ -663,7 +665,7 @@ static int build_impl(ace_ctx* c, const ace_grid* g, int norb, const double* phi
   int* info;
   if (xi) WS(c, "W", size_t(norb) * ng * es, W);
   else W = nullptr;
-  WS(c, "spec", size_t(S.max_launch) * ng * 2 * es, spec);
+  WS(c, "spec", size_t(S.max_launch) * pair_spec_elems(prec, N, sh) * 2 * es, spec);
   WS(c, "packs", size_t(npk) * sizeof(Pack), dpk);
   WS(c, "pidx", size_t(npk) * 2 * sizeof(int64_t), dpidx);
   if (pair_energy) WS(c, "epart", size_t(S.max_launch) * nblk * 2 * sizeof(double), epart);

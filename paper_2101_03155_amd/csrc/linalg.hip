@@ -387,16 +387,17 @@ __device__ void block_top1(double v, int64_t idx, double* outv, int64_t* outi) {
 }
 
 // One update of the pool residuals (q == nullptr: only the norms).  A block
-// covers 64 columns with NT/64 row groups; partial sums meet in LDS in a fixed
-// order.  Retired columns (res = -1) are skipped.  Writes the block's best
-// live column to pv[blockIdx.x], pi[blockIdx.x].
-template <int NT>
+// covers CW columns with NT/CW row groups (a wave reads CW-column row
+// segments); partial sums meet in LDS in a fixed order.  Retired columns
+// (res = -1) are skipped.  Writes the block's best live column to
+// pv[blockIdx.x], pi[blockIdx.x].
+template <int NT, int CW>
 __global__ __launch_bounds__(NT) void k_qrcp_update_r(double* __restrict__ R, int n, int P,
                                                       const double* __restrict__ q, double* __restrict__ res,
                                                       double* __restrict__ pv, int64_t* __restrict__ pi,
                                                       const int* __restrict__ stop) {
   if (*stop) return;
-  constexpr int CW = 64, RG = NT / CW;
+  constexpr int RG = NT / CW;
   __shared__ double qs[1024];
   __shared__ double red[RG][CW];
   __shared__ double bv;
@@ -408,10 +409,21 @@ __global__ __launch_bounds__(NT) void k_qrcp_update_r(double* __restrict__ R, in
     for (int i = threadIdx.x; i < n; i += NT) qs[i] = q[i];
   const bool live = c < P && res[c] > -0.5;
   __syncthreads();
+  double* col = R + c;
   double l = 0.0;
   if (upd) {
-    if (live)
-      for (int i = g; i < n; i += RG) l += qs[i] * R[int64_t(i) * P + c];
+    if (live) {
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int i = g;
+      for (; i + 3 * RG < n; i += 4 * RG) {
+        a0 += qs[i] * col[int64_t(i) * P];
+        a1 += qs[i + RG] * col[int64_t(i + RG) * P];
+        a2 += qs[i + 2 * RG] * col[int64_t(i + 2 * RG) * P];
+        a3 += qs[i + 3 * RG] * col[int64_t(i + 3 * RG) * P];
+      }
+      for (; i < n; i += RG) a0 += qs[i] * col[int64_t(i) * P];
+      l = (a0 + a1) + (a2 + a3);
+    }
     red[g][lane] = l;
     __syncthreads();
     l = 0.0;
@@ -420,15 +432,30 @@ __global__ __launch_bounds__(NT) void k_qrcp_update_r(double* __restrict__ R, in
     __syncthreads();
   }
   double v = 0.0;
-  if (live)
-    for (int i = g; i < n; i += RG) {
-      double x = R[int64_t(i) * P + c];
+  if (live) {
+    double v0 = 0.0, v1 = 0.0;
+    int i = g;
+    for (; i + RG < n; i += 2 * RG) {
+      double x0 = col[int64_t(i) * P], x1 = col[int64_t(i + RG) * P];
+      if (upd) {
+        x0 -= qs[i] * l;
+        x1 -= qs[i + RG] * l;
+        col[int64_t(i) * P] = x0;
+        col[int64_t(i + RG) * P] = x1;
+      }
+      v0 += x0 * x0;
+      v1 += x1 * x1;
+    }
+    for (; i < n; i += RG) {
+      double x = col[int64_t(i) * P];
       if (upd) {
         x -= qs[i] * l;
-        R[int64_t(i) * P + c] = x;
+        col[int64_t(i) * P] = x;
       }
-      v += x * x;
+      v0 += x * x;
     }
+    v = v0 + v1;
+  }
   red[g][lane] = v;
   __syncthreads();
   double cand = -INFINITY;
@@ -870,10 +897,11 @@ void launch_qrcp_select(const double* A, int n, int64_t ng, int* kdev, const dou
   hipLaunchKernelGGL(k_qrcp_select<512>, dim3(1), dim3(512), 0, s, A, n, ng, kdev, pv, pi, nblk, Q, res, piv, qout,
                      pool, t_out, stop);
 }
-int qrcp_pool_blocks(int P) { return (P + 63) / 64; }
+constexpr int QCW = 16;  // pool columns per update block
+int qrcp_pool_blocks(int P) { return (P + QCW - 1) / QCW; }
 void launch_qrcp_update_r(double* R, int n, int P, const double* q, double* res, double* pv, int64_t* pi,
                           const int* stop, hipStream_t s) {
-  hipLaunchKernelGGL(k_qrcp_update_r<256>, dim3(qrcp_pool_blocks(P)), dim3(256), 0, s, R, n, P, q, res, pv, pi, stop);
+  hipLaunchKernelGGL((k_qrcp_update_r<256, QCW>), dim3(qrcp_pool_blocks(P)), dim3(256), 0, s, R, n, P, q, res, pv, pi, stop);
 }
 void launch_qrcp_select_r(const double* R, int n, int P, int* kdev, const double* pv, const int64_t* pi,
                           double* Q, double* res, int32_t* piv, double* qout, const int32_t* pool,

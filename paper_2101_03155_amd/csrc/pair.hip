@@ -145,6 +145,71 @@ __global__ __launch_bounds__(NT) void k_inv_x(const T* __restrict__ phi, const c
                                  threadIdx.x);
 }
 
+
+// ------------------------------------------------------------ real-to-complex path
+// One pair per workgroup: blockIdx.y = 2 * pack + (0: pair a, 1: pair b); the
+// spectrum of slot y is N * N * XS complex values at spec + y * N * N * XS.
+
+template <typename T, int N>
+constexpr bool r2c_fits_t() {
+  return (size_t(N) * r2c_xs<N>() + N) * sizeof(cplx<T>) + 1024 <= 163840;
+}
+
+template <typename T, int N, int NT>
+__global__ __launch_bounds__(NT) void k_fwd_xy_r(const T* __restrict__ phi, cplx<T>* __restrict__ spec,
+                                                 const Pack* __restrict__ packs,
+                                                 const cplx<T>* __restrict__ twg) {
+  using C = cplx<T>;
+  constexpr int XS = r2c_xs<N>();
+  constexpr size_t NG = size_t(N) * N * N, PL = size_t(N) * XS;
+  __shared__ C buf[N * XS];
+  __shared__ C tw[N];
+  const int tid = threadIdx.x, z = blockIdx.x, slot = blockIdx.y;
+  const Pack pk = packs[slot >> 1];
+  const int i = (slot & 1) ? pk.ib : pk.ia, j = (slot & 1) ? pk.jb : pk.ja;
+  if (j < 0) return;
+  for (int t = tid; t < N; t += NT) tw[t] = twg[t];
+  const size_t zo = size_t(z) * N * N;
+  body_fwd_xy_r<T, N, NT>(phi + size_t(i) * NG + zo, phi + size_t(j) * NG + zo,
+                          spec + size_t(slot) * N * PL + size_t(z) * PL, buf, tw, tid);
+}
+
+template <typename T, int N, int TX, int NT>
+__global__ __launch_bounds__(NT) void k_conv_z_r(cplx<T>* __restrict__ spec, const Pack* __restrict__ packs,
+                                                 const cplx<T>* __restrict__ twg, KernelParams kp) {
+  constexpr size_t PL = size_t(N) * r2c_xs<N>();
+  __shared__ cplx<T> buf[N * TX];
+  __shared__ cplx<T> tw[N];
+  const int slot = blockIdx.y;
+  if ((slot & 1) && packs[slot >> 1].jb < 0) return;
+  for (int t = threadIdx.x; t < N; t += NT) tw[t] = twg[t];
+  body_conv_z_r<T, N, TX, NT>(spec + size_t(slot) * N * PL, blockIdx.x * TX, kp, buf, tw, threadIdx.x);
+}
+
+template <typename T, int N, int NT, bool EN>
+__global__ __launch_bounds__(NT) void k_inv_xy_r(const T* __restrict__ phi, const cplx<T>* __restrict__ spec,
+                                                 const Pack* __restrict__ packs, T* __restrict__ W,
+                                                 double* __restrict__ epart,
+                                                 const cplx<T>* __restrict__ twg) {
+  using C = cplx<T>;
+  constexpr int XS = r2c_xs<N>();
+  constexpr size_t NG = size_t(N) * N * N, PL = size_t(N) * XS;
+  __shared__ C buf[N * XS];
+  __shared__ C tw[N];
+  __shared__ double red[NT / 64];
+  const int tid = threadIdx.x, z = blockIdx.x, slot = blockIdx.y;
+  const Pack pk = packs[slot >> 1];
+  const int i = (slot & 1) ? pk.ib : pk.ia, j = (slot & 1) ? pk.jb : pk.ja;
+  if (j < 0) return;
+  for (int t = tid; t < N; t += NT) tw[t] = twg[t];
+  body_inv_xy_r<T, N, NT>(spec + size_t(slot) * N * PL + size_t(z) * PL, buf, tw, tid);
+  const size_t zo = size_t(z) * N * N;
+  T* wi = W ? W + size_t(i) * NG + zo : nullptr;
+  T* wj = W ? W + size_t(j) * NG + zo : nullptr;
+  accumulate_w_r<T, N, NT, EN>(phi + size_t(i) * NG + zo, phi + size_t(j) * NG + zo, wi, wj, i != j,
+                               EN ? epart + 2 * (size_t(slot >> 1) * N + z) + (slot & 1) : nullptr, buf, red, tid);
+}
+
 // ------------------------------------------------------------ dispatch
 
 template <typename T, int N>
@@ -163,6 +228,28 @@ static hipError_t pair_round_t(const PairShape& sh, const void* phi_, void* spec
   // read phi_i, phi_j (2) + spectrum write (1) | spectrum read + write (2) |
   // spectrum read (1) + phi re-read (2) + W_i, W_j read-modify-write (4)
   const double u = double(npairs) * double(N) * N * N * sizeof(T);
+  if constexpr (r2c_fits_t<T, N>()) {
+    if (sh.fused_xy == 2) {
+      constexpr int NTR = 512;
+      constexpr int TXR = r2c_tx<N>();
+      rec_begin(rec, KC_FWD_XY, s);
+      hipLaunchKernelGGL((k_fwd_xy_r<T, N, NTR>), dim3(N, 2 * npacks), dim3(NTR), 0, s, phi, spec, packs, tw);
+      rec_end(rec, KC_FWD_XY, s, 3 * u);
+      rec_begin(rec, KC_CONV_Z, s);
+      hipLaunchKernelGGL((k_conv_z_r<T, N, TXR, NTL>), dim3(N * r2c_xs<N>() / TXR, 2 * npacks), dim3(NTL), 0, s, spec,
+                         packs, tw, kp);
+      rec_end(rec, KC_CONV_Z, s, 2 * u);
+      rec_begin(rec, KC_INV_XY, s);
+      if (epart)
+        hipLaunchKernelGGL((k_inv_xy_r<T, N, NTR, true>), dim3(N, 2 * npacks), dim3(NTR), 0, s, phi, spec, packs, W,
+                           epart, tw);
+      else
+        hipLaunchKernelGGL((k_inv_xy_r<T, N, NTR, false>), dim3(N, 2 * npacks), dim3(NTR), 0, s, phi, spec, packs, W,
+                           epart, tw);
+      rec_end(rec, KC_INV_XY, s, 7 * u);
+      return hipGetLastError();
+    }
+  }
   if constexpr (fused_fits_t<T, N>()) {
     if (sh.fused_xy) {
       constexpr int NTP = 512;
@@ -215,6 +302,21 @@ bool pair_supported(int N) {
   }
 }
 
+bool pair_r2c_fits(int prec, int N) {
+  switch (N) {
+#define X(n) case n: return prec == 0 ? r2c_fits_t<double, n>() : r2c_fits_t<float, n>();
+    ACE_PAIR_SIZES(X)
+#undef X
+    default: return false;
+  }
+}
+
+// Complex spectrum elements per pack (two pairs) for a launch shape.
+size_t pair_spec_elems(int prec, int N, const PairShape& sh) {
+  if (sh.fused_xy == 2 && pair_r2c_fits(prec, N)) return 2 * size_t(N) * N * (N / 2 + 1);
+  return size_t(N) * N * N;
+}
+
 bool pair_fused_fits(int prec, int N) {
   switch (N) {
 #define X(n) case n: return prec == 0 ? fused_fits_t<double, n>() : fused_fits_t<float, n>();
@@ -224,9 +326,26 @@ bool pair_fused_fits(int prec, int N) {
   }
 }
 
+// The real-to-complex path is the default where two of its planes fit in one
+// CU's LDS (two workgroups per CU hide the HBM latency of each other's
+// loads); elsewhere the split passes are.
+template <typename T, int N>
+constexpr bool r2c_two_per_cu_t() {
+  return 2 * ((size_t(N) * r2c_xs<N>() + N) * sizeof(cplx<T>) + 1024) <= 163840;
+}
+
+static bool pair_r2c_preferred(int prec, int N) {
+  switch (N) {
+#define X(n) case n: return prec == 0 ? r2c_two_per_cu_t<double, n>() : r2c_two_per_cu_t<float, n>();
+    ACE_PAIR_SIZES(X)
+#undef X
+    default: return false;
+  }
+}
+
 PairShape pair_default_shape(int prec, int N) {
   PairShape sh;
-  sh.fused_xy = pair_fused_fits(prec, N) ? 1 : 0;
+  sh.fused_xy = pair_r2c_preferred(prec, N) ? 2 : 0;
   sh.nt_xy = 512;
   sh.tx = pick_tx(N);
   return sh;
@@ -241,7 +360,8 @@ hipError_t pair_round(int prec, int N, const PairShape& sh, const void* phi, voi
                       const Pack* packs, int npacks, int npairs, void* W, double* epart, const void* tw,
                       const KernelParams& kp, hipStream_t s, EventRecorder* rec) {
   PairShape use = sh;
-  if (!pair_fused_fits(prec, N)) use.fused_xy = 0;
+  if ((use.fused_xy == 1 && !pair_fused_fits(prec, N)) || (use.fused_xy == 2 && !pair_r2c_fits(prec, N)))
+    use.fused_xy = 0;
   switch (N) {
 #define X(n)                                                                                          \
   case n:                                                                                             \

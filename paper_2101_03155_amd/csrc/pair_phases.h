@@ -166,4 +166,181 @@ __device__ __forceinline__ void body_inv_x(const T* __restrict__ phi, const cplx
   accumulate_w<T, NT, EN>(phi, pk, NG, ro, E, W, eslot, buf, red, tid);
 }
 
+
+// ------------------------------------------------------------ real-to-complex path
+// One orbital pair per workgroup and z-plane.  The x transform of the real
+// pair density uses the two-for-one trick: rows y and y + N/2 form one
+// complex line Z, and after its FFT the two half spectra are separated as
+// X1[k] = (Z[k] + conj Z[N-k]) / 2, X2[k] = (Z[k] - conj Z[N-k]) / 2i for
+// 0 <= k <= N/2.  The plane then holds N rows of XS = N/2 + 1 complex values
+// (the non-negative x frequencies; the others follow by Hermitian symmetry)
+// and the y and z transforms act on those columns only.  The spectrum of a
+// pair is [z][y][kx], N * N * XS complex values, and the z pass runs over
+// tiles of consecutive (y, kx) columns of the flattened planes.
+
+template <int N> __host__ __device__ constexpr int r2c_xs() { return N / 2 + 1; }
+template <int N> __host__ __device__ constexpr int r2c_tx() {
+  return (N * r2c_xs<N>()) % 16 == 0 ? 16 : (N * r2c_xs<N>()) % 8 == 0 ? 8 : (N * r2c_xs<N>()) % 4 == 0 ? 4 : 2;
+}
+
+// Pair density of plane z (phi_i, phi_j point at the plane) -> its half
+// spectrum after the x and y transforms, stored to out (N * XS values).
+template <typename T, int N, int NT, int V = 0>
+__device__ __forceinline__ void body_fwd_xy_r(const T* __restrict__ pi_, const T* __restrict__ pj_, cplx<T>* out,
+                                              cplx<T>* buf, const cplx<T>* tw, int tid) {
+  using C = cplx<T>;
+  constexpr int H = N / 2, XS = r2c_xs<N>();
+  constexpr int HN = H * N;
+  for (int e = tid; e < HN; e += NT) {
+    C v;
+    v.x = pi_[e] * pj_[e];
+    v.y = pi_[e + HN] * pj_[e + HN];
+    buf[e] = v;
+  }
+  __syncthreads();
+  fft_lines<T, N, H, N, 1, NT, -1, true, V>(buf, tw, tid);
+  // separate the two half spectra; all reads before the barrier, all writes after
+  constexpr int ITEMS = H * XS;
+  constexpr int PER = (ITEMS + NT - 1) / NT;
+  C a[PER], b[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int it = tid + q * NT;
+    if (ITEMS % NT == 0 || it < ITEMS) {
+      const int l = it / XS, k = it % XS;
+      a[q] = buf[l * N + k];
+      b[q] = buf[l * N + (k == 0 ? 0 : N - k)];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int it = tid + q * NT;
+    if (ITEMS % NT == 0 || it < ITEMS) {
+      const int l = it / XS, k = it % XS;
+      C x1, x2;
+      x1.x = T(0.5) * (a[q].x + b[q].x);
+      x1.y = T(0.5) * (a[q].y - b[q].y);
+      // (a - conj b) / 2i
+      x2.x = T(0.5) * (a[q].y + b[q].y);
+      x2.y = T(0.5) * (b[q].x - a[q].x);
+      buf[l * XS + k] = x1;
+      buf[(l + H) * XS + k] = x2;
+    }
+  }
+  __syncthreads();
+  fft_lines<T, N, XS, 1, XS, NT, -1, false, V>(buf, tw, tid);
+  for (int e = tid; e < N * XS; e += NT) out[e] = buf[e];
+}
+
+// z lines of the TX consecutive flattened columns starting at f0 of one
+// pair's half spectrum: forward FFT, times v(G)/N^3, inverse FFT; in place.
+template <typename T, int N, int TX, int NT, int V = 0>
+__device__ __forceinline__ void body_conv_z_r(cplx<T>* spec_p, int f0, const KernelParams& kp, cplx<T>* buf,
+                                              const cplx<T>* tw, int tid) {
+  using C = cplx<T>;
+  constexpr int XS = r2c_xs<N>(), PL = N * XS, E = N * TX;
+  C* base = spec_p + f0;
+  for (int e = tid; e < E; e += NT) buf[e] = base[size_t(e / TX) * PL + (e % TX)];
+  __syncthreads();
+  fft_lines<T, N, TX, 1, TX, NT, -1, false, V>(buf, tw, tid);
+  for (int e = tid; e < E; e += NT) {
+    const int f = f0 + e % TX;
+    const T v = kernel_value<T, N>(kp, f % XS, f / XS, e / TX);
+    C c = buf[e];
+    c.x *= v;
+    c.y *= v;
+    buf[e] = c;
+  }
+  __syncthreads();
+  fft_lines<T, N, TX, 1, TX, NT, +1, false, V>(buf, tw, tid);
+  for (int e = tid; e < E; e += NT) base[size_t(e / TX) * PL + (e % TX)] = buf[e];
+}
+
+// Half spectrum of plane z -> the real potential of the plane, left in buf as
+// H complex lines: line l holds row l in .x and row l + N/2 in .y.
+template <typename T, int N, int NT, int V = 0>
+__device__ __forceinline__ void body_inv_xy_r(const cplx<T>* in, cplx<T>* buf, const cplx<T>* tw, int tid) {
+  using C = cplx<T>;
+  constexpr int H = N / 2, XS = r2c_xs<N>();
+  for (int e = tid; e < N * XS; e += NT) buf[e] = in[e];
+  __syncthreads();
+  fft_lines<T, N, XS, 1, XS, NT, +1, false, V>(buf, tw, tid);
+  // re-pack: Z[k] = X1[k] + i X2[k], Z[N-k] = conj X1[k] + i conj X2[k]; the
+  // zero and Nyquist bins of a real row are real, as a c2r transform takes them
+  constexpr int ITEMS = H * XS;
+  constexpr int PER = (ITEMS + NT - 1) / NT;
+  C a[PER], b[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int it = tid + q * NT;
+    if (ITEMS % NT == 0 || it < ITEMS) {
+      const int l = it / XS, k = it % XS;
+      a[q] = buf[l * XS + k];
+      b[q] = buf[(l + H) * XS + k];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int it = tid + q * NT;
+    if (ITEMS % NT == 0 || it < ITEMS) {
+      const int l = it / XS, k = it % XS;
+      C x1 = a[q], x2 = b[q];
+      if (k == 0 || k == H) { x1.y = T(0); x2.y = T(0); }
+      C z;
+      z.x = x1.x - x2.y;
+      z.y = x1.y + x2.x;
+      buf[l * N + k] = z;
+      if (k != 0 && k != H) {
+        C w;
+        w.x = x1.x + x2.y;
+        w.y = x2.x - x1.y;
+        buf[l * N + N - k] = w;
+      }
+    }
+  }
+  __syncthreads();
+  fft_lines<T, N, H, N, 1, NT, +1, true, V>(buf, tw, tid);
+}
+
+// W_i -= v phi_j and (i != j) W_j -= v phi_i over plane z for one pair, with
+// v from the packed lines of body_inv_xy_r; optional partial sum of v rho.
+template <typename T, int N, int NT, bool EN>
+__device__ __forceinline__ void accumulate_w_r(const T* __restrict__ pi_, const T* __restrict__ pj_, T* wi, T* wj,
+                                               bool off, double* eslot, const cplx<T>* buf, double* red, int tid) {
+  constexpr int HN = (N / 2) * N;
+  T ea = T(0);
+  if (wi) {
+    for (int e = tid; e < HN; e += NT) {
+      const cplx<T> v = buf[e];
+      const T fi0 = pi_[e], fj0 = pj_[e], fi1 = pi_[e + HN], fj1 = pj_[e + HN];
+      wi[e] -= v.x * fj0;
+      wi[e + HN] -= v.y * fj1;
+      if (off) {
+        wj[e] -= v.x * fi0;
+        wj[e + HN] -= v.y * fi1;
+      }
+      if (EN) ea += v.x * fi0 * fj0 + v.y * fi1 * fj1;
+    }
+  } else if (EN) {
+    for (int e = tid; e < HN; e += NT) {
+      const cplx<T> v = buf[e];
+      ea += v.x * pi_[e] * pj_[e] + v.y * pi_[e + HN] * pj_[e + HN];
+    }
+  }
+  if (EN) {
+    double x = ea;
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) red[wv] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double sx = 0;
+      for (int w = 0; w < NT / 64; ++w) sx += red[w];
+      eslot[0] = sx;
+    }
+  }
+}
+
 }  // namespace ace

@@ -17,11 +17,10 @@ from . import ace
 DEFAULT_PACKS = (16, 32, 64, 128)
 
 
-def candidates(precision: str, n: int, packs: Sequence[int] = DEFAULT_PACKS) -> Iterable[Tuple[bool, int]]:
-    lib = ace.load()
-    for fused in (True, False):
+def candidates(precision: str, n: int, packs: Sequence[int] = DEFAULT_PACKS) -> Iterable[Tuple[str, int]]:
+    for path in ("r2c", "fused", "split"):
         for mp in packs:
-            yield fused, mp
+            yield path, mp
 
 
 def _key(precision, n, norb):
@@ -33,7 +32,7 @@ def _key(precision, n, norb):
 
 def autotune(ctx: "ace.Context", phi, pairs, grid: "ace.Grid", kernel: str, omega: float, precision: str,
              packs: Sequence[int] = DEFAULT_PACKS, reps: int = 2, cache: Optional[str] = None):
-    """Pick the fastest pair-stage shape; returns dict(fused, max_packs, ms, table)."""
+    """Pick the fastest pair-stage shape; returns dict(fused=path name, max_packs, ms, table)."""
     import torch
 
     n = int(grid.n[0])

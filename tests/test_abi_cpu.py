@@ -66,6 +66,13 @@ def test_argument_validation(ctx):
     f, m = C.c_int(), C.c_int()
     assert lib.ace_get_pair_shape(h, 0, 96, C.byref(f), C.byref(m)) == 0
     assert (f.value, m.value) == (0, 16)
+    # real-to-complex path: fits FP64 up to 120^3, not 160^3 (half-spectrum plane beyond LDS)
+    assert lib.ace_set_pair_shape(h, 0, 96, 2, 16) == 0
+    assert lib.ace_get_pair_shape(h, 0, 96, C.byref(f), C.byref(m)) == 0 and f.value == 2
+    assert lib.ace_set_pair_shape(h, 0, 160, 2, 16) == 0
+    assert lib.ace_get_pair_shape(h, 0, 160, C.byref(f), C.byref(m)) == 0 and f.value == 0
+    assert lib.ace_set_pair_shape(h, 1, 160, 2, 16) == 0
+    assert lib.ace_get_pair_shape(h, 1, 160, C.byref(f), C.byref(m)) == 0 and f.value == 2
     assert lib.ace_profile_read(h, 99, None, None, None, 0) == -1
     # batched: argument checks before any device work
     arr = (ace.ace_system * 2)()

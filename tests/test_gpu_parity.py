@@ -181,11 +181,14 @@ def test_bad_pairs_rejected(ctx, c1):
 
 # ------------------------------------------------------------------ other grid sizes, ragged lists
 
-@pytest.mark.parametrize("n,kind,prec", [(8, "erfc", "fp64"), (12, "bare", "fp64"), (16, "erfc", "fp64"),
-                                         (32, "erfc", "fp64"), (48, "bare", "fp64"), (16, "erfc", "fp32"),
-                                         (48, "erfc", "fp32")])
-def test_sizes_and_screened_lists(ctx, n, kind, prec):
-    _say(f"sizes N={n} {kind} {prec}")
+SIZE_CASES = [(8, "erfc", "fp64"), (12, "bare", "fp64"), (16, "erfc", "fp64"), (32, "erfc", "fp64"),
+              (48, "bare", "fp64"), (16, "erfc", "fp32"), (48, "erfc", "fp32")]
+
+
+@pytest.mark.parametrize("path", ["fused", "r2c", "split"])
+@pytest.mark.parametrize("n,kind,prec", SIZE_CASES)
+def test_sizes_and_screened_lists(ctx, n, kind, prec, path):
+    _say(f"sizes N={n} {kind} {prec} path={path}")
     L = n * 0.3
     spec = SystemSpec(n_mol=3, L=L, N=n, sigma=0.7, offset=0.6, placement="uniform", seed=40 + n,
                       kernel=kind, omega=0.4)
@@ -204,7 +207,9 @@ def test_sizes_and_screened_lists(ctx, n, kind, prec):
     except oracle.NotPositiveDefinite:
         pd = False
     from paper_2101_03155_amd import AceError
-    ctx.set_pair_shape(prec, n, True, 3)
+    saved = ctx.get_pair_shape(prec, n)
+    ctx.set_pair_shape(prec, n, path, 3)
+    assert ctx.get_pair_shape(prec, n)[0] == path
     try:
         if not pd:
             with pytest.raises(AceError) as ei:
@@ -214,7 +219,7 @@ def test_sizes_and_screened_lists(ctx, n, kind, prec):
         r = ctx.build(_dev(o.psi), _dev(pairs), _grid(spec), kernel=kind, omega=0.4, precision=prec,
                       want_W=True, want_energies=True)
     finally:
-        ctx.set_pair_shape(prec, n, True, 64)
+        ctx.set_pair_shape(prec, n, *saved)
     tol = 1e-12 if prec == "fp64" else 2e-5
     assert _rel(r["W"].cpu().numpy(), ref_W) < tol
     np.testing.assert_allclose(r["e"].cpu().numpy(), ref_e, atol=tol * np.abs(ref_e).max())
@@ -246,19 +251,33 @@ def test_c2_localize_and_pairlist(ctx, c2):
     np.testing.assert_allclose(gov.cpu().numpy(), c2["ov"], rtol=1e-12)
 
 
+def _c2_screened_ref(c2):
+    if "e_ref" not in c2:
+        s = c2["s"]
+        c2["e_ref"] = oracle.exchange_energy_pairs(c2["phi"], c2["pairs"], c2["v"], s.dV)
+        c2["W_rows"] = oracle.build_W_rows(c2["phi"], c2["pairs"], [5, 77], c2["v"])
+    return c2["e_ref"], c2["W_rows"]
+
+
+@pytest.mark.parametrize("path", ["split", "fused", "r2c"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_c2_screened_build(ctx, c2, prec):
-    _say(f"c2 screened build {prec}")
+def test_c2_screened_build(ctx, c2, prec, path):
+    _say(f"c2 screened build {prec} path={path}")
     s, phi, pairs = c2["s"], c2["phi"], c2["pairs"]
-    r = ctx.build(_dev(phi), _dev(pairs.astype(np.int32)), _grid(s), kernel="erfc", omega=s.omega,
-                  precision=prec, want_W=True, want_energies=True)
-    e_ref = oracle.exchange_energy_pairs(phi, pairs, c2["v"], s.dV)
+    saved = ctx.get_pair_shape(prec, s.N)
+    ctx.set_pair_shape(prec, s.N, path, 16)
+    assert ctx.get_pair_shape(prec, s.N)[0] == path
+    try:
+        r = ctx.build(_dev(phi), _dev(pairs.astype(np.int32)), _grid(s), kernel="erfc", omega=s.omega,
+                      precision=prec, want_W=True, want_energies=True)
+    finally:
+        ctx.set_pair_shape(prec, s.N, *saved)
+    e_ref, Wref = _c2_screened_ref(c2)
     ex_ref = e_ref.sum()
     tol = 1e-10 if prec == "fp64" else 1e-6
     assert abs(r["ex"].item() - ex_ref) <= tol * abs(ex_ref)
     np.testing.assert_allclose(r["e"].cpu().numpy(), e_ref, atol=(1e-12 if prec == "fp64" else 1e-7))
     rows = [5, 77]
-    Wref = oracle.build_W_rows(phi, pairs, rows, c2["v"])
     Wg = r["W"][rows].cpu().numpy()
     assert _rel(Wg, Wref) < (1e-12 if prec == "fp64" else 1e-5)
     # M columns of the sampled rows: M_kl = dV <phi_k | W_l>
