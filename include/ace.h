@@ -217,9 +217,13 @@ typedef struct {
 int ace_build_batched(ace_ctx* ctx, int nsys, ace_system* systems, int prec, int mode);
 
 /* Batched launch shape (set by the autotuner): x-tile width of the line
- * passes (8 or 16), radix order of the FFT plans (0 large radices first, 1
- * small first), workgroups per compute unit of the persistent launch. */
-int ace_set_batched_shape(ace_ctx* ctx, int txv, int plan_variant, int blocks_per_cu);
+ * passes of the split layout (8 or 16), radix order of the FFT plans (0 large
+ * radices first, 1 small first), workgroups per compute unit of the
+ * persistent launch (1..32), and the layout of the pair stage: 0 the five
+ * split passes over packed complex fields, 2 (the default) real-to-complex
+ * half spectra in three phases, used for every grid size whose half-spectrum
+ * plane fits in LDS (all supported sizes).  ACE_E_ARG for other values. */
+int ace_set_batched_shape(ace_ctx* ctx, int txv, int plan_variant, int blocks_per_cu, int layout);
 
 /*
  * Learned pair screener (the learned replacement of the screening criterion

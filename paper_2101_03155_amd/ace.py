@@ -115,7 +115,7 @@ def load(path: str = LIB_PATH):
         "ace_set_pair_shape": ([P, I, I, I, I], I),
         "ace_get_pair_shape": ([P, I, I, C.POINTER(I), C.POINTER(I)], I),
         "ace_build_batched": ([P, I, C.POINTER(ace_system), I, I], I),
-        "ace_set_batched_shape": ([P, I, I, I], I),
+        "ace_set_batched_shape": ([P, I, I, I, I], I),
         "ace_pair_features": ([P, GP, I, P, P, I64, P], I),
         "ace_pair_energies": ([P, GP, I, P, P, I64, I, D, I, P], I),
         "ace_mlp_init": ([P, P, C.c_uint64], I),
@@ -339,8 +339,10 @@ class Context:
         self._check(rc)
         return outs
 
-    def set_batched_shape(self, txv: int, plan_variant: int, blocks_per_cu: int):
-        self._check(self.lib.ace_set_batched_shape(self.h, txv, plan_variant, blocks_per_cu))
+    def set_batched_shape(self, txv: int, plan_variant: int, blocks_per_cu: int, layout: str = "r2c"):
+        """layout: "r2c" (half spectra, three phases) or "split" (five passes)."""
+        code = {"split": 0, "r2c": 2}[layout]
+        self._check(self.lib.ace_set_batched_shape(self.h, txv, plan_variant, blocks_per_cu, code))
 
     # ------------------------------------------------------------ learned screener
     def pair_features(self, phi, grid: Grid, pairs=None):

@@ -84,9 +84,11 @@ size_t pair_spec_elems(int prec, int N, const PairShape& sh);
 
 // Dense kernels (gemm.hip, linalg.hip).
 // op: 0 A B^T, 1 |A| |B|^T, 2 (A.A)(B.B)^T  (FP64 only for op != 0)
+// sym: A == B (same rows, same op) and M == Nn; only the upper triangle of
+// 128 x 128 tiles is computed and mirrored (FP64 only).
 hipError_t gemm_nt(int prec, int op, const void* A, int64_t lda, const void* B, int64_t ldb, int M,
                    int Nn, int64_t K, double alpha, double* Cpart, double* C, hipStream_t s,
-                   EventRecorder* rec);
+                   EventRecorder* rec, bool sym = false);
 int64_t gemm_nt_nsplit(int M, int Nn, int64_t K, int64_t* kchunk_out);
 hipError_t gemm_ls(int bprec, bool trans, bool lower, const double* S, int lds, const void* B, int64_t ldb,
                    double* C, int64_t ldc, int M, int K, int64_t R, double alpha, hipStream_t s,
@@ -135,7 +137,9 @@ int64_t batched_phase_items(int n, int phase, int txv);
 // mode 1: one cooperative launch for all the segments.
 hipError_t batched_segments(int prec, int n, int mode, int txv, int plan_v, int blocks_per_cu, int nseg,
                             const BRound* h_segs, const BRound* d_segs, const BSys* sys, const BPack* packs,
-                            const int64_t* starts, hipStream_t s);
+                            const int64_t* starts, bool r2c, hipStream_t s);
+bool batched_r2c_fits(int prec, int n);
+int64_t batched_r2c_slot_items(int n, int phase);  // work items per pair slot of phase 0..2
 void launch_zero(void* p, size_t bytes, hipStream_t s);
 
 // Learned screener (screener.hip).

@@ -124,7 +124,7 @@ struct ace_ctx {
   hipEvent_t bev_in = nullptr, bev_out = nullptr;
   std::map<uint64_t, hipGraphExec_t> graphs;
   std::vector<uint64_t> graph_order;
-  int b_txv = 16, b_plan = 0, b_bpc = 8;
+  int b_txv = 16, b_plan = 0, b_bpc = 8, b_layout = 2;
 };
 
 static int fail(ace_ctx* c, int code, const char* fmt, ...) {
@@ -592,7 +592,7 @@ int ace_pairlist(ace_ctx* c, const ace_grid* g, int norb, const double* phi, dou
   WS(c, "mpart", size_t(nsplit) * norb * norb * sizeof(double), part);
   WS(c, "O", size_t(norb) * norb * sizeof(double), O);
   WS(c, "cnt", 64, cnt);
-  HIPCHK(c, gemm_nt(0, 1, phi, ng, phi, ng, norb, norb, ng, grid_dv(g), part, O, s, c->R()));
+  HIPCHK(c, gemm_nt(0, 1, phi, ng, phi, ng, norb, norb, ng, grid_dv(g), part, O, s, c->R(), true));
   launch_compact_pairs(O, norb, rho_cut, capacity, pairs, overlap, cnt, s);
   int64_t h = 0;
   HIPCHK(c, hipMemcpyAsync(&h, cnt, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -756,13 +756,14 @@ int ace_apply(ace_ctx* c, const ace_grid* g, int norb, const double* xi, int nve
 
 
 // ------------------------------------------------------------------ batched form
-int ace_set_batched_shape(ace_ctx* c, int txv, int plan_variant, int blocks_per_cu) {
+int ace_set_batched_shape(ace_ctx* c, int txv, int plan_variant, int blocks_per_cu, int layout) {
   if (!c || (txv != 8 && txv != 16) || (plan_variant != 0 && plan_variant != 1) || blocks_per_cu < 1 ||
-      blocks_per_cu > 32)
+      blocks_per_cu > 32 || (layout != 0 && layout != 2))
     return fail(c, ACE_E_ARG, "bad batched shape");
   c->b_txv = txv;
   c->b_plan = plan_variant;
   c->b_bpc = blocks_per_cu;
+  c->b_layout = layout;
   return ACE_OK;
 }
 
@@ -806,6 +807,7 @@ int ace_build_batched(ace_ctx* c, int nsys, ace_system* sys, int prec, int mode)
   uint64_t key = 1469598103934665603ull;
   auto mix = [&key](uint64_t v) { key = (key ^ v) * 1099511628211ull; };
   mix(uint64_t(prec)); mix(uint64_t(mode)); mix(uint64_t(c->b_txv)); mix(uint64_t(c->b_plan)); mix(uint64_t(c->b_bpc));
+  mix(uint64_t(c->b_layout));
   int nrounds = 0;
   for (int q = 0; q < nsys; ++q) {
     int rc = schedule_for(c, prs[q], sys[q].npairs, sys[q].norb, 1 << 30, &sch[q]);
@@ -833,8 +835,12 @@ int ace_build_batched(ace_ctx* c, int nsys, ace_system* sys, int prec, int mode)
   std::vector<int64_t> starts;
   std::vector<int64_t> bp_off;  // spec offset of each pack (bytes, within its segment)
   size_t spec_bytes = 0;
+  std::vector<char> seg_r2c;
   for (int n : sizes) {
     const int64_t ngn = int64_t(n) * n * n;
+    const bool r2c = c->b_layout == 2 && batched_r2c_fits(prec, n);
+    // complex spectrum values per pack: two half spectra (real-to-complex) or one full field
+    const int64_t pack_elems = r2c ? 2 * int64_t(n) * n * (n / 2 + 1) : ngn;
     for (int r = 0; r < nrounds; ++r) {
       BRound sg{};
       sg.pack0 = int(bp.size());
@@ -848,7 +854,7 @@ int ace_build_batched(ace_ctx* c, int nsys, ace_system* sys, int prec, int mode)
           b.pk = S.packs[S.round_first[r] + k];
           bp.push_back(b);
           bp_off.push_back(int64_t(off));
-          off += size_t(ngn) * 2 * es;
+          off += size_t(pack_elems) * 2 * es;
         }
       }
       sg.npacks = int(bp.size()) - sg.pack0;
@@ -859,13 +865,15 @@ int ace_build_batched(ace_ctx* c, int nsys, ace_system* sys, int prec, int mode)
         int64_t acc = 0;
         for (int k = 0; k < sg.npacks; ++k) {
           starts.push_back(acc);
-          acc += batched_phase_items(n, p, c->b_txv);
+          if (!r2c) acc += batched_phase_items(n, p, c->b_txv);
+          else if (p < 3) acc += (bp[sg.pack0 + k].pk.jb >= 0 ? 2 : 1) * batched_r2c_slot_items(n, p);
         }
         starts.push_back(acc);
         sg.nitems[p] = acc;
       }
       segs.push_back(sg);
       seg_n.push_back(n);
+      seg_r2c.push_back(r2c ? 1 : 0);
     }
   }
   // workspaces
@@ -942,7 +950,7 @@ int ace_build_batched(ace_ctx* c, int nsys, ace_system* sys, int prec, int mode)
       size_t b = a;
       while (b < segs.size() && seg_n[b] == seg_n[a]) ++b;
       hipError_t e = batched_segments(prec, seg_n[a], mode == 1 ? 1 : 0, c->b_txv, c->b_plan, c->b_bpc, int(b - a),
-                                      segs.data() + a, dsegs + a, dsys, dbp, dstarts, s);
+                                      segs.data() + a, dsegs + a, dsys, dbp, dstarts, seg_r2c[a] != 0, s);
       if (e != hipSuccess) return fail(c, ACE_E_HIP, "batched pair launch failed: %s", hipGetErrorString(e));
       a = b;
     }
@@ -1029,8 +1037,8 @@ static int features_impl(ace_ctx* c, const ace_grid* g, int norb, const double* 
   WS(c, "mpart", size_t(nsplit) * norb * norb * sizeof(double), part);
   launch_marginals(phi, norb, n, pz, py, px, s);
   launch_centroids(pz, py, px, norb, n, g->L[0], grid_dv(g), cen, spr, s);
-  HIPCHK(c, gemm_nt(0, 1, phi, ng, phi, ng, norb, norb, ng, grid_dv(g), part, O, s, nullptr));
-  HIPCHK(c, gemm_nt(0, 2, phi, ng, phi, ng, norb, norb, ng, grid_dv(g), part, P, s, nullptr));
+  HIPCHK(c, gemm_nt(0, 1, phi, ng, phi, ng, norb, norb, ng, grid_dv(g), part, O, s, nullptr, true));
+  HIPCHK(c, gemm_nt(0, 2, phi, ng, phi, ng, norb, norb, ng, grid_dv(g), part, P, s, nullptr, true));
   launch_pair_features(pairs, np, norb, cen, spr, O, P, g->L[0], feats, s);
   HIPCHK(c, hipGetLastError());
   if (O_out) *O_out = O;

@@ -122,6 +122,159 @@ __global__ __launch_bounds__(BNT) void k_batched_persistent(int nseg, const BRou
   }
 }
 
+// ------------------------------------------------------------ real-to-complex layout
+// Three phases per segment: (0) product + x and y transforms per (pair,
+// z-plane), (1) z lines + v(G) over tiles of flattened half-spectrum columns,
+// (2) inverse y and x transforms + W update per (pair, z-plane).  A pack has
+// one or two pair slots, each with its own N * N * (N/2 + 1) half spectrum.
+constexpr int BNTR = 512;
+
+// LDS buffer of the three phases: the in-plane bodies use N * XS values, the
+// z pass N * TX (TX can exceed XS on small grids, e.g. 16 > 9 at N = 16).
+template <int N>
+__host__ __device__ constexpr int r2c_buf_elems() {
+  return N * r2c_tx<N>() > N * r2c_xs<N>() ? N * r2c_tx<N>() : N * r2c_xs<N>();
+}
+
+template <int N>
+__host__ __device__ constexpr int64_t r2c_slot_items(int phase) {
+  return phase == 1 ? int64_t(N) * r2c_xs<N>() / r2c_tx<N>() : int64_t(N);
+}
+
+template <typename T, int N, int V>
+__device__ __forceinline__ void run_item_r(int p, int64_t j, const BRound& sg, const BSys* __restrict__ sys,
+                                           const BPack* __restrict__ packs, const int64_t* __restrict__ starts,
+                                           cplx<T>* buf, cplx<T>* tw, double* red) {
+  constexpr int XS = r2c_xs<N>();
+  constexpr size_t NG = size_t(N) * N * N, PL = size_t(N) * XS;
+  // an opaque copy of the thread index: keeps the per-thread index arithmetic
+  // of the three phase bodies inside this item instead of hoisted out of the
+  // item loop (where it would all stay live at once)
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  const int64_t* st = starts + sg.start_off[p];
+  int lo = 0, hi = sg.npacks;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (st[mid] <= j) lo = mid; else hi = mid;
+  }
+  const BPack bp = packs[sg.pack0 + lo];
+  const BSys& sy = sys[bp.sys];
+  const int64_t b = j - st[lo];
+  const int64_t per = r2c_slot_items<N>(p);
+  const int slot = int(b / per);
+  const int sub = int(b % per);
+  const int oi = slot ? bp.pk.ib : bp.pk.ia, oj = slot ? bp.pk.jb : bp.pk.ja;
+  cplx<T>* spec = static_cast<cplx<T>*>(bp.spec) + size_t(slot) * N * PL;
+  const T* phi = static_cast<const T*>(sy.phi);
+  const cplx<T>* twg = static_cast<const cplx<T>*>(sy.tw);
+  __syncthreads();  // the previous item's last reads of buf/tw are done
+  for (int i = tid; i < N; i += BNTR) tw[i] = twg[i];
+  if (p == 0) {
+    const size_t zo = size_t(sub) * N * N;
+    body_fwd_xy_r<T, N, BNTR, V>(phi + size_t(oi) * NG + zo, phi + size_t(oj) * NG + zo, spec + size_t(sub) * PL,
+                                 buf, tw, tid);
+  } else if (p == 1) {
+    KernelParams kp;
+    kp.kind = sy.kind;
+    kp.omega = sy.omega;
+    kp.inv_ng = sy.inv_ng;
+    kp.g[0] = sy.g[0]; kp.g[1] = sy.g[1]; kp.g[2] = sy.g[2];
+    body_conv_z_r<T, N, r2c_tx<N>(), BNTR, V>(spec, sub * r2c_tx<N>(), kp, buf, tw, tid);
+  } else {
+    const size_t zo = size_t(sub) * N * N;
+    body_inv_xy_r<T, N, BNTR, V>(spec + size_t(sub) * PL, buf, tw, tid);
+    T* W = static_cast<T*>(sy.W);
+    accumulate_w_r<T, N, BNTR, false>(phi + size_t(oi) * NG + zo, phi + size_t(oj) * NG + zo,
+                                      W + size_t(oi) * NG + zo, W + size_t(oj) * NG + zo, oi != oj, nullptr, buf,
+                                      red, tid);
+  }
+}
+
+// One phase P of one segment (the phase is a template parameter so that each
+// launch carries only its own body).
+template <typename T, int N, int V, int P>
+__global__ __launch_bounds__(BNTR, 4) void k_batched_phase_r(BRound sg, const BSys* __restrict__ sys,
+                                                          const BPack* __restrict__ packs,
+                                                          const int64_t* __restrict__ starts) {
+  __shared__ cplx<T> buf[r2c_buf_elems<N>()];
+  __shared__ cplx<T> tw[N];
+  __shared__ double red[BNTR / 64];
+  for (int64_t j = blockIdx.x; j < sg.nitems[P]; j += gridDim.x)
+    run_item_r<T, N, V>(P, j, sg, sys, packs, starts, buf, tw, red);
+}
+
+template <typename T, int N, int V>
+__global__ __launch_bounds__(BNTR, 4) void k_batched_persistent_r(int nseg, const BRound* __restrict__ segs,
+                                                               const BSys* __restrict__ sys,
+                                                               const BPack* __restrict__ packs,
+                                                               const int64_t* __restrict__ starts) {
+  __shared__ cplx<T> buf[r2c_buf_elems<N>()];
+  __shared__ cplx<T> tw[N];
+  __shared__ double red[BNTR / 64];
+  cg::grid_group grid = cg::this_grid();
+  for (int r = 0; r < nseg; ++r) {
+    const BRound sg = segs[r];
+    for (int p = 0; p < 3; ++p) {
+      for (int64_t j = blockIdx.x; j < sg.nitems[p]; j += gridDim.x)
+        run_item_r<T, N, V>(p, j, sg, sys, packs, starts, buf, tw, red);
+      grid.sync();
+    }
+  }
+}
+
+template <typename T, int N, int V>
+static hipError_t launch_seg_r(int mode, int nseg, const BRound* h_segs, const BRound* d_segs, const BSys* sys,
+                               const BPack* packs, const int64_t* starts, int blocks_per_cu, hipStream_t s) {
+  if (mode == 1) {
+    int dev = 0, ncu = 0, per = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched_persistent_r<T, N, V>, BNTR, 0);
+    if (e != hipSuccess) return e;
+    if (per < 1) return hipErrorInvalidConfiguration;
+    const int use = (blocks_per_cu > 0 && blocks_per_cu < per) ? blocks_per_cu : per;
+    dim3 grid(unsigned(ncu * use)), block(BNTR);
+    void* args[] = {&nseg, (void*)&d_segs, (void*)&sys, (void*)&packs, (void*)&starts};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_batched_persistent_r<T, N, V>), grid, block,
+                                      args, 0, s);
+  }
+  const int grid_cap = 256 * (blocks_per_cu > 0 ? blocks_per_cu : 8);
+  for (int r = 0; r < nseg; ++r)
+    for (int p = 0; p < 3; ++p) {
+      const int64_t n = h_segs[r].nitems[p];
+      if (n == 0) continue;
+      const unsigned g = unsigned(n < grid_cap ? n : grid_cap);
+      if (p == 0)
+        hipLaunchKernelGGL((k_batched_phase_r<T, N, V, 0>), dim3(g), dim3(BNTR), 0, s, h_segs[r], sys, packs, starts);
+      else if (p == 1)
+        hipLaunchKernelGGL((k_batched_phase_r<T, N, V, 1>), dim3(g), dim3(BNTR), 0, s, h_segs[r], sys, packs, starts);
+      else
+        hipLaunchKernelGGL((k_batched_phase_r<T, N, V, 2>), dim3(g), dim3(BNTR), 0, s, h_segs[r], sys, packs, starts);
+    }
+  return hipGetLastError();
+}
+
+bool batched_r2c_fits(int prec, int n) {
+  switch (n) {
+#define X(nn) case nn: return (size_t(r2c_buf_elems<nn>()) + nn) * (prec == 0 ? 16 : 8) + 1024 <= 163840;
+    X(16) X(24) X(32) X(48) X(64) X(80) X(96)
+#undef X
+    default: return false;
+  }
+}
+
+int64_t batched_r2c_slot_items(int n, int phase) {
+  switch (n) {
+#define X(nn) case nn: return r2c_slot_items<nn>(phase);
+    X(16) X(24) X(32) X(48) X(64) X(80) X(96)
+#undef X
+    default: return 0;
+  }
+}
+
 bool batched_supported(int n) {
   return n == 16 || n == 24 || n == 32 || n == 48 || n == 64 || n == 80 || n == 96;
 }
@@ -170,7 +323,22 @@ static hipError_t launch_seg_n(int mode, int txv, int plan_v, int nseg, const BR
 // Launch the segments [h_segs, h_segs + nseg), all of grid size n.
 hipError_t batched_segments(int prec, int n, int mode, int txv, int plan_v, int blocks_per_cu, int nseg,
                             const BRound* h_segs, const BRound* d_segs, const BSys* sys, const BPack* packs,
-                            const int64_t* starts, hipStream_t s) {
+                            const int64_t* starts, bool r2c, hipStream_t s) {
+  if (r2c) {
+    switch (n) {
+#define X(nn)                                                                                                   \
+  case nn:                                                                                                      \
+    if (prec == 0)                                                                                              \
+      return plan_v ? launch_seg_r<double, nn, 1>(mode, nseg, h_segs, d_segs, sys, packs, starts, blocks_per_cu, s) \
+                    : launch_seg_r<double, nn, 0>(mode, nseg, h_segs, d_segs, sys, packs, starts, blocks_per_cu, s); \
+    return plan_v ? launch_seg_r<float, nn, 1>(mode, nseg, h_segs, d_segs, sys, packs, starts, blocks_per_cu, s)    \
+                  : launch_seg_r<float, nn, 0>(mode, nseg, h_segs, d_segs, sys, packs, starts, blocks_per_cu, s);
+      X(16) X(24) X(32) X(48) X(64) X(80) X(96)
+#undef X
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
   switch (n) {
 #define X(nn)                                                                                                  \
   case nn:                                                                                                     \

@@ -259,15 +259,196 @@ __global__ __launch_bounds__(64) void k_gemm_tiny(const double* __restrict__ S, 
   }
 }
 
+// ---------------------------------------------------------------- 128 x 128 MFMA tiles
+// One workgroup (4 waves) computes a 128 x 128 tile of
+//   C(m, n) = sum_{k in [kb, ke)} f(A(m, k)) f(B(k, n)),
+// each wave a 64 x 64 quarter (4 x 4 blocks of v_mfma_f64_16x16x4f64).
+// Operand sources: A(m, k) = A[m][k] (AK = false) or A[k][m] (AK = true);
+// B(k, n) = B[n][k] (BK = false) or B[k][n] (BK = true).  Each K step of 16
+// is staged in k-major LDS tiles, double buffered: the next step's global
+// loads are issued before the current step's MFMAs.  Row pitch TP = 144
+// doubles puts the four k-rows a lane group reads in alternating halves of
+// the LDS banks.
+constexpr int TT = 128, KS = 16, TP = TT + 16;
+
+// element e (0..2047) of a 128 x 16 step: (row, k) in the operand's tile
+template <bool KM>
+__device__ __forceinline__ void tile_rk(int e, int& r, int& k) {
+  if (KM) { r = e % TT; k = e / TT; } else { r = e / KS; k = e % KS; }
+}
+
+template <typename TX, bool KM, int OP>
+__device__ __forceinline__ void tile_load(const TX* __restrict__ X, int64_t ld, int r0, int rows, int64_t k0,
+                                          int64_t ke, int tid, double (&v)[8]) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    int r, k;
+    tile_rk<KM>(tid + 256 * i, r, k);
+    const int64_t kk = k0 + k;
+    double x = 0.0;
+    if (r0 + r < rows && kk < ke) x = double(KM ? X[kk * ld + r0 + r] : X[int64_t(r0 + r) * ld + kk]);
+    v[i] = opmap<OP>(x);
+  }
+}
+
+template <bool KM>
+__device__ __forceinline__ void tile_store(double* S, int tid, const double (&v)[8]) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    int r, k;
+    tile_rk<KM>(tid + 256 * i, r, k);
+    S[k * TP + r] = v[i];
+  }
+}
+
+// Accumulate the tile over [kb, ke) into acc (per wave 4 x 4 blocks).
+template <typename TA, typename TB, bool AK, bool BK, int OP>
+__device__ __forceinline__ void tile_mma(const TA* __restrict__ A, int64_t lda, const TB* __restrict__ B,
+                                         int64_t ldb, int m0, int M, int n0, int Nn, int64_t kb, int64_t ke,
+                                         double* As, double* Bs, d4 (&acc)[4][4]) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = wv >> 1, wn = wv & 1;
+  double va[8], vb[8];
+  int buf = 0;
+  if (kb < ke) {
+    tile_load<TA, AK, OP>(A, lda, m0, M, kb, ke, tid, va);
+    tile_load<TB, BK, OP>(B, ldb, n0, Nn, kb, ke, tid, vb);
+    tile_store<AK>(As, tid, va);
+    tile_store<BK>(Bs, tid, vb);
+  }
+  __syncthreads();
+  for (int64_t k0 = kb; k0 < ke; k0 += KS) {
+    const bool more = k0 + KS < ke;
+    if (more) {
+      tile_load<TA, AK, OP>(A, lda, m0, M, k0 + KS, ke, tid, va);
+      tile_load<TB, BK, OP>(B, ldb, n0, Nn, k0 + KS, ke, tid, vb);
+    }
+    const double* as = As + buf * KS * TP;
+    const double* bs = Bs + buf * KS * TP;
+#pragma unroll
+    for (int kk = 0; kk < KS; kk += 4) {
+      const int kr = (kk + lane / 16) * TP, li = lane % 16;
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = as[kr + wm * 64 + i * 16 + li];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = bs[kr + wn * 64 + j * 16 + li];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) {
+      buf ^= 1;
+      tile_store<AK>(As + buf * KS * TP, tid, va);
+      tile_store<BK>(Bs + buf * KS * TP, tid, vb);
+    }
+    __syncthreads();
+  }
+}
+
+// acc -> out[m][n] (ld) for rows < M, columns < Nn, times alpha
+__device__ __forceinline__ void tile_write(const d4 (&acc)[4][4], int m0, int M, int64_t n0, int64_t Nn,
+                                           double* __restrict__ out, int64_t ld, double alpha) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wm = wv >> 1, wn = wv & 1;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm * 64 + i * 16 + lane / 16 + 4 * r;
+        const int64_t n = n0 + wn * 64 + j * 16 + lane % 16;
+        if (m < M && n < Nn) out[int64_t(m) * ld + n] = alpha * acc[i][j][r];
+      }
+}
+
+// NT split-K: blockIdx.x = tile t of the tile list (tm, tn) = (t / ntn, t % ntn),
+// or with SYM the t-th tile of the upper triangle tm <= tn; blockIdx.y = split.
+// Cpart[split][M][Nn] receives the tile's partial sums.
+template <int OP, bool SYM>
+__global__ __launch_bounds__(256, 2) void k_gemm_nt_t128(const double* __restrict__ A, int64_t lda,
+                                                         const double* __restrict__ B, int64_t ldb, int M, int Nn,
+                                                         int64_t K, int64_t kchunk, int ntn,
+                                                         double* __restrict__ Cpart) {
+  __shared__ double As[2 * KS * TP];
+  __shared__ double Bs[2 * KS * TP];
+  int tm, tn;
+  if (SYM) {
+    // upper-triangle enumeration row by row: row tm holds ntn - tm tiles
+    int t = blockIdx.x;
+    tm = 0;
+    while (t >= ntn - tm) { t -= ntn - tm; ++tm; }
+    tn = tm + t;
+  } else {
+    tm = blockIdx.x / ntn;
+    tn = blockIdx.x % ntn;
+  }
+  const int m0 = tm * TT, n0 = tn * TT;
+  const int64_t kb = int64_t(blockIdx.y) * kchunk;
+  const int64_t ke = (kb + kchunk < K) ? kb + kchunk : K;
+  d4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0, 0, 0, 0};
+  tile_mma<double, double, false, false, OP>(A, lda, B, ldb, m0, M, n0, Nn, kb, ke, As, Bs, acc);
+  tile_write(acc, m0, M, n0, Nn, Cpart + int64_t(blockIdx.y) * M * Nn, Nn, 1.0);
+}
+
+// C = alpha * sum_s Cpart[s]; with SYM only tiles tm <= tn were computed and
+// the lower triangle of tiles is read transposed.
+template <bool SYM>
+__global__ void k_reduce_parts_t(const double* __restrict__ Cpart, int nsplit, int M, int Nn, double alpha,
+                                 double* __restrict__ C) {
+  const int64_t mn = int64_t(M) * Nn;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < mn; e += int64_t(gridDim.x) * blockDim.x) {
+    int64_t src = e;
+    if (SYM) {
+      const int i = int(e / Nn), j = int(e % Nn);
+      if (i / TT > j / TT) src = int64_t(j) * Nn + i;
+    }
+    double s = 0.0;
+    for (int p = 0; p < nsplit; ++p) s += Cpart[int64_t(p) * mn + src];
+    C[e] = alpha * s;
+  }
+}
+
+// Left-small: C[m][r] = alpha * sum_k S(m, k) B[k][r], S(m, k) = TRANS ? S[k][m] : S[m][k];
+// LOWER: S(m, k) = 0 for k > m.  blockIdx.x = 128-column tile of r, blockIdx.y = 128-row tile of m.
+template <typename TB, bool TRANS, bool LOWER>
+__global__ __launch_bounds__(256, 2) void k_gemm_ls_t128(const double* __restrict__ S, int lds,
+                                                         const TB* __restrict__ B, int64_t ldb,
+                                                         double* __restrict__ C, int64_t ldc, int M, int K,
+                                                         int64_t R, double alpha) {
+  __shared__ double As[2 * KS * TP];
+  __shared__ double Bs[2 * KS * TP];
+  const int m0 = blockIdx.y * TT;
+  const int64_t r0 = int64_t(blockIdx.x) * TT;
+  const int64_t ke = LOWER ? ((m0 + TT < K) ? m0 + TT : K) : K;
+  d4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0, 0, 0, 0};
+  // B columns r0 .. r0 + 127 are addressed from the tile origin
+  const TB* Bt = B + r0;
+  const int64_t rrem = R - r0;
+  tile_mma<double, TB, TRANS, true, 0>(S, lds, Bt, ldb, m0, M, 0, int(rrem < TT ? rrem : TT), 0, ke, As, Bs, acc);
+  tile_write(acc, m0, M, 0, rrem < TT ? rrem : TT, C + r0, ldc, alpha);
+}
+
 // ---------------------------------------------------------------- host wrappers
 
 int64_t gemm_nt_nsplit(int M, int Nn, int64_t K, int64_t* kchunk_out) {
-  // aim for >= ~1024 workgroups in total, chunks a multiple of GK
-  const int64_t tiles = int64_t((M + GB - 1) / GB) * ((Nn + GB - 1) / GB);
-  int64_t want = (2048 + tiles - 1) / tiles;
+  // about 512 workgroups (two per CU) over the 128 x 128 tiles, K chunks a
+  // multiple of 256 (the compensated FP32 sub-chunk)
+  const int64_t tiles = int64_t((M + TT - 1) / TT) * ((Nn + TT - 1) / TT);
+  const int64_t want = (512 + tiles - 1) / tiles;
   int64_t kchunk = (K + want - 1) / want;
-  kchunk = ((kchunk + 1023) / 1024) * 1024;
-  if (kchunk < 1024) kchunk = 1024;
+  kchunk = ((kchunk + 255) / 256) * 256;
+  if (kchunk < 256) kchunk = 256;
   const int64_t nsplit = (K + kchunk - 1) / kchunk;
   *kchunk_out = kchunk;
   return nsplit;
@@ -275,30 +456,41 @@ int64_t gemm_nt_nsplit(int M, int Nn, int64_t K, int64_t* kchunk_out) {
 
 hipError_t gemm_nt(int prec, int op, const void* A, int64_t lda, const void* B, int64_t ldb, int M,
                    int Nn, int64_t K, double alpha, double* Cpart, double* C, hipStream_t s,
-                   EventRecorder* rec) {
+                   EventRecorder* rec, bool sym) {
   int64_t kchunk;
   const int64_t nsplit = gemm_nt_nsplit(M, Nn, K, &kchunk);
-  dim3 grid((Nn + GB - 1) / GB, (M + GB - 1) / GB, unsigned(nsplit));
   rec_begin(rec, KC_GEMM_NT, s);
-  if (prec == 0) {
-    if (op == 1)
-      hipLaunchKernelGGL(k_gemm_nt_f64<1>, grid, dim3(256), 0, s, (const double*)A, lda, (const double*)B,
-                         ldb, M, Nn, K, kchunk, Cpart);
-    else if (op == 2)
-      hipLaunchKernelGGL(k_gemm_nt_f64<2>, grid, dim3(256), 0, s, (const double*)A, lda, (const double*)B,
-                         ldb, M, Nn, K, kchunk, Cpart);
-    else
-      hipLaunchKernelGGL(k_gemm_nt_f64<0>, grid, dim3(256), 0, s, (const double*)A, lda, (const double*)B,
-                         ldb, M, Nn, K, kchunk, Cpart);
-  } else {
-    hipLaunchKernelGGL(k_gemm_nt_f32c, grid, dim3(256), 0, s, (const float*)A, lda, (const float*)B, ldb, M, Nn,
-                       K, kchunk, 256, Cpart);
-  }
   const int64_t mn = int64_t(M) * Nn;
   int nb = int((mn + 255) / 256);
   if (nb > 1024) nb = 1024;
-  hipLaunchKernelGGL(k_reduce_parts, dim3(nb), dim3(256), 0, s, Cpart, int(nsplit), mn, alpha, C);
-  rec_end(rec, KC_GEMM_NT, s, 2.0 * double(M) * Nn * double(K));
+  if (prec == 0) {
+    const int ntm = (M + TT - 1) / TT, ntn = (Nn + TT - 1) / TT;
+    sym = sym && M == Nn && A == B && lda == ldb;
+    const unsigned ntiles = unsigned(sym ? ntn * (ntn + 1) / 2 : ntm * ntn);
+    dim3 grid(ntiles, unsigned(nsplit));
+    const double* a = (const double*)A;
+    const double* b = (const double*)B;
+#define NT_LAUNCH(OPV, SYMV) \
+    hipLaunchKernelGGL((k_gemm_nt_t128<OPV, SYMV>), grid, dim3(256), 0, s, a, lda, b, ldb, M, Nn, K, kchunk, ntn, Cpart)
+    if (sym) {
+      if (op == 1) NT_LAUNCH(1, true);
+      else if (op == 2) NT_LAUNCH(2, true);
+      else NT_LAUNCH(0, true);
+      hipLaunchKernelGGL(k_reduce_parts_t<true>, dim3(nb), dim3(256), 0, s, Cpart, int(nsplit), M, Nn, alpha, C);
+    } else {
+      if (op == 1) NT_LAUNCH(1, false);
+      else if (op == 2) NT_LAUNCH(2, false);
+      else NT_LAUNCH(0, false);
+      hipLaunchKernelGGL(k_reduce_parts_t<false>, dim3(nb), dim3(256), 0, s, Cpart, int(nsplit), M, Nn, alpha, C);
+    }
+#undef NT_LAUNCH
+  } else {
+    dim3 grid((Nn + GB - 1) / GB, (M + GB - 1) / GB, unsigned(nsplit));
+    hipLaunchKernelGGL(k_gemm_nt_f32c, grid, dim3(256), 0, s, (const float*)A, lda, (const float*)B, ldb, M, Nn,
+                       K, kchunk, 256, Cpart);
+    hipLaunchKernelGGL(k_reduce_parts, dim3(nb), dim3(256), 0, s, Cpart, int(nsplit), mn, alpha, C);
+  }
+  rec_end(rec, KC_GEMM_NT, s, (sym && prec == 0 ? 1.0 : 2.0) * double(M) * Nn * double(K));
   return hipGetLastError();
 }
 
@@ -309,8 +501,8 @@ static void launch_ls(const double* S, int lds, const TB* B, int64_t ldb, double
     dim3 grid(unsigned((R + 15) / 16), unsigned((M + 15) / 16));
     hipLaunchKernelGGL((k_gemm_tiny<TB, TRANS, LOWER>), grid, dim3(64), 0, s, S, lds, B, ldb, C, ldc, M, K, R, alpha);
   } else if (M > 64) {
-    dim3 grid(unsigned((R + GB - 1) / GB), unsigned((M + 127) / 128));
-    hipLaunchKernelGGL((k_gemm_ls<TB, TRANS, LOWER, 128>), grid, dim3(256), 0, s, S, lds, B, ldb, C, ldc, M, K, R,
+    dim3 grid(unsigned((R + TT - 1) / TT), unsigned((M + TT - 1) / TT));
+    hipLaunchKernelGGL((k_gemm_ls_t128<TB, TRANS, LOWER>), grid, dim3(256), 0, s, S, lds, B, ldb, C, ldc, M, K, R,
                        alpha);
   } else {
     dim3 grid(unsigned((R + GB - 1) / GB), unsigned((M + 63) / 64));

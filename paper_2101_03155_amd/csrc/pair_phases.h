@@ -51,6 +51,25 @@ __device__ __forceinline__ void block_sum2(T a, T b, double* out, double* red) {
 }
 
 
+// Copy E elements to LDS (dst[e] = src(e)) with every global load of a thread
+// issued before its first LDS store, so a workgroup keeps all its loads in
+// flight at once.
+template <typename C, int E, int NT, typename F>
+__device__ __forceinline__ void stage_in(C* dst, F src, int tid) {
+  constexpr int LP = (E + NT - 1) / NT;
+  C r[LP];
+#pragma unroll
+  for (int q = 0; q < LP; ++q) {
+    const int e = tid + q * NT;
+    if (E % NT == 0 || e < E) r[q] = src(e);
+  }
+#pragma unroll
+  for (int q = 0; q < LP; ++q) {
+    const int e = tid + q * NT;
+    if (E % NT == 0 || e < E) dst[e] = r[q];
+  }
+}
+
 // W_i -= v phi_j and (i != j) W_j -= v phi_i for the E grid points starting
 // at ro, with v = Re (pair a) and Im (pair b) of buf; with W == nullptr only
 // the energy sums are formed.  Optional partial sums of v rho go to eslot.
@@ -191,11 +210,31 @@ __device__ __forceinline__ void body_fwd_xy_r(const T* __restrict__ pi_, const T
   using C = cplx<T>;
   constexpr int H = N / 2, XS = r2c_xs<N>();
   constexpr int HN = H * N;
-  for (int e = tid; e < HN; e += NT) {
-    C v;
-    v.x = pi_[e] * pj_[e];
-    v.y = pi_[e + HN] * pj_[e + HN];
-    buf[e] = v;
+  {
+    // all of a thread's loads are issued before its first use (latency hiding
+    // at two workgroups per CU)
+    constexpr int LP = (HN + NT - 1) / NT;
+    T a0[LP], b0[LP], a1[LP], b1[LP];
+#pragma unroll
+    for (int q = 0; q < LP; ++q) {
+      const int e = tid + q * NT;
+      if (HN % NT == 0 || e < HN) {
+        a0[q] = pi_[e];
+        b0[q] = pj_[e];
+        a1[q] = pi_[e + HN];
+        b1[q] = pj_[e + HN];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < LP; ++q) {
+      const int e = tid + q * NT;
+      if (HN % NT == 0 || e < HN) {
+        C v;
+        v.x = a0[q] * b0[q];
+        v.y = a1[q] * b1[q];
+        buf[e] = v;
+      }
+    }
   }
   __syncthreads();
   fft_lines<T, N, H, N, 1, NT, -1, true, V>(buf, tw, tid);
@@ -241,7 +280,7 @@ __device__ __forceinline__ void body_conv_z_r(cplx<T>* spec_p, int f0, const Ker
   using C = cplx<T>;
   constexpr int XS = r2c_xs<N>(), PL = N * XS, E = N * TX;
   C* base = spec_p + f0;
-  for (int e = tid; e < E; e += NT) buf[e] = base[size_t(e / TX) * PL + (e % TX)];
+  stage_in<C, E, NT>(buf, [&](int e) { return base[size_t(e / TX) * PL + (e % TX)]; }, tid);
   __syncthreads();
   fft_lines<T, N, TX, 1, TX, NT, -1, false, V>(buf, tw, tid);
   for (int e = tid; e < E; e += NT) {
@@ -263,7 +302,7 @@ template <typename T, int N, int NT, int V = 0>
 __device__ __forceinline__ void body_inv_xy_r(const cplx<T>* in, cplx<T>* buf, const cplx<T>* tw, int tid) {
   using C = cplx<T>;
   constexpr int H = N / 2, XS = r2c_xs<N>();
-  for (int e = tid; e < N * XS; e += NT) buf[e] = in[e];
+  stage_in<C, N * XS, NT>(buf, [&](int e) { return in[e]; }, tid);
   __syncthreads();
   fft_lines<T, N, XS, 1, XS, NT, +1, false, V>(buf, tw, tid);
   // re-pack: Z[k] = X1[k] + i X2[k], Z[N-k] = conj X1[k] + i conj X2[k]; the
@@ -312,16 +351,35 @@ __device__ __forceinline__ void accumulate_w_r(const T* __restrict__ pi_, const 
   constexpr int HN = (N / 2) * N;
   T ea = T(0);
   if (wi) {
-    for (int e = tid; e < HN; e += NT) {
-      const cplx<T> v = buf[e];
-      const T fi0 = pi_[e], fj0 = pj_[e], fi1 = pi_[e + HN], fj1 = pj_[e + HN];
-      wi[e] -= v.x * fj0;
-      wi[e + HN] -= v.y * fj1;
-      if (off) {
-        wj[e] -= v.x * fi0;
-        wj[e + HN] -= v.y * fi1;
+    // batches of U elements per thread: all global loads of a batch first
+    constexpr int U = 3;
+    constexpr int LP = (HN + NT - 1) / NT;
+#pragma unroll
+    for (int q0 = 0; q0 < LP; q0 += U) {
+      T fi0[U], fj0[U], fi1[U], fj1[U], w0[U], w1[U], u0[U], u1[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = tid + (q0 + u) * NT;
+        if (q0 + u < LP && (HN % NT == 0 || e < HN)) {
+          fi0[u] = pi_[e]; fj0[u] = pj_[e]; fi1[u] = pi_[e + HN]; fj1[u] = pj_[e + HN];
+          w0[u] = wi[e]; w1[u] = wi[e + HN];
+          if (off) { u0[u] = wj[e]; u1[u] = wj[e + HN]; }
+        }
       }
-      if (EN) ea += v.x * fi0 * fj0 + v.y * fi1 * fj1;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = tid + (q0 + u) * NT;
+        if (q0 + u < LP && (HN % NT == 0 || e < HN)) {
+          const cplx<T> v = buf[e];
+          wi[e] = w0[u] - v.x * fj0[u];
+          wi[e + HN] = w1[u] - v.y * fj1[u];
+          if (off) {
+            wj[e] = u0[u] - v.x * fi0[u];
+            wj[e + HN] = u1[u] - v.y * fi1[u];
+          }
+          if (EN) ea += v.x * fi0[u] * fj0[u] + v.y * fi1[u] * fj1[u];
+        }
+      }
     }
   } else if (EN) {
     for (int e = tid; e < HN; e += NT) {

@@ -82,35 +82,40 @@ def autotune(ctx: "ace.Context", phi, pairs, grid: "ace.Grid", kernel: str, omeg
 
 
 def autotune_batched(ctx: "ace.Context", systems, precision: str = "fp32", reps: int = 2,
-                     modes=("graph", "persistent"), txvs=(8, 16), plans=(0, 1), bpcs=(4, 8)):
-    """Pick the batched launch form and shape (mode, x-tile, radix order,
-    workgroups per CU) by timing whole batched builds; returns dict(best, table)."""
+                     modes=("graph", "persistent"), layouts=("r2c", "split"), txvs=(8, 16), plans=(0, 1),
+                     bpcs=(2, 4, 8)):
+    """Pick the batched launch form and shape (mode, layout, x-tile, radix
+    order, workgroups per CU) by timing whole batched builds; returns
+    dict(best, table)."""
     import time
 
     import torch
 
     table = []
     for mode in modes:
-        for txv in txvs:
-            for plan in plans:
-                for bpc in bpcs:
-                    if mode == "graph" and bpc != bpcs[-1]:
-                        continue  # the per-phase launches size their own grids
-                    ctx.set_batched_shape(txv, plan, bpc)
-                    try:
-                        ctx.build_batched(systems, precision=precision, mode=mode, want_M=False)
-                    except ace.AceError as e:
-                        table.append({"mode": mode, "txv": txv, "plan": plan, "bpc": bpc, "error": str(e)})
-                        continue
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                    for _ in range(reps):
-                        ctx.build_batched(systems, precision=precision, mode=mode, want_M=False)
-                    torch.cuda.synchronize()
-                    ms = (time.perf_counter() - t0) * 1000.0 / reps
-                    table.append({"mode": mode, "txv": txv, "plan": plan, "bpc": bpc, "ms": ms})
+        for layout in layouts:
+            for txv in txvs:
+                if layout == "r2c" and txv != txvs[-1]:
+                    continue  # the x-tile only shapes the split layout
+                for plan in plans:
+                    for bpc in bpcs:
+                        if mode == "graph" and bpc != bpcs[-1]:
+                            continue  # the per-phase launches size their own grids
+                        row = {"mode": mode, "layout": layout, "txv": txv, "plan": plan, "bpc": bpc}
+                        ctx.set_batched_shape(txv, plan, bpc, layout)
+                        try:
+                            ctx.build_batched(systems, precision=precision, mode=mode, want_M=False)
+                        except ace.AceError as e:
+                            table.append(dict(row, error=str(e)))
+                            continue
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        for _ in range(reps):
+                            ctx.build_batched(systems, precision=precision, mode=mode, want_M=False)
+                        torch.cuda.synchronize()
+                        table.append(dict(row, ms=(time.perf_counter() - t0) * 1000.0 / reps))
     ok = [r for r in table if "ms" in r]
     best = min(ok, key=lambda r: r["ms"])
-    ctx.set_batched_shape(best["txv"], best["plan"], best["bpc"])
+    ctx.set_batched_shape(best["txv"], best["plan"], best["bpc"], best["layout"])
     return {"best": best, "table": table}
 

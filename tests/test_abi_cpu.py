@@ -89,8 +89,10 @@ def test_argument_validation(ctx):
     arr[1].grid = ace.Grid.cubic(24, 8.0).c()
     arr[0].npairs = 11
     assert lib.ace_build_batched(h, 2, arr, 1, 0) == -1
-    assert lib.ace_set_batched_shape(h, 12, 0, 4) == -1
-    assert lib.ace_set_batched_shape(h, 8, 1, 4) == 0
+    assert lib.ace_set_batched_shape(h, 12, 0, 4, 2) == -1
+    assert lib.ace_set_batched_shape(h, 8, 1, 4, 1) == -1
+    assert lib.ace_set_batched_shape(h, 8, 1, 4, 0) == 0
+    assert lib.ace_set_batched_shape(h, 16, 0, 8, 2) == 0
 
 
 def test_binding_refuses_without_gpu():

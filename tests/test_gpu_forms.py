@@ -104,19 +104,25 @@ def _small_batch(ctx, n_sys=5):
     return out
 
 
+@pytest.mark.parametrize("layout", ["r2c", "split"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_batched_equals_single_builds_bitwise(ctx, prec):
-    _say(f"batched vs single bitwise {prec}")
+def test_batched_equals_single_builds_bitwise(ctx, prec, layout):
+    _say(f"batched vs single bitwise {prec} layout={layout}")
     systems = _small_batch(ctx)
-    ctx.set_batched_shape(16, 0, 8)
-    res = ctx.build_batched(systems, precision=prec, mode="graph")
+    ctx.set_batched_shape(16, 0, 8, layout)
+    try:
+        res = ctx.build_batched(systems, precision=prec, mode="graph")
+    finally:
+        ctx.set_batched_shape(16, 0, 8)
     for q, sy in enumerate(systems):
         n = sy["grid"].n[0]
-        ctx.set_pair_shape(prec, n, False, 64)
+        saved = ctx.get_pair_shape(prec, n)
+        ctx.set_pair_shape(prec, n, layout, 64)
+        assert ctx.get_pair_shape(prec, n)[0] == layout
         try:
             r = ctx.build(sy["phi"], sy["pairs"], sy["grid"], kernel=sy["kernel"], omega=sy["omega"], precision=prec)
         finally:
-            ctx.set_pair_shape(prec, n, True, 64)
+            ctx.set_pair_shape(prec, n, *saved)
         assert res[q]["status"] == "ACE_OK"
         assert torch.equal(res[q]["ex"], r["ex"]), (q, res[q]["ex"].item(), r["ex"].item())
         assert torch.equal(res[q]["M"], r["M"])
