@@ -94,7 +94,9 @@ hipError_t gemm_ls(int bprec, bool trans, bool lower, const double* S, int lds, 
                    double* C, int64_t ldc, int M, int K, int64_t R, double alpha, hipStream_t s,
                    EventRecorder* rec);
 void launch_symmetrize(const double* M, int n, double* out, double* negM, double* ex, double* asym, hipStream_t s);
-void launch_cholesky(double* A, int n, int* info, hipStream_t s);
+// Blocked Cholesky of the lower triangle of A (n <= 512) in place; info must
+// be zero on entry; tinv is 64 x 64 doubles of scratch.
+void launch_cholesky(double* A, int n, int* info, double* tinv, hipStream_t s);
 void launch_trinv(const double* L, int n, double* X, hipStream_t s);
 void launch_colnorm(const double* A, int n, int64_t ng, double* res, hipStream_t s);
 int qrcp_blocks(int64_t ng);
@@ -139,7 +141,9 @@ hipError_t batched_segments(int prec, int n, int mode, int txv, int plan_v, int 
                             const BRound* h_segs, const BRound* d_segs, const BSys* sys, const BPack* packs,
                             const int64_t* starts, bool r2c, hipStream_t s);
 bool batched_r2c_fits(int prec, int n);
-int64_t batched_r2c_slot_items(int n, int phase);  // work items per pair slot of phase 0..2
+// work items per pair slot of phase 0..2 (the z pass packs two tiles per item
+// in the persistent launch, one in the per-phase launches)
+int64_t batched_r2c_slot_items(int n, int phase, bool persistent);
 void launch_zero(void* p, size_t bytes, hipStream_t s);
 
 // Learned screener (screener.hip).

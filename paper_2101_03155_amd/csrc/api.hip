@@ -677,6 +677,8 @@ static int build_impl(ace_ctx* c, const ace_grid* g, int norb, const double* phi
   WS(c, "Linv", size_t(norb) * norb * sizeof(double), Li);
   WS(c, "scal", 64 * sizeof(double), scal);
   WS(c, "info", 64, info);
+  double* tinv;
+  WS(c, "tinv", 64 * 64 * sizeof(double), tinv);
   if (prec == 1) WS(c, "phi32", size_t(norb) * ng * sizeof(float), phiw);
   else phiw = (void*)phi;
   const void* tw;
@@ -720,7 +722,8 @@ static int build_impl(ace_ctx* c, const ace_grid* g, int norb, const double* phi
   rec_begin(R, ST_TAIL, s);
   HIPCHK(c, gemm_nt(prec, 0, phiw, ng, W, ng, norb, norb, ng, dV, part, Mraw, s, R));
   launch_symmetrize(Mraw, norb, Mout, Lb, ex ? ex : scal, scal + 1, s);
-  launch_cholesky(Lb, norb, info, s);
+  launch_zero(info, sizeof(int), s);
+  launch_cholesky(Lb, norb, info, tinv, s);
   int hinfo = 0;
   HIPCHK(c, hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
@@ -866,7 +869,7 @@ int ace_build_batched(ace_ctx* c, int nsys, ace_system* sys, int prec, int mode)
         for (int k = 0; k < sg.npacks; ++k) {
           starts.push_back(acc);
           if (!r2c) acc += batched_phase_items(n, p, c->b_txv);
-          else if (p < 3) acc += (bp[sg.pack0 + k].pk.jb >= 0 ? 2 : 1) * batched_r2c_slot_items(n, p);
+          else if (p < 3) acc += (bp[sg.pack0 + k].pk.jb >= 0 ? 2 : 1) * batched_r2c_slot_items(n, p, mode == 1);
         }
         starts.push_back(acc);
         sg.nitems[p] = acc;
@@ -907,6 +910,8 @@ int ace_build_batched(ace_ctx* c, int nsys, ace_system* sys, int prec, int mode)
   WS(c, "bLinv", size_t(max_norb) * max_norb * sizeof(double), Li);
   WS(c, "bex", size_t(nsys) * 2 * sizeof(double), exs);
   WS(c, "binfo", size_t(nsys) * sizeof(int), infos);
+  double* btinv;
+  WS(c, "btinv", 64 * 64 * sizeof(double), btinv);
   WS(c, "bsys", size_t(nsys) * sizeof(BSys), dsys);
   WS(c, "bpacks", std::max<size_t>(bp.size(), 1) * sizeof(BPack), dbp);
   WS(c, "bsegs", std::max<size_t>(segs.size(), 1) * sizeof(BRound), dsegs);
@@ -942,6 +947,7 @@ int ace_build_batched(ace_ctx* c, int nsys, ace_system* sys, int prec, int mode)
   // the whole build, in stream order on the private stream
   auto enqueue = [&](hipStream_t s) -> int {
     launch_zero(bW, size_t(w_total) * es, s);
+    launch_zero(infos, size_t(nsys) * sizeof(int), s);
     if (prec == 1)
       for (int q = 0; q < nsys; ++q)
         launch_d2f(sys[q].phi, (float*)(bphi + size_t(w_off[q]) * es), int64_t(sys[q].norb) * grid_size(&sys[q].grid),
@@ -963,7 +969,7 @@ int ace_build_batched(ace_ctx* c, int nsys, ace_system* sys, int prec, int mode)
       hipError_t e = gemm_nt(prec, 0, ph, ng, W, ng, n, n, ng, grid_dv(&y.grid), part, Mraw, s, nullptr);
       if (e != hipSuccess) return fail(c, ACE_E_HIP, "batched M launch failed: %s", hipGetErrorString(e));
       launch_symmetrize(Mraw, n, y.M, Lb, y.ex ? y.ex : exs + 2 * q, exs + 2 * q + 1, s);
-      launch_cholesky(Lb, n, infos + q, s);
+      launch_cholesky(Lb, n, infos + q, btinv, s);
       launch_trinv(Lb, n, Li, s);
       e = gemm_ls(prec, false, true, Li, n, W, ng, y.xi, ng, n, n, ng, 1.0, s, nullptr);
       if (e != hipSuccess) return fail(c, ACE_E_HIP, "batched projector launch failed: %s", hipGetErrorString(e));

@@ -130,21 +130,28 @@ __global__ __launch_bounds__(BNT) void k_batched_persistent(int nseg, const BRou
 constexpr int BNTR = 512;
 
 // LDS buffer of the three phases: the in-plane bodies use N * XS values, the
-// z pass N * TX (TX can exceed XS on small grids, e.g. 16 > 9 at N = 16).
+// z pass two tiles of N * TX (TX can exceed XS on small grids, e.g. 16 > 9 at
+// N = 16).
 template <int N>
 __host__ __device__ constexpr int r2c_buf_elems() {
-  return N * r2c_tx<N>() > N * r2c_xs<N>() ? N * r2c_tx<N>() : N * r2c_xs<N>();
+  return 2 * N * r2c_tx<N>() > N * r2c_xs<N>() ? 2 * N * r2c_tx<N>() : N * r2c_xs<N>();
 }
 
+// Items per pair slot: one per z-plane in phases 0 and 2; in phase 1 one per
+// tpi z-pass tiles: 1 for the per-phase launches (256-thread workgroups), 2
+// in the persistent launch (each half of a 512-thread workgroup transforms one
+// tile).
 template <int N>
-__host__ __device__ constexpr int64_t r2c_slot_items(int phase) {
-  return phase == 1 ? int64_t(N) * r2c_xs<N>() / r2c_tx<N>() : int64_t(N);
+__host__ __device__ constexpr int64_t r2c_slot_items(int phase, int tpi) {
+  return phase == 1 ? (int64_t(N) * r2c_xs<N>() / r2c_tx<N>() + tpi - 1) / tpi : int64_t(N);
 }
 
-template <typename T, int N, int V>
-__device__ __forceinline__ void run_item_r(int p, int64_t j, const BRound& sg, const BSys* __restrict__ sys,
-                                           const BPack* __restrict__ packs, const int64_t* __restrict__ starts,
-                                           cplx<T>* buf, cplx<T>* tw, double* red) {
+// Item j of phase p, which belongs to pack q of the segment (the caller has
+// located q).  tw holds the twiddles of system *tw_sys (-1: none yet).
+template <typename T, int N, int V, int NT>
+__device__ __forceinline__ void run_item_r(int p, int64_t j, int q, const BRound& sg, const BSys* __restrict__ sys,
+                                           const BPack* __restrict__ packs, const int64_t* __restrict__ st,
+                                           cplx<T>* buf, cplx<T>* tw, int& tw_sys, double* red) {
   constexpr int XS = r2c_xs<N>();
   constexpr size_t NG = size_t(N) * N * N, PL = size_t(N) * XS;
   // an opaque copy of the thread index: keeps the per-thread index arithmetic
@@ -152,25 +159,31 @@ __device__ __forceinline__ void run_item_r(int p, int64_t j, const BRound& sg, c
   // item loop (where it would all stay live at once)
   int tid = threadIdx.x;
   asm volatile("" : "+v"(tid));
-  const int64_t* st = starts + sg.start_off[p];
-  int lo = 0, hi = sg.npacks;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (st[mid] <= j) lo = mid; else hi = mid;
-  }
-  const BPack bp = packs[sg.pack0 + lo];
+  const BPack bp = packs[sg.pack0 + q];
   const BSys& sy = sys[bp.sys];
-  const int64_t b = j - st[lo];
-  const int64_t per = r2c_slot_items<N>(p);
+  const int64_t b = j - st[q];
+  constexpr int TPI = NT == BNTR ? 2 : 1;
+  const int64_t per = r2c_slot_items<N>(p, TPI);
   const int slot = int(b / per);
   const int sub = int(b % per);
   const int oi = slot ? bp.pk.ib : bp.pk.ia, oj = slot ? bp.pk.jb : bp.pk.ja;
   cplx<T>* spec = static_cast<cplx<T>*>(bp.spec) + size_t(slot) * N * PL;
   const T* phi = static_cast<const T*>(sy.phi);
-  const cplx<T>* twg = static_cast<const cplx<T>*>(sy.tw);
   __syncthreads();  // the previous item's last reads of buf/tw are done
-  for (int i = tid; i < N; i += BNTR) tw[i] = twg[i];
-  if (p == 0) {
+  if (bp.sys != tw_sys) {
+    const cplx<T>* twg = static_cast<const cplx<T>*>(sy.tw);
+    for (int i = tid; i < N; i += NT) tw[i] = twg[i];
+    tw_sys = bp.sys;
+  }
+  if (NT != BNTR) {
+    // per-phase launch of the z pass with 256-thread workgroups: one tile per item
+    KernelParams kp;
+    kp.kind = sy.kind;
+    kp.omega = sy.omega;
+    kp.inv_ng = sy.inv_ng;
+    kp.g[0] = sy.g[0]; kp.g[1] = sy.g[1]; kp.g[2] = sy.g[2];
+    body_conv_z_r<T, N, r2c_tx<N>(), NT, V>(spec, sub * r2c_tx<N>(), kp, buf, tw, tid);
+  } else if (p == 0) {
     const size_t zo = size_t(sub) * N * N;
     body_fwd_xy_r<T, N, BNTR, V>(phi + size_t(oi) * NG + zo, phi + size_t(oj) * NG + zo, spec + size_t(sub) * PL,
                                  buf, tw, tid);
@@ -180,7 +193,12 @@ __device__ __forceinline__ void run_item_r(int p, int64_t j, const BRound& sg, c
     kp.omega = sy.omega;
     kp.inv_ng = sy.inv_ng;
     kp.g[0] = sy.g[0]; kp.g[1] = sy.g[1]; kp.g[2] = sy.g[2];
-    body_conv_z_r<T, N, r2c_tx<N>(), BNTR, V>(spec, sub * r2c_tx<N>(), kp, buf, tw, tid);
+    constexpr int TXR = r2c_tx<N>(), NTILE = N * XS / TXR, HALF = BNTR / 2;
+    const int half = tid >= HALF ? 1 : 0;
+    const int tile = 2 * sub + half;
+    // each half has its own N * TXR slice of the LDS buffer
+    body_conv_z_r<T, N, TXR, HALF, V>(spec, (tile < NTILE ? tile : NTILE - 1) * TXR, kp, buf + half * N * TXR, tw,
+                                      tid - half * HALF, tile < NTILE);
   } else {
     const size_t zo = size_t(sub) * N * N;
     body_inv_xy_r<T, N, BNTR, V>(spec + size_t(sub) * PL, buf, tw, tid);
@@ -191,17 +209,54 @@ __device__ __forceinline__ void run_item_r(int p, int64_t j, const BRound& sg, c
   }
 }
 
+// The items of phase p of one segment, split into contiguous ranges, one per
+// workgroup: the pack of the first item is found by bisection, then the pack
+// index only moves forward.
+template <typename T, int N, int V, int NT>
+__device__ __forceinline__ void run_range_r(int p, const BRound& sg, const BSys* __restrict__ sys,
+                                            const BPack* __restrict__ packs, const int64_t* __restrict__ starts,
+                                            cplx<T>* buf, cplx<T>* tw, int& tw_sys, double* red) {
+  const int64_t total = sg.nitems[p];
+  const int64_t per = (total + gridDim.x - 1) / gridDim.x;
+  int64_t j = int64_t(blockIdx.x) * per;
+  const int64_t jend = (j + per < total) ? j + per : total;
+  if (j >= jend) return;
+  const int64_t* st = starts + sg.start_off[p];
+  int lo = 0, hi = sg.npacks;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (st[mid] <= j) lo = mid; else hi = mid;
+  }
+  int q = lo;
+  for (; j < jend; ++j) {
+    while (q + 1 < sg.npacks && st[q + 1] <= j) ++q;
+    run_item_r<T, N, V, NT>(p, j, q, sg, sys, packs, st, buf, tw, tw_sys, red);
+  }
+}
+
 // One phase P of one segment (the phase is a template parameter so that each
 // launch carries only its own body).
 template <typename T, int N, int V, int P>
 __global__ __launch_bounds__(BNTR, 4) void k_batched_phase_r(BRound sg, const BSys* __restrict__ sys,
                                                           const BPack* __restrict__ packs,
                                                           const int64_t* __restrict__ starts) {
-  __shared__ cplx<T> buf[r2c_buf_elems<N>()];
+  __shared__ cplx<T> buf[N * r2c_xs<N>()];
   __shared__ cplx<T> tw[N];
   __shared__ double red[BNTR / 64];
-  for (int64_t j = blockIdx.x; j < sg.nitems[P]; j += gridDim.x)
-    run_item_r<T, N, V>(P, j, sg, sys, packs, starts, buf, tw, red);
+  int tw_sys = -1;
+  run_range_r<T, N, V, BNTR>(P, sg, sys, packs, starts, buf, tw, tw_sys, red);
+}
+
+// The z pass as its own per-phase launch: 256-thread workgroups, one tile each.
+template <typename T, int N, int V>
+__global__ __launch_bounds__(256, 8) void k_batched_conv_r(BRound sg, const BSys* __restrict__ sys,
+                                                        const BPack* __restrict__ packs,
+                                                        const int64_t* __restrict__ starts) {
+  __shared__ cplx<T> buf[N * r2c_tx<N>()];
+  __shared__ cplx<T> tw[N];
+  __shared__ double red[4];
+  int tw_sys = -1;
+  run_range_r<T, N, V, 256>(1, sg, sys, packs, starts, buf, tw, tw_sys, red);
 }
 
 template <typename T, int N, int V>
@@ -213,11 +268,11 @@ __global__ __launch_bounds__(BNTR, 4) void k_batched_persistent_r(int nseg, cons
   __shared__ cplx<T> tw[N];
   __shared__ double red[BNTR / 64];
   cg::grid_group grid = cg::this_grid();
+  int tw_sys = -1;
   for (int r = 0; r < nseg; ++r) {
     const BRound sg = segs[r];
     for (int p = 0; p < 3; ++p) {
-      for (int64_t j = blockIdx.x; j < sg.nitems[p]; j += gridDim.x)
-        run_item_r<T, N, V>(p, j, sg, sys, packs, starts, buf, tw, red);
+      run_range_r<T, N, V, BNTR>(p, sg, sys, packs, starts, buf, tw, tw_sys, red);
       grid.sync();
     }
   }
@@ -246,11 +301,14 @@ static hipError_t launch_seg_r(int mode, int nseg, const BRound* h_segs, const B
     for (int p = 0; p < 3; ++p) {
       const int64_t n = h_segs[r].nitems[p];
       if (n == 0) continue;
-      const unsigned g = unsigned(n < grid_cap ? n : grid_cap);
+      // one workgroup per item: the dispatcher overlaps the item prologues
+      // (blocks_per_cu > 8 caps the grid and loops instead)
+      const unsigned g = unsigned(blocks_per_cu > 8 && n > grid_cap ? grid_cap : n);
       if (p == 0)
         hipLaunchKernelGGL((k_batched_phase_r<T, N, V, 0>), dim3(g), dim3(BNTR), 0, s, h_segs[r], sys, packs, starts);
       else if (p == 1)
-        hipLaunchKernelGGL((k_batched_phase_r<T, N, V, 1>), dim3(g), dim3(BNTR), 0, s, h_segs[r], sys, packs, starts);
+        hipLaunchKernelGGL((k_batched_conv_r<T, N, V>), dim3(unsigned(n)), dim3(256), 0, s, h_segs[r], sys,
+                           packs, starts);
       else
         hipLaunchKernelGGL((k_batched_phase_r<T, N, V, 2>), dim3(g), dim3(BNTR), 0, s, h_segs[r], sys, packs, starts);
     }
@@ -266,9 +324,9 @@ bool batched_r2c_fits(int prec, int n) {
   }
 }
 
-int64_t batched_r2c_slot_items(int n, int phase) {
+int64_t batched_r2c_slot_items(int n, int phase, bool persistent) {
   switch (n) {
-#define X(nn) case nn: return r2c_slot_items<nn>(phase);
+#define X(nn) case nn: return r2c_slot_items<nn>(phase, persistent ? 2 : 1);
     X(16) X(24) X(32) X(48) X(64) X(80) X(96)
 #undef X
     default: return 0;

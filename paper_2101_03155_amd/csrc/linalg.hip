@@ -42,49 +42,146 @@ __global__ void k_symmetrize(const double* __restrict__ M, int n, double* __rest
   }
 }
 
-// In-place right-looking Cholesky of the lower triangle of A (n x n, one
-// workgroup).  info: 0 ok, k+1 if the pivot of column k is not positive,
-// -(k+1) if it is not finite.  The strict upper triangle is zeroed.  With
-// INLDS the matrix is staged in LDS (n <= 128).
-template <bool INLDS>
-__global__ __launch_bounds__(1024) void k_cholesky(double* __restrict__ Ag, int n, int* __restrict__ info) {
-  __shared__ double piv;
-  __shared__ int bad;
-  __shared__ double As[INLDS ? 128 * 128 : 1];
-  double* A = INLDS ? As : Ag;
-  if (INLDS)
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) As[e] = Ag[e];
-  if (threadIdx.x == 0) bad = 0;
+
+// ---------------------------------------------------------------- blocked Cholesky
+// -M = L L^T for n <= 512, right-looking over panels of CB = 64 columns:
+//   diagonal block: factor in LDS and form its inverse (one workgroup);
+//   panel:          L21 = A21 L11^-T (rows below the block);
+//   update:         A22 -= L21 L21^T (lower 64 x 64 tiles of the trailing matrix).
+// Only the lower triangle is read; the strict upper triangle is zeroed.  info
+// = k + 1 when the pivot of column k is not positive, -(k + 1) when it is not
+// finite; every kernel returns at once when info is already set.
+constexpr int CB = 64;
+
+__global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ A, int n, int k0,
+                                                   double* __restrict__ Tinv, int* __restrict__ info) {
+  __shared__ double D[CB][CB + 1];
+  __shared__ double X[CB][CB + 1];
+  if (*info) return;
+  const int b = (n - k0 < CB) ? n - k0 : CB;
+  const int tid = threadIdx.x;
+  // thread (tr, tc) owns rows 4 tr .. 4 tr + 3 and columns 4 tc .. 4 tc + 3
+  const int r0 = (tid >> 4) * 4, c0 = (tid & 15) * 4;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = r0 + a, j = c0 + q;
+      D[i][j] = (i < b && j <= i) ? A[int64_t(k0 + i) * n + k0 + j] : 0.0;
+    }
   __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    if (threadIdx.x == 0) {
-      const double d = A[k * n + k];
-      if (!isfinite(d)) bad = -(k + 1);
-      else if (!(d > 0.0)) bad = k + 1;
-      else { piv = sqrt(d); A[k * n + k] = piv; }
-    }
-    __syncthreads();
-    if (bad) break;
-    const double inv = 1.0 / piv;
-    for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) A[i * n + k] *= inv;
-    __syncthreads();
-    const int m = n - k - 1;  // trailing size
-    const int64_t tot = int64_t(m) * (m + 1) / 2;
-    for (int64_t t = threadIdx.x; t < tot; t += blockDim.x) {
-      // t -> (i, j) with 0 <= j <= i < m  (row-major lower triangle)
-      int i = int((sqrt(8.0 * double(t) + 1.0) - 1.0) * 0.5);
-      while (int64_t(i) * (i + 1) / 2 > t) --i;
-      while (int64_t(i + 1) * (i + 2) / 2 <= t) ++i;
-      const int j = int(t - int64_t(i) * (i + 1) / 2);
-      const int gi = k + 1 + i, gj = k + 1 + j;
-      A[gi * n + gj] -= A[gi * n + k] * A[gj * n + k];
-    }
+  // a_ij -= a_ik a_jk / a_kk on unscaled columns: one barrier per column
+  int bad = 0;
+  for (int k = 0; k < b; ++k) {
+    const double d = D[k][k];
+    if (!isfinite(d)) { bad = -(k0 + k + 1); break; }
+    if (!(d > 0.0)) { bad = k0 + k + 1; break; }
+    const double inv = 1.0 / d;
+    double li[4], lj[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) { li[a] = D[r0 + a][k] * inv; lj[a] = D[c0 + a][k]; }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = r0 + a, j = c0 + q;
+        if (j > k && j <= i) D[i][j] -= li[a] * lj[q];
+      }
     __syncthreads();
   }
-  if (threadIdx.x == 0) info[0] = bad;
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-    const int i = e / n, j = e % n;
-    Ag[e] = (j > i) ? 0.0 : A[e];
+  if (bad) {
+    if (tid == 0) *info = bad;
+    return;
+  }
+  // scale: L[i][k] = a_ik / sqrt(a_kk) (zero above the diagonal and beyond b)
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = r0 + a, k = c0 + q;
+      X[i][k] = (i < b && k <= i) ? D[i][k] / sqrt(D[k][k]) : 0.0;
+    }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) D[r0 + a][c0 + q] = X[r0 + a][c0 + q];
+  __syncthreads();
+  // inverse by rows: X[i][c] = (delta_ic - sum_{c <= k < i} L[i][k] X[k][c]) / L[i][i],
+  // four lanes per column c, combined with shuffles
+  const int c = tid >> 2, part = tid & 3;
+  for (int i = 0; i < b; ++i) {
+    double acc = 0.0;
+    if (c < i)
+      for (int k = c + part; k < i; k += 4) acc += D[i][k] * X[k][c];
+    acc += __shfl_xor(acc, 1, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    if (part == 0 && c < b) X[i][c] = (c > i) ? 0.0 : (((i == c) ? 1.0 : 0.0) - acc) / D[i][i];
+    __syncthreads();
+  }
+  for (int e = tid; e < b * b; e += 256) {
+    const int i = e / b, j = e % b;
+    A[int64_t(k0 + i) * n + k0 + j] = D[i][j];
+    Tinv[i * CB + j] = X[i][j];
+  }
+  // the strict upper triangle right of the block
+  for (int e = tid; e < b * (n - k0 - b); e += 256) {
+    const int i = e / (n - k0 - b), j = k0 + b + e % (n - k0 - b);
+    A[int64_t(k0 + i) * n + j] = 0.0;
+  }
+}
+
+// Rows r0 .. r0 + 63 (below the block): L21[i][c] = sum_{d <= c} A21[i][d] Tinv[c][d].
+__global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ A, int n, int k0,
+                                                    const double* __restrict__ Tinv, const int* __restrict__ info) {
+  __shared__ double T[CB][CB + 1];
+  __shared__ double R[CB][CB + 1];
+  if (*info) return;
+  const int b = (n - k0 < CB) ? n - k0 : CB;
+  const int r0 = k0 + b + blockIdx.x * CB;
+  const int rows = (n - r0 < CB) ? n - r0 : CB;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < CB * CB; e += 256) {
+    const int i = e / CB, j = e % CB;
+    T[i][j] = (i < b && j < b) ? Tinv[i * CB + j] : 0.0;
+    R[i][j] = (i < rows && j < b) ? A[int64_t(r0 + i) * n + k0 + j] : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < rows * b; e += 256) {
+    const int i = e / b, c = e % b;
+    double acc = 0.0;
+    for (int d = 0; d <= c; ++d) acc += R[i][d] * T[c][d];
+    A[int64_t(r0 + i) * n + k0 + c] = acc;
+  }
+}
+
+// Trailing update of the lower 64 x 64 tile (ti, tj), tj <= ti, of rows and
+// columns from k0 + b: A[i][j] -= sum_c L21[i][c] L21[j][c] for j <= i.
+__global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ A, int n, int k0,
+                                                     const int* __restrict__ info) {
+  __shared__ double Li[CB][CB + 1];
+  __shared__ double Lj[CB][CB + 1];
+  if (*info) return;
+  const int b = (n - k0 < CB) ? n - k0 : CB;
+  const int base = k0 + b;
+  int t = blockIdx.x, ti = 0;
+  while (t > ti) { t -= ti + 1; ++ti; }
+  const int tj = t;
+  const int i0 = base + ti * CB, j0 = base + tj * CB;
+  const int ri = (n - i0 < CB) ? n - i0 : CB, rj = (n - j0 < CB) ? n - j0 : CB;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < CB * CB; e += 256) {
+    const int r = e / CB, c = e % CB;
+    Li[r][c] = (r < ri && c < b) ? A[int64_t(i0 + r) * n + k0 + c] : 0.0;
+    Lj[r][c] = (r < rj && c < b) ? A[int64_t(j0 + r) * n + k0 + c] : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < ri * rj; e += 256) {
+    const int r = e / rj, q = e % rj;
+    if (j0 + q > i0 + r) continue;
+    double acc = 0.0;
+    for (int c = 0; c < b; ++c) acc += Li[r][c] * Lj[q][c];
+    A[int64_t(i0 + r) * n + j0 + q] -= acc;
   }
 }
 
@@ -874,11 +971,16 @@ static int grid_for(int64_t n, int nt, int cap = 4096) {
 void launch_symmetrize(const double* M, int n, double* out, double* negM, double* ex, double* asym, hipStream_t s) {
   hipLaunchKernelGGL(k_symmetrize, dim3(1), dim3(256), 0, s, M, n, out, negM, ex, asym);
 }
-void launch_cholesky(double* A, int n, int* info, hipStream_t s) {
-  if (n <= 128)
-    hipLaunchKernelGGL(k_cholesky<true>, dim3(1), dim3(1024), 0, s, A, n, info);
-  else
-    hipLaunchKernelGGL(k_cholesky<false>, dim3(1), dim3(1024), 0, s, A, n, info);
+// info must be zero on entry (the blocked kernels skip work once it is set).
+void launch_cholesky(double* A, int n, int* info, double* tinv, hipStream_t s) {
+  for (int k0 = 0; k0 < n; k0 += CB) {
+    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, A, n, k0, tinv, info);
+    const int rest = n - k0 - CB;
+    if (rest <= 0) break;
+    const int tiles = (rest + CB - 1) / CB;
+    hipLaunchKernelGGL(k_chol_panel, dim3(tiles), dim3(256), 0, s, A, n, k0, tinv, info);
+    hipLaunchKernelGGL(k_chol_update, dim3(tiles * (tiles + 1) / 2), dim3(256), 0, s, A, n, k0, info);
+  }
 }
 void launch_trinv(const double* L, int n, double* X, hipStream_t s) {
   hipLaunchKernelGGL(k_trinv_lower, dim3(n), dim3(64), 0, s, L, n, X);

@@ -274,13 +274,16 @@ __device__ __forceinline__ void body_fwd_xy_r(const T* __restrict__ pi_, const T
 
 // z lines of the TX consecutive flattened columns starting at f0 of one
 // pair's half spectrum: forward FFT, times v(G)/N^3, inverse FFT; in place.
+// With active == false the caller's threads take part in the barriers only
+// (no global loads or stores), so a workgroup can split into independent
+// groups of NT threads working on different tiles.
 template <typename T, int N, int TX, int NT, int V = 0>
 __device__ __forceinline__ void body_conv_z_r(cplx<T>* spec_p, int f0, const KernelParams& kp, cplx<T>* buf,
-                                              const cplx<T>* tw, int tid) {
+                                              const cplx<T>* tw, int tid, bool active = true) {
   using C = cplx<T>;
   constexpr int XS = r2c_xs<N>(), PL = N * XS, E = N * TX;
   C* base = spec_p + f0;
-  stage_in<C, E, NT>(buf, [&](int e) { return base[size_t(e / TX) * PL + (e % TX)]; }, tid);
+  if (active) stage_in<C, E, NT>(buf, [&](int e) { return base[size_t(e / TX) * PL + (e % TX)]; }, tid);
   __syncthreads();
   fft_lines<T, N, TX, 1, TX, NT, -1, false, V>(buf, tw, tid);
   for (int e = tid; e < E; e += NT) {
@@ -293,7 +296,8 @@ __device__ __forceinline__ void body_conv_z_r(cplx<T>* spec_p, int f0, const Ker
   }
   __syncthreads();
   fft_lines<T, N, TX, 1, TX, NT, +1, false, V>(buf, tw, tid);
-  for (int e = tid; e < E; e += NT) base[size_t(e / TX) * PL + (e % TX)] = buf[e];
+  if (active)
+    for (int e = tid; e < E; e += NT) base[size_t(e / TX) * PL + (e % TX)] = buf[e];
 }
 
 // Half spectrum of plane z -> the real potential of the plane, left in buf as
