@@ -49,10 +49,9 @@ def parse():
     ap.add_argument("--screener", default=os.path.join(ROOT, "paper_2101_03155_amd", "models",
                                                        "screener_water_erfc.npz"))
     ap.add_argument("--skip-forms", default="", help="comma list of precision,batched,learned")
-    ap.add_argument("--shape", default="r2c", choices=["auto", "default", "fused", "split", "r2c"],
-                    help="pair-stage launch shape: autotuned, library default, or forced (default: r2c with 32 "
-                         "packs per launch, the fastest measured for this workload, fixed so that profiles and "
-                         "the bench line agree)")
+    ap.add_argument("--shape", default="owner", choices=["auto", "default", "fused", "split", "r2c", "owner"],
+                    help="pair-stage launch shape: autotuned, library default, or forced (default: owner, the "
+                         "fastest measured for this workload, fixed so that profiles and the bench line agree)")
     ap.add_argument("--max-packs", type=int, default=32, help="packs per pair-stage launch for a forced shape")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB three times (calibrates FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -307,7 +306,7 @@ def main():
         pairs0, _ = ctx.pairlist(phi0, grid, args.rho_cut)
         tuned = autotune(ctx, phi0, pairs0, grid, kind, omega, prec)
         del phi0, pairs0
-    elif args.shape in ("fused", "split", "r2c"):
+    elif args.shape in ("fused", "split", "r2c", "owner"):
         ctx.set_pair_shape(prec, spec.N, args.shape, args.max_packs)
     shape = ctx.get_pair_shape(prec, spec.N)
 
@@ -344,7 +343,9 @@ def main():
         peak = HBM_PEAK_GBS
         achieved = units / (ms_l / 1000.0) / 1e9
         roof = {"bound": "hbm", "unit": "GB/s"}
-    kname = CLASS_KERNEL[dom] + ("_r" if shape[0] == "r2c" and dom in (0, 1, 2) else "")
+    kname = CLASS_KERNEL[dom]
+    if shape[0] in ("r2c", "owner") and dom in (0, 1, 2):
+        kname = "k_inv_owner_r" if (shape[0] == "owner" and dom == 2) else kname + "_r"
     roof.update({"kernel": kname, "class": CLASS_NAMES[dom], "launches_per_step": n_l / args.steps,
                  "avg_launch_us": 1000.0 * ms_l / max(n_l, 1),
                  "algorithmic_per_launch": units / max(n_l, 1),

@@ -169,8 +169,16 @@ int ace_profile_read(ace_ctx* ctx, int cls, int64_t* launches, double* total_ms,
  *   fused = 1  one workgroup per (z-plane, pack) does both in-plane FFTs with
  *              the plane in LDS (12 N^3 s per pair);
  *   fused = 2  real-to-complex: one workgroup per (z-plane, pair) on the half
- *              spectrum N x N x (N/2 + 1) (12 N^3 s per pair, half the LDS).
- * A path whose plane does not fit in LDS for this size falls back to 0.
+ *              spectrum N x N x (N/2 + 1) (12 N^3 s per pair, half the LDS);
+ *   fused = 3  real-to-complex with the half spectra of all pairs resident and
+ *              W formed per owner row: one workgroup per (z-plane, orbital k)
+ *              sums v_kj phi_j over k's pairs and writes W_k once (about
+ *              9 N^3 s per pair; no conflict-free rounds).  When the spectra
+ *              exceed ACE_OWNER_SPECTRA_MAX bytes (default 96 GiB) the build
+ *              uses fused = 2 instead.  The default where two real-to-complex
+ *              planes fit in one CU's LDS.
+ * A path whose plane does not fit in LDS for this size falls back to 0; other
+ * values of fused are ACE_E_ARG.
  * max_packs (>= 1) caps the packs per launch.  Results agree between paths to
  * rounding.
  */

@@ -22,7 +22,7 @@ STATUS = {0: "ACE_OK", -1: "ACE_E_ARG", -2: "ACE_E_HIP", -3: "ACE_E_NOMEM", -4: 
           -5: "ACE_E_CAPACITY", -6: "ACE_E_NONFINITE", -7: "ACE_E_UNSUPPORTED"}
 KERNELS = {"bare": 0, "coulomb": 0, "erfc": 1}
 PRECISIONS = {"fp64": 0, "fp32": 1}
-PAIR_PATHS = {"split": 0, "fused": 1, "r2c": 2}
+PAIR_PATHS = {"split": 0, "fused": 1, "r2c": 2, "owner": 3}
 PAIR_PATH_NAMES = {v: k for k, v in PAIR_PATHS.items()}
 
 # profile classes (see include/ace.h)
@@ -283,8 +283,8 @@ class Context:
         return n.value, ms.value, u.value
 
     def set_pair_shape(self, precision: str, n: int, path, max_packs: int):
-        """path: "split" (or False/0), "fused" (True/1) or "r2c" (2); a path that
-        does not fit the grid size falls back to the split passes."""
+        """path: "split" (or False/0), "fused" (True/1), "r2c" (2) or "owner" (3);
+        a path that does not fit the grid size falls back to the split passes."""
         code = PAIR_PATHS[path] if isinstance(path, str) else int(path)
         self._check(self.lib.ace_set_pair_shape(self.h, PRECISIONS[precision], n, code, max_packs))
 

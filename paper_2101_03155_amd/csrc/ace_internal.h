@@ -47,7 +47,8 @@ struct BRound {                // one segment: the packs of one grid size in one
 // Kernel launch shape of the pair stage, chosen by the tuner.
 struct PairShape {
   int fused_xy;    // 0: split passes; 1: one workgroup per (plane, pack) does both in-plane FFTs;
-                   // 2: real-to-complex, one workgroup per (plane, pair) on the half spectrum
+                   // 2: real-to-complex, one workgroup per (plane, pair) on the half spectrum;
+                   // 3: real-to-complex with all spectra resident and W formed per owner row
   int nt_xy;       // threads of the in-plane kernels (fused path)
   int tx;          // x-tile of the strided line kernels
 };
@@ -80,6 +81,12 @@ hipError_t pair_round(int prec, int N, const PairShape& sh, const void* phi, voi
 int pair_energy_blocks(int N, const PairShape& sh);
 bool pair_supported(int N);
 bool pair_r2c_fits(int prec, int N);
+int pair_r2c_ntile(int N);  // z-pass tiles per pair slot of the real-to-complex path
+// Owner-computes W over all pairs (spectra of every pair resident); W may be
+// null (energies only); epart: per (pack, tile) partial energies or null.
+hipError_t pair_owner(int prec, int N, const void* phi, void* spec, const Pack* packs, int npacks, int npairs,
+                      const int32_t* adj_ptr, const int32_t* adj, int norb, int64_t nadj, void* W, double* epart,
+                      const void* tw, const KernelParams& kp, int chunk, hipStream_t s, EventRecorder* rec);
 size_t pair_spec_elems(int prec, int N, const PairShape& sh);
 
 // Dense kernels (gemm.hip, linalg.hip).

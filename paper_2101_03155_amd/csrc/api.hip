@@ -103,6 +103,12 @@ struct Schedule {
   std::vector<Launch> launches;  // (first pack, pack count, pair count) per launch
   std::vector<int> round_first, round_count;  // packs of each conflict-free round
   int max_launch = 0;
+  // owner-computes W: packs of consecutive pairs in input order, their pair
+  // indices, and per orbital k the adjacency entries (pair index, partner)
+  // adj[2 * a], adj[2 * a + 1] for a in [adj_ptr[k], adj_ptr[k + 1])
+  std::vector<Pack> opacks;
+  std::vector<int64_t> opidx;
+  std::vector<int32_t> adj_ptr, adj;
 };
 
 struct ace_ctx {
@@ -125,6 +131,7 @@ struct ace_ctx {
   std::map<uint64_t, hipGraphExec_t> graphs;
   std::vector<uint64_t> graph_order;
   int b_txv = 16, b_plan = 0, b_bpc = 8, b_layout = 2;
+  size_t owner_max = size_t(96) << 30;  // resident spectra budget of the owner-computes path
 };
 
 static int fail(ace_ctx* c, int code, const char* fmt, ...) {
@@ -295,6 +302,46 @@ static void make_schedule(const std::vector<int32_t>& pr, int64_t npairs, int no
 }
 
 // Validate a host copy of a pair list and return its (cached) schedule.
+static void make_owner_schedule(const std::vector<int32_t>& pr, int64_t npairs, int norb, Schedule& S) {
+  const int64_t npk = (npairs + 1) / 2;
+  S.opacks.resize(size_t(npk));
+  S.opidx.assign(size_t(2 * npk), -1);
+  for (int64_t p = 0; p < npk; ++p) {
+    Pack& pk = S.opacks[size_t(p)];
+    pk.ia = pr[4 * p];
+    pk.ja = pr[4 * p + 1];
+    S.opidx[size_t(2 * p)] = 2 * p;
+    if (2 * p + 1 < npairs) {
+      pk.ib = pr[4 * p + 2];
+      pk.jb = pr[4 * p + 3];
+      S.opidx[size_t(2 * p + 1)] = 2 * p + 1;
+    } else {
+      pk.ib = -1;
+      pk.jb = -1;
+    }
+  }
+  std::vector<int32_t> deg(size_t(norb) + 1, 0);
+  for (int64_t t = 0; t < npairs; ++t) {
+    ++deg[size_t(pr[2 * t])];
+    if (pr[2 * t + 1] != pr[2 * t]) ++deg[size_t(pr[2 * t + 1])];
+  }
+  S.adj_ptr.assign(size_t(norb) + 1, 0);
+  for (int k = 0; k < norb; ++k) S.adj_ptr[size_t(k) + 1] = S.adj_ptr[size_t(k)] + deg[size_t(k)];
+  S.adj.assign(size_t(2) * S.adj_ptr[size_t(norb)], 0);
+  std::vector<int32_t> fill(S.adj_ptr.begin(), S.adj_ptr.end() - 1);
+  for (int64_t t = 0; t < npairs; ++t) {
+    const int i = pr[2 * t], j = pr[2 * t + 1];
+    int32_t a = fill[size_t(i)]++;
+    S.adj[size_t(2 * a)] = int32_t(t);
+    S.adj[size_t(2 * a + 1)] = j;
+    if (j != i) {
+      a = fill[size_t(j)]++;
+      S.adj[size_t(2 * a)] = int32_t(t);
+      S.adj[size_t(2 * a + 1)] = i;
+    }
+  }
+}
+
 static int schedule_for(ace_ctx* c, const std::vector<int32_t>& pr, int64_t npairs, int norb, int max_packs,
                         const Schedule** out) {
   uint64_t h = 1469598103934665603ull;
@@ -313,6 +360,7 @@ static int schedule_for(ace_ctx* c, const std::vector<int32_t>& pr, int64_t npai
     if (c->schedules.size() > 64) c->schedules.clear();
     Schedule S;
     make_schedule(pr, npairs, norb, max_packs, S);
+    make_owner_schedule(pr, npairs, norb, S);
     sit = c->schedules.emplace(key, std::move(S)).first;
   }
   *out = &sit->second;
@@ -331,6 +379,7 @@ int ace_create(ace_ctx** out, void* stream) {
   // first HIP call then reports ACE_E_HIP.
   if (hipGetDevice(&c->device) != hipSuccess) c->device = -1;
   if (const char* cap = getenv("ACE_WORKSPACE_MAX")) c->ws_cap = (size_t)strtoull(cap, nullptr, 10);
+  if (const char* om = getenv("ACE_OWNER_SPECTRA_MAX")) c->owner_max = (size_t)strtoull(om, nullptr, 10);
   *out = c;
   return ACE_OK;
 }
@@ -381,10 +430,11 @@ int ace_profile_read(ace_ctx* c, int cls, int64_t* launches, double* total_ms, d
 }
 
 int ace_set_pair_shape(ace_ctx* c, int prec, int n, int fused, int max_packs) {
-  if (!c || (prec != 0 && prec != 1) || !pair_supported(n) || max_packs < 1)
+  if (!c || (prec != 0 && prec != 1) || !pair_supported(n) || max_packs < 1 || fused < 0 || fused > 3)
     return fail(c, ACE_E_ARG, "bad pair shape");
   PairShape sh = pair_default_shape(prec, n);
-  sh.fused_xy = (fused == 2 && pair_r2c_fits(prec, n)) ? 2 : (fused && pair_fused_fits(prec, n)) ? 1 : 0;
+  sh.fused_xy = (fused >= 2 && fused <= 3 && pair_r2c_fits(prec, n)) ? fused
+                : (fused == 1 && pair_fused_fits(prec, n)) ? 1 : 0;
   c->shapes[n * 2 + prec] = sh;
   c->max_packs[n * 2 + prec] = max_packs;
   c->schedules.clear();
@@ -657,18 +707,32 @@ static int build_impl(ace_ctx* c, const ace_grid* g, int norb, const double* phi
 
   const size_t es = prec == 0 ? sizeof(double) : sizeof(float);
   const PairShape sh = shape_for(c, prec, N);
-  const int nblk = pair_energy_blocks(N, sh);
+  // owner-computes W when every pair's half spectrum fits the budget
+  const int64_t onpk = int64_t(S.opacks.size());
+  const size_t slot_bytes = size_t(N) * N * (N / 2 + 1) * 2 * es;
+  const bool owner = sh.fused_xy == 3 && pair_r2c_fits(prec, N) && size_t(2 * onpk) * slot_bytes <= c->owner_max;
+  const int nblk = owner ? pair_r2c_ntile(N) : pair_energy_blocks(N, sh);
   void *W, *spec, *phiw;
   Pack* dpk;
   int64_t* dpidx;
+  int32_t *dadjp = nullptr, *dadj = nullptr;
   double *epart = nullptr, *part, *Mraw, *Lb, *Li, *scal;
   int* info;
   if (xi) WS(c, "W", size_t(norb) * ng * es, W);
   else W = nullptr;
-  WS(c, "spec", size_t(S.max_launch) * pair_spec_elems(prec, N, sh) * 2 * es, spec);
-  WS(c, "packs", size_t(npk) * sizeof(Pack), dpk);
-  WS(c, "pidx", size_t(npk) * 2 * sizeof(int64_t), dpidx);
-  if (pair_energy) WS(c, "epart", size_t(S.max_launch) * nblk * 2 * sizeof(double), epart);
+  if (owner) {
+    WS(c, "spec", size_t(2 * onpk) * slot_bytes, spec);
+    WS(c, "packs", size_t(onpk) * sizeof(Pack), dpk);
+    WS(c, "pidx", size_t(onpk) * 2 * sizeof(int64_t), dpidx);
+    WS(c, "adjp", S.adj_ptr.size() * sizeof(int32_t), dadjp);
+    WS(c, "adj", std::max<size_t>(S.adj.size(), 2) * sizeof(int32_t), dadj);
+    if (pair_energy) WS(c, "epart", size_t(onpk) * nblk * 2 * sizeof(double), epart);
+  } else {
+    WS(c, "spec", size_t(S.max_launch) * pair_spec_elems(prec, N, sh) * 2 * es, spec);
+    WS(c, "packs", size_t(npk) * sizeof(Pack), dpk);
+    WS(c, "pidx", size_t(npk) * 2 * sizeof(int64_t), dpidx);
+    if (pair_energy) WS(c, "epart", size_t(S.max_launch) * nblk * 2 * sizeof(double), epart);
+  }
   int64_t kchunk;
   const int64_t nsplit = gemm_nt_nsplit(norb, norb, ng, &kchunk);
   WS(c, "mpart", size_t(nsplit) * norb * norb * sizeof(double), part);
@@ -685,10 +749,18 @@ static int build_impl(ace_ctx* c, const ace_grid* g, int norb, const double* phi
   rc = twiddles(c, N, prec, &tw);
   if (rc) return rc;
 
-  HIPCHK(c, hipMemcpyAsync(dpk, S.packs.data(), size_t(npk) * sizeof(Pack), hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemcpyAsync(dpidx, S.pidx.data(), size_t(npk) * 2 * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  if (owner) {
+    HIPCHK(c, hipMemcpyAsync(dpk, S.opacks.data(), size_t(onpk) * sizeof(Pack), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(dpidx, S.opidx.data(), size_t(onpk) * 2 * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(dadjp, S.adj_ptr.data(), S.adj_ptr.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    if (!S.adj.empty())
+      HIPCHK(c, hipMemcpyAsync(dadj, S.adj.data(), S.adj.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  } else {
+    HIPCHK(c, hipMemcpyAsync(dpk, S.packs.data(), size_t(npk) * sizeof(Pack), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(dpidx, S.pidx.data(), size_t(npk) * 2 * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  }
   if (prec == 1) launch_d2f(phi, (float*)phiw, int64_t(norb) * ng, s);
-  if (W) HIPCHK(c, hipMemsetAsync(W, 0, size_t(norb) * ng * es, s));
+  if (W && !owner) HIPCHK(c, hipMemsetAsync(W, 0, size_t(norb) * ng * es, s));  // the owner path writes every row
 
   KernelParams kp;
   kp.kind = kernel;
@@ -698,10 +770,16 @@ static int build_impl(ace_ctx* c, const ace_grid* g, int norb, const double* phi
 
   // (c) pair Poisson solves, round by round
   rec_begin(R, ST_PAIRS, s);
-  for (const auto& L : S.launches) {
-    HIPCHK(c, pair_round(prec, N, sh, phiw, spec, dpk + L.first, L.second, L.npairs, W, epart, tw, kp, s, R));
-    if (pair_energy)
-      launch_pair_energy(epart, L.second, nblk, dpk + L.first, dpidx + 2 * L.first, dV, pair_energy, s);
+  if (owner) {
+    HIPCHK(c, pair_owner(prec, N, phiw, spec, dpk, int(onpk), int(npairs), dadjp, dadj, norb,
+                         int64_t(S.adj.size() / 2), W, epart, tw, kp, 1 << 30, s, R));
+    if (pair_energy) launch_pair_energy(epart, int(onpk), nblk, dpk, dpidx, dV, pair_energy, s);
+  } else {
+    for (const auto& L : S.launches) {
+      HIPCHK(c, pair_round(prec, N, sh, phiw, spec, dpk + L.first, L.second, L.npairs, W, epart, tw, kp, s, R));
+      if (pair_energy)
+        launch_pair_energy(epart, L.second, nblk, dpk + L.first, dpidx + 2 * L.first, dV, pair_energy, s);
+    }
   }
   rec_end(R, ST_PAIRS, s);
   if (!xi) {  // energies only

@@ -174,16 +174,38 @@ __global__ __launch_bounds__(NT) void k_fwd_xy_r(const T* __restrict__ phi, cplx
                           spec + size_t(slot) * N * PL + size_t(z) * PL, buf, tw, tid);
 }
 
+// epart != nullptr: per-tile partial sums of sum_r rho v for the pair
+// energies, epart[2 * (pack * ntile + tile) + (slot & 1)].
 template <typename T, int N, int TX, int NT>
 __global__ __launch_bounds__(NT) void k_conv_z_r(cplx<T>* __restrict__ spec, const Pack* __restrict__ packs,
-                                                 const cplx<T>* __restrict__ twg, KernelParams kp) {
+                                                 const cplx<T>* __restrict__ twg, KernelParams kp,
+                                                 double* __restrict__ epart) {
   constexpr size_t PL = size_t(N) * r2c_xs<N>();
   __shared__ cplx<T> buf[N * TX];
   __shared__ cplx<T> tw[N];
+  __shared__ double red[NT / 64];
   const int slot = blockIdx.y;
   if ((slot & 1) && packs[slot >> 1].jb < 0) return;
   for (int t = threadIdx.x; t < N; t += NT) tw[t] = twg[t];
-  body_conv_z_r<T, N, TX, NT>(spec + size_t(slot) * N * PL, blockIdx.x * TX, kp, buf, tw, threadIdx.x);
+  double* es = epart ? epart + 2 * (size_t(slot >> 1) * gridDim.x + blockIdx.x) + (slot & 1) : nullptr;
+  body_conv_z_r<T, N, TX, NT>(spec + size_t(slot) * N * PL, blockIdx.x * TX, kp, buf, tw, threadIdx.x, true, es, red);
+}
+
+// Owner-computes W: blockIdx.x = z-plane, blockIdx.y = orbital k; adjacency
+// entries adj_ptr[k] .. adj_ptr[k + 1] of (pair slot, partner).
+template <typename T, int N, int NT>
+__global__ __launch_bounds__(NT, 4) void k_inv_owner_r(const T* __restrict__ phi, const cplx<T>* __restrict__ spec,
+                                                    const int32_t* __restrict__ adj_ptr,
+                                                    const int32_t* __restrict__ adj, T* __restrict__ W,
+                                                    const cplx<T>* __restrict__ twg) {
+  constexpr size_t NG = size_t(N) * N * N;
+  __shared__ cplx<T> buf[N * r2c_xs<N>()];
+  __shared__ cplx<T> tw[N];
+  const int z = blockIdx.x, k = blockIdx.y;
+  for (int t = threadIdx.x; t < N; t += NT) tw[t] = twg[t];
+  const size_t zo = size_t(z) * N * N;
+  body_inv_owner_r<T, N, NT>(phi, spec, adj, adj_ptr[k], adj_ptr[k + 1], zo, W + size_t(k) * NG + zo, buf, tw,
+                             threadIdx.x);
 }
 
 template <typename T, int N, int NT, bool EN>
@@ -237,7 +259,7 @@ static hipError_t pair_round_t(const PairShape& sh, const void* phi_, void* spec
       rec_end(rec, KC_FWD_XY, s, 3 * u);
       rec_begin(rec, KC_CONV_Z, s);
       hipLaunchKernelGGL((k_conv_z_r<T, N, TXR, NTL>), dim3(N * r2c_xs<N>() / TXR, 2 * npacks), dim3(NTL), 0, s, spec,
-                         packs, tw, kp);
+                         packs, tw, kp, nullptr);
       rec_end(rec, KC_CONV_Z, s, 2 * u);
       rec_begin(rec, KC_INV_XY, s);
       if (epart)
@@ -291,6 +313,56 @@ static hipError_t pair_round_t(const PairShape& sh, const void* phi_, void* spec
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------ owner-computes W
+// All pairs are transformed forward (packs of consecutive pairs, no conflict
+// constraints: only phi is read) and convolved, with every pair's half
+// spectrum kept in HBM; then one workgroup per (z-plane, orbital k) forms W_k
+// from k's adjacency list and writes it once.  Algorithmic bytes per pair:
+// forward 3, z pass 2 (N^3 s units, as for the other paths); the owner pass
+// reads each adjacency entry's spectrum plane and partner row (2 per
+// off-diagonal pair, 1 per diagonal one) and writes each W row once.
+template <typename T, int N>
+static hipError_t pair_owner_t(const void* phi_, void* spec_, const Pack* packs, int npacks, int npairs,
+                               const int32_t* adj_ptr, const int32_t* adj, int norb, int64_t nadj, void* W_,
+                               double* epart, const void* tw_, const KernelParams& kp, int chunk, hipStream_t s,
+                               EventRecorder* rec) {
+  if constexpr (!r2c_fits_t<T, N>()) {
+    return hipErrorInvalidValue;
+  } else {
+    using C = cplx<T>;
+    const T* phi = static_cast<const T*>(phi_);
+    T* W = static_cast<T*>(W_);
+    C* spec = static_cast<C*>(spec_);
+    const C* tw = static_cast<const C*>(tw_);
+    constexpr int NTR = 512, NTL = 256, TXR = r2c_tx<N>();
+    constexpr int NTILE = N * r2c_xs<N>() / TXR;
+    constexpr size_t SLOT = size_t(N) * N * r2c_xs<N>();  // complex values per pair slot
+    const double u3 = double(N) * N * N * sizeof(T);
+    // forward and z pass in launches of at most `chunk` packs (grid y = 2 *
+    // packs <= 65534); one launch each over all pairs measured fastest
+    const int CH = chunk < 1 ? 1 : (chunk > 32767 ? 32767 : chunk);
+    for (int c0 = 0; c0 < npacks; c0 += CH) {
+      const int nc = (npacks - c0 < CH) ? npacks - c0 : CH;
+      const int pc = (2 * c0 + 2 * nc <= npairs) ? 2 * nc : npairs - 2 * c0;  // pairs in this chunk
+      rec_begin(rec, KC_FWD_XY, s);
+      hipLaunchKernelGGL((k_fwd_xy_r<T, N, NTR>), dim3(N, 2 * nc), dim3(NTR), 0, s, phi, spec + 2 * size_t(c0) * SLOT,
+                         packs + c0, tw);
+      rec_end(rec, KC_FWD_XY, s, 3 * u3 * pc);
+      rec_begin(rec, KC_CONV_Z, s);
+      hipLaunchKernelGGL((k_conv_z_r<T, N, TXR, NTL>), dim3(NTILE, 2 * nc), dim3(NTL), 0, s,
+                         spec + 2 * size_t(c0) * SLOT, packs + c0, tw, kp,
+                         epart ? epart + 2 * size_t(c0) * NTILE : nullptr);
+      rec_end(rec, KC_CONV_Z, s, 2 * u3 * pc);
+    }
+    if (W) {
+      rec_begin(rec, KC_INV_XY, s);
+      hipLaunchKernelGGL((k_inv_owner_r<T, N, NTR>), dim3(N, norb), dim3(NTR), 0, s, phi, spec, adj_ptr, adj, W, tw);
+      rec_end(rec, KC_INV_XY, s, double(nadj) * (2.0 * SLOT * sizeof(T) + u3) + double(norb) * u3);
+    }
+    return hipGetLastError();
+  }
+}
+
 #define ACE_PAIR_SIZES(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(80) X(96) X(100) X(108) X(120) X(160)
 
 bool pair_supported(int N) {
@@ -299,6 +371,33 @@ bool pair_supported(int N) {
     ACE_PAIR_SIZES(X)
 #undef X
     default: return false;
+  }
+}
+
+hipError_t pair_owner(int prec, int N, const void* phi, void* spec, const Pack* packs, int npacks, int npairs,
+                      const int32_t* adj_ptr, const int32_t* adj, int norb, int64_t nadj, void* W, double* epart,
+                      const void* tw, const KernelParams& kp, int chunk, hipStream_t s, EventRecorder* rec) {
+  switch (N) {
+#define X(n)                                                                                                       \
+  case n:                                                                                                          \
+    return prec == 0 ? pair_owner_t<double, n>(phi, spec, packs, npacks, npairs, adj_ptr, adj, norb, nadj, W,      \
+                                               epart, tw, kp, chunk, s, rec)                                       \
+                     : pair_owner_t<float, n>(phi, spec, packs, npacks, npairs, adj_ptr, adj, norb, nadj, W, epart, \
+                                              tw, kp, chunk, s, rec);
+    ACE_PAIR_SIZES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+int pair_r2c_ntile(int N) {
+  switch (N) {
+#define X(n) case n: return n * r2c_xs<n>() / r2c_tx<n>();
+    ACE_PAIR_SIZES(X)
+#undef X
+    default:
+      return 0;
   }
 }
 
@@ -313,7 +412,7 @@ bool pair_r2c_fits(int prec, int N) {
 
 // Complex spectrum elements per pack (two pairs) for a launch shape.
 size_t pair_spec_elems(int prec, int N, const PairShape& sh) {
-  if (sh.fused_xy == 2 && pair_r2c_fits(prec, N)) return 2 * size_t(N) * N * (N / 2 + 1);
+  if (sh.fused_xy >= 2 && pair_r2c_fits(prec, N)) return 2 * size_t(N) * N * (N / 2 + 1);
   return size_t(N) * N * N;
 }
 
@@ -345,7 +444,7 @@ static bool pair_r2c_preferred(int prec, int N) {
 
 PairShape pair_default_shape(int prec, int N) {
   PairShape sh;
-  sh.fused_xy = pair_r2c_preferred(prec, N) ? 2 : 0;
+  sh.fused_xy = pair_r2c_preferred(prec, N) ? 3 : 0;
   sh.nt_xy = 512;
   sh.tx = pick_tx(N);
   return sh;
@@ -360,6 +459,7 @@ hipError_t pair_round(int prec, int N, const PairShape& sh, const void* phi, voi
                       const Pack* packs, int npacks, int npairs, void* W, double* epart, const void* tw,
                       const KernelParams& kp, hipStream_t s, EventRecorder* rec) {
   PairShape use = sh;
+  if (use.fused_xy == 3) use.fused_xy = 2;  // owner path over budget: real-to-complex rounds
   if ((use.fused_xy == 1 && !pair_fused_fits(prec, N)) || (use.fused_xy == 2 && !pair_r2c_fits(prec, N)))
     use.fused_xy = 0;
   switch (N) {

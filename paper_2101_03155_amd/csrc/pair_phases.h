@@ -277,24 +277,41 @@ __device__ __forceinline__ void body_fwd_xy_r(const T* __restrict__ pi_, const T
 // With active == false the caller's threads take part in the barriers only
 // (no global loads or stores), so a workgroup can split into independent
 // groups of NT threads working on different tiles.
+// With eslot != nullptr the tile's share of sum_r rho v_ij is formed on the
+// way (Parseval: sum_r rho v = sum_G (v(G)/N^3) |rho^(G)|^2, the half spectrum
+// weighted 2 except at kx = 0 and N/2) and written to eslot[0]; red holds
+// NT / 64 doubles.
 template <typename T, int N, int TX, int NT, int V = 0>
 __device__ __forceinline__ void body_conv_z_r(cplx<T>* spec_p, int f0, const KernelParams& kp, cplx<T>* buf,
-                                              const cplx<T>* tw, int tid, bool active = true) {
+                                              const cplx<T>* tw, int tid, bool active = true,
+                                              double* eslot = nullptr, double* red = nullptr) {
   using C = cplx<T>;
   constexpr int XS = r2c_xs<N>(), PL = N * XS, E = N * TX;
   C* base = spec_p + f0;
   if (active) stage_in<C, E, NT>(buf, [&](int e) { return base[size_t(e / TX) * PL + (e % TX)]; }, tid);
   __syncthreads();
   fft_lines<T, N, TX, 1, TX, NT, -1, false, V>(buf, tw, tid);
+  double es = 0.0;
   for (int e = tid; e < E; e += NT) {
     const int f = f0 + e % TX;
-    const T v = kernel_value<T, N>(kp, f % XS, f / XS, e / TX);
+    const int kx = f % XS;
+    const T v = kernel_value<T, N>(kp, kx, f / XS, e / TX);
     C c = buf[e];
+    if (eslot) es += double((kx == 0 || kx == N / 2) ? 1 : 2) * double(v) * (double(c.x) * c.x + double(c.y) * c.y);
     c.x *= v;
     c.y *= v;
     buf[e] = c;
   }
+  if (eslot) {
+    for (int off = 32; off > 0; off >>= 1) es += __shfl_down(es, off, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = es;
+  }
   __syncthreads();
+  if (eslot && tid == 0) {
+    double sx = 0.0;
+    for (int w = 0; w < NT / 64; ++w) sx += red[w];
+    eslot[0] = sx;
+  }
   fft_lines<T, N, TX, 1, TX, NT, +1, false, V>(buf, tw, tid);
   if (active)
     for (int e = tid; e < E; e += NT) base[size_t(e / TX) * PL + (e % TX)] = buf[e];
@@ -402,6 +419,59 @@ __device__ __forceinline__ void accumulate_w_r(const T* __restrict__ pi_, const 
       for (int w = 0; w < NT / 64; ++w) sx += red[w];
       eslot[0] = sx;
     }
+  }
+}
+
+
+// W_k of plane z from all pairs containing orbital k (the owner of row k):
+// W_k = -sum_j v_kj phi_j.  For each adjacency entry (pair slot p, partner j)
+// the pair's half-spectrum plane is transformed back and v_kj phi_j is added
+// to an accumulator in registers; the row is written once, never read.
+template <typename T, int N, int NT, int V = 0>
+__device__ __forceinline__ void body_inv_owner_r(const T* __restrict__ phi, const cplx<T>* __restrict__ spec,
+                                                 const int32_t* __restrict__ adj, int a0, int a1, size_t zo,
+                                                 T* __restrict__ wk, cplx<T>* buf, const cplx<T>* tw, int tid) {
+  constexpr int XS = r2c_xs<N>(), HN = (N / 2) * N;
+  constexpr size_t NG = size_t(N) * N * N, PL = size_t(N) * XS;
+  constexpr int LP = (HN + NT - 1) / NT;
+  T acc0[LP], acc1[LP];
+#pragma unroll
+  for (int q = 0; q < LP; ++q) { acc0[q] = T(0); acc1[q] = T(0); }
+  const size_t zp = zo / (size_t(N) * N) * PL;  // plane offset in a pair's half spectrum
+  for (int a = a0; a < a1; ++a) {
+    // an opaque copy of the thread index keeps the transform's index
+    // arithmetic inside the loop (hoisted, it would all stay live)
+    int t = tid;
+    asm volatile("" : "+v"(t));
+    const int p = adj[2 * a], j = adj[2 * a + 1];
+    body_inv_xy_r<T, N, NT, V>(spec + size_t(p) * N * PL + zp, buf, tw, t);
+    const T* fj = phi + size_t(j) * NG + zo;
+    // partner row in batches of U elements per thread, loads first
+    constexpr int U = 3;
+#pragma unroll
+    for (int q0 = 0; q0 < LP; q0 += U) {
+      T f0[U], f1[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = t + (q0 + u) * NT;
+        if (q0 + u < LP && (HN % NT == 0 || e < HN)) { f0[u] = fj[e]; f1[u] = fj[e + HN]; }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = t + (q0 + u) * NT;
+        if (q0 + u < LP && (HN % NT == 0 || e < HN)) {
+          const cplx<T> v = buf[e];
+          acc0[q0 + u] += v.x * f0[u];
+          acc1[q0 + u] += v.y * f1[u];
+        }
+      }
+    }
+    __syncthreads();  // buf is refilled by the next entry
+  }
+#pragma unroll
+  for (int q = 0; q < LP; ++q) {
+    const int e = tid + q * NT;
+    if (HN % NT == 0 || e < HN) { wk[e] = -acc0[q]; wk[e + HN] = -acc1[q]; }
   }
 }
 

@@ -18,7 +18,7 @@ DEFAULT_PACKS = (16, 32, 64, 128)
 
 
 def candidates(precision: str, n: int, packs: Sequence[int] = DEFAULT_PACKS) -> Iterable[Tuple[str, int]]:
-    for path in ("r2c", "fused", "split"):
+    for path in ("owner", "r2c", "fused", "split"):
         for mp in packs:
             yield path, mp
 

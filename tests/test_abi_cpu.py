@@ -73,6 +73,10 @@ def test_argument_validation(ctx):
     assert lib.ace_get_pair_shape(h, 0, 160, C.byref(f), C.byref(m)) == 0 and f.value == 0
     assert lib.ace_set_pair_shape(h, 1, 160, 2, 16) == 0
     assert lib.ace_get_pair_shape(h, 1, 160, C.byref(f), C.byref(m)) == 0 and f.value == 2
+    assert lib.ace_set_pair_shape(h, 0, 96, 3, 16) == 0
+    assert lib.ace_get_pair_shape(h, 0, 96, C.byref(f), C.byref(m)) == 0 and f.value == 3
+    assert lib.ace_set_pair_shape(h, 0, 96, 4, 16) == -1
+    assert lib.ace_set_pair_shape(h, 0, 96, -1, 16) == -1
     assert lib.ace_profile_read(h, 99, None, None, None, 0) == -1
     # batched: argument checks before any device work
     arr = (ace.ace_system * 2)()

@@ -185,7 +185,7 @@ SIZE_CASES = [(8, "erfc", "fp64"), (12, "bare", "fp64"), (16, "erfc", "fp64"), (
               (48, "bare", "fp64"), (16, "erfc", "fp32"), (48, "erfc", "fp32")]
 
 
-@pytest.mark.parametrize("path", ["fused", "r2c", "split"])
+@pytest.mark.parametrize("path", ["fused", "r2c", "split", "owner"])
 @pytest.mark.parametrize("n,kind,prec", SIZE_CASES)
 def test_sizes_and_screened_lists(ctx, n, kind, prec, path):
     _say(f"sizes N={n} {kind} {prec} path={path}")
@@ -259,7 +259,7 @@ def _c2_screened_ref(c2):
     return c2["e_ref"], c2["W_rows"]
 
 
-@pytest.mark.parametrize("path", ["split", "fused", "r2c"])
+@pytest.mark.parametrize("path", ["split", "fused", "r2c", "owner"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_c2_screened_build(ctx, c2, prec, path):
     _say(f"c2 screened build {prec} path={path}")
