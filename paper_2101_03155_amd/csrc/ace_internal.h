@@ -96,7 +96,9 @@ size_t pair_spec_elems(int prec, int N, const PairShape& sh);
 hipError_t gemm_nt(int prec, int op, const void* A, int64_t lda, const void* B, int64_t ldb, int M,
                    int Nn, int64_t K, double alpha, double* Cpart, double* C, hipStream_t s,
                    EventRecorder* rec, bool sym = false);
-int64_t gemm_nt_nsplit(int M, int Nn, int64_t K, int64_t* kchunk_out);
+// Split count of gemm_nt; the default (sym = true) is the largest count any
+// product of this shape uses, for sizing the partial-sum buffer.
+int64_t gemm_nt_nsplit(int M, int Nn, int64_t K, int64_t* kchunk_out, bool sym = true);
 hipError_t gemm_ls(int bprec, bool trans, bool lower, const double* S, int lds, const void* B, int64_t ldb,
                    double* C, int64_t ldc, int M, int K, int64_t R, double alpha, hipStream_t s,
                    EventRecorder* rec);
@@ -171,7 +173,7 @@ void launch_mlp_adam(const float* gpart, const float* lpart, int nb, float* m, f
                      float lr, float b1, float b2, float eps, float* loss_acc, hipStream_t s);
 void launch_select(const float* pred, const float* feats, int64_t np, int norb, const float* model, double budget,
                    const double* O, double rho_cut, float ood_tol, int* ood, double* tau, uint8_t* keep, int64_t cap,
-                   int32_t* pairs, int64_t* count, hipStream_t s);
+                   int32_t* pairs, int64_t* count, float* q, double* w, hipStream_t s);
 PairShape pair_default_shape(int prec, int N);
 
 }  // namespace ace

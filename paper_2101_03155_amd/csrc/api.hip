@@ -1241,12 +1241,16 @@ int ace_screen_learned(ace_ctx* c, const ace_grid* g, int norb, const double* ph
   WS(c, "s_tau", 64, tau);
   WS(c, "s_ood", 64, ood);
   WS(c, "cnt", 64, cnt);
+  float* bq;
+  double* bw;
+  WS(c, "s_bq", size_t(np) * sizeof(float), bq);
+  WS(c, "s_bw", size_t(np) * sizeof(double), bw);
   rc = features_impl(c, g, norb, phi, nullptr, np, f, &O);
   if (rc) return rc;
   launch_mlp_forward(model, f, np, 1, pred, s);
   HIPCHK(c, hipMemsetAsync(ood, 0, sizeof(int), s));
   launch_select(pred, f, np, norb, model, budget, O, rho_cut_fallback, float(ood_tol), ood, tau, keep, capacity, pairs,
-                cnt, s);
+                cnt, bq, bw, s);
   int64_t h = 0;
   int hood = 0;
   HIPCHK(c, hipMemcpyAsync(&h, cnt, sizeof(int64_t), hipMemcpyDeviceToHost, s));

@@ -441,10 +441,14 @@ __global__ __launch_bounds__(256, 2) void k_gemm_ls_t128(const double* __restric
 
 // ---------------------------------------------------------------- host wrappers
 
-int64_t gemm_nt_nsplit(int M, int Nn, int64_t K, int64_t* kchunk_out) {
-  // about 512 workgroups (two per CU) over the 128 x 128 tiles, K chunks a
-  // multiple of 256 (the compensated FP32 sub-chunk)
-  const int64_t tiles = int64_t((M + TT - 1) / TT) * ((Nn + TT - 1) / TT);
+int64_t gemm_nt_nsplit(int M, int Nn, int64_t K, int64_t* kchunk_out, bool sym) {
+  // about 512 workgroups (two per CU) over the 128 x 128 tiles that are
+  // computed (the upper triangle only for a symmetric product), K chunks a
+  // multiple of 256 (the compensated FP32 sub-chunk).  With sym = true for a
+  // square product the count is the larger of the two cases, which is what
+  // partial-sum buffers are sized for.
+  const int64_t tm = (M + TT - 1) / TT, tn = (Nn + TT - 1) / TT;
+  const int64_t tiles = (sym && M == Nn) ? tm * (tm + 1) / 2 : tm * tn;
   const int64_t want = (512 + tiles - 1) / tiles;
   int64_t kchunk = (K + want - 1) / want;
   kchunk = ((kchunk + 255) / 256) * 256;
@@ -458,14 +462,14 @@ hipError_t gemm_nt(int prec, int op, const void* A, int64_t lda, const void* B, 
                    int Nn, int64_t K, double alpha, double* Cpart, double* C, hipStream_t s,
                    EventRecorder* rec, bool sym) {
   int64_t kchunk;
-  const int64_t nsplit = gemm_nt_nsplit(M, Nn, K, &kchunk);
+  sym = sym && prec == 0 && M == Nn && A == B && lda == ldb;
+  const int64_t nsplit = gemm_nt_nsplit(M, Nn, K, &kchunk, sym);
   rec_begin(rec, KC_GEMM_NT, s);
   const int64_t mn = int64_t(M) * Nn;
   int nb = int((mn + 255) / 256);
   if (nb > 1024) nb = 1024;
   if (prec == 0) {
     const int ntm = (M + TT - 1) / TT, ntn = (Nn + TT - 1) / TT;
-    sym = sym && M == Nn && A == B && lda == ldb;
     const unsigned ntiles = unsigned(sym ? ntn * (ntn + 1) / 2 : ntm * ntn);
     dim3 grid(ntiles, unsigned(nsplit));
     const double* a = (const double*)A;

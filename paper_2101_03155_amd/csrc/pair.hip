@@ -155,7 +155,10 @@ constexpr bool r2c_fits_t() {
   return (size_t(N) * r2c_xs<N>() + N) * sizeof(cplx<T>) + 1024 <= 163840;
 }
 
-template <typename T, int N, int NT>
+// ZFAST: blockIdx.x = z-plane, blockIdx.y = pair slot; otherwise the slot
+// runs fastest, so the workgroups in flight share a few z-planes and the
+// phi rows of those planes stay in the caches.
+template <typename T, int N, int NT, bool ZFAST = true>
 __global__ __launch_bounds__(NT) void k_fwd_xy_r(const T* __restrict__ phi, cplx<T>* __restrict__ spec,
                                                  const Pack* __restrict__ packs,
                                                  const cplx<T>* __restrict__ twg) {
@@ -164,7 +167,8 @@ __global__ __launch_bounds__(NT) void k_fwd_xy_r(const T* __restrict__ phi, cplx
   constexpr size_t NG = size_t(N) * N * N, PL = size_t(N) * XS;
   __shared__ C buf[N * XS];
   __shared__ C tw[N];
-  const int tid = threadIdx.x, z = blockIdx.x, slot = blockIdx.y;
+  const int tid = threadIdx.x;
+  const int z = ZFAST ? blockIdx.x : blockIdx.y, slot = ZFAST ? blockIdx.y : blockIdx.x;
   const Pack pk = packs[slot >> 1];
   const int i = (slot & 1) ? pk.ib : pk.ia, j = (slot & 1) ? pk.jb : pk.ja;
   if (j < 0) return;
@@ -193,6 +197,9 @@ __global__ __launch_bounds__(NT) void k_conv_z_r(cplx<T>* __restrict__ spec, con
 
 // Owner-computes W: blockIdx.x = z-plane, blockIdx.y = orbital k; adjacency
 // entries adj_ptr[k] .. adj_ptr[k + 1] of (pair slot, partner).
+// blockIdx.x = z-plane, blockIdx.y = orbital k (measured faster than the
+// orbital-fastest order, which shares phi planes in the caches but not the
+// spectra).
 template <typename T, int N, int NT>
 __global__ __launch_bounds__(NT, 4) void k_inv_owner_r(const T* __restrict__ phi, const cplx<T>* __restrict__ spec,
                                                     const int32_t* __restrict__ adj_ptr,
@@ -345,8 +352,8 @@ static hipError_t pair_owner_t(const void* phi_, void* spec_, const Pack* packs,
       const int nc = (npacks - c0 < CH) ? npacks - c0 : CH;
       const int pc = (2 * c0 + 2 * nc <= npairs) ? 2 * nc : npairs - 2 * c0;  // pairs in this chunk
       rec_begin(rec, KC_FWD_XY, s);
-      hipLaunchKernelGGL((k_fwd_xy_r<T, N, NTR>), dim3(N, 2 * nc), dim3(NTR), 0, s, phi, spec + 2 * size_t(c0) * SLOT,
-                         packs + c0, tw);
+      hipLaunchKernelGGL((k_fwd_xy_r<T, N, NTR, false>), dim3(2 * nc, N), dim3(NTR), 0, s, phi,
+                         spec + 2 * size_t(c0) * SLOT, packs + c0, tw);
       rec_end(rec, KC_FWD_XY, s, 3 * u3 * pc);
       rec_begin(rec, KC_CONV_Z, s);
       hipLaunchKernelGGL((k_conv_z_r<T, N, TXR, NTL>), dim3(NTILE, 2 * nc), dim3(NTL), 0, s,
@@ -425,26 +432,12 @@ bool pair_fused_fits(int prec, int N) {
   }
 }
 
-// The real-to-complex path is the default where two of its planes fit in one
-// CU's LDS (two workgroups per CU hide the HBM latency of each other's
-// loads); elsewhere the split passes are.
-template <typename T, int N>
-constexpr bool r2c_two_per_cu_t() {
-  return 2 * ((size_t(N) * r2c_xs<N>() + N) * sizeof(cplx<T>) + 1024) <= 163840;
-}
-
-static bool pair_r2c_preferred(int prec, int N) {
-  switch (N) {
-#define X(n) case n: return prec == 0 ? r2c_two_per_cu_t<double, n>() : r2c_two_per_cu_t<float, n>();
-    ACE_PAIR_SIZES(X)
-#undef X
-    default: return false;
-  }
-}
-
+// The owner-computes path (real-to-complex transforms) is the default wherever
+// its half-spectrum plane fits in LDS: measured faster than the split passes
+// even at one workgroup per CU (120^3 FP64, 160^3 FP32).
 PairShape pair_default_shape(int prec, int N) {
   PairShape sh;
-  sh.fused_xy = pair_r2c_preferred(prec, N) ? 3 : 0;
+  sh.fused_xy = pair_r2c_fits(prec, N) ? 3 : 0;
   sh.nt_xy = 512;
   sh.tx = pick_tx(N);
   return sh;

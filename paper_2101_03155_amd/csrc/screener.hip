@@ -38,37 +38,46 @@ static_assert(NMODEL == 4631, "model size");
 // (x) sums; pz[orb][z], py[orb][z][y], px[orb][z][x].
 __global__ __launch_bounds__(256) void k_plane_marginals(const double* __restrict__ phi, int n, double* __restrict__ pz,
                                                          double* __restrict__ py, double* __restrict__ px) {
+  // one read of the plane: wave w takes rows y = w, w + 4, ...; lanes read the
+  // row coalesced, its sum comes from a shuffle reduction, and each lane keeps
+  // its columns' partial sums, combined over the waves in LDS at the end
+  constexpr int CPL = 4;  // columns per lane (n <= 256)
   const int z = blockIdx.x, orb = blockIdx.y, tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
   const int64_t ng = int64_t(n) * n * n;
   const double* P = phi + int64_t(orb) * ng + int64_t(z) * n * n;
-  __shared__ double red[256];
-  // columns (x): thread handles column x, sums over y
+  __shared__ double col[4][256];
+  double cs[CPL];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) cs[c] = 0.0;
+  for (int y = wv; y < n; y += 4) {
+    double rs = 0.0;
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const int x = lane + 64 * c;
+      if (x < n) {
+        const double v = P[y * n + x];
+        cs[c] += v * v;
+        rs += v * v;
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) rs += __shfl_down(rs, off, 64);
+    if (lane == 0) py[(int64_t(orb) * n + z) * n + y] = rs;
+  }
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) col[wv][lane + 64 * c] = cs[c];
+  __syncthreads();
   double tot = 0.0;
   for (int x = tid; x < n; x += 256) {
-    double s = 0.0;
-    for (int y = 0; y < n; ++y) {
-      const double v = P[y * n + x];
-      s += v * v;
-    }
+    const double s = col[0][x] + col[1][x] + col[2][x] + col[3][x];
     px[(int64_t(orb) * n + z) * n + x] = s;
     tot += s;
   }
-  // rows (y): thread handles row y
-  for (int y = tid; y < n; y += 256) {
-    double s = 0.0;
-    for (int x = 0; x < n; ++x) {
-      const double v = P[y * n + x];
-      s += v * v;
-    }
-    py[(int64_t(orb) * n + z) * n + y] = s;
-  }
-  red[tid] = tot;
+  for (int off = 32; off > 0; off >>= 1) tot += __shfl_down(tot, off, 64);
   __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if (tid < h) red[tid] += red[tid + h];
-    __syncthreads();
-  }
-  if (tid == 0) pz[int64_t(orb) * n + z] = red[0];
+  if (lane == 0) col[0][wv] = tot;
+  __syncthreads();
+  if (tid == 0) pz[int64_t(orb) * n + z] = col[0][0] + col[0][1] + col[0][2] + col[0][3];
 }
 
 // Per orbital: marginals along each axis, periodic centroid (argument of the
@@ -432,20 +441,32 @@ __global__ void k_ood_count(const float* __restrict__ f, int64_t np, int n, cons
   if (c) atomicAdd(count, c);
 }
 
-// Largest tau (in log10) with sum over off-diagonal pairs of 10^pred below
-// tau at most budget; bisection in one workgroup.
-__global__ __launch_bounds__(1024) void k_budget_threshold(const float* __restrict__ pred, int64_t np, int n,
-                                                           double budget, double* __restrict__ tau) {
-  __shared__ double red[1024];
-  __shared__ double lohi[2];
-  // bracket: prediction range
-  double mn = 1e300, mx = -1e300;
-  for (int64_t t = threadIdx.x; t < np; t += 1024) {
+// Budget threshold preparation: q[t] = pred[t] for off-diagonal pairs and
+// +inf for the diagonal (never dropped), w[t] = 10^pred[t] (0 on the diagonal).
+__global__ void k_budget_prep(const float* __restrict__ pred, int64_t np, int n, float* __restrict__ q,
+                              double* __restrict__ w) {
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < np; t += int64_t(gridDim.x) * blockDim.x) {
     int i, j;
     tri_ij(t, n, i, j);
-    if (i == j) continue;
-    mn = fmin(mn, double(pred[t]));
-    mx = fmax(mx, double(pred[t]));
+    const double p = double(pred[t]);
+    q[t] = (i == j) ? INFINITY : pred[t];
+    w[t] = (i == j) ? 0.0 : pow(10.0, p);
+  }
+}
+
+// Largest tau (in log10) with sum over off-diagonal pairs of 10^pred below
+// tau at most budget; bisection in one workgroup over the prepared arrays.
+__global__ __launch_bounds__(1024) void k_budget_threshold(const float* __restrict__ q, const double* __restrict__ w,
+                                                           int64_t np, double budget, double* __restrict__ tau) {
+  __shared__ double red[1024];
+  __shared__ double lohi[2];
+  // bracket: prediction range over the off-diagonal pairs
+  double mn = 1e300, mx = -1e300;
+  for (int64_t t = threadIdx.x; t < np; t += 1024) {
+    const float v = q[t];
+    if (v == INFINITY) continue;
+    mn = fmin(mn, double(v));
+    mx = fmax(mx, double(v));
   }
   red[threadIdx.x] = mn;
   __syncthreads();
@@ -466,13 +487,8 @@ __global__ __launch_bounds__(1024) void k_budget_threshold(const float* __restri
   for (int it = 0; it < 64; ++it) {
     const double mid = 0.5 * (lohi[0] + lohi[1]);
     double s = 0.0;
-    for (int64_t t = threadIdx.x; t < np; t += 1024) {
-      int i, j;
-      tri_ij(t, n, i, j);
-      if (i == j) continue;
-      const double p = double(pred[t]);
-      if (p < mid) s += pow(10.0, p);
-    }
+    for (int64_t t = threadIdx.x; t < np; t += 1024)
+      if (double(q[t]) < mid) s += w[t];
     red[threadIdx.x] = s;
     __syncthreads();
     for (int h = 512; h > 0; h >>= 1) {
@@ -588,9 +604,10 @@ void launch_mlp_adam(const float* gpart, const float* lpart, int nb, float* m, f
 }
 void launch_select(const float* pred, const float* feats, int64_t np, int norb, const float* model, double budget,
                    const double* O, double rho_cut, float ood_tol, int* ood, double* tau, uint8_t* keep, int64_t cap,
-                   int32_t* pairs, int64_t* count, hipStream_t s) {
+                   int32_t* pairs, int64_t* count, float* q, double* w, hipStream_t s) {
   hipLaunchKernelGGL(k_ood_count, dim3(gridn(np, 256)), dim3(256), 0, s, feats, np, norb, model, ood_tol, ood);
-  hipLaunchKernelGGL(k_budget_threshold, dim3(1), dim3(1024), 0, s, pred, np, norb, budget, tau);
+  hipLaunchKernelGGL(k_budget_prep, dim3(gridn(np, 256)), dim3(256), 0, s, pred, np, norb, q, w);
+  hipLaunchKernelGGL(k_budget_threshold, dim3(1), dim3(1024), 0, s, q, w, np, budget, tau);
   hipLaunchKernelGGL(k_keep_flags, dim3(gridn(np, 256)), dim3(256), 0, s, pred, np, norb, tau, O, rho_cut, ood, keep);
   hipLaunchKernelGGL(k_compact_keep, dim3(1), dim3(1024), 0, s, keep, np, norb, cap, pairs, count);
 }
