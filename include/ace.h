@@ -243,11 +243,13 @@ int ace_set_batched_shape(ace_ctx* ctx, int txv, int plan_variant, int blocks_pe
 /* Features of each pair, float32 [npairs][5]: minimum-image distance of the
  * periodic centroids of |phi_i|^2 and |phi_j|^2 (bohr); the smaller and the
  * larger spread sqrt(dV sum |phi|^2 |r - c|^2) (bohr); log10 of
- * dV sum |phi_i||phi_j|; log10 of dV sum phi_i^2 phi_j^2.  pairs == NULL
- * means every pair i <= j in row-major triangle order (npairs must then be
+ * dV sum |phi_i||phi_j|; log10 of dV sum phi_i^2 phi_j^2.  With stride s > 1
+ * the two overlap sums run over the grid points whose indices are multiples
+ * of s (weight dV s^3; s must divide the grid size).  pairs == NULL means
+ * every pair i <= j in row-major triangle order (npairs must then be
  * norb(norb+1)/2).  Cubic boxes. */
 int ace_pair_features(ace_ctx* ctx, const ace_grid* grid, int norb, const double* phi, const int32_t* pairs,
-                      int64_t npairs, float* feats);
+                      int64_t npairs, float* feats, int stride);
 
 /* Exact pair energies e_ij = -(2 - d_ij) dV sum_r phi_i phi_j v_ij (Eq. e:vij)
  * of a pair list, without building W or the ACE operator: the training
@@ -298,11 +300,13 @@ int ace_mlp_train(ace_ctx* ctx, float* model, float* adam_m, float* adam_v, cons
  * by ood_tol times each span) on the interacting side (closer centroids,
  * larger overlaps, unseen spreads), the overlap rule O_ij >= rho_cut_fallback
  * is used instead and *used_fallback is set; pairs beyond the range on the far
- * side are predicted with clipped features.  pairs [capacity][2] sorted by
- * (i, j); *npairs (HOST) as for ace_pairlist. */
+ * side are predicted with clipped features.  stride: the feature stride the
+ * model was trained with (see ace_pair_features); the fallback always
+ * evaluates O_ij on the full grid.  pairs [capacity][2] sorted by (i, j);
+ * *npairs (HOST) as for ace_pairlist. */
 int ace_screen_learned(ace_ctx* ctx, const ace_grid* grid, int norb, const double* phi, const float* model,
                        double budget, double rho_cut_fallback, double ood_tol, int64_t capacity, int32_t* pairs,
-                       int64_t* npairs, int* used_fallback);
+                       int64_t* npairs, int* used_fallback, int stride);
 
 #ifdef __cplusplus
 }

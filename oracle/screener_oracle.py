@@ -13,7 +13,8 @@ features of a pair (i, j):
   2  larger of the two spreads
   3  log10 of O_ij = dV sum_r |phi_i||phi_j|      (the screening integral)
   4  log10 of P_ij = dV sum_r phi_i^2 phi_j^2     (pair-density L2 overlap)
-  (logs of max(., 1e-30))
+  (logs of max(., 1e-30); O and P optionally on the grid subsampled by a
+  stride s per axis, weight dV s^3)
 
 model: x -> standardize -> tanh(W1 x + b1) -> tanh(W2 h + b2) -> w3 . h + b3,
        prediction = tmean + tstd * output, target = log10 |e_ij|;
@@ -118,15 +119,19 @@ def centroids_spreads(phi, L):
     return cen, spr
 
 
-def pair_features(phi, L, pairs):
-    """The five features of every listed pair (float64)."""
+def pair_features(phi, L, pairs, stride=1):
+    """The five features of every listed pair (float64).  With stride s > 1
+    the two overlap integrals O and P are Riemann sums over the grid points
+    whose three indices are multiples of s (weight dV s^3); centroids and
+    spreads always use the full grid."""
     n = phi.shape[0]
     N = phi.shape[1]
     dV = (float(L) / N) ** 3
     cen, spr = centroids_spreads(phi, L)
-    A = phi.reshape(n, -1)
-    O = dV * np.abs(A) @ np.abs(A).T
-    P = dV * (A * A) @ (A * A).T
+    A = phi[:, ::stride, ::stride, ::stride].reshape(n, -1)
+    dVs = dV * stride ** 3
+    O = dVs * np.abs(A) @ np.abs(A).T
+    P = dVs * (A * A) @ (A * A).T
     pairs = np.asarray(pairs)
     i, j = pairs[:, 0], pairs[:, 1]
     d = cen[i] - cen[j]

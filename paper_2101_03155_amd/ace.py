@@ -116,14 +116,14 @@ def load(path: str = LIB_PATH):
         "ace_get_pair_shape": ([P, I, I, C.POINTER(I), C.POINTER(I)], I),
         "ace_build_batched": ([P, I, C.POINTER(ace_system), I, I], I),
         "ace_set_batched_shape": ([P, I, I, I, I], I),
-        "ace_pair_features": ([P, GP, I, P, P, I64, P], I),
+        "ace_pair_features": ([P, GP, I, P, P, I64, P, I], I),
         "ace_pair_energies": ([P, GP, I, P, P, I64, I, D, I, P], I),
         "ace_mlp_init": ([P, P, C.c_uint64], I),
         "ace_mlp_fit_norm": ([P, P, P, P, I64], I),
         "ace_mlp_forward": ([P, P, P, I64, I, P], I),
         "ace_mlp_grad": ([P, P, P, P, I64, P, P], I),
         "ace_mlp_train": ([P, P, P, P, P, P, I64, C.POINTER(ace_mlp_hparams), P], I),
-        "ace_screen_learned": ([P, GP, I, P, P, D, D, D, I64, P, C.POINTER(I64), C.POINTER(I)], I),
+        "ace_screen_learned": ([P, GP, I, P, P, D, D, D, I64, P, C.POINTER(I64), C.POINTER(I), I], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -345,8 +345,10 @@ class Context:
         self._check(self.lib.ace_set_batched_shape(self.h, txv, plan_variant, blocks_per_cu, code))
 
     # ------------------------------------------------------------ learned screener
-    def pair_features(self, phi, grid: Grid, pairs=None):
-        """float32 [npairs][5] features (every pair i <= j when pairs is None)."""
+    def pair_features(self, phi, grid: Grid, pairs=None, stride: int = 1):
+        """float32 [npairs][5] features (every pair i <= j when pairs is None);
+        stride > 1 evaluates the two overlap integrals on the grid subsampled
+        by that stride per axis."""
         import torch
 
         _require(phi, torch.float64, "phi")
@@ -357,7 +359,8 @@ class Context:
         f = torch.empty(n, 5, dtype=torch.float32, device=phi.device)
         self._sync_stream()
         g = grid.c()
-        self._check(self.lib.ace_pair_features(self.h, C.byref(g), norb, _ptr(phi), _ptr(pairs), n, _ptr(f)))
+        self._check(self.lib.ace_pair_features(self.h, C.byref(g), norb, _ptr(phi), _ptr(pairs), n, _ptr(f),
+                                               int(stride)))
         return f
 
     def pair_energies(self, phi, pairs, grid: Grid, kernel: str = "erfc", omega: float = 0.106,
@@ -415,7 +418,7 @@ class Context:
         return curve
 
     def screen_learned(self, phi, grid: Grid, model, budget: float, rho_cut_fallback: float = 1e-3,
-                       ood_tol: float = 0.05):
+                       ood_tol: float = 0.05, stride: int = 1):
         """Learned pair list: returns (pairs[int32, n x 2], used_fallback)."""
         import torch
 
@@ -429,6 +432,6 @@ class Context:
         g = grid.c()
         self._check(self.lib.ace_screen_learned(self.h, C.byref(g), norb, _ptr(phi), _ptr(model), float(budget),
                                                 float(rho_cut_fallback), float(ood_tol), cap, _ptr(pairs),
-                                                C.byref(n), C.byref(fb)))
+                                                C.byref(n), C.byref(fb), int(stride)))
         return pairs[: n.value], bool(fb.value)
 

@@ -157,6 +157,7 @@ void launch_zero(void* p, size_t bytes, hipStream_t s);
 
 // Learned screener (screener.hip).
 void launch_marginals(const double* phi, int norb, int n, double* pz, double* py, double* px, hipStream_t s);
+void launch_subsample(const double* phi, int norb, int n, int st, double* out, hipStream_t s);
 void launch_centroids(const double* pz, const double* py, const double* px, int norb, int n, double L, double dV,
                       double* cen, double* spr, hipStream_t s);
 void launch_pair_features(const int32_t* pairs, int64_t np, int norb, const double* cen, const double* spr,

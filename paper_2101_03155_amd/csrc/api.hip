@@ -1104,13 +1104,24 @@ int ace_build_batched(ace_ctx* c, int nsys, ace_system* sys, int prec, int mode)
 
 // ------------------------------------------------------------------ learned screener
 static int features_impl(ace_ctx* c, const ace_grid* g, int norb, const double* phi, const int32_t* pairs,
-                         int64_t np, float* feats, double** O_out) {
+                         int64_t np, float* feats, int stride, double** O_out) {
   const int n = g->n[0];
   const int64_t ng = grid_size(g);
   hipStream_t s = c->stream;
   double *pz, *py, *px, *cen, *spr, *O, *P, *part;
+  // the overlap integrals run over the grid subsampled by the stride
+  const int m = n / stride;
+  const int64_t ngs = int64_t(m) * m * m;
+  const double dVs = grid_dv(g) * double(stride) * stride * stride;
+  const double* phis = phi;
+  if (stride > 1) {
+    double* sub;
+    WS(c, "f_sub", size_t(norb) * ngs * sizeof(double), sub);
+    launch_subsample(phi, norb, n, stride, sub, s);
+    phis = sub;
+  }
   int64_t kchunk;
-  const int64_t nsplit = gemm_nt_nsplit(norb, norb, ng, &kchunk);
+  const int64_t nsplit = gemm_nt_nsplit(norb, norb, ngs, &kchunk);
   WS(c, "f_pz", size_t(norb) * n * sizeof(double), pz);
   WS(c, "f_py", size_t(norb) * n * n * sizeof(double), py);
   WS(c, "f_px", size_t(norb) * n * n * sizeof(double), px);
@@ -1121,8 +1132,9 @@ static int features_impl(ace_ctx* c, const ace_grid* g, int norb, const double* 
   WS(c, "mpart", size_t(nsplit) * norb * norb * sizeof(double), part);
   launch_marginals(phi, norb, n, pz, py, px, s);
   launch_centroids(pz, py, px, norb, n, g->L[0], grid_dv(g), cen, spr, s);
-  HIPCHK(c, gemm_nt(0, 1, phi, ng, phi, ng, norb, norb, ng, grid_dv(g), part, O, s, nullptr, true));
-  HIPCHK(c, gemm_nt(0, 2, phi, ng, phi, ng, norb, norb, ng, grid_dv(g), part, P, s, nullptr, true));
+  HIPCHK(c, gemm_nt(0, 1, phis, ngs, phis, ngs, norb, norb, ngs, dVs, part, O, s, nullptr, true));
+  HIPCHK(c, gemm_nt(0, 2, phis, ngs, phis, ngs, norb, norb, ngs, dVs, part, P, s, nullptr, true));
+  (void)ng;
   launch_pair_features(pairs, np, norb, cen, spr, O, P, g->L[0], feats, s);
   HIPCHK(c, hipGetLastError());
   if (O_out) *O_out = O;
@@ -1130,17 +1142,18 @@ static int features_impl(ace_ctx* c, const ace_grid* g, int norb, const double* 
 }
 
 int ace_pair_features(ace_ctx* c, const ace_grid* g, int norb, const double* phi, const int32_t* pairs, int64_t npairs,
-                      float* feats) {
+                      float* feats, int stride) {
   if (!c) return ACE_E_ARG;
   int rc = check_grid(c, g, norb);
   if (rc) return rc;
   if (g->L[0] != g->L[1] || g->L[1] != g->L[2]) return fail(c, ACE_E_UNSUPPORTED, "features need a cubic box");
   if (!phi || !feats) return fail(c, ACE_E_ARG, "phi and feats must be non-NULL");
+  if (stride < 1 || g->n[0] % stride != 0) return fail(c, ACE_E_ARG, "stride must be >= 1 and divide the grid size");
   const int64_t all = int64_t(norb) * (norb + 1) / 2;
   if (pairs ? (npairs < 1 || npairs > all) : (npairs != all))
     return fail(c, ACE_E_ARG, "npairs must be in [1, %lld] (or exactly %lld with pairs == NULL)", (long long)all,
                 (long long)all);
-  return features_impl(c, g, norb, phi, pairs, npairs, feats, nullptr);
+  return features_impl(c, g, norb, phi, pairs, npairs, feats, stride, nullptr);
 }
 
 int ace_mlp_init(ace_ctx* c, float* model, uint64_t seed) {
@@ -1220,7 +1233,7 @@ int ace_mlp_train(ace_ctx* c, float* model, float* adam_m, float* adam_v, const 
 
 int ace_screen_learned(ace_ctx* c, const ace_grid* g, int norb, const double* phi, const float* model,
                        double budget, double rho_cut_fallback, double ood_tol, int64_t capacity, int32_t* pairs,
-                       int64_t* npairs, int* used_fallback) {
+                       int64_t* npairs, int* used_fallback, int stride) {
   if (!c) return ACE_E_ARG;
   int rc = check_grid(c, g, norb);
   if (rc) return rc;
@@ -1228,6 +1241,7 @@ int ace_screen_learned(ace_ctx* c, const ace_grid* g, int norb, const double* ph
   if (!phi || !model || !pairs || !npairs) return fail(c, ACE_E_ARG, "phi, model, pairs and npairs must be non-NULL");
   if (!(budget >= 0) || !std::isfinite(rho_cut_fallback) || !(ood_tol >= 0) || capacity < 0)
     return fail(c, ACE_E_ARG, "budget >= 0, finite rho_cut, ood_tol >= 0 and capacity >= 0 required");
+  if (stride < 1 || g->n[0] % stride != 0) return fail(c, ACE_E_ARG, "stride must be >= 1 and divide the grid size");
   hipStream_t s = c->stream;
   const int64_t np = int64_t(norb) * (norb + 1) / 2;
   float *f, *pred;
@@ -1245,7 +1259,7 @@ int ace_screen_learned(ace_ctx* c, const ace_grid* g, int norb, const double* ph
   double* bw;
   WS(c, "s_bq", size_t(np) * sizeof(float), bq);
   WS(c, "s_bw", size_t(np) * sizeof(double), bw);
-  rc = features_impl(c, g, norb, phi, nullptr, np, f, &O);
+  rc = features_impl(c, g, norb, phi, nullptr, np, f, stride, &O);
   if (rc) return rc;
   launch_mlp_forward(model, f, np, 1, pred, s);
   HIPCHK(c, hipMemsetAsync(ood, 0, sizeof(int), s));
@@ -1256,8 +1270,11 @@ int ace_screen_learned(ace_ctx* c, const ace_grid* g, int norb, const double* ph
   HIPCHK(c, hipMemcpyAsync(&h, cnt, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipMemcpyAsync(&hood, ood, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
-  *npairs = h;
   if (used_fallback) *used_fallback = hood > 0 ? 1 : 0;
+  // the fallback is the screening criterion itself: with subsampled features
+  // it is redone on the full grid
+  if (hood > 0 && stride > 1) return ace_pairlist(c, g, norb, phi, rho_cut_fallback, capacity, pairs, nullptr, npairs);
+  *npairs = h;
   if (h > capacity) return fail(c, ACE_E_CAPACITY, "%lld pairs kept but capacity is %lld", (long long)h,
                                 (long long)capacity);
   return ACE_OK;

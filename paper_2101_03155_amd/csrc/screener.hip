@@ -80,6 +80,22 @@ __global__ __launch_bounds__(256) void k_plane_marginals(const double* __restric
   if (tid == 0) pz[int64_t(orb) * n + z] = col[0][0] + col[0][1] + col[0][2] + col[0][3];
 }
 
+// out[orb][zs][ys][xs] = phi[orb][s zs][s ys][s xs]: the grid subsampled by
+// the stride s per axis (m = n / s points per axis).
+__global__ void k_subsample(const double* __restrict__ phi, int norb, int n, int st, double* __restrict__ out) {
+  const int m = n / st;
+  const int64_t tot = int64_t(norb) * m * m * m;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < tot; e += int64_t(gridDim.x) * blockDim.x) {
+    const int xs = int(e % m);
+    int64_t r = e / m;
+    const int ys = int(r % m);
+    r /= m;
+    const int zs = int(r % m);
+    const int64_t orb = r / m;
+    out[e] = phi[((orb * n + int64_t(zs) * st) * n + int64_t(ys) * st) * n + int64_t(xs) * st];
+  }
+}
+
 // Per orbital: marginals along each axis, periodic centroid (argument of the
 // first Fourier coefficient of the marginal) and spread with minimum-image
 // displacements.  cen[orb][3] (x, y, z), spr[orb].
@@ -567,6 +583,10 @@ static unsigned gridn(int64_t n, int nt, int cap = 4096) {
 
 void launch_marginals(const double* phi, int norb, int n, double* pz, double* py, double* px, hipStream_t s) {
   hipLaunchKernelGGL(k_plane_marginals, dim3(n, norb), dim3(256), 0, s, phi, n, pz, py, px);
+}
+void launch_subsample(const double* phi, int norb, int n, int st, double* out, hipStream_t s) {
+  const int m = n / st;
+  hipLaunchKernelGGL(k_subsample, dim3(gridn(int64_t(norb) * m * m * m, 256)), dim3(256), 0, s, phi, norb, n, st, out);
 }
 void launch_centroids(const double* pz, const double* py, const double* px, int norb, int n, double L, double dV,
                       double* cen, double* spr, hipStream_t s) {

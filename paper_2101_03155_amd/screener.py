@@ -40,6 +40,7 @@ class TrainingSet:
     n_configs: int
     seconds: float
     per_config: List[dict] = field(default_factory=list)
+    stride: int = 1  # feature stride of x
 
 
 def _system(ctx, spec, device="cuda"):
@@ -55,8 +56,11 @@ def _system(ctx, spec, device="cuda"):
     return phi, grid
 
 
+FEATURE_STRIDE = 2  # the overlap features of new screeners use every second grid point per axis
+
+
 def training_set(ctx, specs: Sequence, rho_near: float = 1e-5, far_fraction: float = 0.1, seed: int = 0,
-                 precision: str = "fp32", log=None) -> TrainingSet:
+                 precision: str = "fp32", stride: int = FEATURE_STRIDE, log=None) -> TrainingSet:
     """Features and exact pair energies of the seeded training systems."""
     import torch
 
@@ -65,7 +69,7 @@ def training_set(ctx, specs: Sequence, rho_near: float = 1e-5, far_fraction: flo
     t0 = time.perf_counter()
     for k, spec in enumerate(specs):
         phi, grid = _system(ctx, spec)
-        f = ctx.pair_features(phi, grid)  # every pair i <= j
+        f = ctx.pair_features(phi, grid, stride=stride)  # every pair i <= j
         n = spec.norb
         iu, ju = np.triu_indices(n)
         logo = f[:, 3].cpu().numpy()
@@ -83,7 +87,8 @@ def training_set(ctx, specs: Sequence, rho_near: float = 1e-5, far_fraction: flo
         del phi, f, e
     x = torch.cat(xs).contiguous()
     t = torch.cat(ts).contiguous()
-    return TrainingSet(x=x, t=t, n_configs=len(specs), seconds=time.perf_counter() - t0, per_config=info)
+    return TrainingSet(x=x, t=t, n_configs=len(specs), seconds=time.perf_counter() - t0, per_config=info,
+                       stride=stride)
 
 
 class LearnedScreener:
@@ -117,8 +122,12 @@ class LearnedScreener:
         torch.cuda.synchronize()
         meta = {"epochs": epochs, "batch": batch, "lr": lr, "train_samples": int(data.x.shape[0]),
                 "train_configs": data.n_configs, "train_seconds": time.perf_counter() - t0,
-                "data_seconds": data.seconds, "loss_curve": curve}
+                "data_seconds": data.seconds, "feature_stride": data.stride, "loss_curve": curve}
         return cls(model, 0.0, meta)
+
+    @property
+    def stride(self) -> int:
+        return int(self.meta.get("feature_stride", 1))
 
     def predict(self, ctx, x):
         return ctx.mlp_forward(self.model, x)
@@ -128,7 +137,7 @@ class LearnedScreener:
                rho_cut_fallback: float = 1e-3, ood_tol: float = 0.05):
         """Pair list under the budget (margin applied); returns (pairs, used_fallback)."""
         budget = budget_per_molecule * n_mol / (1.0 + self.margin)
-        return ctx.screen_learned(phi, grid, self.model, budget, rho_cut_fallback, ood_tol)
+        return ctx.screen_learned(phi, grid, self.model, budget, rho_cut_fallback, ood_tol, stride=self.stride)
 
     def calibrate(self, ctx, specs: Sequence, budget_per_molecule: float = BUDGET_PER_MOLECULE,
                   safety: float = 0.25, precision: str = "fp64", log=None) -> dict:
@@ -140,7 +149,7 @@ class LearnedScreener:
             phi, grid = _system(ctx, spec)
             n = spec.norb
             budget = budget_per_molecule * spec.n_mol
-            pairs, fb = ctx.screen_learned(phi, grid, self.model, budget, 1e-3, 1e9)
+            pairs, fb = ctx.screen_learned(phi, grid, self.model, budget, 1e-3, 1e9, stride=self.stride)
             kept = {tuple(p) for p in pairs.cpu().numpy().tolist()}
             iu, ju = np.triu_indices(n)
             drop = np.array([(i, j) for i, j in zip(iu, ju) if i != j and (i, j) not in kept], dtype=np.int32)
@@ -148,7 +157,7 @@ class LearnedScreener:
                 continue
             dpairs = torch.as_tensor(drop, device="cuda")
             e = ctx.pair_energies(phi, dpairs, grid, kernel=spec.kernel, omega=spec.omega, precision=precision)
-            f = ctx.pair_features(phi, grid, dpairs)
+            f = ctx.pair_features(phi, grid, dpairs, stride=self.stride)
             pred = (10.0 ** ctx.mlp_forward(self.model, f, clamp=True).double()).sum().item()
             true = e.abs().sum().item()
             ratios.append(true / max(pred, 1e-300))

@@ -77,6 +77,9 @@ def test_argument_validation(ctx):
     assert lib.ace_get_pair_shape(h, 0, 96, C.byref(f), C.byref(m)) == 0 and f.value == 3
     assert lib.ace_set_pair_shape(h, 0, 96, 4, 16) == -1
     assert lib.ace_set_pair_shape(h, 0, 96, -1, 16) == -1
+    # feature stride must be >= 1 and divide the grid size
+    assert lib.ace_pair_features(h, C.byref(g), 4, fake, None, 10, fake, 0) == -1
+    assert lib.ace_pair_features(h, C.byref(g), 4, fake, None, 10, fake, 5) == -1
     assert lib.ace_profile_read(h, 99, None, None, None, 0) == -1
     # batched: argument checks before any device work
     arr = (ace.ace_system * 2)()

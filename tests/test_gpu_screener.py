@@ -42,6 +42,11 @@ def test_features_match_oracle(ctx):
     fs = ctx.pair_features(phi, g, sub).cpu().numpy()
     np.testing.assert_array_equal(fs, f[[5, np.flatnonzero((iu == 3) & (ju == 3))[0],
                                          np.flatnonzero((iu == 2) & (ju == 11))[0]]])
+    # overlap features on the grid subsampled by 2 per axis
+    f2 = ctx.pair_features(phi, g, stride=2).cpu().numpy()
+    ref2 = so.pair_features(phi.cpu().numpy(), spec.L, np.stack([iu, ju], 1), stride=2)
+    np.testing.assert_array_equal(f2[:, :3], f[:, :3])
+    np.testing.assert_allclose(f2[:, 3:], ref2[:, 3:], atol=2e-5)
 
 
 def test_pair_energies_match_oracle(ctx):

@@ -56,14 +56,20 @@ def test_features_of_gaussians_closed_form():
     np.testing.assert_allclose(cen[1], b, atol=1e-10)
     # |phi|^2 has variance sigma^2/2 per axis
     np.testing.assert_allclose(spr, np.sqrt(1.5) * spec.sigma, rtol=1e-9)
-    f = so.pair_features(g, spec.L, [(0, 1)])[0]
     d = a - b
     d -= spec.L * np.round(d / spec.L)
     dist = np.linalg.norm(d)
     s = spec.sigma
-    assert abs(f[0] - dist) < 1e-10
-    assert abs(f[3] - np.log10(np.exp(-dist ** 2 / (4 * s * s)))) < 1e-9
-    assert abs(f[4] - np.log10((2 * np.pi * s * s) ** -1.5 * np.exp(-dist ** 2 / (2 * s * s)))) < 1e-9
+    # the overlap integrals in closed form, on the full grid and on the grid
+    # subsampled by 2 per axis.  At stride 2 (spacing 0.58 bohr) the Riemann
+    # sum of |phi_i||phi_j| (width sigma) is still exact to ~1e-8 in log10; the
+    # one of phi_i^2 phi_j^2 (width sigma / 2 = 0.4 bohr) aliases at ~2e-4.  A
+    # wrong weight or stride would be off by O(1).
+    for stride, tol_o, tol_p in ((1, 1e-9, 1e-9), (2, 1e-7, 5e-4)):
+        f = so.pair_features(g, spec.L, [(0, 1)], stride=stride)[0]
+        assert abs(f[0] - dist) < 1e-10
+        assert abs(f[3] - np.log10(np.exp(-dist ** 2 / (4 * s * s)))) < tol_o
+        assert abs(f[4] - np.log10((2 * np.pi * s * s) ** -1.5 * np.exp(-dist ** 2 / (2 * s * s)))) < tol_p
 
 
 def test_budget_rule():
