@@ -414,6 +414,8 @@ def main():
                          ("learned", lambda: form_learned(ctx, log, args.screener))):
             if name in args.skip_forms:
                 continue
+            ctx.release_workspace()  # each form starts from an empty device workspace
+            torch.cuda.empty_cache()
             try:
                 forms[name] = fn()
             except Exception as e:  # a failing form is reported, not hidden

@@ -73,6 +73,11 @@ int ace_destroy(ace_ctx* ctx);
 const char* ace_last_error(const ace_ctx* ctx);
 int ace_set_stream(ace_ctx* ctx, void* hip_stream);
 
+/* Free every workspace the context has grown (device buffers of earlier
+ * calls) and the batched graphs that refer to them; the next call allocates
+ * again.  Synchronizes the context's streams first. */
+int ace_release_workspace(ace_ctx* ctx);
+
 /*
  * (a) Localization by selected columns of the density matrix (SCDM), the
  * unitary rotation of Eq. (unit), as used in the SCDM paragraph of Sec. Theory.

@@ -113,6 +113,7 @@ def load(path: str = LIB_PATH):
         "ace_profile_enable": ([P, I], I),
         "ace_profile_read": ([P, I, C.POINTER(I64), C.POINTER(D), C.POINTER(D), I], I),
         "ace_set_pair_shape": ([P, I, I, I, I], I),
+        "ace_release_workspace": ([P], I),
         "ace_get_pair_shape": ([P, I, I, C.POINTER(I), C.POINTER(I)], I),
         "ace_build_batched": ([P, I, C.POINTER(ace_system), I, I], I),
         "ace_set_batched_shape": ([P, I, I, I, I], I),
@@ -281,6 +282,10 @@ class Context:
         u = C.c_double()
         self._check(self.lib.ace_profile_read(self.h, cls, C.byref(n), C.byref(ms), C.byref(u), 1 if reset else 0))
         return n.value, ms.value, u.value
+
+    def release_workspace(self):
+        """Free the device workspaces the context has grown."""
+        self._check(self.lib.ace_release_workspace(self.h))
 
     def set_pair_shape(self, precision: str, n: int, path, max_packs: int):
         """path: "split" (or False/0), "fused" (True/1), "r2c" (2) or "owner" (3);

@@ -400,6 +400,22 @@ int ace_destroy(ace_ctx* c) {
   return ACE_OK;
 }
 
+int ace_release_workspace(ace_ctx* c) {
+  if (!c) return ACE_E_ARG;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->bstream) HIPCHK(c, hipStreamSynchronize(c->bstream));
+  for (auto& kv : c->bufs)
+    if (kv.second.p) (void)hipFree(kv.second.p);
+  c->bufs.clear();
+  c->ws_total = 0;
+  // captured graphs hold workspace pointers
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+  c->graph_order.clear();
+  ++c->ws_gen;
+  return ACE_OK;
+}
+
 const char* ace_last_error(const ace_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
 int ace_set_stream(ace_ctx* c, void* stream) {
@@ -710,7 +726,17 @@ static int build_impl(ace_ctx* c, const ace_grid* g, int norb, const double* phi
   // owner-computes W when every pair's half spectrum fits the budget
   const int64_t onpk = int64_t(S.opacks.size());
   const size_t slot_bytes = size_t(N) * N * (N / 2 + 1) * 2 * es;
-  const bool owner = sh.fused_xy == 3 && pair_r2c_fits(prec, N) && size_t(2 * onpk) * slot_bytes <= c->owner_max;
+  // ... and when the spectra, beyond what the workspace already holds, take
+  // at most 60% of the free device memory (a fuller device slows down)
+  bool owner = sh.fused_xy == 3 && pair_r2c_fits(prec, N) && size_t(2 * onpk) * slot_bytes <= c->owner_max;
+  if (owner) {
+    const size_t need = size_t(2 * onpk) * slot_bytes;
+    auto it = c->bufs.find("spec");
+    const size_t have = it == c->bufs.end() ? 0 : it->second.bytes;
+    size_t freeb = 0, totb = 0;
+    if (need > have && hipMemGetInfo(&freeb, &totb) == hipSuccess)
+      owner = double(need) <= 0.6 * double(freeb + have);
+  }
   const int nblk = owner ? pair_r2c_ntile(N) : pair_energy_blocks(N, sh);
   void *W, *spec, *phiw;
   Pack* dpk;

@@ -143,6 +143,17 @@ def test_split_path_matches_fused(ctx, c1):
     assert abs(b["ex"].item() - a["ex"].item()) < 1e-13 * abs(a["ex"].item())
 
 
+def test_release_workspace_then_rebuild(ctx, c1):
+    _say("release workspaces, rebuild c1")
+    o, _, _, phi = c1
+    s = o.spec
+    pairs = _dev(_full_pairs(s.norb))
+    a = ctx.build(_dev(phi), pairs, _grid(s), kernel="bare")
+    ctx.release_workspace()
+    b = ctx.build(_dev(phi), pairs, _grid(s), kernel="bare")
+    assert torch.equal(a["ex"], b["ex"]) and torch.equal(a["xi"], b["xi"])
+
+
 def test_fp32_c1(ctx, c1):
     _say("build c1 fp32")
     o, _, _, phi = c1
