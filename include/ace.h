@@ -233,9 +233,16 @@ int ace_build_batched(ace_ctx* ctx, int nsys, ace_system* systems, int prec, int
  * passes of the split layout (8 or 16), radix order of the FFT plans (0 large
  * radices first, 1 small first), workgroups per compute unit of the
  * persistent launch (1..32), and the layout of the pair stage: 0 the five
- * split passes over packed complex fields, 2 (the default) real-to-complex
- * half spectra in three phases, used for every grid size whose half-spectrum
- * plane fits in LDS (all supported sizes).  ACE_E_ARG for other values. */
+ * split passes over packed complex fields in conflict-free rounds, 2
+ * real-to-complex half spectra in three phases per round, 3 (the default) the
+ * owner layout: the half spectra of all pairs of a grid size stay resident,
+ * the forward and z passes run over all of them in one launch each, and each
+ * row of W is formed once from the pairs that contain its orbital.  Layouts
+ * 2 and 3 apply to every grid size whose half-spectrum plane fits in LDS (all
+ * supported sizes).  Layout 3 needs the spectra within the budget of the
+ * owner path of ace_build (ACE_OWNER_SPECTRA_MAX bytes, and 60% of the free
+ * device memory) and is not used by the persistent launch (mode 1); in those
+ * cases layout 2 runs instead.  ACE_E_ARG for other values. */
 int ace_set_batched_shape(ace_ctx* ctx, int txv, int plan_variant, int blocks_per_cu, int layout);
 
 /*

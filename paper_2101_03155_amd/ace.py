@@ -344,9 +344,11 @@ class Context:
         self._check(rc)
         return outs
 
-    def set_batched_shape(self, txv: int, plan_variant: int, blocks_per_cu: int, layout: str = "r2c"):
-        """layout: "r2c" (half spectra, three phases) or "split" (five passes)."""
-        code = {"split": 0, "r2c": 2}[layout]
+    def set_batched_shape(self, txv: int, plan_variant: int, blocks_per_cu: int, layout: str = "owner"):
+        """layout: "owner" (all half spectra resident, W formed once per
+        row), "r2c" (half spectra, three phases per round) or "split" (five
+        passes per round)."""
+        code = {"split": 0, "r2c": 2, "owner": 3}[layout]
         self._check(self.lib.ace_set_batched_shape(self.h, txv, plan_variant, blocks_per_cu, code))
 
     # ------------------------------------------------------------ learned screener

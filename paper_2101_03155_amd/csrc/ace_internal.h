@@ -44,6 +44,14 @@ struct BRound {                // one segment: the packs of one grid size in one
   int64_t nitems[5];         // per phase: number of work items
 };
 
+// Owner layout of the batched form: one system of a grid-size segment.
+struct BOwner {
+  int sys;                   // index into the BSys table
+  int norb;
+  int64_t item0;             // first (orbital, plane) work item of the system
+  const int32_t* adj_ptr;    // [norb + 1] absolute offsets into the entry table
+};
+
 // Kernel launch shape of the pair stage, chosen by the tuner.
 struct PairShape {
   int fused_xy;    // 0: split passes; 1: one workgroup per (plane, pack) does both in-plane FFTs;
@@ -81,7 +89,7 @@ hipError_t pair_round(int prec, int N, const PairShape& sh, const void* phi, voi
 int pair_energy_blocks(int N, const PairShape& sh);
 bool pair_supported(int N);
 bool pair_r2c_fits(int prec, int N);
-int pair_r2c_ntile(int N);  // z-pass tiles per pair slot of the real-to-complex path
+int pair_owner_ntile(int prec, int N);  // z-pass tiles per pair slot of the owner path
 // Owner-computes W over all pairs (spectra of every pair resident); W may be
 // null (energies only); epart: per (pack, tile) partial energies or null.
 hipError_t pair_owner(int prec, int N, const void* phi, void* spec, const Pack* packs, int npacks, int npairs,
@@ -150,6 +158,12 @@ hipError_t batched_segments(int prec, int n, int mode, int txv, int plan_v, int 
                             const BRound* h_segs, const BRound* d_segs, const BSys* sys, const BPack* packs,
                             const int64_t* starts, bool r2c, hipStream_t s);
 bool batched_r2c_fits(int prec, int n);
+// Owner layout for the systems of grid size n: forward and z pass over the
+// nslots pair slots of packs (whose spectra are all resident), then W of
+// every system from its adjacency entries (slot, partner) in adj; items is the
+// sum over the systems of norb * n.
+hipError_t batched_owner(int prec, int n, int plan_v, int nslots, int nown, int64_t items, const BSys* sys,
+                         const BPack* packs, const BOwner* own, const int32_t* adj, const void* spec, hipStream_t s);
 // work items per pair slot of phase 0..2 (the z pass packs two tiles per item
 // in the persistent launch, one in the per-phase launches)
 int64_t batched_r2c_slot_items(int n, int phase, bool persistent);

@@ -130,7 +130,7 @@ struct ace_ctx {
   hipEvent_t bev_in = nullptr, bev_out = nullptr;
   std::map<uint64_t, hipGraphExec_t> graphs;
   std::vector<uint64_t> graph_order;
-  int b_txv = 16, b_plan = 0, b_bpc = 8, b_layout = 2;
+  int b_txv = 16, b_plan = 0, b_bpc = 8, b_layout = 3;
   size_t owner_max = size_t(96) << 30;  // resident spectra budget of the owner-computes path
 };
 
@@ -737,7 +737,7 @@ static int build_impl(ace_ctx* c, const ace_grid* g, int norb, const double* phi
     if (need > have && hipMemGetInfo(&freeb, &totb) == hipSuccess)
       owner = double(need) <= 0.6 * double(freeb + have);
   }
-  const int nblk = owner ? pair_r2c_ntile(N) : pair_energy_blocks(N, sh);
+  const int nblk = owner ? pair_owner_ntile(prec, N) : pair_energy_blocks(N, sh);
   void *W, *spec, *phiw;
   Pack* dpk;
   int64_t* dpidx;
@@ -865,7 +865,7 @@ int ace_apply(ace_ctx* c, const ace_grid* g, int norb, const double* xi, int nve
 // ------------------------------------------------------------------ batched form
 int ace_set_batched_shape(ace_ctx* c, int txv, int plan_variant, int blocks_per_cu, int layout) {
   if (!c || (txv != 8 && txv != 16) || (plan_variant != 0 && plan_variant != 1) || blocks_per_cu < 1 ||
-      blocks_per_cu > 32 || (layout != 0 && layout != 2))
+      blocks_per_cu > 32 || (layout != 0 && layout != 2 && layout != 3))
     return fail(c, ACE_E_ARG, "bad batched shape");
   c->b_txv = txv;
   c->b_plan = plan_variant;
@@ -936,16 +936,91 @@ int ace_build_batched(ace_ctx* c, int nsys, ace_system* sys, int prec, int mode)
   for (int q = 0; q < nsys; ++q) sizes.push_back(sys[q].grid.n[0]);
   std::sort(sizes.begin(), sizes.end());
   sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
+  // Owner layout (graph and eager launches): the spectra of all pairs of the
+  // sizes that take it stay resident, within the same budget as a single
+  // build (the persistent launch keeps the rounds).
+  std::vector<char> size_owner(sizes.size(), 0);
+  size_t owner_bytes = 0;
+  if (c->b_layout == 3 && mode != 1) {
+    for (size_t a = 0; a < sizes.size(); ++a) {
+      const int n = sizes[a];
+      if (!batched_r2c_fits(prec, n)) continue;
+      size_owner[a] = 1;
+      const size_t slot_bytes = size_t(n) * n * (n / 2 + 1) * 2 * es;
+      for (int q = 0; q < nsys; ++q)
+        if (sys[q].grid.n[0] == n) owner_bytes += sch[q]->opacks.size() * 2 * slot_bytes;
+    }
+    bool fits = owner_bytes <= c->owner_max;
+    if (fits && owner_bytes > 0) {
+      auto it = c->bufs.find("bspec");
+      const size_t have = it == c->bufs.end() ? 0 : it->second.bytes;
+      size_t freeb = 0, totb = 0;
+      if (owner_bytes > have && hipMemGetInfo(&freeb, &totb) == hipSuccess)
+        fits = double(owner_bytes) <= 0.6 * double(freeb + have);
+    }
+    if (!fits) {
+      std::fill(size_owner.begin(), size_owner.end(), 0);
+      owner_bytes = 0;
+    }
+  }
+  for (char o : size_owner) mix(uint64_t(o));
   std::vector<BRound> segs;
   std::vector<int> seg_n;
   std::vector<BPack> bp;
   std::vector<int64_t> starts;
   std::vector<int64_t> bp_off;  // spec offset of each pack (bytes, within its segment)
+  std::vector<char> bp_owner;   // the pack belongs to an owner segment (offset within the owner region)
   size_t spec_bytes = 0;
   std::vector<char> seg_r2c;
-  for (int n : sizes) {
+  // owner segments: one per grid size, all packs of its systems
+  struct OwnerSeg { int n, pack0, npacks, own0, nown; int64_t items; size_t spec_off; };
+  std::vector<OwnerSeg> osegs;
+  std::vector<BOwner> hown;
+  std::vector<int64_t> own_adjp_off;     // offset of each system's adjacency offsets in the table
+  std::vector<int32_t> hadjp, hadj;
+  size_t owner_off = 0;
+  for (size_t a = 0; a < sizes.size(); ++a) {
+    if (!size_owner[a]) continue;
+    const int n = sizes[a];
+    const size_t pack_bytes = 2 * size_t(n) * n * (n / 2 + 1) * 2 * es;
+    OwnerSeg os{n, int(bp.size()), 0, int(hown.size()), 0, 0, owner_off};
+    for (int q = 0; q < nsys; ++q) {
+      if (sys[q].grid.n[0] != n) continue;
+      const Schedule& S = *sch[q];
+      const int32_t slot0 = int32_t(2 * (bp.size() - size_t(os.pack0)));
+      for (const Pack& pk : S.opacks) {
+        BPack b{};
+        b.sys = q;
+        b.pk = pk;
+        bp.push_back(b);
+        bp_off.push_back(int64_t(owner_off));
+        bp_owner.push_back(1);
+        owner_off += pack_bytes;
+      }
+      BOwner o{};
+      o.sys = q;
+      o.norb = sys[q].norb;
+      o.item0 = os.items;
+      own_adjp_off.push_back(int64_t(hadjp.size()));
+      const int32_t e0 = int32_t(hadj.size() / 2);
+      for (int32_t v : S.adj_ptr) hadjp.push_back(v + e0);
+      for (size_t e = 0; e < S.adj.size(); e += 2) {
+        hadj.push_back(S.adj[e] + slot0);
+        hadj.push_back(S.adj[e + 1]);
+      }
+      hown.push_back(o);
+      os.items += int64_t(sys[q].norb) * n;
+    }
+    os.npacks = int(bp.size()) - os.pack0;
+    os.nown = int(hown.size()) - os.own0;
+    if (int64_t(hadj.size()) > int64_t(0x7fffffff)) return fail(c, ACE_E_CAPACITY, "batched adjacency too large");
+    osegs.push_back(os);
+  }
+  for (size_t a = 0; a < sizes.size(); ++a) {
+    if (size_owner[a]) continue;
+    const int n = sizes[a];
     const int64_t ngn = int64_t(n) * n * n;
-    const bool r2c = c->b_layout == 2 && batched_r2c_fits(prec, n);
+    const bool r2c = c->b_layout >= 2 && batched_r2c_fits(prec, n);
     // complex spectrum values per pack: two half spectra (real-to-complex) or one full field
     const int64_t pack_elems = r2c ? 2 * int64_t(n) * n * (n / 2 + 1) : ngn;
     for (int r = 0; r < nrounds; ++r) {
@@ -961,6 +1036,7 @@ int ace_build_batched(ace_ctx* c, int nsys, ace_system* sys, int prec, int mode)
           b.pk = S.packs[S.round_first[r] + k];
           bp.push_back(b);
           bp_off.push_back(int64_t(off));
+          bp_owner.push_back(0);
           off += size_t(pack_elems) * 2 * es;
         }
       }
@@ -1007,7 +1083,17 @@ int ace_build_batched(ace_ctx* c, int nsys, ace_system* sys, int prec, int mode)
   int64_t* dstarts;
   WS(c, "bW", size_t(w_total) * es, bW);
   if (prec == 1) WS(c, "bphi32", size_t(w_total) * es, bphi);
-  WS(c, "bspec", std::max<size_t>(spec_bytes, 256), bspec);
+  // the owner region follows the (reused) round region
+  const size_t owner_base = (spec_bytes + 255) / 256 * 256;
+  WS(c, "bspec", std::max<size_t>(owner_base + owner_off, 256), bspec);
+  BOwner* dbown = nullptr;
+  int32_t *dbadjp = nullptr, *dbadj = nullptr;
+  if (!osegs.empty()) {
+    WS(c, "bown", std::max<size_t>(hown.size(), 1) * sizeof(BOwner), dbown);
+    WS(c, "badjp", std::max<size_t>(hadjp.size(), 1) * sizeof(int32_t), dbadjp);
+    WS(c, "badj", std::max<size_t>(hadj.size(), 2) * sizeof(int32_t), dbadj);
+    for (size_t q = 0; q < hown.size(); ++q) hown[q].adj_ptr = dbadjp + own_adjp_off[q];
+  }
   WS(c, "bmpart", size_t(max_nsplit) * max_norb * max_norb * sizeof(double), part);
   WS(c, "bMraw", size_t(max_norb) * max_norb * sizeof(double), Mraw);
   WS(c, "bLc", size_t(max_norb) * max_norb * sizeof(double), Lb);
@@ -1037,7 +1123,7 @@ int ace_build_batched(ace_ctx* c, int nsys, ace_system* sys, int prec, int mode)
     b.W = bW + size_t(w_off[q]) * es;
     b.tw = tw;
   }
-  for (size_t k = 0; k < bp.size(); ++k) bp[k].spec = bspec + bp_off[k];
+  for (size_t k = 0; k < bp.size(); ++k) bp[k].spec = bspec + (bp_owner[k] ? owner_base : 0) + bp_off[k];
   // a captured graph holds raw workspace pointers: any reallocation retires it
   mix(c->ws_gen);
   mix(uint64_t(uintptr_t(bW))); mix(uint64_t(uintptr_t(bspec))); mix(uint64_t(uintptr_t(part)));
@@ -1045,12 +1131,20 @@ int ace_build_batched(ace_ctx* c, int nsys, ace_system* sys, int prec, int mode)
   if (!bp.empty()) HIPCHK(c, hipMemcpyAsync(dbp, bp.data(), bp.size() * sizeof(BPack), hipMemcpyHostToDevice, us));
   if (!segs.empty())
     HIPCHK(c, hipMemcpyAsync(dsegs, segs.data(), segs.size() * sizeof(BRound), hipMemcpyHostToDevice, us));
-  HIPCHK(c, hipMemcpyAsync(dstarts, starts.data(), starts.size() * sizeof(int64_t), hipMemcpyHostToDevice, us));
+  if (!starts.empty())
+    HIPCHK(c, hipMemcpyAsync(dstarts, starts.data(), starts.size() * sizeof(int64_t), hipMemcpyHostToDevice, us));
+  if (!osegs.empty()) {
+    HIPCHK(c, hipMemcpyAsync(dbown, hown.data(), hown.size() * sizeof(BOwner), hipMemcpyHostToDevice, us));
+    HIPCHK(c, hipMemcpyAsync(dbadjp, hadjp.data(), hadjp.size() * sizeof(int32_t), hipMemcpyHostToDevice, us));
+    if (!hadj.empty())
+      HIPCHK(c, hipMemcpyAsync(dbadj, hadj.data(), hadj.size() * sizeof(int32_t), hipMemcpyHostToDevice, us));
+  }
   HIPCHK(c, hipStreamSynchronize(us));
 
   // the whole build, in stream order on the private stream
   auto enqueue = [&](hipStream_t s) -> int {
-    launch_zero(bW, size_t(w_total) * es, s);
+    // the owner kernels write every row of W once; the rounds accumulate
+    if (!segs.empty()) launch_zero(bW, size_t(w_total) * es, s);
     launch_zero(infos, size_t(nsys) * sizeof(int), s);
     if (prec == 1)
       for (int q = 0; q < nsys; ++q)
@@ -1063,6 +1157,11 @@ int ace_build_batched(ace_ctx* c, int nsys, ace_system* sys, int prec, int mode)
                                       segs.data() + a, dsegs + a, dsys, dbp, dstarts, seg_r2c[a] != 0, s);
       if (e != hipSuccess) return fail(c, ACE_E_HIP, "batched pair launch failed: %s", hipGetErrorString(e));
       a = b;
+    }
+    for (const OwnerSeg& os : osegs) {
+      hipError_t e = batched_owner(prec, os.n, c->b_plan, 2 * os.npacks, os.nown, os.items, dsys, dbp + os.pack0,
+                                   dbown + os.own0, dbadj, bspec + owner_base + os.spec_off, s);
+      if (e != hipSuccess) return fail(c, ACE_E_HIP, "batched owner launch failed: %s", hipGetErrorString(e));
     }
     for (int q = 0; q < nsys; ++q) {
       const ace_system& y = sys[q];

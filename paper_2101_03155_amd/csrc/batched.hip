@@ -249,7 +249,7 @@ __global__ __launch_bounds__(BNTR, 4) void k_batched_phase_r(BRound sg, const BS
 
 // The z pass as its own per-phase launch: 256-thread workgroups, one tile each.
 template <typename T, int N, int V>
-__global__ __launch_bounds__(256, 8) void k_batched_conv_r(BRound sg, const BSys* __restrict__ sys,
+__global__ __launch_bounds__(256) void k_batched_conv_r(BRound sg, const BSys* __restrict__ sys,
                                                         const BPack* __restrict__ packs,
                                                         const int64_t* __restrict__ starts) {
   __shared__ cplx<T> buf[N * r2c_tx<N>()];
@@ -313,6 +313,118 @@ static hipError_t launch_seg_r(int mode, int nseg, const BRound* h_segs, const B
         hipLaunchKernelGGL((k_batched_phase_r<T, N, V, 2>), dim3(g), dim3(BNTR), 0, s, h_segs[r], sys, packs, starts);
     }
   return hipGetLastError();
+}
+
+// ---- owner layout: the spectra of every pair of the segment's systems are
+// resident, so the forward and z passes run over all pairs in one launch each
+// and W_k of each system is formed once per (orbital, plane) from the pairs
+// that contain k (no rounds, no read-modify-write of W).
+
+// Forward: grid (pair slots, N), slot fastest so that the planes of the
+// orbitals of one system are read by neighbouring workgroups.
+template <typename T, int N, int V>
+__global__ __launch_bounds__(BNTR, 4) void k_batched_owner_fwd_r(const BSys* __restrict__ sys,
+                                                              const BPack* __restrict__ packs) {
+  constexpr size_t NG = size_t(N) * N * N, PL = size_t(N) * r2c_xs<N>();
+  __shared__ cplx<T> buf[N * r2c_xs<N>()];
+  __shared__ cplx<T> tw[N];
+  const int slot = blockIdx.x, z = blockIdx.y;
+  const BPack bp = packs[slot >> 1];
+  const int i = (slot & 1) ? bp.pk.ib : bp.pk.ia, j = (slot & 1) ? bp.pk.jb : bp.pk.ja;
+  if (j < 0) return;
+  const BSys& sy = sys[bp.sys];
+  const cplx<T>* twg = static_cast<const cplx<T>*>(sy.tw);
+  for (int t = threadIdx.x; t < N; t += BNTR) tw[t] = twg[t];
+  const T* phi = static_cast<const T*>(sy.phi);
+  const size_t zo = size_t(z) * N * N;
+  cplx<T>* spec = static_cast<cplx<T>*>(bp.spec) + size_t(slot & 1) * N * PL + size_t(z) * PL;
+  body_fwd_xy_r<T, N, BNTR, V>(phi + size_t(i) * NG + zo, phi + size_t(j) * NG + zo, spec, buf, tw, threadIdx.x);
+}
+
+// z pass: one 256-thread workgroup per (pair slot, tile), tiles of a slot adjacent.
+template <typename T, int N, int V>
+__global__ __launch_bounds__(256) void k_batched_owner_conv_r(const BSys* __restrict__ sys,
+                                                              const BPack* __restrict__ packs) {
+  constexpr int TXR = own_tx<T, N>(), NTILE = own_ntile<T, N>();
+  constexpr size_t PL = size_t(N) * r2c_xs<N>();
+  __shared__ cplx<T> buf[N * TXR];
+  __shared__ cplx<T> tw[N];
+  const int64_t g = blockIdx.x;
+  const int slot = int(g / NTILE), tile = int(g % NTILE);
+  const BPack bp = packs[slot >> 1];
+  if ((slot & 1) && bp.pk.jb < 0) return;
+  const BSys& sy = sys[bp.sys];
+  const cplx<T>* twg = static_cast<const cplx<T>*>(sy.tw);
+  for (int t = threadIdx.x; t < N; t += 256) tw[t] = twg[t];
+  KernelParams kp;
+  kp.kind = sy.kind;
+  kp.omega = sy.omega;
+  kp.inv_ng = sy.inv_ng;
+  kp.g[0] = sy.g[0]; kp.g[1] = sy.g[1]; kp.g[2] = sy.g[2];
+  cplx<T>* spec = static_cast<cplx<T>*>(bp.spec) + size_t(slot & 1) * N * PL;
+  body_conv_z_r<T, N, TXR, 256, V>(spec, tile * TXR, kp, buf, tw, threadIdx.x);
+}
+
+// W_k of plane z of one system: one workgroup per (system, orbital, plane)
+// item, plane fastest; the system is found by bisection over the item offsets.
+// Adjacency entries (slot, partner) index the slots of the segment's spectra.
+template <typename T, int N, int V>
+__global__ __launch_bounds__(BNTR, 4) void k_batched_owner_r(int nown, const BOwner* __restrict__ own,
+                                                          const BSys* __restrict__ sys,
+                                                          const int32_t* __restrict__ adj,
+                                                          const cplx<T>* __restrict__ spec) {
+  constexpr size_t NG = size_t(N) * N * N;
+  __shared__ cplx<T> buf[N * r2c_xs<N>()];
+  __shared__ cplx<T> tw[N];
+  const int64_t j = blockIdx.x;
+  int lo = 0, hi = nown;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (own[mid].item0 <= j) lo = mid; else hi = mid;
+  }
+  const BOwner o = own[lo];
+  const BSys& sy = sys[o.sys];
+  const int64_t b = j - o.item0;
+  const int k = int(b / N), z = int(b % N);
+  const cplx<T>* twg = static_cast<const cplx<T>*>(sy.tw);
+  for (int t = threadIdx.x; t < N; t += BNTR) tw[t] = twg[t];
+  const size_t zo = size_t(z) * N * N;
+  T* W = static_cast<T*>(sy.W) + size_t(k) * NG + zo;
+  body_inv_owner_r<T, N, BNTR, V>(static_cast<const T*>(sy.phi), spec, adj, o.adj_ptr[k], o.adj_ptr[k + 1], zo, W,
+                                  buf, tw, threadIdx.x);
+}
+
+template <typename T, int N, int V>
+static hipError_t launch_owner_t(int nslots, int nown, int64_t items, const BSys* sys, const BPack* packs,
+                                 const BOwner* own, const int32_t* adj, const void* spec, hipStream_t s) {
+  constexpr int64_t NTILE = own_ntile<T, N>();
+  if (NTILE * nslots > int64_t(0x7fffffff) || items > int64_t(0x7fffffff)) return hipErrorInvalidValue;
+  if (nslots > 0) {
+    hipLaunchKernelGGL((k_batched_owner_fwd_r<T, N, V>), dim3(unsigned(nslots), N), dim3(BNTR), 0, s, sys, packs);
+    hipLaunchKernelGGL((k_batched_owner_conv_r<T, N, V>), dim3(unsigned(NTILE * nslots)), dim3(256), 0, s, sys,
+                       packs);
+  }
+  if (items > 0)
+    hipLaunchKernelGGL((k_batched_owner_r<T, N, V>), dim3(unsigned(items)), dim3(BNTR), 0, s, nown, own, sys, adj,
+                       static_cast<const cplx<T>*>(spec));
+  return hipGetLastError();
+}
+
+hipError_t batched_owner(int prec, int n, int plan_v, int nslots, int nown, int64_t items, const BSys* sys,
+                         const BPack* packs, const BOwner* own, const int32_t* adj, const void* spec, hipStream_t s) {
+  switch (n) {
+#define X(nn)                                                                                                  \
+  case nn:                                                                                                     \
+    if (prec == 0)                                                                                             \
+      return plan_v ? launch_owner_t<double, nn, 1>(nslots, nown, items, sys, packs, own, adj, spec, s)         \
+                    : launch_owner_t<double, nn, 0>(nslots, nown, items, sys, packs, own, adj, spec, s);        \
+    return plan_v ? launch_owner_t<float, nn, 1>(nslots, nown, items, sys, packs, own, adj, spec, s)            \
+                  : launch_owner_t<float, nn, 0>(nslots, nown, items, sys, packs, own, adj, spec, s);
+    X(16) X(24) X(32) X(48) X(64) X(80) X(96)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
 bool batched_r2c_fits(int prec, int n) {

@@ -50,20 +50,36 @@ constexpr bool smooth235(int n) {
   while (n % 5 == 0) n /= 5;
   return n == 1;
 }
-constexpr int plan_len(int n) {
+// The grid sizes of the pair stage whose factors do not pair up into radix-8
+// passes take composite radices 9, 10, 12 and 16 instead (two passes, so two
+// LDS round trips per line rather than three or four).
+constexpr int plan_fill(int n, int* r) {
+  switch (n) {
+    case 12: r[0] = 12; return 1;
+    case 16: r[0] = 16; return 1;
+    case 48: r[0] = 4; r[1] = 12; return 2;
+    case 80: r[0] = 8; r[1] = 10; return 2;
+    case 96: r[0] = 8; r[1] = 12; return 2;
+    case 100: r[0] = 10; r[1] = 10; return 2;
+    case 108: r[0] = 12; r[1] = 9; return 2;
+    case 120: r[0] = 12; r[1] = 10; return 2;
+    case 160: r[0] = 16; r[1] = 10; return 2;
+    default: break;
+  }
   int a = pow_of(n, 2), cnt = 0;
-  while (a >= 3 && a != 4) { a -= 3; ++cnt; }
-  if (a == 4) cnt += 2; else if (a > 0) cnt += 1;
-  return cnt + pow_of(n, 3) + pow_of(n, 5);
-}
-constexpr int plan_radix(int n, int p) {
-  int a = pow_of(n, 2);
-  int r[24] = {0};
-  int cnt = 0;
   while (a >= 3 && a != 4) { a -= 3; r[cnt++] = 8; }
   if (a == 4) { r[cnt++] = 4; r[cnt++] = 4; } else if (a == 2) r[cnt++] = 4; else if (a == 1) r[cnt++] = 2;
   for (int i = 0; i < pow_of(n, 3); ++i) r[cnt++] = 3;
   for (int i = 0; i < pow_of(n, 5); ++i) r[cnt++] = 5;
+  return cnt;
+}
+constexpr int plan_len(int n) {
+  int r[24] = {0};
+  return plan_fill(n, r);
+}
+constexpr int plan_radix(int n, int p) {
+  int r[24] = {0};
+  plan_fill(n, r);
   return r[p];
 }
 // Plan variants: 0 takes the radices in the order above, 1 in reverse order
@@ -145,6 +161,111 @@ template <int S, typename C> struct Dft<8, S, C> {
     v[2] = cadd(e[2], o2);   v[6] = csub(e[2], o2);
     v[3] = cadd(e[3], o3);   v[7] = csub(e[3], o3);
   }
+};
+
+// Composite lengths R = R1 R2 by one Cooley-Tukey step in registers:
+// x[R2 n1 + n2] -> R2 DFTs of length R1 over n1, twiddles w^(n2 k1) with
+// w = exp(S 2 pi i / R), then R1 DFTs of length R2 over n2, giving
+// X[k1 + R1 k2].  The twiddles are compile-time constants.
+constexpr double cx_sin_red(double x) {  // Taylor series, |x| <= pi/4
+  double t = x, sum = x;
+  for (int k = 1; k < 40; ++k) {
+    t *= -x * x / double((2 * k) * (2 * k + 1));
+    sum += t;
+  }
+  return sum;
+}
+constexpr double cx_cos_red(double x) {
+  double t = 1.0, sum = 1.0;
+  for (int k = 1; k < 40; ++k) {
+    t *= -x * x / double((2 * k - 1) * (2 * k));
+    sum += t;
+  }
+  return sum;
+}
+// cos (c = true) or sin of 2 pi m / R: the angle is reduced to |x| <= pi/4
+// by the half-turn and quarter-turn symmetries before the series
+constexpr double root_cs(int m, int R, bool c) {
+  const double pi = 3.141592653589793238462643383279502884;
+  const int mm = ((m % R) + R) % R;
+  double x = 2.0 * pi * double(2 * mm > R ? mm - R : mm) / double(R);  // in (-pi, pi]
+  double sg = 1.0;
+  if (x > pi / 2) { x -= pi; sg = -1.0; }
+  else if (x < -pi / 2) { x += pi; sg = -1.0; }
+  if (x > pi / 4) return sg * (c ? cx_sin_red(pi / 2 - x) : cx_cos_red(pi / 2 - x));
+  if (x < -pi / 4) return sg * (c ? cx_sin_red(pi / 2 + x) : -cx_cos_red(pi / 2 + x));
+  return sg * (c ? cx_cos_red(x) : cx_sin_red(x));
+}
+constexpr double root_cos(int m, int R) { return root_cs(m, R, true); }
+constexpr double root_sin(int m, int R) { return root_cs(m, R, false); }
+
+template <int M, int R, int S, typename C>
+__device__ __forceinline__ C rotate(C a) {
+  using T = decltype(a.x);
+  constexpr int m = M % R;
+  if constexpr (m == 0) {
+    return a;
+  } else if constexpr (4 * m == R) {
+    return cmul_si<S>(a);
+  } else if constexpr (2 * m == R) {
+    C r; r.x = -a.x; r.y = -a.y; return r;
+  } else if constexpr (4 * m == 3 * R) {
+    return cmul_si<-S>(a);
+  } else {
+    constexpr T c = T(root_cos(m, R)), sn = T(S * root_sin(m, R));
+    // explicit fused multiply-adds: the rounding does not depend on how the
+    // compiler contracts the expression in a given kernel
+    C r; r.x = fma(a.x, c, -(a.y * sn)); r.y = fma(a.x, sn, a.y * c); return r;
+  }
+}
+
+template <int R1, int R2, int S, typename C, int N2, int K = 0>
+__device__ __forceinline__ void ct_twiddle_row(C (&y)[R2][R1]) {
+  if constexpr (K < R1) {
+    y[N2][K] = rotate<N2 * K, R1 * R2, S>(y[N2][K]);
+    ct_twiddle_row<R1, R2, S, C, N2, K + 1>(y);
+  }
+}
+template <int R1, int R2, int S, typename C, int N2 = 0>
+__device__ __forceinline__ void ct_twiddle(C (&y)[R2][R1]) {
+  if constexpr (N2 < R2) {
+    ct_twiddle_row<R1, R2, S, C, N2>(y);
+    ct_twiddle<R1, R2, S, C, N2 + 1>(y);
+  }
+}
+
+template <int R1, int R2, int S, typename C>
+__device__ __forceinline__ void dft_ct(C* v) {
+  C y[R2][R1];
+#pragma unroll
+  for (int n2 = 0; n2 < R2; ++n2) {
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) y[n2][n1] = v[R2 * n1 + n2];
+    Dft<R1, S, C>::run(y[n2]);
+  }
+  ct_twiddle<R1, R2, S, C>(y);
+#pragma unroll
+  for (int k1 = 0; k1 < R1; ++k1) {
+    C z[R2];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) z[n2] = y[n2][k1];
+    Dft<R2, S, C>::run(z);
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) v[k1 + R1 * k2] = z[k2];
+  }
+}
+
+template <int S, typename C> struct Dft<9, S, C> {
+  static __device__ __forceinline__ void run(C* v) { dft_ct<3, 3, S, C>(v); }
+};
+template <int S, typename C> struct Dft<10, S, C> {
+  static __device__ __forceinline__ void run(C* v) { dft_ct<2, 5, S, C>(v); }
+};
+template <int S, typename C> struct Dft<12, S, C> {
+  static __device__ __forceinline__ void run(C* v) { dft_ct<4, 3, S, C>(v); }
+};
+template <int S, typename C> struct Dft<16, S, C> {
+  static __device__ __forceinline__ void run(C* v) { dft_ct<4, 4, S, C>(v); }
 };
 
 // ---------------------------------------------------------------- one pass

@@ -211,8 +211,8 @@ __global__ __launch_bounds__(NT, 4) void k_inv_owner_r(const T* __restrict__ phi
   const int z = blockIdx.x, k = blockIdx.y;
   for (int t = threadIdx.x; t < N; t += NT) tw[t] = twg[t];
   const size_t zo = size_t(z) * N * N;
-  body_inv_owner_r<T, N, NT>(phi, spec, adj, adj_ptr[k], adj_ptr[k + 1], zo, W + size_t(k) * NG + zo, buf, tw,
-                             threadIdx.x);
+  body_inv_owner_r<T, N, NT>(phi, spec, adj, adj_ptr[k], adj_ptr[k + 1], zo,
+                                                W + size_t(k) * NG + zo, buf, tw, threadIdx.x);
 }
 
 template <typename T, int N, int NT, bool EN>
@@ -341,8 +341,8 @@ static hipError_t pair_owner_t(const void* phi_, void* spec_, const Pack* packs,
     T* W = static_cast<T*>(W_);
     C* spec = static_cast<C*>(spec_);
     const C* tw = static_cast<const C*>(tw_);
-    constexpr int NTR = 512, NTL = 256, TXR = r2c_tx<N>();
-    constexpr int NTILE = N * r2c_xs<N>() / TXR;
+    constexpr int NTR = 512, NTL = 256, TXR = own_tx<T, N>();
+    constexpr int NTILE = own_ntile<T, N>();
     constexpr size_t SLOT = size_t(N) * N * r2c_xs<N>();  // complex values per pair slot
     const double u3 = double(N) * N * N * sizeof(T);
     // forward and z pass in launches of at most `chunk` packs (grid y = 2 *
@@ -398,9 +398,9 @@ hipError_t pair_owner(int prec, int N, const void* phi, void* spec, const Pack* 
   }
 }
 
-int pair_r2c_ntile(int N) {
+int pair_owner_ntile(int prec, int N) {
   switch (N) {
-#define X(n) case n: return n * r2c_xs<n>() / r2c_tx<n>();
+#define X(n) case n: return prec == 0 ? own_ntile<double, n>() : own_ntile<float, n>();
     ACE_PAIR_SIZES(X)
 #undef X
     default:

@@ -201,6 +201,13 @@ template <int N> __host__ __device__ constexpr int r2c_xs() { return N / 2 + 1; 
 template <int N> __host__ __device__ constexpr int r2c_tx() {
   return (N * r2c_xs<N>()) % 16 == 0 ? 16 : (N * r2c_xs<N>()) % 8 == 0 ? 8 : (N * r2c_xs<N>()) % 4 == 0 ? 4 : 2;
 }
+// z-pass tile of the owner paths: 256 bytes of each plane row per tile (16
+// FP64 or 32 FP32 columns), the last tile of a slot ragged where the width
+// does not divide N * XS.
+template <typename T, int N> __host__ __device__ constexpr int own_tx() { return sizeof(T) == 4 ? 32 : 16; }
+template <typename T, int N> __host__ __device__ constexpr int own_ntile() {
+  return (N * r2c_xs<N>() + own_tx<T, N>() - 1) / own_tx<T, N>();
+}
 
 // Pair density of plane z (phi_i, phi_j point at the plane) -> its half
 // spectrum after the x and y transforms, stored to out (N * XS values).
@@ -288,11 +295,22 @@ __device__ __forceinline__ void body_conv_z_r(cplx<T>* spec_p, int f0, const Ker
   using C = cplx<T>;
   constexpr int XS = r2c_xs<N>(), PL = N * XS, E = N * TX;
   C* base = spec_p + f0;
-  if (active) stage_in<C, E, NT>(buf, [&](int e) { return base[size_t(e / TX) * PL + (e % TX)]; }, tid);
+  // columns of this tile inside the plane (fewer than TX in a ragged last
+  // tile, whose other columns are transformed as zeros and not stored)
+  const int ncol = PL - f0 < TX ? PL - f0 : TX;
+  if (active)
+    stage_in<C, E, NT>(buf, [&](int e) {
+      if (PL % TX == 0 || e % TX < ncol) return base[size_t(e / TX) * PL + (e % TX)];
+      C zr;
+      zr.x = T(0);
+      zr.y = T(0);
+      return zr;
+    }, tid);
   __syncthreads();
   fft_lines<T, N, TX, 1, TX, NT, -1, false, V>(buf, tw, tid);
   double es = 0.0;
   for (int e = tid; e < E; e += NT) {
+    if (PL % TX != 0 && e % TX >= ncol) continue;
     const int f = f0 + e % TX;
     const int kx = f % XS;
     const T v = kernel_value<T, N>(kp, kx, f / XS, e / TX);
@@ -314,17 +332,27 @@ __device__ __forceinline__ void body_conv_z_r(cplx<T>* spec_p, int f0, const Ker
   }
   fft_lines<T, N, TX, 1, TX, NT, +1, false, V>(buf, tw, tid);
   if (active)
-    for (int e = tid; e < E; e += NT) base[size_t(e / TX) * PL + (e % TX)] = buf[e];
+    for (int e = tid; e < E; e += NT)
+      if (PL % TX == 0 || e % TX < ncol) base[size_t(e / TX) * PL + (e % TX)] = buf[e];
 }
 
 // Half spectrum of plane z -> the real potential of the plane, left in buf as
 // H complex lines: line l holds row l in .x and row l + N/2 in .y.
+// body_inv_xy_t: the same on a plane already staged in buf (and synchronized).
+template <typename T, int N, int NT, int V = 0>
+__device__ __forceinline__ void body_inv_xy_t(cplx<T>* buf, const cplx<T>* tw, int tid);
+
 template <typename T, int N, int NT, int V = 0>
 __device__ __forceinline__ void body_inv_xy_r(const cplx<T>* in, cplx<T>* buf, const cplx<T>* tw, int tid) {
+  stage_in<cplx<T>, N * r2c_xs<N>(), NT>(buf, [&](int e) { return in[e]; }, tid);
+  __syncthreads();
+  body_inv_xy_t<T, N, NT, V>(buf, tw, tid);
+}
+
+template <typename T, int N, int NT, int V>
+__device__ __forceinline__ void body_inv_xy_t(cplx<T>* buf, const cplx<T>* tw, int tid) {
   using C = cplx<T>;
   constexpr int H = N / 2, XS = r2c_xs<N>();
-  stage_in<C, N * XS, NT>(buf, [&](int e) { return in[e]; }, tid);
-  __syncthreads();
   fft_lines<T, N, XS, 1, XS, NT, +1, false, V>(buf, tw, tid);
   // re-pack: Z[k] = X1[k] + i X2[k], Z[N-k] = conj X1[k] + i conj X2[k]; the
   // zero and Nyquist bins of a real row are real, as a c2r transform takes them

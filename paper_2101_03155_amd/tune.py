@@ -82,7 +82,7 @@ def autotune(ctx: "ace.Context", phi, pairs, grid: "ace.Grid", kernel: str, omeg
 
 
 def autotune_batched(ctx: "ace.Context", systems, precision: str = "fp32", reps: int = 2,
-                     modes=("graph", "persistent"), layouts=("r2c", "split"), txvs=(8, 16), plans=(0, 1),
+                     modes=("graph", "persistent"), layouts=("owner", "r2c", "split"), txvs=(8, 16), plans=(0, 1),
                      bpcs=(2, 4, 8)):
     """Pick the batched launch form and shape (mode, layout, x-tile, radix
     order, workgroups per CU) by timing whole batched builds; returns
@@ -95,8 +95,10 @@ def autotune_batched(ctx: "ace.Context", systems, precision: str = "fp32", reps:
     for mode in modes:
         for layout in layouts:
             for txv in txvs:
-                if layout == "r2c" and txv != txvs[-1]:
+                if layout != "split" and txv != txvs[-1]:
                     continue  # the x-tile only shapes the split layout
+                if layout == "owner" and mode == "persistent":
+                    continue  # the persistent launch keeps the rounds
                 for plan in plans:
                     for bpc in bpcs:
                         if mode == "graph" and bpc != bpcs[-1]:

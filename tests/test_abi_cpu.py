@@ -100,6 +100,8 @@ def test_argument_validation(ctx):
     assert lib.ace_set_batched_shape(h, 8, 1, 4, 1) == -1
     assert lib.ace_set_batched_shape(h, 8, 1, 4, 0) == 0
     assert lib.ace_set_batched_shape(h, 16, 0, 8, 2) == 0
+    assert lib.ace_set_batched_shape(h, 16, 0, 8, 3) == 0
+    assert lib.ace_set_batched_shape(h, 16, 0, 8, 4) == -1
 
 
 def test_binding_refuses_without_gpu():

@@ -104,7 +104,7 @@ def _small_batch(ctx, n_sys=5):
     return out
 
 
-@pytest.mark.parametrize("layout", ["r2c", "split"])
+@pytest.mark.parametrize("layout", ["owner", "r2c", "split"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_batched_equals_single_builds_bitwise(ctx, prec, layout):
     _say(f"batched vs single bitwise {prec} layout={layout}")
@@ -124,9 +124,27 @@ def test_batched_equals_single_builds_bitwise(ctx, prec, layout):
         finally:
             ctx.set_pair_shape(prec, n, *saved)
         assert res[q]["status"] == "ACE_OK"
+        if layout == "split":
+            # the five-pass kernels of the two launch forms are compiled
+            # separately and may round their FFTs differently: equal to
+            # rounding (each launch form is itself deterministic, checked below)
+            tol = 1e-13 if prec == "fp64" else 1e-5
+            assert abs(res[q]["ex"].item() - r["ex"].item()) <= tol * abs(r["ex"].item())
+            assert (res[q]["M"] - r["M"]).abs().max().item() <= tol * r["M"].abs().max().item()
+            assert (res[q]["xi"] - r["xi"]).abs().max().item() <= 1e3 * tol * r["xi"].abs().max().item()
+            continue
         assert torch.equal(res[q]["ex"], r["ex"]), (q, res[q]["ex"].item(), r["ex"].item())
         assert torch.equal(res[q]["M"], r["M"])
         assert torch.equal(res[q]["xi"], r["xi"])
+    if layout == "split":
+        ctx.set_batched_shape(16, 0, 8, layout)
+        try:
+            again = ctx.build_batched(systems, precision=prec, mode="graph")
+        finally:
+            ctx.set_batched_shape(16, 0, 8)
+        for q in range(len(systems)):
+            assert torch.equal(again[q]["M"], res[q]["M"]), q
+            assert torch.equal(again[q]["xi"], res[q]["xi"]), q
 
 
 def test_batched_graph_replays_and_modes(ctx):
@@ -137,7 +155,8 @@ def test_batched_graph_replays_and_modes(ctx):
         sy["xi"] = torch.empty_like(sy["phi"])
         sy["M"] = torch.empty(n, n, dtype=torch.float64, device="cuda")
         sy["ex"] = torch.empty(1, dtype=torch.float64, device="cuda")
-    ctx.set_batched_shape(16, 0, 8)
+    # the rounds layout, which all three launch forms share
+    ctx.set_batched_shape(16, 0, 8, "r2c")
     first = ctx.build_batched(systems, precision="fp32", mode="graph")
     ref = [(r["ex"].clone(), r["xi"].clone()) for r in first]
     for rep in range(3):
@@ -155,11 +174,42 @@ def test_batched_graph_replays_and_modes(ctx):
             assert torch.equal(other[q]["xi"], ref[q][1]), (mode, q)
     # tile and radix-order variants agree to rounding
     for txv, plan in ((8, 0), (16, 1), (8, 1)):
-        ctx.set_batched_shape(txv, plan, 4)
+        ctx.set_batched_shape(txv, plan, 4, "r2c")
         alt = ctx.build_batched(systems, precision="fp32", mode="persistent")
         for q in range(len(systems)):
             assert abs(alt[q]["ex"].item() - ref[q][0].item()) <= 1e-6 * abs(ref[q][0].item())
     ctx.set_batched_shape(16, 0, 8)
+
+
+def test_batched_owner_layout_graph_replays_and_eager(ctx):
+    _say("batched owner layout: graph replays + eager")
+    systems = _small_batch(ctx, 7)
+    for sy in systems:
+        n = sy["phi"].shape[0]
+        sy["xi"] = torch.empty_like(sy["phi"])
+        sy["M"] = torch.empty(n, n, dtype=torch.float64, device="cuda")
+        sy["ex"] = torch.empty(1, dtype=torch.float64, device="cuda")
+    ctx.set_batched_shape(16, 0, 8, "owner")
+    try:
+        first = ctx.build_batched(systems, precision="fp64", mode="graph")
+        ref = [(r["ex"].clone(), r["xi"].clone()) for r in first]
+        for rep in range(2):
+            x = torch.randn(1 << 20, device="cuda")
+            _ = (x * x).sum().item()
+            again = ctx.build_batched(systems, precision="fp64", mode="graph")
+            for q in range(len(systems)):
+                assert torch.equal(again[q]["ex"], ref[q][0]), (rep, q)
+                assert torch.equal(again[q]["xi"], ref[q][1]), (rep, q)
+        eager = ctx.build_batched(systems, precision="fp64", mode="eager")
+        for q in range(len(systems)):
+            assert torch.equal(eager[q]["ex"], ref[q][0]), q
+            assert torch.equal(eager[q]["xi"], ref[q][1]), q
+        # the persistent launch keeps the rounds: equal to rounding
+        pers = ctx.build_batched(systems, precision="fp64", mode="persistent")
+        for q in range(len(systems)):
+            assert abs(pers[q]["ex"].item() - ref[q][0].item()) <= 1e-12 * abs(ref[q][0].item()), q
+    finally:
+        ctx.set_batched_shape(16, 0, 8)
 
 
 def test_batched_fp64_matches_oracle(ctx):
