@@ -31,6 +31,7 @@ struct BSys {
   const void* phi;  // [norb][N^3] in the pair-stage precision
   void* W;          // [norb][N^3] in the pair-stage precision
   const void* tw;   // N twiddles
+  const void* vt;   // v(G) table of launch_vtable (owner layout) or null
 };
 struct BPack {
   int sys;
@@ -91,10 +92,15 @@ bool pair_supported(int N);
 bool pair_r2c_fits(int prec, int N);
 int pair_owner_ntile(int prec, int N);  // z-pass tiles per pair slot of the owner path
 // Owner-computes W over all pairs (spectra of every pair resident); W may be
-// null (energies only); epart: per (pack, tile) partial energies or null.
+// null (energies only); epart: per (pack, tile) partial energies or null; vt:
+// the table of launch_vtable or null (v(G) evaluated per element).
 hipError_t pair_owner(int prec, int N, const void* phi, void* spec, const Pack* packs, int npacks, int npairs,
                       const int32_t* adj_ptr, const int32_t* adj, int norb, int64_t nadj, void* W, double* epart,
-                      const void* tw, const KernelParams& kp, int chunk, hipStream_t s, EventRecorder* rec);
+                      const void* tw, const KernelParams& kp, const void* vt, int chunk, hipStream_t s,
+                      EventRecorder* rec);
+// v(G) / N^3 of every half-spectrum point, [z][y][kx] (N * N * (N/2 + 1)
+// values in the pair-stage precision).
+hipError_t launch_vtable(int prec, int N, const KernelParams& kp, void* vt, hipStream_t s);
 size_t pair_spec_elems(int prec, int N, const PairShape& sh);
 
 // Dense kernels (gemm.hip, linalg.hip).

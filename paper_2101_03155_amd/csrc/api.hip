@@ -743,6 +743,7 @@ static int build_impl(ace_ctx* c, const ace_grid* g, int norb, const double* phi
   int64_t* dpidx;
   int32_t *dadjp = nullptr, *dadj = nullptr;
   double *epart = nullptr, *part, *Mraw, *Lb, *Li, *scal;
+  void* vtab = nullptr;
   int* info;
   if (xi) WS(c, "W", size_t(norb) * ng * es, W);
   else W = nullptr;
@@ -753,6 +754,7 @@ static int build_impl(ace_ctx* c, const ace_grid* g, int norb, const double* phi
     WS(c, "adjp", S.adj_ptr.size() * sizeof(int32_t), dadjp);
     WS(c, "adj", std::max<size_t>(S.adj.size(), 2) * sizeof(int32_t), dadj);
     if (pair_energy) WS(c, "epart", size_t(onpk) * nblk * 2 * sizeof(double), epart);
+    WS(c, "vtab", size_t(N) * N * (N / 2 + 1) * es, vtab);
   } else {
     WS(c, "spec", size_t(S.max_launch) * pair_spec_elems(prec, N, sh) * 2 * es, spec);
     WS(c, "packs", size_t(npk) * sizeof(Pack), dpk);
@@ -797,8 +799,9 @@ static int build_impl(ace_ctx* c, const ace_grid* g, int norb, const double* phi
   // (c) pair Poisson solves, round by round
   rec_begin(R, ST_PAIRS, s);
   if (owner) {
+    HIPCHK(c, launch_vtable(prec, N, kp, vtab, s));
     HIPCHK(c, pair_owner(prec, N, phiw, spec, dpk, int(onpk), int(npairs), dadjp, dadj, norb,
-                         int64_t(S.adj.size() / 2), W, epart, tw, kp, 1 << 30, s, R));
+                         int64_t(S.adj.size() / 2), W, epart, tw, kp, vtab, 1 << 30, s, R));
     if (pair_energy) launch_pair_energy(epart, int(onpk), nblk, dpk, dpidx, dV, pair_energy, s);
   } else {
     for (const auto& L : S.launches) {
@@ -1086,6 +1089,20 @@ int ace_build_batched(ace_ctx* c, int nsys, ace_system* sys, int prec, int mode)
   // the owner region follows the (reused) round region
   const size_t owner_base = (spec_bytes + 255) / 256 * 256;
   WS(c, "bspec", std::max<size_t>(owner_base + owner_off, 256), bspec);
+  // v(G) tables of the systems in the owner layout
+  std::vector<int64_t> vt_off(nsys, -1);
+  int64_t vt_total = 0;
+  for (size_t a = 0; a < sizes.size(); ++a) {
+    if (!size_owner[a]) continue;
+    for (int q = 0; q < nsys; ++q) {
+      const int n = sys[q].grid.n[0];
+      if (n != sizes[a]) continue;
+      vt_off[q] = vt_total;
+      vt_total += (int64_t(n) * n * (n / 2 + 1) * int64_t(es) + 255) / 256 * 256;
+    }
+  }
+  char* bvt = nullptr;
+  if (vt_total > 0) WS(c, "bvtab", size_t(vt_total), bvt);
   BOwner* dbown = nullptr;
   int32_t *dbadjp = nullptr, *dbadj = nullptr;
   if (!osegs.empty()) {
@@ -1122,11 +1139,13 @@ int ace_build_batched(ace_ctx* c, int nsys, ace_system* sys, int prec, int mode)
     b.phi = prec == 0 ? (const void*)y.phi : (const void*)(bphi + size_t(w_off[q]) * es);
     b.W = bW + size_t(w_off[q]) * es;
     b.tw = tw;
+    b.vt = vt_off[q] >= 0 ? (const void*)(bvt + vt_off[q]) : nullptr;
   }
   for (size_t k = 0; k < bp.size(); ++k) bp[k].spec = bspec + (bp_owner[k] ? owner_base : 0) + bp_off[k];
   // a captured graph holds raw workspace pointers: any reallocation retires it
   mix(c->ws_gen);
   mix(uint64_t(uintptr_t(bW))); mix(uint64_t(uintptr_t(bspec))); mix(uint64_t(uintptr_t(part)));
+  mix(uint64_t(uintptr_t(bvt)));
   HIPCHK(c, hipMemcpyAsync(dsys, hs.data(), hs.size() * sizeof(BSys), hipMemcpyHostToDevice, us));
   if (!bp.empty()) HIPCHK(c, hipMemcpyAsync(dbp, bp.data(), bp.size() * sizeof(BPack), hipMemcpyHostToDevice, us));
   if (!segs.empty())
@@ -1157,6 +1176,17 @@ int ace_build_batched(ace_ctx* c, int nsys, ace_system* sys, int prec, int mode)
                                       segs.data() + a, dsegs + a, dsys, dbp, dstarts, seg_r2c[a] != 0, s);
       if (e != hipSuccess) return fail(c, ACE_E_HIP, "batched pair launch failed: %s", hipGetErrorString(e));
       a = b;
+    }
+    for (int q = 0; q < nsys; ++q) {
+      if (vt_off[q] < 0) continue;
+      const BSys& b = hs[q];
+      KernelParams kp;
+      kp.kind = b.kind;
+      kp.omega = b.omega;
+      kp.inv_ng = b.inv_ng;
+      for (int d = 0; d < 3; ++d) kp.g[d] = b.g[d];
+      hipError_t e = launch_vtable(prec, b.N, kp, bvt + vt_off[q], s);
+      if (e != hipSuccess) return fail(c, ACE_E_HIP, "batched v(G) table launch failed: %s", hipGetErrorString(e));
     }
     for (const OwnerSeg& os : osegs) {
       hipError_t e = batched_owner(prec, os.n, c->b_plan, 2 * os.npacks, os.nown, os.items, dsys, dbp + os.pack0,

@@ -362,7 +362,8 @@ __global__ __launch_bounds__(256) void k_batched_owner_conv_r(const BSys* __rest
   kp.inv_ng = sy.inv_ng;
   kp.g[0] = sy.g[0]; kp.g[1] = sy.g[1]; kp.g[2] = sy.g[2];
   cplx<T>* spec = static_cast<cplx<T>*>(bp.spec) + size_t(slot & 1) * N * PL;
-  body_conv_z_r<T, N, TXR, 256, V>(spec, tile * TXR, kp, buf, tw, threadIdx.x);
+  body_conv_z_r<T, N, TXR, 256, V>(spec, tile * TXR, kp, buf, tw, threadIdx.x, true, nullptr, nullptr,
+                                   static_cast<const T*>(sy.vt));
 }
 
 // W_k of plane z of one system: one workgroup per (system, orbital, plane)

@@ -397,6 +397,129 @@ __global__ __launch_bounds__(256, 2) void k_gemm_nt_t128(const double* __restric
   tile_write(acc, m0, M, n0, Nn, Cpart + int64_t(blockIdx.y) * M * Nn, Nn, 1.0);
 }
 
+// ---------------------------------------------------------------- 128 x 64 FP32 compensated tiles
+// The compensated FP32 product on 128 x 64 tiles: each wave accumulates a
+// 64 x 32 quarter (4 x 2 blocks of v_mfma_f32_16x16x4f32) over K steps of 16
+// staged in k-major LDS tiles and double buffered through registers (float4
+// loads of four consecutive k); every `sub` products the FP32 block sums are
+// merged into (hi, lo) pairs by TwoSum (the hi/lo pairs of a 64 x 64 quarter
+// would not fit the register file), and the tile writes hi + lo in FP64 to
+// its split's partial-sum slice.  Requires K, lda and ldb multiples of 4 and
+// 16-byte aligned operands.
+constexpr int TPF = TT + 16;  // row pitch of the FP32 LDS tiles (floats)
+constexpr int TNF = 64;       // tile columns
+
+// rows r0 .. r0 + 16 * Q - 1 of a 16-wide K step: Q float4 per thread
+template <int Q>
+__device__ __forceinline__ void f32t_load(const float* __restrict__ X, int64_t ld, int r0, int rows, int64_t k0,
+                                          int64_t ke, int tid, f4 (&v)[Q]) {
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int e = tid + 256 * i;
+    const int r = e >> 2, kq = (e & 3) * 4;
+    const int64_t k = k0 + kq;
+    f4 x = f4{0.f, 0.f, 0.f, 0.f};
+    if (r0 + r < rows && k < ke) x = *reinterpret_cast<const f4*>(X + int64_t(r0 + r) * ld + k);
+    v[i] = x;
+  }
+}
+
+template <int Q>
+__device__ __forceinline__ void f32t_store(float* S, int tid, const f4 (&v)[Q]) {
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int e = tid + 256 * i;
+    const int r = e >> 2, kq = (e & 3) * 4;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) S[(kq + c) * TPF + r] = v[i][c];
+  }
+}
+
+__global__ __launch_bounds__(256, 2) void k_gemm_nt_f32t(const float* __restrict__ A, int64_t lda,
+                                                         const float* __restrict__ B, int64_t ldb, int M, int Nn,
+                                                         int64_t K, int64_t kchunk, int ntn, int sub,
+                                                         double* __restrict__ Cpart) {
+  __shared__ float As[2 * KS * TPF];
+  __shared__ float Bs[2 * KS * TPF];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = wv >> 1, wn = wv & 1;
+  const int tm = blockIdx.x / ntn, tn = blockIdx.x % ntn;
+  const int m0 = tm * TT, n0 = tn * TNF;
+  const int64_t kb = int64_t(blockIdx.y) * kchunk;
+  const int64_t ke = (kb + kchunk < K) ? kb + kchunk : K;
+  f4 acc[4][2];
+  float hi[4][2][4], lo[4][2][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) hi[i][j][r] = lo[i][j][r] = 0.f;
+    }
+  f4 va[2], vb[1];
+  int buf = 0;
+  if (kb < ke) {
+    f32t_load<2>(A, lda, m0, M, kb, ke, tid, va);
+    f32t_load<1>(B, ldb, n0, Nn, kb, ke, tid, vb);
+    f32t_store<2>(As, tid, va);
+    f32t_store<1>(Bs, tid, vb);
+  }
+  __syncthreads();
+  int64_t since = 0;
+  for (int64_t k0 = kb; k0 < ke; k0 += KS) {
+    const bool more = k0 + KS < ke;
+    if (more) {
+      f32t_load<2>(A, lda, m0, M, k0 + KS, ke, tid, va);
+      f32t_load<1>(B, ldb, n0, Nn, k0 + KS, ke, tid, vb);
+    }
+    const float* as = As + buf * KS * TPF;
+    const float* bs = Bs + buf * KS * TPF;
+#pragma unroll
+    for (int kk = 0; kk < KS; kk += 4) {
+      const int kr = (kk + lane / 16) * TPF, li = lane % 16;
+      float a[4], b[2];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = as[kr + wm * 64 + i * 16 + li];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = bs[kr + wn * 32 + j * 16 + li];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    since += KS;
+    if (since >= sub || !more) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) two_sum(hi[i][j][r], lo[i][j][r], acc[i][j][r]);
+          acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+      since = 0;
+    }
+    if (more) {
+      buf ^= 1;
+      f32t_store<2>(As + buf * KS * TPF, tid, va);
+      f32t_store<1>(Bs + buf * KS * TPF, tid, vb);
+    }
+    __syncthreads();
+  }
+  double* out = Cpart + int64_t(blockIdx.y) * M * Nn;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm * 64 + i * 16 + 4 * (lane / 16) + r;
+        const int n = n0 + wn * 32 + j * 16 + lane % 16;
+        if (m < M && n < Nn) out[int64_t(m) * Nn + n] = double(hi[i][j][r]) + double(lo[i][j][r]);
+      }
+}
+
 // C = alpha * sum_s Cpart[s]; with SYM only tiles tm <= tn were computed and
 // the lower triangle of tiles is read transposed.
 template <bool SYM>
@@ -416,7 +539,9 @@ __global__ void k_reduce_parts_t(const double* __restrict__ Cpart, int nsplit, i
 }
 
 // Left-small: C[m][r] = alpha * sum_k S(m, k) B[k][r], S(m, k) = TRANS ? S[k][m] : S[m][k];
-// LOWER: S(m, k) = 0 for k > m.  blockIdx.x = 128-column tile of r, blockIdx.y = 128-row tile of m.
+// LOWER: S(m, k) = 0 for k > m.  blockIdx.x = 128-column tile of r (fastest:
+// neighbouring workgroups write neighbouring segments of the same rows of C,
+// measured faster than the row tiles fastest), blockIdx.y = 128-row tile of m.
 template <typename TB, bool TRANS, bool LOWER>
 __global__ __launch_bounds__(256, 2) void k_gemm_ls_t128(const double* __restrict__ S, int lds,
                                                          const TB* __restrict__ B, int64_t ldb,
@@ -489,9 +614,17 @@ hipError_t gemm_nt(int prec, int op, const void* A, int64_t lda, const void* B, 
     }
 #undef NT_LAUNCH
   } else {
-    dim3 grid((Nn + GB - 1) / GB, (M + GB - 1) / GB, unsigned(nsplit));
-    hipLaunchKernelGGL(k_gemm_nt_f32c, grid, dim3(256), 0, s, (const float*)A, lda, (const float*)B, ldb, M, Nn,
-                       K, kchunk, 256, Cpart);
+    const bool vec = K % 4 == 0 && lda % 4 == 0 && ldb % 4 == 0 && (uintptr_t(A) & 15) == 0 &&
+                     (uintptr_t(B) & 15) == 0;
+    if (vec) {
+      const int ntm = (M + TT - 1) / TT, ntn = (Nn + TNF - 1) / TNF;
+      hipLaunchKernelGGL(k_gemm_nt_f32t, dim3(unsigned(ntm * ntn), unsigned(nsplit)), dim3(256), 0, s,
+                         (const float*)A, lda, (const float*)B, ldb, M, Nn, K, kchunk, ntn, 256, Cpart);
+    } else {
+      dim3 grid((Nn + GB - 1) / GB, (M + GB - 1) / GB, unsigned(nsplit));
+      hipLaunchKernelGGL(k_gemm_nt_f32c, grid, dim3(256), 0, s, (const float*)A, lda, (const float*)B, ldb, M, Nn,
+                         K, kchunk, 256, Cpart);
+    }
     hipLaunchKernelGGL(k_reduce_parts, dim3(nb), dim3(256), 0, s, Cpart, int(nsplit), mn, alpha, C);
   }
   rec_end(rec, KC_GEMM_NT, s, (sym && prec == 0 ? 1.0 : 2.0) * double(M) * Nn * double(K));

@@ -23,6 +23,8 @@
 //    (inverse y FFT + inverse x FFT + accumulate) per z-plane.  Three
 //    HBM round trips of the spectrum per direction pair.
 //  * split (planes larger than LDS): x, y and z passes as separate kernels.
+#include <algorithm>
+
 #include "ace_internal.h"
 #include "fft.h"
 #include "pair_phases.h"
@@ -183,7 +185,7 @@ __global__ __launch_bounds__(NT) void k_fwd_xy_r(const T* __restrict__ phi, cplx
 template <typename T, int N, int TX, int NT>
 __global__ __launch_bounds__(NT) void k_conv_z_r(cplx<T>* __restrict__ spec, const Pack* __restrict__ packs,
                                                  const cplx<T>* __restrict__ twg, KernelParams kp,
-                                                 double* __restrict__ epart) {
+                                                 double* __restrict__ epart, const T* __restrict__ vt) {
   constexpr size_t PL = size_t(N) * r2c_xs<N>();
   __shared__ cplx<T> buf[N * TX];
   __shared__ cplx<T> tw[N];
@@ -192,7 +194,8 @@ __global__ __launch_bounds__(NT) void k_conv_z_r(cplx<T>* __restrict__ spec, con
   if ((slot & 1) && packs[slot >> 1].jb < 0) return;
   for (int t = threadIdx.x; t < N; t += NT) tw[t] = twg[t];
   double* es = epart ? epart + 2 * (size_t(slot >> 1) * gridDim.x + blockIdx.x) + (slot & 1) : nullptr;
-  body_conv_z_r<T, N, TX, NT>(spec + size_t(slot) * N * PL, blockIdx.x * TX, kp, buf, tw, threadIdx.x, true, es, red);
+  body_conv_z_r<T, N, TX, NT>(spec + size_t(slot) * N * PL, blockIdx.x * TX, kp, buf, tw, threadIdx.x, true, es, red,
+                              vt);
 }
 
 // Owner-computes W: blockIdx.x = z-plane, blockIdx.y = orbital k; adjacency
@@ -266,7 +269,7 @@ static hipError_t pair_round_t(const PairShape& sh, const void* phi_, void* spec
       rec_end(rec, KC_FWD_XY, s, 3 * u);
       rec_begin(rec, KC_CONV_Z, s);
       hipLaunchKernelGGL((k_conv_z_r<T, N, TXR, NTL>), dim3(N * r2c_xs<N>() / TXR, 2 * npacks), dim3(NTL), 0, s, spec,
-                         packs, tw, kp, nullptr);
+                         packs, tw, kp, nullptr, static_cast<const T*>(nullptr));
       rec_end(rec, KC_CONV_Z, s, 2 * u);
       rec_begin(rec, KC_INV_XY, s);
       if (epart)
@@ -331,8 +334,8 @@ static hipError_t pair_round_t(const PairShape& sh, const void* phi_, void* spec
 template <typename T, int N>
 static hipError_t pair_owner_t(const void* phi_, void* spec_, const Pack* packs, int npacks, int npairs,
                                const int32_t* adj_ptr, const int32_t* adj, int norb, int64_t nadj, void* W_,
-                               double* epart, const void* tw_, const KernelParams& kp, int chunk, hipStream_t s,
-                               EventRecorder* rec) {
+                               double* epart, const void* tw_, const KernelParams& kp, const void* vt_, int chunk,
+                               hipStream_t s, EventRecorder* rec) {
   if constexpr (!r2c_fits_t<T, N>()) {
     return hipErrorInvalidValue;
   } else {
@@ -341,7 +344,10 @@ static hipError_t pair_owner_t(const void* phi_, void* spec_, const Pack* packs,
     T* W = static_cast<T*>(W_);
     C* spec = static_cast<C*>(spec_);
     const C* tw = static_cast<const C*>(tw_);
-    constexpr int NTR = 512, NTL = 256, TXR = own_tx<T, N>();
+    // planes too large for two workgroups per CU take 1024 threads, so that
+    // one workgroup still runs four waves per SIMD
+    constexpr int NTR = size_t(N) * r2c_xs<N>() * sizeof(C) > 81920 ? 1024 : 512;
+    constexpr int NTL = 256, TXR = own_tx<T, N>();
     constexpr int NTILE = own_ntile<T, N>();
     constexpr size_t SLOT = size_t(N) * N * r2c_xs<N>();  // complex values per pair slot
     const double u3 = double(N) * N * N * sizeof(T);
@@ -358,7 +364,7 @@ static hipError_t pair_owner_t(const void* phi_, void* spec_, const Pack* packs,
       rec_begin(rec, KC_CONV_Z, s);
       hipLaunchKernelGGL((k_conv_z_r<T, N, TXR, NTL>), dim3(NTILE, 2 * nc), dim3(NTL), 0, s,
                          spec + 2 * size_t(c0) * SLOT, packs + c0, tw, kp,
-                         epart ? epart + 2 * size_t(c0) * NTILE : nullptr);
+                         epart ? epart + 2 * size_t(c0) * NTILE : nullptr, static_cast<const T*>(vt_));
       rec_end(rec, KC_CONV_Z, s, 2 * u3 * pc);
     }
     if (W) {
@@ -383,14 +389,45 @@ bool pair_supported(int N) {
 
 hipError_t pair_owner(int prec, int N, const void* phi, void* spec, const Pack* packs, int npacks, int npairs,
                       const int32_t* adj_ptr, const int32_t* adj, int norb, int64_t nadj, void* W, double* epart,
-                      const void* tw, const KernelParams& kp, int chunk, hipStream_t s, EventRecorder* rec) {
+                      const void* tw, const KernelParams& kp, const void* vt, int chunk, hipStream_t s,
+                      EventRecorder* rec) {
   switch (N) {
 #define X(n)                                                                                                       \
   case n:                                                                                                          \
     return prec == 0 ? pair_owner_t<double, n>(phi, spec, packs, npacks, npairs, adj_ptr, adj, norb, nadj, W,      \
-                                               epart, tw, kp, chunk, s, rec)                                       \
+                                               epart, tw, kp, vt, chunk, s, rec)                                   \
                      : pair_owner_t<float, n>(phi, spec, packs, npacks, npairs, adj_ptr, adj, norb, nadj, W, epart, \
-                                              tw, kp, chunk, s, rec);
+                                              tw, kp, vt, chunk, s, rec);
+    ACE_PAIR_SIZES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+// v(G) of the half spectrum, [z][y][kx], in the pair-stage precision: the
+// same values the z pass would evaluate per element (kernel_value).
+template <typename T, int N>
+__global__ void k_vtable(KernelParams kp, T* __restrict__ vt) {
+  constexpr int XS = r2c_xs<N>();
+  constexpr int64_t TOT = int64_t(N) * N * XS;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < TOT; e += int64_t(gridDim.x) * blockDim.x) {
+    const int kx = int(e % XS), y = int((e / XS) % N), z = int(e / (int64_t(XS) * N));
+    vt[e] = kernel_value<T, N>(kp, kx, y, z);
+  }
+}
+
+hipError_t launch_vtable(int prec, int N, const KernelParams& kp, void* vt, hipStream_t s) {
+  const int64_t tot = int64_t(N) * N * (N / 2 + 1);
+  const unsigned g = unsigned(std::min<int64_t>((tot + 255) / 256, 2048));
+  switch (N) {
+#define X(n)                                                                                                   \
+  case n:                                                                                                      \
+    if (prec == 0)                                                                                             \
+      hipLaunchKernelGGL((k_vtable<double, n>), dim3(g), dim3(256), 0, s, kp, static_cast<double*>(vt));       \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_vtable<float, n>), dim3(g), dim3(256), 0, s, kp, static_cast<float*>(vt));         \
+    return hipGetLastError();
     ACE_PAIR_SIZES(X)
 #undef X
     default:

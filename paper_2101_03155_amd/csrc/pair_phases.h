@@ -287,11 +287,14 @@ __device__ __forceinline__ void body_fwd_xy_r(const T* __restrict__ pi_, const T
 // With eslot != nullptr the tile's share of sum_r rho v_ij is formed on the
 // way (Parseval: sum_r rho v = sum_G (v(G)/N^3) |rho^(G)|^2, the half spectrum
 // weighted 2 except at kx = 0 and N/2) and written to eslot[0]; red holds
-// NT / 64 doubles.
+// NT / 64 doubles.  vt (nullable): the kernel values v(G) of the whole half
+// spectrum, [z][y][kx] as the spectrum, read (before the forward transform,
+// so the loads overlap it) instead of evaluated per element.
 template <typename T, int N, int TX, int NT, int V = 0>
 __device__ __forceinline__ void body_conv_z_r(cplx<T>* spec_p, int f0, const KernelParams& kp, cplx<T>* buf,
                                               const cplx<T>* tw, int tid, bool active = true,
-                                              double* eslot = nullptr, double* red = nullptr) {
+                                              double* eslot = nullptr, double* red = nullptr,
+                                              const T* __restrict__ vt = nullptr) {
   using C = cplx<T>;
   constexpr int XS = r2c_xs<N>(), PL = N * XS, E = N * TX;
   C* base = spec_p + f0;
@@ -306,14 +309,26 @@ __device__ __forceinline__ void body_conv_z_r(cplx<T>* spec_p, int f0, const Ker
       zr.y = T(0);
       return zr;
     }, tid);
+  constexpr int LV = (E + NT - 1) / NT;
+  T vv[LV];
+  if (vt) {
+#pragma unroll
+    for (int q = 0; q < LV; ++q) {
+      const int e = tid + q * NT;
+      if ((E % NT == 0 || e < E) && (PL % TX == 0 || e % TX < ncol)) vv[q] = vt[size_t(e / TX) * PL + f0 + e % TX];
+    }
+  }
   __syncthreads();
   fft_lines<T, N, TX, 1, TX, NT, -1, false, V>(buf, tw, tid);
   double es = 0.0;
-  for (int e = tid; e < E; e += NT) {
+#pragma unroll
+  for (int q = 0; q < LV; ++q) {
+    const int e = tid + q * NT;
+    if (E % NT != 0 && e >= E) continue;
     if (PL % TX != 0 && e % TX >= ncol) continue;
     const int f = f0 + e % TX;
     const int kx = f % XS;
-    const T v = kernel_value<T, N>(kp, kx, f / XS, e / TX);
+    const T v = vt ? vv[q] : kernel_value<T, N>(kp, kx, f / XS, e / TX);
     C c = buf[e];
     if (eslot) es += double((kx == 0 || kx == N / 2) ? 1 : 2) * double(v) * (double(c.x) * c.x + double(c.y) * c.y);
     c.x *= v;
