@@ -49,7 +49,7 @@ struct BRound {                // one segment: the packs of one grid size in one
 struct BOwner {
   int sys;                   // index into the BSys table
   int norb;
-  int64_t item0;             // first (orbital, plane) work item of the system
+  int64_t orb0;              // offset of the system's orbitals among those of the segment
   const int32_t* adj_ptr;    // [norb + 1] absolute offsets into the entry table
 };
 
@@ -167,7 +167,7 @@ bool batched_r2c_fits(int prec, int n);
 // Owner layout for the systems of grid size n: forward and z pass over the
 // nslots pair slots of packs (whose spectra are all resident), then W of
 // every system from its adjacency entries (slot, partner) in adj; items is the
-// sum over the systems of norb * n.
+// sum over the systems of norb * n (n a multiple of 8).
 hipError_t batched_owner(int prec, int n, int plan_v, int nslots, int nown, int64_t items, const BSys* sys,
                          const BPack* packs, const BOwner* own, const int32_t* adj, const void* spec, hipStream_t s);
 // work items per pair slot of phase 0..2 (the z pass packs two tiles per item

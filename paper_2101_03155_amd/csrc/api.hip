@@ -1003,7 +1003,7 @@ int ace_build_batched(ace_ctx* c, int nsys, ace_system* sys, int prec, int mode)
       BOwner o{};
       o.sys = q;
       o.norb = sys[q].norb;
-      o.item0 = os.items;
+      o.orb0 = os.items / n;
       own_adjp_off.push_back(int64_t(hadjp.size()));
       const int32_t e0 = int32_t(hadj.size() / 2);
       for (int32_t v : S.adj_ptr) hadjp.push_back(v + e0);

@@ -367,8 +367,11 @@ __global__ __launch_bounds__(256) void k_batched_owner_conv_r(const BSys* __rest
 }
 
 // W_k of plane z of one system: one workgroup per (system, orbital, plane)
-// item, plane fastest; the system is found by bisection over the item offsets.
-// Adjacency entries (slot, partner) index the slots of the segment's spectra.
+// item.  The items are dealt to the eight XCDs in turn: XCD x is given the
+// planes z = x mod 8, with the orbitals of all systems fastest (as in the
+// single-build owner pass); the system is found by bisection over the orbital
+// offsets.  Adjacency entries (slot, partner) index the slots of the
+// segment's spectra.
 template <typename T, int N, int V>
 __global__ __launch_bounds__(BNTR, 4) void k_batched_owner_r(int nown, const BOwner* __restrict__ own,
                                                           const BSys* __restrict__ sys,
@@ -377,16 +380,18 @@ __global__ __launch_bounds__(BNTR, 4) void k_batched_owner_r(int nown, const BOw
   constexpr size_t NG = size_t(N) * N * N;
   __shared__ cplx<T> buf[N * r2c_xs<N>()];
   __shared__ cplx<T> tw[N];
-  const int64_t j = blockIdx.x;
+  const int64_t g = blockIdx.x, l = g >> 3;
+  const int64_t norb_all = int64_t(gridDim.x) / N;
+  const int z = int(l / norb_all) * 8 + int(g & 7);
+  const int64_t j = l % norb_all;
   int lo = 0, hi = nown;
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
-    if (own[mid].item0 <= j) lo = mid; else hi = mid;
+    if (own[mid].orb0 <= j) lo = mid; else hi = mid;
   }
   const BOwner o = own[lo];
   const BSys& sy = sys[o.sys];
-  const int64_t b = j - o.item0;
-  const int k = int(b / N), z = int(b % N);
+  const int k = int(j - o.orb0);
   const cplx<T>* twg = static_cast<const cplx<T>*>(sy.tw);
   for (int t = threadIdx.x; t < N; t += BNTR) tw[t] = twg[t];
   const size_t zo = size_t(z) * N * N;
