@@ -272,8 +272,20 @@ template <int S, typename C> struct Dft<16, S, C> {
 // LINES lines of length N in LDS; element p of line l at buf[l*LS + p*PS].
 // JFAST: consecutive threads take consecutive butterflies of one line
 // (unit-stride lines) rather than the same butterfly of consecutive lines.
+// The pass's inputs come from load(l, p) (by default buf[l*LS + p*PS]); all
+// of them are read before the barrier, so a first pass may read another
+// layout of the same buffer than the one it writes.
+template <typename T, int N, int P, int LINES, int LS, int PS, int NT, int S, bool JFAST, int V, typename L>
+__device__ __forceinline__ void fft_pass_l(cplx<T>* buf, const cplx<T>* tw, int tid, L load);
+
 template <typename T, int N, int P, int LINES, int LS, int PS, int NT, int S, bool JFAST, int V>
 __device__ __forceinline__ void fft_pass(cplx<T>* buf, const cplx<T>* tw, int tid) {
+  fft_pass_l<T, N, P, LINES, LS, PS, NT, S, JFAST, V>(buf, tw, tid,
+                                                      [buf](int l, int p) { return buf[l * LS + p * PS]; });
+}
+
+template <typename T, int N, int P, int LINES, int LS, int PS, int NT, int S, bool JFAST, int V, typename L>
+__device__ __forceinline__ void fft_pass_l(cplx<T>* buf, const cplx<T>* tw, int tid, L load) {
   using C = cplx<T>;
   constexpr int R = plan_radix_v(N, P, V);
   constexpr int NS = plan_ns(N, P, V);
@@ -288,9 +300,8 @@ __device__ __forceinline__ void fft_pass(cplx<T>* buf, const cplx<T>* tw, int ti
     if ((TOT % NT) == 0 || b < TOT) {
       const int l = JFAST ? b / NB : b % LINES;
       const int j = JFAST ? b % NB : b / LINES;
-      const C* base = buf + l * LS;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[s][r] = base[(j + r * NB) * PS];
+      for (int r = 0; r < R; ++r) v[s][r] = load(l, j + r * NB);
     }
   }
   __syncthreads();
@@ -332,6 +343,15 @@ template <typename T, int N, int LINES, int LS, int PS, int NT, int S, bool JFAS
 __device__ __forceinline__ void fft_lines(cplx<T>* buf, const cplx<T>* tw, int tid) {
   static_assert(smooth235(N), "FFT length must be 2^a 3^b 5^c");
   fft_lines_from<T, N, 0, LINES, LS, PS, NT, S, JFAST, V>(buf, tw, tid);
+}
+
+// The same, with the first pass reading its inputs through load(l, p) (an
+// element-wise step fused into the transform's first LDS read).
+template <typename T, int N, int LINES, int LS, int PS, int NT, int S, bool JFAST, int V, typename L>
+__device__ __forceinline__ void fft_lines_load(cplx<T>* buf, const cplx<T>* tw, int tid, L load) {
+  static_assert(smooth235(N), "FFT length must be 2^a 3^b 5^c");
+  fft_pass_l<T, N, 0, LINES, LS, PS, NT, S, JFAST, V>(buf, tw, tid, load);
+  fft_lines_from<T, N, 1, LINES, LS, PS, NT, S, JFAST, V>(buf, tw, tid);
 }
 
 }  // namespace ace

@@ -245,37 +245,24 @@ __device__ __forceinline__ void body_fwd_xy_r(const T* __restrict__ pi_, const T
   }
   __syncthreads();
   fft_lines<T, N, H, N, 1, NT, -1, true, V>(buf, tw, tid);
-  // separate the two half spectra; all reads before the barrier, all writes after
-  constexpr int ITEMS = H * XS;
-  constexpr int PER = (ITEMS + NT - 1) / NT;
-  C a[PER], b[PER];
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int it = tid + q * NT;
-    if (ITEMS % NT == 0 || it < ITEMS) {
-      const int l = it / XS, k = it % XS;
-      a[q] = buf[l * N + k];
-      b[q] = buf[l * N + (k == 0 ? 0 : N - k)];
+  // The y transforms of the half spectra, whose first pass separates the two
+  // rows of each packed line on the way in: row y < H of column k is
+  // X1 = (Z[k] + conj Z[N-k]) / 2 of line y, row y >= H is
+  // X2 = (Z[k] - conj Z[N-k]) / 2i of line y - H (Z = line after the x
+  // transform, still in the packed layout [l][N] of buf).
+  fft_lines_load<T, N, XS, 1, XS, NT, -1, false, V>(buf, tw, tid, [buf](int k, int y) {
+    const int l = y < H ? y : y - H;
+    const C a = buf[l * N + k], b = buf[l * N + (k == 0 ? 0 : N - k)];
+    C x;
+    if (y < H) {
+      x.x = T(0.5) * (a.x + b.x);
+      x.y = T(0.5) * (a.y - b.y);
+    } else {
+      x.x = T(0.5) * (a.y + b.y);
+      x.y = T(0.5) * (b.x - a.x);
     }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int it = tid + q * NT;
-    if (ITEMS % NT == 0 || it < ITEMS) {
-      const int l = it / XS, k = it % XS;
-      C x1, x2;
-      x1.x = T(0.5) * (a[q].x + b[q].x);
-      x1.y = T(0.5) * (a[q].y - b[q].y);
-      // (a - conj b) / 2i
-      x2.x = T(0.5) * (a[q].y + b[q].y);
-      x2.y = T(0.5) * (b[q].x - a[q].x);
-      buf[l * XS + k] = x1;
-      buf[(l + H) * XS + k] = x2;
-    }
-  }
-  __syncthreads();
-  fft_lines<T, N, XS, 1, XS, NT, -1, false, V>(buf, tw, tid);
+    return x;
+  });
   for (int e = tid; e < N * XS; e += NT) out[e] = buf[e];
 }
 
@@ -369,42 +356,29 @@ __device__ __forceinline__ void body_inv_xy_t(cplx<T>* buf, const cplx<T>* tw, i
   using C = cplx<T>;
   constexpr int H = N / 2, XS = r2c_xs<N>();
   fft_lines<T, N, XS, 1, XS, NT, +1, false, V>(buf, tw, tid);
-  // re-pack: Z[k] = X1[k] + i X2[k], Z[N-k] = conj X1[k] + i conj X2[k]; the
-  // zero and Nyquist bins of a real row are real, as a c2r transform takes them
-  constexpr int ITEMS = H * XS;
-  constexpr int PER = (ITEMS + NT - 1) / NT;
-  C a[PER], b[PER];
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int it = tid + q * NT;
-    if (ITEMS % NT == 0 || it < ITEMS) {
-      const int l = it / XS, k = it % XS;
-      a[q] = buf[l * XS + k];
-      b[q] = buf[(l + H) * XS + k];
+  // The x transforms, whose first pass re-packs rows l and l + H into line
+  // l on the way in: Z[k] = X1[k] + i X2[k] and Z[N-k] = conj X1[k] +
+  // i conj X2[k] for k <= H (X1, X2 = rows l, l + H of the [y][kx] layout);
+  // the zero and Nyquist bins of a real row are real, as a c2r transform
+  // takes them.
+  fft_lines_load<T, N, H, N, 1, NT, +1, true, V>(buf, tw, tid, [buf](int l, int p) {
+    const bool lowk = p <= H;
+    const int k = lowk ? p : N - p;
+    C x1 = buf[l * XS + k], x2 = buf[(l + H) * XS + k];
+    if (k == 0 || k == H) {
+      x1.y = T(0);
+      x2.y = T(0);
     }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int it = tid + q * NT;
-    if (ITEMS % NT == 0 || it < ITEMS) {
-      const int l = it / XS, k = it % XS;
-      C x1 = a[q], x2 = b[q];
-      if (k == 0 || k == H) { x1.y = T(0); x2.y = T(0); }
-      C z;
+    C z;
+    if (lowk) {
       z.x = x1.x - x2.y;
       z.y = x1.y + x2.x;
-      buf[l * N + k] = z;
-      if (k != 0 && k != H) {
-        C w;
-        w.x = x1.x + x2.y;
-        w.y = x2.x - x1.y;
-        buf[l * N + N - k] = w;
-      }
+    } else {
+      z.x = x1.x + x2.y;
+      z.y = x2.x - x1.y;
     }
-  }
-  __syncthreads();
-  fft_lines<T, N, H, N, 1, NT, +1, true, V>(buf, tw, tid);
+    return z;
+  });
 }
 
 // W_i -= v phi_j and (i != j) W_j -= v phi_i over plane z for one pair, with
