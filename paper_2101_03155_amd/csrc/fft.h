@@ -274,9 +274,20 @@ template <int S, typename C> struct Dft<16, S, C> {
 // (unit-stride lines) rather than the same butterfly of consecutive lines.
 // The pass's inputs come from load(l, p) (by default buf[l*LS + p*PS]); all
 // of them are read before the barrier, so a first pass may read another
-// layout of the same buffer than the one it writes.
+// layout of the same buffer than the one it writes, or global memory.  Its
+// outputs go to store(l, p, value) (by default buf[l*LS + p*PS] = value),
+// followed by a barrier unless END_SYNC is false (a last pass storing to
+// global memory; the barrier between reads and writes stays, so the buffer's
+// previous contents are read by all threads before a first pass writes it).
+template <typename T, int N, int P, int LINES, int LS, int PS, int NT, int S, bool JFAST, int V, bool END_SYNC,
+          typename L, typename St>
+__device__ __forceinline__ void fft_pass_ls(cplx<T>* buf, const cplx<T>* tw, int tid, L load, St store);
+
 template <typename T, int N, int P, int LINES, int LS, int PS, int NT, int S, bool JFAST, int V, typename L>
-__device__ __forceinline__ void fft_pass_l(cplx<T>* buf, const cplx<T>* tw, int tid, L load);
+__device__ __forceinline__ void fft_pass_l(cplx<T>* buf, const cplx<T>* tw, int tid, L load) {
+  fft_pass_ls<T, N, P, LINES, LS, PS, NT, S, JFAST, V, true>(
+      buf, tw, tid, load, [buf](int l, int p, cplx<T> x) { buf[l * LS + p * PS] = x; });
+}
 
 template <typename T, int N, int P, int LINES, int LS, int PS, int NT, int S, bool JFAST, int V>
 __device__ __forceinline__ void fft_pass(cplx<T>* buf, const cplx<T>* tw, int tid) {
@@ -284,8 +295,9 @@ __device__ __forceinline__ void fft_pass(cplx<T>* buf, const cplx<T>* tw, int ti
                                                       [buf](int l, int p) { return buf[l * LS + p * PS]; });
 }
 
-template <typename T, int N, int P, int LINES, int LS, int PS, int NT, int S, bool JFAST, int V, typename L>
-__device__ __forceinline__ void fft_pass_l(cplx<T>* buf, const cplx<T>* tw, int tid, L load) {
+template <typename T, int N, int P, int LINES, int LS, int PS, int NT, int S, bool JFAST, int V, bool END_SYNC,
+          typename L, typename St>
+__device__ __forceinline__ void fft_pass_ls(cplx<T>* buf, const cplx<T>* tw, int tid, L load, St store) {
   using C = cplx<T>;
   constexpr int R = plan_radix_v(N, P, V);
   constexpr int NS = plan_ns(N, P, V);
@@ -320,13 +332,12 @@ __device__ __forceinline__ void fft_pass_l(cplx<T>* buf, const cplx<T>* tw, int 
         }
       }
       Dft<R, S, C>::run(v[s]);
-      C* base = buf + l * LS;
       const int o = (j / NS) * NS * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) base[(o + r * NS) * PS] = v[s][r];
+      for (int r = 0; r < R; ++r) store(l, o + r * NS, v[s][r]);
     }
   }
-  __syncthreads();
+  if (END_SYNC) __syncthreads();
 }
 
 template <typename T, int N, int P, int LINES, int LS, int PS, int NT, int S, bool JFAST, int V>
@@ -343,6 +354,33 @@ template <typename T, int N, int LINES, int LS, int PS, int NT, int S, bool JFAS
 __device__ __forceinline__ void fft_lines(cplx<T>* buf, const cplx<T>* tw, int tid) {
   static_assert(smooth235(N), "FFT length must be 2^a 3^b 5^c");
   fft_lines_from<T, N, 0, LINES, LS, PS, NT, S, JFAST, V>(buf, tw, tid);
+}
+
+// Passes P .. plan_len(N) - 2 in place, then the last pass through the storer.
+template <typename T, int N, int P, int LINES, int LS, int PS, int NT, int S, bool JFAST, int V, typename St>
+__device__ __forceinline__ void fft_lines_to(cplx<T>* buf, const cplx<T>* tw, int tid, St store) {
+  if constexpr (P + 1 < plan_len(N)) {
+    fft_pass<T, N, P, LINES, LS, PS, NT, S, JFAST, V>(buf, tw, tid);
+    fft_lines_to<T, N, P + 1, LINES, LS, PS, NT, S, JFAST, V>(buf, tw, tid, store);
+  } else {
+    fft_pass_ls<T, N, P, LINES, LS, PS, NT, S, JFAST, V, false>(
+        buf, tw, tid, [buf](int l, int p) { return buf[l * LS + p * PS]; }, store);
+  }
+}
+
+// Full transform with the first pass reading through load(l, p) and the last
+// writing through store(l, p, value) (to global memory: no closing barrier).
+// Expects nothing of buf (the first pass fills it after a barrier); ends
+// unsynchronized.
+template <typename T, int N, int LINES, int LS, int PS, int NT, int S, bool JFAST, int V, typename L, typename St>
+__device__ __forceinline__ void fft_lines_ls(cplx<T>* buf, const cplx<T>* tw, int tid, L load, St store) {
+  static_assert(smooth235(N), "FFT length must be 2^a 3^b 5^c");
+  if constexpr (plan_len(N) == 1) {
+    fft_pass_ls<T, N, 0, LINES, LS, PS, NT, S, JFAST, V, false>(buf, tw, tid, load, store);
+  } else {
+    fft_pass_l<T, N, 0, LINES, LS, PS, NT, S, JFAST, V>(buf, tw, tid, load);
+    fft_lines_to<T, N, 1, LINES, LS, PS, NT, S, JFAST, V>(buf, tw, tid, store);
+  }
 }
 
 // The same, with the first pass reading its inputs through load(l, p) (an

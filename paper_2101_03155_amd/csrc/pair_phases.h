@@ -216,41 +216,32 @@ __device__ __forceinline__ void body_fwd_xy_r(const T* __restrict__ pi_, const T
                                               cplx<T>* buf, const cplx<T>* tw, int tid) {
   using C = cplx<T>;
   constexpr int H = N / 2, XS = r2c_xs<N>();
-  constexpr int HN = H * N;
-  {
-    // all of a thread's loads are issued before its first use (latency hiding
-    // at two workgroups per CU)
-    constexpr int LP = (HN + NT - 1) / NT;
-    T a0[LP], b0[LP], a1[LP], b1[LP];
-#pragma unroll
-    for (int q = 0; q < LP; ++q) {
-      const int e = tid + q * NT;
-      if (HN % NT == 0 || e < HN) {
-        a0[q] = pi_[e];
-        b0[q] = pj_[e];
-        a1[q] = pi_[e + HN];
-        b1[q] = pj_[e + HN];
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < LP; ++q) {
-      const int e = tid + q * NT;
-      if (HN % NT == 0 || e < HN) {
-        C v;
-        v.x = a0[q] * b0[q];
-        v.y = a1[q] * b1[q];
-        buf[e] = v;
-      }
-    }
+  // The x transforms of the packed lines (line l: row l in .x, row l + H in
+  // .y).  When the first pass has a butterfly for every thread it forms the
+  // products from global memory itself (all of a thread's loads are issued
+  // before the pass's barrier); otherwise (1024-thread workgroups) the
+  // products are staged through LDS by all threads first, which keeps more
+  // loads in flight (measured).
+  auto prod = [pi_, pj_](int l, int p) {
+    C v;
+    v.x = pi_[l * N + p] * pj_[l * N + p];
+    v.y = pi_[(l + H) * N + p] * pj_[(l + H) * N + p];
+    return v;
+  };
+  if constexpr (H * (N / plan_radix_v(N, 0, V)) >= NT) {
+    fft_lines_load<T, N, H, N, 1, NT, -1, true, V>(buf, tw, tid, prod);
+  } else {
+    stage_in<C, H * N, NT>(buf, [&](int e) { return prod(e / N, e % N); }, tid);
+    __syncthreads();
+    fft_lines<T, N, H, N, 1, NT, -1, true, V>(buf, tw, tid);
   }
-  __syncthreads();
-  fft_lines<T, N, H, N, 1, NT, -1, true, V>(buf, tw, tid);
   // The y transforms of the half spectra, whose first pass separates the two
   // rows of each packed line on the way in: row y < H of column k is
   // X1 = (Z[k] + conj Z[N-k]) / 2 of line y, row y >= H is
   // X2 = (Z[k] - conj Z[N-k]) / 2i of line y - H (Z = line after the x
-  // transform, still in the packed layout [l][N] of buf).
-  fft_lines_load<T, N, XS, 1, XS, NT, -1, false, V>(buf, tw, tid, [buf](int k, int y) {
+  // transform, still in the packed layout [l][N] of buf); the last pass
+  // stores the spectrum ([y][kx]) to global memory.
+  auto sep = [buf](int k, int y) {
     const int l = y < H ? y : y - H;
     const C a = buf[l * N + k], b = buf[l * N + (k == 0 ? 0 : N - k)];
     C x;
@@ -262,8 +253,9 @@ __device__ __forceinline__ void body_fwd_xy_r(const T* __restrict__ pi_, const T
       x.y = T(0.5) * (b.x - a.x);
     }
     return x;
-  });
-  for (int e = tid; e < N * XS; e += NT) out[e] = buf[e];
+  };
+  fft_lines_ls<T, N, XS, 1, XS, NT, -1, false, V>(buf, tw, tid, sep,
+                                                  [out](int l, int p, C x) { out[p * XS + l] = x; });
 }
 
 // z lines of the TX consecutive flattened columns starting at f0 of one
@@ -288,14 +280,6 @@ __device__ __forceinline__ void body_conv_z_r(cplx<T>* spec_p, int f0, const Ker
   // columns of this tile inside the plane (fewer than TX in a ragged last
   // tile, whose other columns are transformed as zeros and not stored)
   const int ncol = PL - f0 < TX ? PL - f0 : TX;
-  if (active)
-    stage_in<C, E, NT>(buf, [&](int e) {
-      if (PL % TX == 0 || e % TX < ncol) return base[size_t(e / TX) * PL + (e % TX)];
-      C zr;
-      zr.x = T(0);
-      zr.y = T(0);
-      return zr;
-    }, tid);
   constexpr int LV = (E + NT - 1) / NT;
   T vv[LV];
   if (vt) {
@@ -305,8 +289,14 @@ __device__ __forceinline__ void body_conv_z_r(cplx<T>* spec_p, int f0, const Ker
       if ((E % NT == 0 || e < E) && (PL % TX == 0 || e % TX < ncol)) vv[q] = vt[size_t(e / TX) * PL + f0 + e % TX];
     }
   }
-  __syncthreads();
-  fft_lines<T, N, TX, 1, TX, NT, -1, false, V>(buf, tw, tid);
+  // forward z transforms, the first pass reading the tile from global memory
+  fft_lines_load<T, N, TX, 1, TX, NT, -1, false, V>(buf, tw, tid, [=](int l, int p) {
+    if (active && (PL % TX == 0 || l < ncol)) return base[size_t(p) * PL + l];
+    C zr;
+    zr.x = T(0);
+    zr.y = T(0);
+    return zr;
+  });
   double es = 0.0;
 #pragma unroll
   for (int q = 0; q < LV; ++q) {
@@ -332,10 +322,10 @@ __device__ __forceinline__ void body_conv_z_r(cplx<T>* spec_p, int f0, const Ker
     for (int w = 0; w < NT / 64; ++w) sx += red[w];
     eslot[0] = sx;
   }
-  fft_lines<T, N, TX, 1, TX, NT, +1, false, V>(buf, tw, tid);
-  if (active)
-    for (int e = tid; e < E; e += NT)
-      if (PL % TX == 0 || e % TX < ncol) base[size_t(e / TX) * PL + (e % TX)] = buf[e];
+  // inverse z transforms, the last pass storing the tile to global memory
+  fft_lines_to<T, N, 0, TX, 1, TX, NT, +1, false, V>(buf, tw, tid, [=](int l, int p, C x) {
+    if (active && (PL % TX == 0 || l < ncol)) base[size_t(p) * PL + l] = x;
+  });
 }
 
 // Half spectrum of plane z -> the real potential of the plane, left in buf as
@@ -351,11 +341,31 @@ __device__ __forceinline__ void body_inv_xy_r(const cplx<T>* in, cplx<T>* buf, c
   body_inv_xy_t<T, N, NT, V>(buf, tw, tid);
 }
 
+// The x transforms of body_inv_xy_t (buf holds the y-transformed plane).
+template <typename T, int N, int NT, int V>
+__device__ __forceinline__ void inv_x_repacked(cplx<T>* buf, const cplx<T>* tw, int tid);
+
 template <typename T, int N, int NT, int V>
 __device__ __forceinline__ void body_inv_xy_t(cplx<T>* buf, const cplx<T>* tw, int tid) {
+  fft_lines<T, N, r2c_xs<N>(), 1, r2c_xs<N>(), NT, +1, false, V>(buf, tw, tid);
+  inv_x_repacked<T, N, NT, V>(buf, tw, tid);
+}
+
+// The same from the half-spectrum plane in global memory: the first pass of
+// the y transforms reads it directly (no staging copy).  Needs no barrier
+// before it: the first pass reads before its barrier and writes after.
+template <typename T, int N, int NT, int V = 0>
+__device__ __forceinline__ void body_inv_xy_g(const cplx<T>* __restrict__ in, cplx<T>* buf, const cplx<T>* tw,
+                                              int tid) {
+  constexpr int XS = r2c_xs<N>();
+  fft_lines_load<T, N, XS, 1, XS, NT, +1, false, V>(buf, tw, tid, [in](int l, int p) { return in[p * XS + l]; });
+  inv_x_repacked<T, N, NT, V>(buf, tw, tid);
+}
+
+template <typename T, int N, int NT, int V>
+__device__ __forceinline__ void inv_x_repacked(cplx<T>* buf, const cplx<T>* tw, int tid) {
   using C = cplx<T>;
   constexpr int H = N / 2, XS = r2c_xs<N>();
-  fft_lines<T, N, XS, 1, XS, NT, +1, false, V>(buf, tw, tid);
   // The x transforms, whose first pass re-packs rows l and l + H into line
   // l on the way in: Z[k] = X1[k] + i X2[k] and Z[N-k] = conj X1[k] +
   // i conj X2[k] for k <= H (X1, X2 = rows l, l + H of the [y][kx] layout);
@@ -461,7 +471,9 @@ __device__ __forceinline__ void body_inv_owner_r(const T* __restrict__ phi, cons
     int t = tid;
     asm volatile("" : "+v"(t));
     const int p = adj[2 * a], j = adj[2 * a + 1];
-    body_inv_xy_r<T, N, NT, V>(spec + size_t(p) * N * PL + zp, buf, tw, t);
+    // (the first pass's barrier also orders the previous entry's reads of buf
+    // before this entry's writes)
+    body_inv_xy_g<T, N, NT, V>(spec + size_t(p) * N * PL + zp, buf, tw, t);
     const T* fj = phi + size_t(j) * NG + zo;
     // partner row in batches of U elements per thread, loads first
     constexpr int U = 3;
@@ -483,7 +495,6 @@ __device__ __forceinline__ void body_inv_owner_r(const T* __restrict__ phi, cons
         }
       }
     }
-    __syncthreads();  // buf is refilled by the next entry
   }
 #pragma unroll
   for (int q = 0; q < LP; ++q) {
