@@ -277,26 +277,9 @@ __device__ __forceinline__ void tile_rk(int e, int& r, int& k) {
   if (KM) { r = e % TT; k = e / TT; } else { r = e / KS; k = e % KS; }
 }
 
-// VEC (k-contiguous FP64 operands, KM false; ld, the K range and X aligned to
-// 4 doubles): each thread loads two 32-byte runs of four consecutive k, the
-// lanes of a wave spanning rows, so that the k-major LDS stores of
-// neighbouring lanes fall in neighbouring banks (the scalar mapping, 16
-// lanes per row, stores 16 lanes TP doubles apart into the same two banks).
-template <typename TX, bool KM, int OP, bool VEC = false>
+template <typename TX, bool KM, int OP>
 __device__ __forceinline__ void tile_load(const TX* __restrict__ X, int64_t ld, int r0, int rows, int64_t k0,
                                           int64_t ke, int tid, double (&v)[8]) {
-  if constexpr (VEC && !KM) {
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int e = tid + 256 * i, r = e & (TT - 1), kq = e >> 7;
-      const int64_t kk = k0 + 4 * kq;
-      d4 x = d4{0.0, 0.0, 0.0, 0.0};
-      if (r0 + r < rows && kk < ke) x = *reinterpret_cast<const d4*>(X + int64_t(r0 + r) * ld + kk);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) v[4 * i + c] = opmap<OP>(double(x[c]));
-    }
-    return;
-  }
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     int r, k;
@@ -308,14 +291,22 @@ __device__ __forceinline__ void tile_load(const TX* __restrict__ X, int64_t ld, 
   }
 }
 
-template <bool KM, bool VEC = false>
+// k-contiguous operands (KM false) are kept row-major in LDS, RP doubles per
+// row: the stores of a wave (16 lanes along k per row) are then contiguous,
+// and the MFMA operand reads (16 rows by 4 k per wave) fall in distinct
+// banks within each half-wave.  (The k-major layout with the TP pitch would
+// put the 16 lanes of a row on the same two banks.)
+constexpr int RP = KS + 1;
+static_assert(TT * RP <= KS * TP, "a row-major tile must fit a k-major tile's buffer");
+
+template <bool KM>
 __device__ __forceinline__ void tile_store(double* S, int tid, const double (&v)[8]) {
-  if constexpr (VEC && !KM) {
+  if constexpr (!KM) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int e = tid + 256 * i, r = e & (TT - 1), kq = e >> 7;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) S[(4 * kq + c) * TP + r] = v[4 * i + c];
+    for (int i = 0; i < 8; ++i) {
+      int r, k;
+      tile_rk<false>(tid + 256 * i, r, k);
+      S[r * RP + k] = v[i];
     }
     return;
   }
@@ -328,7 +319,7 @@ __device__ __forceinline__ void tile_store(double* S, int tid, const double (&v)
 }
 
 // Accumulate the tile over [kb, ke) into acc (per wave 4 x 4 blocks).
-template <typename TA, typename TB, bool AK, bool BK, int OP, bool VA = false, bool VB = false>
+template <typename TA, typename TB, bool AK, bool BK, int OP>
 __device__ __forceinline__ void tile_mma(const TA* __restrict__ A, int64_t lda, const TB* __restrict__ B,
                                          int64_t ldb, int m0, int M, int n0, int Nn, int64_t kb, int64_t ke,
                                          double* As, double* Bs, d4 (&acc)[4][4]) {
@@ -337,28 +328,28 @@ __device__ __forceinline__ void tile_mma(const TA* __restrict__ A, int64_t lda, 
   double va[8], vb[8];
   int buf = 0;
   if (kb < ke) {
-    tile_load<TA, AK, OP, VA>(A, lda, m0, M, kb, ke, tid, va);
-    tile_load<TB, BK, OP, VB>(B, ldb, n0, Nn, kb, ke, tid, vb);
-    tile_store<AK, VA>(As, tid, va);
-    tile_store<BK, VB>(Bs, tid, vb);
+    tile_load<TA, AK, OP>(A, lda, m0, M, kb, ke, tid, va);
+    tile_load<TB, BK, OP>(B, ldb, n0, Nn, kb, ke, tid, vb);
+    tile_store<AK>(As, tid, va);
+    tile_store<BK>(Bs, tid, vb);
   }
   __syncthreads();
   for (int64_t k0 = kb; k0 < ke; k0 += KS) {
     const bool more = k0 + KS < ke;
     if (more) {
-      tile_load<TA, AK, OP, VA>(A, lda, m0, M, k0 + KS, ke, tid, va);
-      tile_load<TB, BK, OP, VB>(B, ldb, n0, Nn, k0 + KS, ke, tid, vb);
+      tile_load<TA, AK, OP>(A, lda, m0, M, k0 + KS, ke, tid, va);
+      tile_load<TB, BK, OP>(B, ldb, n0, Nn, k0 + KS, ke, tid, vb);
     }
     const double* as = As + buf * KS * TP;
     const double* bs = Bs + buf * KS * TP;
 #pragma unroll
     for (int kk = 0; kk < KS; kk += 4) {
-      const int kr = (kk + lane / 16) * TP, li = lane % 16;
+      const int kq = kk + lane / 16, kr = kq * TP, li = lane % 16;
       double a[4], b[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = as[kr + wm * 64 + i * 16 + li];
+      for (int i = 0; i < 4; ++i) a[i] = AK ? as[kr + wm * 64 + i * 16 + li] : as[(wm * 64 + i * 16 + li) * RP + kq];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = bs[kr + wn * 64 + j * 16 + li];
+      for (int j = 0; j < 4; ++j) b[j] = BK ? bs[kr + wn * 64 + j * 16 + li] : bs[(wn * 64 + j * 16 + li) * RP + kq];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -366,8 +357,8 @@ __device__ __forceinline__ void tile_mma(const TA* __restrict__ A, int64_t lda, 
     }
     if (more) {
       buf ^= 1;
-      tile_store<AK, VA>(As + buf * KS * TP, tid, va);
-      tile_store<BK, VB>(Bs + buf * KS * TP, tid, vb);
+      tile_store<AK>(As + buf * KS * TP, tid, va);
+      tile_store<BK>(Bs + buf * KS * TP, tid, vb);
     }
     __syncthreads();
   }
@@ -393,7 +384,7 @@ __device__ __forceinline__ void tile_write(const d4 (&acc)[4][4], int m0, int M,
 // NT split-K: blockIdx.x = tile t of the tile list (tm, tn) = (t / ntn, t % ntn),
 // or with SYM the t-th tile of the upper triangle tm <= tn; blockIdx.y = split.
 // Cpart[split][M][Nn] receives the tile's partial sums.
-template <int OP, bool SYM, bool VEC = false>
+template <int OP, bool SYM>
 __global__ __launch_bounds__(256, 2) void k_gemm_nt_t128(const double* __restrict__ A, int64_t lda,
                                                          const double* __restrict__ B, int64_t ldb, int M, int Nn,
                                                          int64_t K, int64_t kchunk, int ntn,
@@ -419,7 +410,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_nt_t128(const double* __restric
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = d4{0, 0, 0, 0};
-  tile_mma<double, double, false, false, OP, VEC, VEC>(A, lda, B, ldb, m0, M, n0, Nn, kb, ke, As, Bs, acc);
+  tile_mma<double, double, false, false, OP>(A, lda, B, ldb, m0, M, n0, Nn, kb, ke, As, Bs, acc);
   tile_write(acc, m0, M, n0, Nn, Cpart + int64_t(blockIdx.y) * M * Nn, Nn, 1.0);
 }
 
@@ -568,7 +559,7 @@ __global__ void k_reduce_parts_t(const double* __restrict__ Cpart, int nsplit, i
 // LOWER: S(m, k) = 0 for k > m.  blockIdx.x = 128-column tile of r (fastest:
 // neighbouring workgroups write neighbouring segments of the same rows of C,
 // measured faster than the row tiles fastest), blockIdx.y = 128-row tile of m.
-template <typename TB, bool TRANS, bool LOWER, bool VEC = false>
+template <typename TB, bool TRANS, bool LOWER>
 __global__ __launch_bounds__(256, 2) void k_gemm_ls_t128(const double* __restrict__ S, int lds,
                                                          const TB* __restrict__ B, int64_t ldb,
                                                          double* __restrict__ C, int64_t ldc, int M, int K,
@@ -586,8 +577,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_ls_t128(const double* __restric
   // B columns r0 .. r0 + 127 are addressed from the tile origin
   const TB* Bt = B + r0;
   const int64_t rrem = R - r0;
-  tile_mma<double, TB, TRANS, true, 0, VEC && !TRANS>(S, lds, Bt, ldb, m0, M, 0, int(rrem < TT ? rrem : TT), 0, ke,
-                                                      As, Bs, acc);
+  tile_mma<double, TB, TRANS, true, 0>(S, lds, Bt, ldb, m0, M, 0, int(rrem < TT ? rrem : TT), 0, ke, As, Bs, acc);
   tile_write(acc, m0, M, 0, rrem < TT ? rrem : TT, C + r0, ldc, alpha);
 }
 
@@ -626,17 +616,8 @@ hipError_t gemm_nt(int prec, int op, const void* A, int64_t lda, const void* B, 
     dim3 grid(ntiles, unsigned(nsplit));
     const double* a = (const double*)A;
     const double* b = (const double*)B;
-    // 32-byte runs of k per lane where the operands allow it (measured:
-    // pair screening 0.96 -> 0.80 ms at 32 waters)
-    const bool v4 = K % 4 == 0 && lda % 4 == 0 && ldb % 4 == 0 && (uintptr_t(a) & 31) == 0 &&
-                    (uintptr_t(b) & 31) == 0;
-#define NT_LAUNCH(OPV, SYMV)                                                                                     \
-    if (v4)                                                                                                      \
-      hipLaunchKernelGGL((k_gemm_nt_t128<OPV, SYMV, true>), grid, dim3(256), 0, s, a, lda, b, ldb, M, Nn, K, kchunk, \
-                         ntn, Cpart);                                                                            \
-    else                                                                                                         \
-      hipLaunchKernelGGL((k_gemm_nt_t128<OPV, SYMV>), grid, dim3(256), 0, s, a, lda, b, ldb, M, Nn, K, kchunk, ntn, \
-                         Cpart)
+#define NT_LAUNCH(OPV, SYMV) \
+    hipLaunchKernelGGL((k_gemm_nt_t128<OPV, SYMV>), grid, dim3(256), 0, s, a, lda, b, ldb, M, Nn, K, kchunk, ntn, Cpart)
     if (sym) {
       if (op == 1) NT_LAUNCH(1, true);
       else if (op == 2) NT_LAUNCH(2, true);
@@ -675,12 +656,8 @@ static void launch_ls(const double* S, int lds, const TB* B, int64_t ldb, double
     hipLaunchKernelGGL((k_gemm_tiny<TB, TRANS, LOWER>), grid, dim3(64), 0, s, S, lds, B, ldb, C, ldc, M, K, R, alpha);
   } else if (M > 64) {
     dim3 grid(unsigned((R + TT - 1) / TT), unsigned((M + TT - 1) / TT));
-    if (!TRANS && K % 4 == 0 && lds % 4 == 0 && (uintptr_t(S) & 31) == 0)
-      hipLaunchKernelGGL((k_gemm_ls_t128<TB, TRANS, LOWER, true>), grid, dim3(256), 0, s, S, lds, B, ldb, C, ldc, M, K,
-                         R, alpha);
-    else
-      hipLaunchKernelGGL((k_gemm_ls_t128<TB, TRANS, LOWER>), grid, dim3(256), 0, s, S, lds, B, ldb, C, ldc, M, K, R,
-                         alpha);
+    hipLaunchKernelGGL((k_gemm_ls_t128<TB, TRANS, LOWER>), grid, dim3(256), 0, s, S, lds, B, ldb, C, ldc, M, K, R,
+                       alpha);
   } else {
     dim3 grid(unsigned((R + GB - 1) / GB), unsigned((M + 63) / 64));
     hipLaunchKernelGGL((k_gemm_ls<TB, TRANS, LOWER, 64>), grid, dim3(256), 0, s, S, lds, B, ldb, C, ldc, M, K, R,
