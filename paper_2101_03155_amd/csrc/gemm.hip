@@ -417,13 +417,14 @@ __global__ __launch_bounds__(256, 2) void k_gemm_nt_t128(const double* __restric
 // ---------------------------------------------------------------- 128 x 64 FP32 compensated tiles
 // The compensated FP32 product on 128 x 64 tiles: each wave accumulates a
 // 64 x 32 quarter (4 x 2 blocks of v_mfma_f32_16x16x4f32) over K steps of 16
-// staged in k-major LDS tiles and double buffered through registers (float4
-// loads of four consecutive k); every `sub` products the FP32 block sums are
+// staged in row-major LDS tiles (pitch RPF = 20 floats: the MFMA operand reads
+// of 16 rows by 4 k fall in 64 distinct banks) and double buffered through
+// registers (float4 loads of four consecutive k); every `sub` products the FP32 block sums are
 // merged into (hi, lo) pairs by TwoSum (the hi/lo pairs of a 64 x 64 quarter
 // would not fit the register file), and the tile writes hi + lo in FP64 to
 // its split's partial-sum slice.  Requires K, lda and ldb multiples of 4 and
 // 16-byte aligned operands.
-constexpr int TPF = TT + 16;  // row pitch of the FP32 LDS tiles (floats)
+constexpr int RPF = KS + 4;   // row pitch of the FP32 LDS tiles (floats)
 constexpr int TNF = 64;       // tile columns
 
 // rows r0 .. r0 + 16 * Q - 1 of a 16-wide K step: Q float4 per thread
@@ -447,8 +448,7 @@ __device__ __forceinline__ void f32t_store(float* S, int tid, const f4 (&v)[Q]) 
   for (int i = 0; i < Q; ++i) {
     const int e = tid + 256 * i;
     const int r = e >> 2, kq = (e & 3) * 4;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) S[(kq + c) * TPF + r] = v[i][c];
+    *reinterpret_cast<f4*>(S + r * RPF + kq) = v[i];
   }
 }
 
@@ -456,8 +456,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_nt_f32t(const float* __restrict
                                                          const float* __restrict__ B, int64_t ldb, int M, int Nn,
                                                          int64_t K, int64_t kchunk, int ntn, int sub,
                                                          double* __restrict__ Cpart) {
-  __shared__ float As[2 * KS * TPF];
-  __shared__ float Bs[2 * KS * TPF];
+  __shared__ __attribute__((aligned(16))) float As[2 * TT * RPF];
+  __shared__ __attribute__((aligned(16))) float Bs[2 * TNF * RPF];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wm = wv >> 1, wn = wv & 1;
   const int tm = blockIdx.x / ntn, tn = blockIdx.x % ntn;
@@ -490,16 +490,16 @@ __global__ __launch_bounds__(256, 2) void k_gemm_nt_f32t(const float* __restrict
       f32t_load<2>(A, lda, m0, M, k0 + KS, ke, tid, va);
       f32t_load<1>(B, ldb, n0, Nn, k0 + KS, ke, tid, vb);
     }
-    const float* as = As + buf * KS * TPF;
-    const float* bs = Bs + buf * KS * TPF;
+    const float* as = As + buf * TT * RPF;
+    const float* bs = Bs + buf * TNF * RPF;
 #pragma unroll
     for (int kk = 0; kk < KS; kk += 4) {
-      const int kr = (kk + lane / 16) * TPF, li = lane % 16;
+      const int kq = kk + lane / 16, li = lane % 16;
       float a[4], b[2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = as[kr + wm * 64 + i * 16 + li];
+      for (int i = 0; i < 4; ++i) a[i] = as[(wm * 64 + i * 16 + li) * RPF + kq];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = bs[kr + wn * 32 + j * 16 + li];
+      for (int j = 0; j < 2; ++j) b[j] = bs[(wn * 32 + j * 16 + li) * RPF + kq];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -519,8 +519,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_nt_f32t(const float* __restrict
     }
     if (more) {
       buf ^= 1;
-      f32t_store<2>(As + buf * KS * TPF, tid, va);
-      f32t_store<1>(Bs + buf * KS * TPF, tid, vb);
+      f32t_store<2>(As + buf * TT * RPF, tid, va);
+      f32t_store<1>(Bs + buf * TNF * RPF, tid, vb);
     }
     __syncthreads();
   }
