@@ -116,6 +116,10 @@ int64_t gemm_nt_nsplit(int M, int Nn, int64_t K, int64_t* kchunk_out, bool sym =
 hipError_t gemm_ls(int bprec, bool trans, bool lower, const double* S, int lds, const void* B, int64_t ldb,
                    double* C, int64_t ldc, int M, int K, int64_t R, double alpha, hipStream_t s,
                    EventRecorder* rec);
+// res[r] -= sum_m (sum_k Q[m][k] Psi[k][r])^2 for r < R, over M <= 128 rows
+// of Q (row pitch ldq) and K rows of Psi (row pitch ldp), in one launch.
+hipError_t refresh_bounds(const double* Q, int ldq, const double* Psi, int64_t ldp, int M, int K, int64_t R,
+                          double* res, hipStream_t s);
 void launch_symmetrize(const double* M, int n, double* out, double* negM, double* ex, double* asym, hipStream_t s);
 // Blocked Cholesky of the lower triangle of A (n <= 512) in place; info must
 // be zero on entry; tinv is 64 x 64 doubles of scratch.

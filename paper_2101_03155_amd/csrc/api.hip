@@ -526,11 +526,16 @@ int ace_localize(ace_ctx* c, const ace_grid* g, int norb, const double* psi, dou
     if (k > kref) {
       // bounds: res = |a_r|^2 - |Q_k a_r|^2, downdated by the directions
       // picked since the last refresh only; then retire the pivots
-      for (int64_t r0 = 0; r0 < ng; r0 += rchunk) {
-        const int64_t w = std::min(rchunk, ng - r0);
-        HIPCHK(c, gemm_ls(0, false, false, Q + size_t(kref) * norb, norb, psi + r0, ng, Lc, w, k - kref, norb, w, 1.0,
-                          s, nullptr));
-        launch_refresh_res(Lc, k - kref, w, res + r0, res + r0, s);
+      if (k - kref <= 128) {
+        // one launch: the projections' squares are summed on the MFMA tile
+        HIPCHK(c, refresh_bounds(Q + size_t(kref) * norb, norb, psi, ng, k - kref, norb, ng, res, s));
+      } else {
+        for (int64_t r0 = 0; r0 < ng; r0 += rchunk) {
+          const int64_t w = std::min(rchunk, ng - r0);
+          HIPCHK(c, gemm_ls(0, false, false, Q + size_t(kref) * norb, norb, psi + r0, ng, Lc, w, k - kref, norb, w,
+                            1.0, s, nullptr));
+          launch_refresh_res(Lc, k - kref, w, res + r0, res + r0, s);
+        }
       }
       launch_retire(pivots, k, res, s);
       kref = k;

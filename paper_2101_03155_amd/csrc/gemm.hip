@@ -581,6 +581,51 @@ __global__ __launch_bounds__(256, 2) void k_gemm_ls_t128(const double* __restric
   tile_write(acc, m0, M, 0, rrem < TT ? rrem : TT, C + r0, ldc, alpha);
 }
 
+// Bound refresh of the pivot search in one pass: for the 128 grid columns of
+// this tile, L = Q Psi[:, cols] (M <= 128 rows of Q, K = ldq columns) on the
+// MFMA tile, then res[r] -= sum_m L[m][r]^2, without writing L.  Column sums
+// run over each lane's rows, then across the four lane groups, then across
+// the two row halves of the tile (fixed order).
+__global__ __launch_bounds__(256, 2) void k_refresh_t128(const double* __restrict__ Q, int ldq,
+                                                         const double* __restrict__ Psi, int64_t ldp, int M, int K,
+                                                         int64_t R, double* __restrict__ res) {
+  __shared__ double As[2 * KS * TP];
+  __shared__ double Bs[2 * KS * TP];
+  __shared__ double colsum[2][TT];
+  const int64_t r0 = int64_t(blockIdx.x) * TT;
+  const int64_t rrem = R - r0;
+  const int ncol = int(rrem < TT ? rrem : TT);
+  d4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0, 0, 0, 0};
+  tile_mma<double, double, false, true, 0>(Q, ldq, Psi + r0, ldp, 0, M, 0, ncol, 0, K, As, Bs, acc);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wm = wv >> 1, wn = wv & 1;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    double sq = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sq += acc[i][j][r] * acc[i][j][r];
+    sq += __shfl_xor(sq, 16, 64);
+    sq += __shfl_xor(sq, 32, 64);
+    if (lane < 16) colsum[wm][wn * 64 + j * 16 + lane] = sq;
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < ncol) res[r0 + t] -= colsum[0][t] + colsum[1][t];
+}
+
+hipError_t refresh_bounds(const double* Q, int ldq, const double* Psi, int64_t ldp, int M, int K, int64_t R,
+                          double* res, hipStream_t s) {
+  if (M < 1 || M > TT || K < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_refresh_t128, dim3(unsigned((R + TT - 1) / TT)), dim3(256), 0, s, Q, ldq, Psi, ldp, M, K, R,
+                     res);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- host wrappers
 
 int64_t gemm_nt_nsplit(int M, int Nn, int64_t K, int64_t* kchunk_out, bool sym) {
