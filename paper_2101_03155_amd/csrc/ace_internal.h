@@ -135,6 +135,11 @@ void launch_qrcp_update_r(double* R, int n, int P, const double* q, double* res,
 void launch_qrcp_select_r(const double* R, int n, int P, int* kdev, const double* pv, const int64_t* pi,
                           double* Q, double* res, int32_t* piv, double* qout, const int32_t* pool,
                           const double* t_out, int* stop, hipStream_t s);
+// Selection and update of one pool step in one launch (candidates read from
+// pv_in/pi_in, written to pv_out/pi_out; n <= 1024).
+void launch_qrcp_step_r(double* R, int n, int P, int* kdev, const double* pv_in, const int64_t* pi_in, double* Q,
+                        double* res, int32_t* piv, const int32_t* pool, const double* t_out, int* stop,
+                        double* pv_out, int64_t* pi_out, hipStream_t s);
 void launch_add_inplace(double* a, const double* b, int64_t cnt, hipStream_t s);
 void launch_qrcp_select(const double* A, int n, int64_t ng, int* kdev, const double* pv, const int64_t* pi,
                         int nblk, double* Q, double* res, int32_t* piv, double* qout, const int32_t* pool,

@@ -488,7 +488,8 @@ int ace_localize(ace_ctx* c, const ace_grid* g, int norb, const double* psi, dou
   const int nbp = pool_blocks(ng);
   WS(c, "res", ng * sizeof(double), res);
   // block candidates: 8 per block of the full sweep, 1 per block of the pool steps
-  const size_t ncand = std::max<size_t>(size_t(nblk_full) * 8, size_t(qrcp_pool_blocks(pmax)));
+  // (the pool steps double buffer their block candidates)
+  const size_t ncand = std::max<size_t>(size_t(nblk_full) * 8, 2 * size_t(qrcp_pool_blocks(pmax)));
   WS(c, "pv", ncand * sizeof(double), pv);
   WS(c, "pi", ncand * sizeof(int64_t), pi);
   WS(c, "Q", size_t(norb) * norb * sizeof(double), Q);
@@ -562,16 +563,25 @@ int ace_localize(ace_ctx* c, const ace_grid* g, int norb, const double* psi, dou
           launch_add_inplace(Apool, Tpool, int64_t(norb) * np, s);
         }
       launch_qrcp_update_r(Apool, norb, np, nullptr, pres, pv, pi, iv + 1, s);
-      // steps are queued in batches; a batch after a certification failure
-      // would only hold no-op launches, so the flag is checked between batches
+      // one launch per step (selection repeated in every block, then the
+      // update), the block candidates alternating between two halves of pv/pi;
+      // steps are queued in batches, and since a batch after a certification
+      // failure would only hold no-op launches the flag is checked between them
+      const int nbp = qrcp_pool_blocks(np);
+      int par = 0;
       for (int kk = k; kk < norb;) {
         const int kend = std::min(norb, kk + 24);
         for (; kk < kend; ++kk) {
-          launch_qrcp_select_r(Apool, norb, np, iv, pv, pi, Q, pres, pivots, q, pool, tvals + 1, iv + 1, s);
+          double* pvi = pv + size_t(par) * nbp;
+          int64_t* pii = pi + size_t(par) * nbp;
           if (kk + 1 < norb) {
             rec_begin(c->R(), KC_QRCP, s);
-            launch_qrcp_update_r(Apool, norb, np, q, pres, pv, pi, iv + 1, s);
+            launch_qrcp_step_r(Apool, norb, np, iv, pvi, pii, Q, pres, pivots, pool, tvals + 1, iv + 1,
+                               pv + size_t(1 - par) * nbp, pi + size_t(1 - par) * nbp, s);
             rec_end(c->R(), KC_QRCP, s, qbytes_pool * double(np));
+            par ^= 1;
+          } else {
+            launch_qrcp_select_r(Apool, norb, np, iv, pvi, pii, Q, pres, pivots, q, pool, tvals + 1, iv + 1, s);
           }
         }
         if (kk < norb) {

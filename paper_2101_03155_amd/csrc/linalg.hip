@@ -638,6 +638,140 @@ __global__ __launch_bounds__(NT) void k_qrcp_select_r(const double* __restrict__
   if (threadIdx.x == 0) *kdev = k + 1;
 }
 
+// One pool step in one launch: every block repeats the selection (the best
+// of the previous step's block candidates pv_in/pi_in, its norm recomputed
+// and certified against t_out, q = R[:,b] / |R[:,b]| in LDS) with the same
+// reductions as k_qrcp_select_r, so all blocks hold the same q; block 0
+// alone appends q to Q, records the pivot, retires the column and advances
+// the step counter.  Then each block updates its columns as
+// k_qrcp_update_r does and writes its best live column to pv_out/pi_out
+// (candidates double buffered: blocks of this launch still read pv_in).  The
+// pivot column itself is left untouched, so the blocks that read it are not
+// racing with its owner.  A failed certification or an exhausted pool
+// raises the stop flag (block 0), and every block returns.
+template <int NT, int CW>
+__global__ __launch_bounds__(NT) void k_qrcp_step_r(double* __restrict__ R, int n, int P, int* __restrict__ kdev,
+                                                    const double* __restrict__ pv_in,
+                                                    const int64_t* __restrict__ pi_in, int nblk,
+                                                    double* __restrict__ Q, double* __restrict__ res,
+                                                    int32_t* __restrict__ piv, const int32_t* __restrict__ pool,
+                                                    const double* __restrict__ t_out, int* __restrict__ stop,
+                                                    double* __restrict__ pv_out, int64_t* __restrict__ pi_out) {
+  if (*stop) return;
+  constexpr int RG = NT / CW;
+  __shared__ double qs[1024];
+  __shared__ double red[RG][CW];
+  __shared__ double r2s[NT / 64];
+  __shared__ double bv;
+  __shared__ int64_t bi;
+  // selection, as k_qrcp_select_r
+  {
+    double v = -INFINITY;
+    int64_t idx = INT64_MAX;
+    for (int e = threadIdx.x; e < nblk; e += NT)
+      if (ranks_before(pv_in[e], pi_in[e], v, idx)) { v = pv_in[e]; idx = pi_in[e]; }
+    block_top1<NT>(v, idx, &bv, &bi);
+  }
+  const int64_t b = bi;
+  if (b < 0 || b >= P) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *stop = 1;
+    return;
+  }
+  {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += NT) {
+      const double x = R[int64_t(i) * P + b];
+      v += x * x;
+    }
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((threadIdx.x & 63) == 0) r2s[threadIdx.x >> 6] = v;
+  }
+  __syncthreads();
+  double r2 = 0.0;
+  for (int w = 0; w < NT / 64; ++w) r2 += r2s[w];
+  const bool ok = r2 > 0.0 && (t_out == nullptr || r2 >= *t_out);
+  if (!ok) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *stop = 1;
+    return;
+  }
+  const double inv = 1.0 / sqrt(r2);
+  for (int i = threadIdx.x; i < n; i += NT) qs[i] = R[int64_t(i) * P + b] * inv;
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    const int k = *kdev;
+    for (int i = threadIdx.x; i < n; i += NT) Q[int64_t(k) * n + i] = qs[i];
+    if (threadIdx.x == 0) {
+      piv[k] = pool[b];
+      res[b] = -1.0;
+      *kdev = k + 1;
+    }
+  }
+  // update, as k_qrcp_update_r with q
+  const int lane = threadIdx.x % CW, g = threadIdx.x / CW;
+  const int c = blockIdx.x * CW + lane;
+  const bool live = c < P && c != b && res[c] > -0.5;
+  double* col = R + c;
+  double l = 0.0;
+  if (live) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int i = g;
+    for (; i + 3 * RG < n; i += 4 * RG) {
+      a0 += qs[i] * col[int64_t(i) * P];
+      a1 += qs[i + RG] * col[int64_t(i + RG) * P];
+      a2 += qs[i + 2 * RG] * col[int64_t(i + 2 * RG) * P];
+      a3 += qs[i + 3 * RG] * col[int64_t(i + 3 * RG) * P];
+    }
+    for (; i < n; i += RG) a0 += qs[i] * col[int64_t(i) * P];
+    l = (a0 + a1) + (a2 + a3);
+  }
+  red[g][lane] = l;
+  __syncthreads();
+  l = 0.0;
+#pragma unroll
+  for (int h = 0; h < RG; ++h) l += red[h][lane];
+  __syncthreads();
+  double v = 0.0;
+  if (live) {
+    double v0 = 0.0, v1 = 0.0;
+    int i = g;
+    for (; i + RG < n; i += 2 * RG) {
+      double x0 = col[int64_t(i) * P], x1 = col[int64_t(i + RG) * P];
+      x0 -= qs[i] * l;
+      x1 -= qs[i + RG] * l;
+      col[int64_t(i) * P] = x0;
+      col[int64_t(i + RG) * P] = x1;
+      v0 += x0 * x0;
+      v1 += x1 * x1;
+    }
+    for (; i < n; i += RG) {
+      double x = col[int64_t(i) * P];
+      x -= qs[i] * l;
+      col[int64_t(i) * P] = x;
+      v0 += x * x;
+    }
+    v = v0 + v1;
+  }
+  red[g][lane] = v;
+  __syncthreads();
+  double cand = -INFINITY;
+  int64_t cidx = INT64_MAX;
+  if (g == 0) {
+    v = 0.0;
+#pragma unroll
+    for (int h = 0; h < RG; ++h) v += red[h][lane];
+    if (live) {
+      res[c] = v;
+      cand = v;
+      cidx = c;
+    }
+  }
+  block_top1<NT>(cand, cidx, &bv, &bi);
+  if (threadIdx.x == 0) {
+    pv_out[blockIdx.x] = bv;
+    pi_out[blockIdx.x] = bi;
+  }
+}
+
 // a += b (elementwise)
 __global__ void k_add_inplace(double* __restrict__ a, const double* __restrict__ b, int64_t cnt) {
   for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < cnt; e += int64_t(gridDim.x) * blockDim.x)
@@ -1010,6 +1144,12 @@ void launch_qrcp_select_r(const double* R, int n, int P, int* kdev, const double
                           const double* t_out, int* stop, hipStream_t s) {
   hipLaunchKernelGGL(k_qrcp_select_r<256>, dim3(1), dim3(256), 0, s, R, n, P, kdev, pv, pi, qrcp_pool_blocks(P), Q,
                      res, piv, qout, pool, t_out, stop);
+}
+void launch_qrcp_step_r(double* R, int n, int P, int* kdev, const double* pv_in, const int64_t* pi_in, double* Q,
+                        double* res, int32_t* piv, const int32_t* pool, const double* t_out, int* stop,
+                        double* pv_out, int64_t* pi_out, hipStream_t s) {
+  hipLaunchKernelGGL((k_qrcp_step_r<256, QCW>), dim3(qrcp_pool_blocks(P)), dim3(256), 0, s, R, n, P, kdev, pv_in,
+                     pi_in, qrcp_pool_blocks(P), Q, res, piv, pool, t_out, stop, pv_out, pi_out);
 }
 void launch_add_inplace(double* a, const double* b, int64_t cnt, hipStream_t s) {
   hipLaunchKernelGGL(k_add_inplace, dim3(grid_for(cnt, 256)), dim3(256), 0, s, a, b, cnt);
