@@ -162,15 +162,6 @@ __global__ __launch_bounds__(256) void k_gemm_nt_f32c(const float* __restrict__ 
       }
 }
 
-// C[m][n] = alpha * sum_s Cpart[s][m][n]   (FP64, fixed order: deterministic)
-__global__ void k_reduce_parts(const double* __restrict__ Cpart, int nsplit, int64_t mn, double alpha,
-                               double* __restrict__ C) {
-  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < mn; e += int64_t(gridDim.x) * blockDim.x) {
-    double s = 0.0;
-    for (int p = 0; p < nsplit; ++p) s += Cpart[int64_t(p) * mn + e];
-    C[e] = alpha * s;
-  }
-}
 
 // ---------------------------------------------------------------- left-small
 // C[m][r] = alpha * sum_k S(m,k) B[k][r],  S(m,k) = TRANS ? S[k][m] : S[m][k].
@@ -538,20 +529,43 @@ __global__ __launch_bounds__(256, 2) void k_gemm_nt_f32t(const float* __restrict
 }
 
 // C = alpha * sum_s Cpart[s]; with SYM only tiles tm <= tn were computed and
-// the lower triangle of tiles is read transposed.
+// the lower triangle of tiles is read transposed.  A block reduces RO
+// consecutive outputs with RG groups of threads, group g summing the splits
+// s = g mod RG (four loads in flight per thread); the groups meet in LDS in a
+// fixed order, so the result is deterministic.  (One thread per output
+// summing every split in turn was latency-bound: 125 us for a 128 x 128
+// result of 500 splits.)
+constexpr int RO = 32, RGR = 8;
 template <bool SYM>
-__global__ void k_reduce_parts_t(const double* __restrict__ Cpart, int nsplit, int M, int Nn, double alpha,
-                                 double* __restrict__ C) {
+__global__ __launch_bounds__(256) void k_reduce_parts_t(const double* __restrict__ Cpart, int nsplit, int M, int Nn,
+                                                        double alpha, double* __restrict__ C) {
+  __shared__ double part[RGR][RO];
+  const int o = threadIdx.x % RO, g = threadIdx.x / RO;
   const int64_t mn = int64_t(M) * Nn;
-  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < mn; e += int64_t(gridDim.x) * blockDim.x) {
+  const int64_t e = int64_t(blockIdx.x) * RO + o;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  if (e < mn) {
     int64_t src = e;
     if (SYM) {
       const int i = int(e / Nn), j = int(e % Nn);
       if (i / TT > j / TT) src = int64_t(j) * Nn + i;
     }
-    double s = 0.0;
-    for (int p = 0; p < nsplit; ++p) s += Cpart[int64_t(p) * mn + src];
-    C[e] = alpha * s;
+    int p = g;
+    for (; p + 3 * RGR < nsplit; p += 4 * RGR) {
+      s0 += Cpart[int64_t(p) * mn + src];
+      s1 += Cpart[int64_t(p + RGR) * mn + src];
+      s2 += Cpart[int64_t(p + 2 * RGR) * mn + src];
+      s3 += Cpart[int64_t(p + 3 * RGR) * mn + src];
+    }
+    for (; p < nsplit; p += RGR) s0 += Cpart[int64_t(p) * mn + src];
+  }
+  part[g][o] = (s0 + s1) + (s2 + s3);
+  __syncthreads();
+  if (g == 0 && e < mn) {
+    double t = 0.0;
+#pragma unroll
+    for (int h = 0; h < RGR; ++h) t += part[h][o];
+    C[e] = alpha * t;
   }
 }
 
@@ -653,8 +667,7 @@ hipError_t gemm_nt(int prec, int op, const void* A, int64_t lda, const void* B, 
   const int64_t nsplit = gemm_nt_nsplit(M, Nn, K, &kchunk, sym);
   rec_begin(rec, KC_GEMM_NT, s);
   const int64_t mn = int64_t(M) * Nn;
-  int nb = int((mn + 255) / 256);
-  if (nb > 1024) nb = 1024;
+  const unsigned nbr = unsigned((mn + RO - 1) / RO);
   if (prec == 0) {
     const int ntm = (M + TT - 1) / TT, ntn = (Nn + TT - 1) / TT;
     const unsigned ntiles = unsigned(sym ? ntn * (ntn + 1) / 2 : ntm * ntn);
@@ -667,12 +680,12 @@ hipError_t gemm_nt(int prec, int op, const void* A, int64_t lda, const void* B, 
       if (op == 1) NT_LAUNCH(1, true);
       else if (op == 2) NT_LAUNCH(2, true);
       else NT_LAUNCH(0, true);
-      hipLaunchKernelGGL(k_reduce_parts_t<true>, dim3(nb), dim3(256), 0, s, Cpart, int(nsplit), M, Nn, alpha, C);
+      hipLaunchKernelGGL(k_reduce_parts_t<true>, dim3(nbr), dim3(256), 0, s, Cpart, int(nsplit), M, Nn, alpha, C);
     } else {
       if (op == 1) NT_LAUNCH(1, false);
       else if (op == 2) NT_LAUNCH(2, false);
       else NT_LAUNCH(0, false);
-      hipLaunchKernelGGL(k_reduce_parts_t<false>, dim3(nb), dim3(256), 0, s, Cpart, int(nsplit), M, Nn, alpha, C);
+      hipLaunchKernelGGL(k_reduce_parts_t<false>, dim3(nbr), dim3(256), 0, s, Cpart, int(nsplit), M, Nn, alpha, C);
     }
 #undef NT_LAUNCH
   } else {
@@ -687,7 +700,7 @@ hipError_t gemm_nt(int prec, int op, const void* A, int64_t lda, const void* B, 
       hipLaunchKernelGGL(k_gemm_nt_f32c, grid, dim3(256), 0, s, (const float*)A, lda, (const float*)B, ldb, M, Nn,
                          K, kchunk, 256, Cpart);
     }
-    hipLaunchKernelGGL(k_reduce_parts, dim3(nb), dim3(256), 0, s, Cpart, int(nsplit), mn, alpha, C);
+    hipLaunchKernelGGL(k_reduce_parts_t<false>, dim3(nbr), dim3(256), 0, s, Cpart, int(nsplit), M, Nn, alpha, C);
   }
   rec_end(rec, KC_GEMM_NT, s, (sym && prec == 0 ? 1.0 : 2.0) * double(M) * Nn * double(K));
   return hipGetLastError();
