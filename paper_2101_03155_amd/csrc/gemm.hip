@@ -316,6 +316,10 @@ __device__ __forceinline__ void tile_mma(const TA* __restrict__ A, int64_t lda, 
                                          double* As, double* Bs, d4 (&acc)[4][4]) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wm = wv >> 1, wn = wv & 1;
+  // 16 x 16 blocks of this wave that hold rows < M and columns < Nn (the
+  // others stay zero, so their MFMAs are skipped; wave-uniform)
+  const int ib = min(4, max(0, (M - m0 - wm * 64 + 15) / 16));
+  const int jb = min(4, max(0, (Nn - n0 - wn * 64 + 15) / 16));
   double va[8], vb[8];
   int buf = 0;
   if (kb < ke) {
@@ -344,7 +348,8 @@ __device__ __forceinline__ void tile_mma(const TA* __restrict__ A, int64_t lda, 
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 4; ++j)
+          if (i < ib && j < jb) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     if (more) {
       buf ^= 1;
