@@ -482,7 +482,9 @@ int ace_localize(ace_ctx* c, const ace_grid* g, int norb, const double* psi, dou
   unsigned* hist;
   int* iv;  // [0] k, [1] stop, [2] pool size
   const int nblk_full = qrcp_blocks(ng);
-  const int pmax = std::max(2048, 8 * norb);  // candidate pool size
+  // candidate pool size (measured: 3072 columns at 128 and 256 orbitals
+  // localize 4.1 -> 3.5 and 14.5 -> 14.3 ms against 2048, fewer redraws)
+  const int pmax = std::max(3072, 12 * norb);
   const int nblk_pool = qrcp_blocks(pmax);
   const int64_t rchunk = std::min<int64_t>(ng, 65536);  // refresh chunk (grid columns)
   const int nbp = pool_blocks(ng);
