@@ -310,7 +310,9 @@ __device__ __forceinline__ void tile_store(double* S, int tid, const double (&v)
 }
 
 // Accumulate the tile over [kb, ke) into acc (per wave 4 x 4 blocks).
-template <typename TA, typename TB, bool AK, bool BK, int OP>
+// LOWA: A(m, k) = 0 for k > m (lower-triangular left factor, global row and
+// k indices): a 16-row block skips the MFMAs of the k beyond its last row.
+template <typename TA, typename TB, bool AK, bool BK, int OP, bool LOWA = false>
 __device__ __forceinline__ void tile_mma(const TA* __restrict__ A, int64_t lda, const TB* __restrict__ B,
                                          int64_t ldb, int m0, int M, int n0, int Nn, int64_t kb, int64_t ke,
                                          double* As, double* Bs, d4 (&acc)[4][4]) {
@@ -349,7 +351,8 @@ __device__ __forceinline__ void tile_mma(const TA* __restrict__ A, int64_t lda, 
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-          if (i < ib && j < jb) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+          if (i < ib && j < jb && (!LOWA || k0 + kk < int64_t(m0) + wm * 64 + i * 16 + 16))
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     if (more) {
       buf ^= 1;
@@ -596,7 +599,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_ls_t128(const double* __restric
   // B columns r0 .. r0 + 127 are addressed from the tile origin
   const TB* Bt = B + r0;
   const int64_t rrem = R - r0;
-  tile_mma<double, TB, TRANS, true, 0>(S, lds, Bt, ldb, m0, M, 0, int(rrem < TT ? rrem : TT), 0, ke, As, Bs, acc);
+  tile_mma<double, TB, TRANS, true, 0, LOWER>(S, lds, Bt, ldb, m0, M, 0, int(rrem < TT ? rrem : TT), 0, ke, As, Bs,
+                                             acc);
   tile_write(acc, m0, M, 0, rrem < TT ? rrem : TT, C + r0, ldc, alpha);
 }
 
