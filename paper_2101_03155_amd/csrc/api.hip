@@ -128,6 +128,10 @@ struct ace_ctx {
   // batched form
   hipStream_t bstream = nullptr;
   hipEvent_t bev_in = nullptr, bev_out = nullptr;
+  // branches of the batched tails (default priority), with their fork/join events
+  static constexpr int kTailBranches = 4;
+  hipStream_t bbr[kTailBranches] = {};
+  hipEvent_t bev_fork = nullptr, bev_join[kTailBranches] = {};
   std::map<uint64_t, hipGraphExec_t> graphs;
   std::vector<uint64_t> graph_order;
   int b_txv = 16, b_plan = 0, b_bpc = 8, b_layout = 3;
@@ -395,6 +399,11 @@ int ace_destroy(ace_ctx* c) {
   for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
   if (c->bev_in) (void)hipEventDestroy(c->bev_in);
   if (c->bev_out) (void)hipEventDestroy(c->bev_out);
+  if (c->bev_fork) (void)hipEventDestroy(c->bev_fork);
+  for (int b = 0; b < ace_ctx::kTailBranches; ++b) {
+    if (c->bev_join[b]) (void)hipEventDestroy(c->bev_join[b]);
+    if (c->bbr[b]) (void)hipStreamDestroy(c->bbr[b]);
+  }
   if (c->bstream) (void)hipStreamDestroy(c->bstream);
   delete c;
   return ACE_OK;
@@ -404,6 +413,8 @@ int ace_release_workspace(ace_ctx* c) {
   if (!c) return ACE_E_ARG;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   if (c->bstream) HIPCHK(c, hipStreamSynchronize(c->bstream));
+  for (int b = 0; b < ace_ctx::kTailBranches; ++b)
+    if (c->bbr[b]) HIPCHK(c, hipStreamSynchronize(c->bbr[b]));
   for (auto& kv : c->bufs)
     if (kv.second.p) (void)hipFree(kv.second.p);
   c->bufs.clear();
@@ -920,6 +931,11 @@ int ace_build_batched(ace_ctx* c, int nsys, ace_system* sys, int prec, int mode)
     HIPCHK(c, hipStreamCreateWithFlags(&c->bstream, hipStreamNonBlocking));
     HIPCHK(c, hipEventCreateWithFlags(&c->bev_in, hipEventDisableTiming));
     HIPCHK(c, hipEventCreateWithFlags(&c->bev_out, hipEventDisableTiming));
+    HIPCHK(c, hipEventCreateWithFlags(&c->bev_fork, hipEventDisableTiming));
+    for (int b = 0; b < ace_ctx::kTailBranches; ++b) {
+      HIPCHK(c, hipStreamCreateWithFlags(&c->bbr[b], hipStreamNonBlocking));
+      HIPCHK(c, hipEventCreateWithFlags(&c->bev_join[b], hipEventDisableTiming));
+    }
   }
   hipStream_t bs = c->bstream;
   // pair lists to the host, schedules
@@ -1128,14 +1144,17 @@ int ace_build_batched(ace_ctx* c, int nsys, ace_system* sys, int prec, int mode)
     WS(c, "badj", std::max<size_t>(hadj.size(), 2) * sizeof(int32_t), dbadj);
     for (size_t q = 0; q < hown.size(); ++q) hown[q].adj_ptr = dbadjp + own_adjp_off[q];
   }
-  WS(c, "bmpart", size_t(max_nsplit) * max_norb * max_norb * sizeof(double), part);
-  WS(c, "bMraw", size_t(max_norb) * max_norb * sizeof(double), Mraw);
-  WS(c, "bLc", size_t(max_norb) * max_norb * sizeof(double), Lb);
-  WS(c, "bLinv", size_t(max_norb) * max_norb * sizeof(double), Li);
+  // per-branch scratch of the tails (the branches run concurrently)
+  constexpr int NBR = ace_ctx::kTailBranches;
+  const size_t part_elems = size_t(max_nsplit) * max_norb * max_norb, mat_elems = size_t(max_norb) * max_norb;
+  WS(c, "bmpart", NBR * part_elems * sizeof(double), part);
+  WS(c, "bMraw", NBR * mat_elems * sizeof(double), Mraw);
+  WS(c, "bLc", NBR * mat_elems * sizeof(double), Lb);
+  WS(c, "bLinv", NBR * mat_elems * sizeof(double), Li);
   WS(c, "bex", size_t(nsys) * 2 * sizeof(double), exs);
   WS(c, "binfo", size_t(nsys) * sizeof(int), infos);
   double* btinv;
-  WS(c, "btinv", 64 * 64 * sizeof(double), btinv);
+  WS(c, "btinv", NBR * 64 * 64 * sizeof(double), btinv);
   WS(c, "bsys", size_t(nsys) * sizeof(BSys), dsys);
   WS(c, "bpacks", std::max<size_t>(bp.size(), 1) * sizeof(BPack), dbp);
   WS(c, "bsegs", std::max<size_t>(segs.size(), 1) * sizeof(BRound), dsegs);
@@ -1210,19 +1229,36 @@ int ace_build_batched(ace_ctx* c, int nsys, ace_system* sys, int prec, int mode)
                                    dbown + os.own0, dbadj, bspec + owner_base + os.spec_off, s);
       if (e != hipSuccess) return fail(c, ACE_E_HIP, "batched owner launch failed: %s", hipGetErrorString(e));
     }
+    // the per-system tails (M, Cholesky, L^-1, xi) on NBR branches forked
+    // from s and joined back, each with its own scratch: the small
+    // latency-bound kernels of one system overlap the GEMMs of another
+    // (captured as parallel graph branches in graph mode)
+    HIPCHK(c, hipEventRecord(c->bev_fork, s));
+    for (int b = 0; b < NBR; ++b) HIPCHK(c, hipStreamWaitEvent(c->bbr[b], c->bev_fork, 0));
     for (int q = 0; q < nsys; ++q) {
+      const int br = q % NBR;
+      hipStream_t sb = c->bbr[br];
+      double* bpart = part + br * part_elems;
+      double* bM = Mraw + br * mat_elems;
+      double* bL = Lb + br * mat_elems;
+      double* bLi = Li + br * mat_elems;
+      double* btv = btinv + br * 64 * 64;
       const ace_system& y = sys[q];
       const int n = y.norb;
       const int64_t ng = grid_size(&y.grid);
       const void* W = bW + size_t(w_off[q]) * es;
       const void* ph = prec == 0 ? (const void*)y.phi : (const void*)(bphi + size_t(w_off[q]) * es);
-      hipError_t e = gemm_nt(prec, 0, ph, ng, W, ng, n, n, ng, grid_dv(&y.grid), part, Mraw, s, nullptr);
+      hipError_t e = gemm_nt(prec, 0, ph, ng, W, ng, n, n, ng, grid_dv(&y.grid), bpart, bM, sb, nullptr);
       if (e != hipSuccess) return fail(c, ACE_E_HIP, "batched M launch failed: %s", hipGetErrorString(e));
-      launch_symmetrize(Mraw, n, y.M, Lb, y.ex ? y.ex : exs + 2 * q, exs + 2 * q + 1, s);
-      launch_cholesky(Lb, n, infos + q, btinv, s);
-      launch_trinv(Lb, n, Li, s);
-      e = gemm_ls(prec, false, true, Li, n, W, ng, y.xi, ng, n, n, ng, 1.0, s, nullptr);
+      launch_symmetrize(bM, n, y.M, bL, y.ex ? y.ex : exs + 2 * q, exs + 2 * q + 1, sb);
+      launch_cholesky(bL, n, infos + q, btv, sb);
+      launch_trinv(bL, n, bLi, sb);
+      e = gemm_ls(prec, false, true, bLi, n, W, ng, y.xi, ng, n, n, ng, 1.0, sb, nullptr);
       if (e != hipSuccess) return fail(c, ACE_E_HIP, "batched projector launch failed: %s", hipGetErrorString(e));
+    }
+    for (int b = 0; b < NBR; ++b) {
+      HIPCHK(c, hipEventRecord(c->bev_join[b], c->bbr[b]));
+      HIPCHK(c, hipStreamWaitEvent(s, c->bev_join[b], 0));
     }
     return ACE_OK;
   };
