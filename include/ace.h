@@ -166,6 +166,12 @@ int ace_apply(ace_ctx* ctx, const ace_grid* grid, int norb, const double* xi, in
  */
 int ace_profile_enable(ace_ctx* ctx, int enable);
 int ace_profile_read(ace_ctx* ctx, int cls, int64_t* launches, double* total_ms, double* units, int reset);
+/* Restrict the bracketing to the classes whose bit (1 << cls) is set in mask
+ * (default: all); the others cost no events.  Lets a caller time a run
+ * without bracketing its many small launches (e.g. the pivot-search steps)
+ * while still timing the stages and the dominant kernels.  ACE_E_ARG for bits
+ * beyond the last class. */
+int ace_profile_classes(ace_ctx* ctx, unsigned mask);
 
 /*
  * Pair-stage launch shape for one (precision, grid size), set by the autotuner:

@@ -112,6 +112,7 @@ def load(path: str = LIB_PATH):
         "ace_apply": ([P, GP, I, P, I, P, P], I),
         "ace_profile_enable": ([P, I], I),
         "ace_profile_read": ([P, I, C.POINTER(I64), C.POINTER(D), C.POINTER(D), I], I),
+        "ace_profile_classes": ([P, C.c_uint], I),
         "ace_set_pair_shape": ([P, I, I, I, I], I),
         "ace_release_workspace": ([P], I),
         "ace_get_pair_shape": ([P, I, I, C.POINTER(I), C.POINTER(I)], I),
@@ -274,6 +275,11 @@ class Context:
     # ------------------------------------------------------------ timing / tuning
     def profile(self, enable: bool):
         self._check(self.lib.ace_profile_enable(self.h, 1 if enable else 0))
+
+    def profile_classes(self, classes=None):
+        """Bracket only the given timing classes (None: all of them)."""
+        mask = (1 << 15) - 1 if classes is None else sum(1 << c for c in classes)
+        self._check(self.lib.ace_profile_classes(self.h, mask))
 
     def profile_read(self, cls: int, reset: bool = True):
         """(launches, total milliseconds, total algorithmic units) of a timing class."""

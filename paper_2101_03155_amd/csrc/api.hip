@@ -19,6 +19,7 @@ namespace ace {
 struct EventRecorder {
   std::vector<hipEvent_t> pool;
   size_t used = 0;
+  uint32_t mask = ~0u;  // classes that are bracketed
   struct Mark { int cls; size_t a, b; };
   std::vector<Mark> marks;
   std::vector<size_t> open[KC_COUNT];
@@ -37,7 +38,7 @@ struct EventRecorder {
 };
 
 void rec_begin(EventRecorder* r, int cls, hipStream_t s) {
-  if (!r) return;
+  if (!r || !((r->mask >> cls) & 1u)) return;
   const size_t idx = r->used;
   hipEvent_t e = r->next();
   if (!e) return;
@@ -46,7 +47,7 @@ void rec_begin(EventRecorder* r, int cls, hipStream_t s) {
 }
 
 void rec_end(EventRecorder* r, int cls, hipStream_t s, double units) {
-  if (!r || r->open[cls].empty()) return;
+  if (!r || !((r->mask >> cls) & 1u) || r->open[cls].empty()) return;
   const size_t idx = r->used;
   hipEvent_t e = r->next();
   if (!e) return;
@@ -439,6 +440,14 @@ int ace_profile_enable(ace_ctx* c, int enable) {
   if (!c) return ACE_E_ARG;
   if (!enable) rec_collect(&c->rec, c->stream);
   c->profiling = enable != 0;
+  return ACE_OK;
+}
+
+int ace_profile_classes(ace_ctx* c, unsigned mask) {
+  if (!c) return ACE_E_ARG;
+  if (mask >> KC_COUNT) return fail(c, ACE_E_ARG, "profile class mask 0x%x names classes beyond %d", mask, KC_COUNT - 1);
+  rec_collect(&c->rec, c->stream);
+  c->rec.mask = mask;
   return ACE_OK;
 }
 

@@ -81,6 +81,7 @@ def test_argument_validation(ctx):
     assert lib.ace_pair_features(h, C.byref(g), 4, fake, None, 10, fake, 0) == -1
     assert lib.ace_pair_features(h, C.byref(g), 4, fake, None, 10, fake, 5) == -1
     assert lib.ace_profile_read(h, 99, None, None, None, 0) == -1
+    assert lib.ace_profile_classes(h, 1 << 20) == -1
     # batched: argument checks before any device work
     arr = (ace.ace_system * 2)()
     for a in arr:
