@@ -107,7 +107,7 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes": a.numel() * 8, "copies": 3, "source_hash": pair_source_hash()}), flush=True)
 
 
-def cpu_baseline(o, pairs_np, kind, omega, sample_pairs=60):
+def cpu_baseline(o, pairs_np, kind, omega, sample_pairs=1000):
     """The FP64 oracle, single-threaded, on a bounded sample of the same step."""
     import numpy as np
     from threadpoolctl import threadpool_limits

@@ -17,6 +17,7 @@
 // D[4(l/16) + r][l%16] for the FP32 one (checked on gfx950 by a lane probe).
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <type_traits>
 #include "ace_internal.h"
 
 namespace ace {
@@ -268,13 +269,22 @@ __device__ __forceinline__ void tile_rk(int e, int& r, int& k) {
   if (KM) { r = e % TT; k = e / TT; } else { r = e / KS; k = e % KS; }
 }
 
-template <typename TX, bool KM, int OP>
+// Threads of a tile workgroup: 2 row waves x NW column waves.
+template <int NW> __host__ __device__ constexpr int tile_threads() { return 128 * NW; }
+// elements of one operand's 128 x 16 step per thread
+template <int NW> __host__ __device__ constexpr int tile_per() { return 2048 / tile_threads<NW>(); }
+// Minimum waves per SIMD for the launch bounds.  NW = 2: 64 x 64 outputs per
+// wave, two waves per SIMD (up to 256 registers); NW = 4: 64 x 32 per wave,
+// four per SIMD (capped at 128 registers).
+template <int NW> __host__ __device__ constexpr int tile_waves() { return NW == 2 ? 2 : 4; }
+
+template <typename TX, bool KM, int OP, int NW = 2>
 __device__ __forceinline__ void tile_load(const TX* __restrict__ X, int64_t ld, int r0, int rows, int64_t k0,
-                                          int64_t ke, int tid, double (&v)[8]) {
+                                          int64_t ke, int tid, double (&v)[tile_per<NW>()]) {
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
+  for (int i = 0; i < tile_per<NW>(); ++i) {
     int r, k;
-    tile_rk<KM>(tid + 256 * i, r, k);
+    tile_rk<KM>(tid + tile_threads<NW>() * i, r, k);
     const int64_t kk = k0 + k;
     double x = 0.0;
     if (r0 + r < rows && kk < ke) x = double(KM ? X[kk * ld + r0 + r] : X[int64_t(r0 + r) * ld + kk]);
@@ -290,92 +300,98 @@ __device__ __forceinline__ void tile_load(const TX* __restrict__ X, int64_t ld, 
 constexpr int RP = KS + 1;
 static_assert(TT * RP <= KS * TP, "a row-major tile must fit a k-major tile's buffer");
 
-template <bool KM>
-__device__ __forceinline__ void tile_store(double* S, int tid, const double (&v)[8]) {
+template <bool KM, int NW = 2>
+__device__ __forceinline__ void tile_store(double* S, int tid, const double (&v)[tile_per<NW>()]) {
   if constexpr (!KM) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < tile_per<NW>(); ++i) {
       int r, k;
-      tile_rk<false>(tid + 256 * i, r, k);
+      tile_rk<false>(tid + tile_threads<NW>() * i, r, k);
       S[r * RP + k] = v[i];
     }
     return;
   }
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
+  for (int i = 0; i < tile_per<NW>(); ++i) {
     int r, k;
-    tile_rk<KM>(tid + 256 * i, r, k);
+    tile_rk<KM>(tid + tile_threads<NW>() * i, r, k);
     S[k * TP + r] = v[i];
   }
 }
 
-// Accumulate the tile over [kb, ke) into acc (per wave 4 x 4 blocks).
+// Accumulate the tile over [kb, ke) into acc: each of the 2 x NW waves owns
+// 64 rows x (128 / NW) columns, JB = 8 / NW blocks of 16 columns.  With NW = 4
+// (512 threads) a wave holds half the accumulators, so four waves fit per
+// SIMD instead of two.
 // LOWA: A(m, k) = 0 for k > m (lower-triangular left factor, global row and
 // k indices): a 16-row block skips the MFMAs of the k beyond its last row.
-template <typename TA, typename TB, bool AK, bool BK, int OP, bool LOWA = false>
+template <typename TA, typename TB, bool AK, bool BK, int OP, bool LOWA = false, int NW = 2>
 __device__ __forceinline__ void tile_mma(const TA* __restrict__ A, int64_t lda, const TB* __restrict__ B,
                                          int64_t ldb, int m0, int M, int n0, int Nn, int64_t kb, int64_t ke,
-                                         double* As, double* Bs, d4 (&acc)[4][4]) {
+                                         double* As, double* Bs, d4 (&acc)[4][8 / NW]) {
+  constexpr int JB = 8 / NW, WC = 128 / NW, PER = tile_per<NW>();
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int wm = wv >> 1, wn = wv & 1;
+  const int wm = wv / NW, wn = wv % NW;
   // 16 x 16 blocks of this wave that hold rows < M and columns < Nn (the
   // others stay zero, so their MFMAs are skipped; wave-uniform)
   const int ib = min(4, max(0, (M - m0 - wm * 64 + 15) / 16));
-  const int jb = min(4, max(0, (Nn - n0 - wn * 64 + 15) / 16));
-  double va[8], vb[8];
+  const int jb = min(JB, max(0, (Nn - n0 - wn * WC + 15) / 16));
+  double va[PER], vb[PER];
   int buf = 0;
   if (kb < ke) {
-    tile_load<TA, AK, OP>(A, lda, m0, M, kb, ke, tid, va);
-    tile_load<TB, BK, OP>(B, ldb, n0, Nn, kb, ke, tid, vb);
-    tile_store<AK>(As, tid, va);
-    tile_store<BK>(Bs, tid, vb);
+    tile_load<TA, AK, OP, NW>(A, lda, m0, M, kb, ke, tid, va);
+    tile_load<TB, BK, OP, NW>(B, ldb, n0, Nn, kb, ke, tid, vb);
+    tile_store<AK, NW>(As, tid, va);
+    tile_store<BK, NW>(Bs, tid, vb);
   }
   __syncthreads();
   for (int64_t k0 = kb; k0 < ke; k0 += KS) {
     const bool more = k0 + KS < ke;
     if (more) {
-      tile_load<TA, AK, OP>(A, lda, m0, M, k0 + KS, ke, tid, va);
-      tile_load<TB, BK, OP>(B, ldb, n0, Nn, k0 + KS, ke, tid, vb);
+      tile_load<TA, AK, OP, NW>(A, lda, m0, M, k0 + KS, ke, tid, va);
+      tile_load<TB, BK, OP, NW>(B, ldb, n0, Nn, k0 + KS, ke, tid, vb);
     }
     const double* as = As + buf * KS * TP;
     const double* bs = Bs + buf * KS * TP;
 #pragma unroll
     for (int kk = 0; kk < KS; kk += 4) {
       const int kq = kk + lane / 16, kr = kq * TP, li = lane % 16;
-      double a[4], b[4];
+      double a[4], b[JB];
 #pragma unroll
       for (int i = 0; i < 4; ++i) a[i] = AK ? as[kr + wm * 64 + i * 16 + li] : as[(wm * 64 + i * 16 + li) * RP + kq];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = BK ? bs[kr + wn * 64 + j * 16 + li] : bs[(wn * 64 + j * 16 + li) * RP + kq];
+      for (int j = 0; j < JB; ++j) b[j] = BK ? bs[kr + wn * WC + j * 16 + li] : bs[(wn * WC + j * 16 + li) * RP + kq];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < JB; ++j)
           if (i < ib && j < jb && (!LOWA || k0 + kk < int64_t(m0) + wm * 64 + i * 16 + 16))
             acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     if (more) {
       buf ^= 1;
-      tile_store<AK>(As + buf * KS * TP, tid, va);
-      tile_store<BK>(Bs + buf * KS * TP, tid, vb);
+      tile_store<AK, NW>(As + buf * KS * TP, tid, va);
+      tile_store<BK, NW>(Bs + buf * KS * TP, tid, vb);
     }
     __syncthreads();
   }
 }
 
 // acc -> out[m][n] (ld) for rows < M, columns < Nn, times alpha
-__device__ __forceinline__ void tile_write(const d4 (&acc)[4][4], int m0, int M, int64_t n0, int64_t Nn,
+template <int NW = 2>
+__device__ __forceinline__ void tile_write(const d4 (&acc)[4][8 / NW], int m0, int M, int64_t n0, int64_t Nn,
                                            double* __restrict__ out, int64_t ld, double alpha) {
+  constexpr int JB = 8 / NW, WC = 128 / NW;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int wm = wv >> 1, wn = wv & 1;
+  const int wm = wv / NW, wn = wv % NW;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < JB; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int m = m0 + wm * 64 + i * 16 + lane / 16 + 4 * r;
-        const int64_t n = n0 + wn * 64 + j * 16 + lane % 16;
+        const int64_t n = n0 + wn * WC + j * 16 + lane % 16;
         if (m < M && n < Nn) out[int64_t(m) * ld + n] = alpha * acc[i][j][r];
       }
 }
@@ -383,11 +399,10 @@ __device__ __forceinline__ void tile_write(const d4 (&acc)[4][4], int m0, int M,
 // NT split-K: blockIdx.x = tile t of the tile list (tm, tn) = (t / ntn, t % ntn),
 // or with SYM the t-th tile of the upper triangle tm <= tn; blockIdx.y = split.
 // Cpart[split][M][Nn] receives the tile's partial sums.
-template <int OP, bool SYM>
-__global__ __launch_bounds__(256, 2) void k_gemm_nt_t128(const double* __restrict__ A, int64_t lda,
-                                                         const double* __restrict__ B, int64_t ldb, int M, int Nn,
-                                                         int64_t K, int64_t kchunk, int ntn,
-                                                         double* __restrict__ Cpart) {
+template <int OP, bool SYM, int NW = 2>
+__global__ __launch_bounds__(tile_threads<NW>(), tile_waves<NW>()) void k_gemm_nt_t128(
+    const double* __restrict__ A, int64_t lda, const double* __restrict__ B, int64_t ldb, int M, int Nn, int64_t K,
+    int64_t kchunk, int ntn, double* __restrict__ Cpart) {
   __shared__ double As[2 * KS * TP];
   __shared__ double Bs[2 * KS * TP];
   int tm, tn;
@@ -404,13 +419,13 @@ __global__ __launch_bounds__(256, 2) void k_gemm_nt_t128(const double* __restric
   const int m0 = tm * TT, n0 = tn * TT;
   const int64_t kb = int64_t(blockIdx.y) * kchunk;
   const int64_t ke = (kb + kchunk < K) ? kb + kchunk : K;
-  d4 acc[4][4];
+  d4 acc[4][8 / NW];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0, 0, 0, 0};
-  tile_mma<double, double, false, false, OP>(A, lda, B, ldb, m0, M, n0, Nn, kb, ke, As, Bs, acc);
-  tile_write(acc, m0, M, n0, Nn, Cpart + int64_t(blockIdx.y) * M * Nn, Nn, 1.0);
+    for (int j = 0; j < 8 / NW; ++j) acc[i][j] = d4{0, 0, 0, 0};
+  tile_mma<double, double, false, false, OP, false, NW>(A, lda, B, ldb, m0, M, n0, Nn, kb, ke, As, Bs, acc);
+  tile_write<NW>(acc, m0, M, n0, Nn, Cpart + int64_t(blockIdx.y) * M * Nn, Nn, 1.0);
 }
 
 // ---------------------------------------------------------------- 128 x 64 FP32 compensated tiles
@@ -581,27 +596,26 @@ __global__ __launch_bounds__(256) void k_reduce_parts_t(const double* __restrict
 // LOWER: S(m, k) = 0 for k > m.  blockIdx.x = 128-column tile of r (fastest:
 // neighbouring workgroups write neighbouring segments of the same rows of C,
 // measured faster than the row tiles fastest), blockIdx.y = 128-row tile of m.
-template <typename TB, bool TRANS, bool LOWER>
-__global__ __launch_bounds__(256, 2) void k_gemm_ls_t128(const double* __restrict__ S, int lds,
-                                                         const TB* __restrict__ B, int64_t ldb,
-                                                         double* __restrict__ C, int64_t ldc, int M, int K,
-                                                         int64_t R, double alpha) {
+template <typename TB, bool TRANS, bool LOWER, int NW = 2>
+__global__ __launch_bounds__(tile_threads<NW>(), tile_waves<NW>()) void k_gemm_ls_t128(
+    const double* __restrict__ S, int lds, const TB* __restrict__ B, int64_t ldb, double* __restrict__ C, int64_t ldc,
+    int M, int K, int64_t R, double alpha) {
   __shared__ double As[2 * KS * TP];
   __shared__ double Bs[2 * KS * TP];
   const int m0 = blockIdx.y * TT;
   const int64_t r0 = int64_t(blockIdx.x) * TT;
   const int64_t ke = LOWER ? ((m0 + TT < K) ? m0 + TT : K) : K;
-  d4 acc[4][4];
+  d4 acc[4][8 / NW];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0, 0, 0, 0};
+    for (int j = 0; j < 8 / NW; ++j) acc[i][j] = d4{0, 0, 0, 0};
   // B columns r0 .. r0 + 127 are addressed from the tile origin
   const TB* Bt = B + r0;
   const int64_t rrem = R - r0;
-  tile_mma<double, TB, TRANS, true, 0, LOWER>(S, lds, Bt, ldb, m0, M, 0, int(rrem < TT ? rrem : TT), 0, ke, As, Bs,
-                                             acc);
-  tile_write(acc, m0, M, 0, rrem < TT ? rrem : TT, C + r0, ldc, alpha);
+  tile_mma<double, TB, TRANS, true, 0, LOWER, NW>(S, lds, Bt, ldb, m0, M, 0, int(rrem < TT ? rrem : TT), 0, ke, As,
+                                                 Bs, acc);
+  tile_write<NW>(acc, m0, M, 0, rrem < TT ? rrem : TT, C + r0, ldc, alpha);
 }
 
 // Bound refresh of the pivot search in one pass: for the 128 grid columns of
@@ -609,24 +623,26 @@ __global__ __launch_bounds__(256, 2) void k_gemm_ls_t128(const double* __restric
 // MFMA tile, then res[r] -= sum_m L[m][r]^2, without writing L.  Column sums
 // run over each lane's rows, then across the four lane groups, then across
 // the two row halves of the tile (fixed order).
-__global__ __launch_bounds__(256, 2) void k_refresh_t128(const double* __restrict__ Q, int ldq,
-                                                         const double* __restrict__ Psi, int64_t ldp, int M, int K,
-                                                         int64_t R, double* __restrict__ res) {
+template <int NW = 2>
+__global__ __launch_bounds__(tile_threads<NW>(), tile_waves<NW>()) void k_refresh_t128(
+    const double* __restrict__ Q, int ldq, const double* __restrict__ Psi, int64_t ldp, int M, int K, int64_t R,
+    double* __restrict__ res) {
   __shared__ double As[2 * KS * TP];
   __shared__ double Bs[2 * KS * TP];
   __shared__ double colsum[2][TT];
   const int64_t r0 = int64_t(blockIdx.x) * TT;
   const int64_t rrem = R - r0;
   const int ncol = int(rrem < TT ? rrem : TT);
-  d4 acc[4][4];
+  constexpr int JB = 8 / NW, WC = 128 / NW;
+  d4 acc[4][JB];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0, 0, 0, 0};
-  tile_mma<double, double, false, true, 0>(Q, ldq, Psi + r0, ldp, 0, M, 0, ncol, 0, K, As, Bs, acc);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wm = wv >> 1, wn = wv & 1;
+    for (int j = 0; j < JB; ++j) acc[i][j] = d4{0, 0, 0, 0};
+  tile_mma<double, double, false, true, 0, false, NW>(Q, ldq, Psi + r0, ldp, 0, M, 0, ncol, 0, K, As, Bs, acc);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wm = wv / NW, wn = wv % NW;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < JB; ++j) {
     double sq = 0.0;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -634,7 +650,7 @@ __global__ __launch_bounds__(256, 2) void k_refresh_t128(const double* __restric
       for (int r = 0; r < 4; ++r) sq += acc[i][j][r] * acc[i][j][r];
     sq += __shfl_xor(sq, 16, 64);
     sq += __shfl_xor(sq, 32, 64);
-    if (lane < 16) colsum[wm][wn * 64 + j * 16 + lane] = sq;
+    if (lane < 16) colsum[wm][wn * WC + j * 16 + lane] = sq;
   }
   __syncthreads();
   const int t = threadIdx.x;
@@ -644,8 +660,8 @@ __global__ __launch_bounds__(256, 2) void k_refresh_t128(const double* __restric
 hipError_t refresh_bounds(const double* Q, int ldq, const double* Psi, int64_t ldp, int M, int K, int64_t R,
                           double* res, hipStream_t s) {
   if (M < 1 || M > TT || K < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_refresh_t128, dim3(unsigned((R + TT - 1) / TT)), dim3(256), 0, s, Q, ldq, Psi, ldp, M, K, R,
-                     res);
+  hipLaunchKernelGGL(k_refresh_t128<4>, dim3(unsigned((R + TT - 1) / TT)), dim3(tile_threads<4>()), 0, s, Q, ldq, Psi,
+                     ldp, M, K, R, res);
   return hipGetLastError();
 }
 
@@ -683,8 +699,9 @@ hipError_t gemm_nt(int prec, int op, const void* A, int64_t lda, const void* B, 
     dim3 grid(ntiles, unsigned(nsplit));
     const double* a = (const double*)A;
     const double* b = (const double*)B;
-#define NT_LAUNCH(OPV, SYMV) \
-    hipLaunchKernelGGL((k_gemm_nt_t128<OPV, SYMV>), grid, dim3(256), 0, s, a, lda, b, ldb, M, Nn, K, kchunk, ntn, Cpart)
+#define NT_LAUNCH(OPV, SYMV)                                                                                  \
+    hipLaunchKernelGGL((k_gemm_nt_t128<OPV, SYMV, 4>), grid, dim3(tile_threads<4>()), 0, s, a, lda, b, ldb, M, Nn, K, \
+                       kchunk, ntn, Cpart)
     if (sym) {
       if (op == 1) NT_LAUNCH(1, true);
       else if (op == 2) NT_LAUNCH(2, true);
@@ -723,8 +740,11 @@ static void launch_ls(const double* S, int lds, const TB* B, int64_t ldb, double
     hipLaunchKernelGGL((k_gemm_tiny<TB, TRANS, LOWER>), grid, dim3(64), 0, s, S, lds, B, ldb, C, ldc, M, K, R, alpha);
   } else if (M > 64) {
     dim3 grid(unsigned((R + TT - 1) / TT), unsigned((M + TT - 1) / TT));
-    hipLaunchKernelGGL((k_gemm_ls_t128<TB, TRANS, LOWER>), grid, dim3(256), 0, s, S, lds, B, ldb, C, ldc, M, K, R,
-                       alpha);
+    // FP32 right operands run 8 waves per tile; with FP64 ones the 512-thread
+    // tile spills and was slower, so they keep 4.
+    constexpr int NW = std::is_same<TB, float>::value ? 4 : 2;
+    hipLaunchKernelGGL((k_gemm_ls_t128<TB, TRANS, LOWER, NW>), grid, dim3(tile_threads<NW>()), 0, s, S, lds, B, ldb, C,
+                       ldc, M, K, R, alpha);
   } else {
     dim3 grid(unsigned((R + GB - 1) / GB), unsigned((M + 63) / 64));
     hipLaunchKernelGGL((k_gemm_ls<TB, TRANS, LOWER, 64>), grid, dim3(256), 0, s, S, lds, B, ldb, C, ldc, M, K, R,
