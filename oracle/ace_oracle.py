@@ -233,6 +233,37 @@ def ace_apply(xi: np.ndarray, X: np.ndarray, dV: float) -> np.ndarray:
     return (-(c.T @ P)).reshape(X.shape)
 
 
+def ace_apply_energy(xi: np.ndarray, X: np.ndarray, dV: float):
+    """V_ACE on a set of functions and their summed exchange energy.
+
+    Returns (Y, E) with Y = V_ACE X (Appendix A, projector form) and
+    E = sum_a <x_a|V_ACE|x_a>, the plain inner product of each function with
+    its image.  With X the occupied orbitals this is the exchange energy of an
+    SCF cycle.  Pinned by P8: with X the orbitals a full-list build was made
+    from, E is that build's tr M (V_ACE phi = W); E is never positive; it is
+    unchanged by an orthogonal mixing of the functions."""
+    Y = ace_apply(xi, X, dV)
+    n = X.shape[0]
+    return Y, dV * float(np.sum(X.reshape(n, -1) * Y.reshape(n, -1)))
+
+
+def exact_exchange(psi: np.ndarray, N, L, kind: str, omega: float):
+    """Exact exchange on the orbitals themselves, Eq. (vx) over every (i, j).
+
+    W_i = V_X psi_i = -sum_j v_ij psi_j with no screening and no localization,
+    M_kl = <psi_k|W_l> symmetrized, E_x = tr M.  Returns (W, M, E_x).  Pinned
+    by P9: W equals the pair-symmetric build over the full list, E_x is
+    unchanged by an orthogonal rotation of the orbitals, -M is positive
+    definite, and one orbital reduces to its self-exchange."""
+    dV = float(np.prod(_len3(L))) / psi[0].size
+    v = coulomb_kernel(N, L, kind, omega)
+    W = apply_vx_direct(psi, psi, v)
+    n = psi.shape[0]
+    M = dV * (psi.reshape(n, -1) @ W.reshape(n, -1).T)
+    M = 0.5 * (M + M.T)
+    return W, M, float(np.trace(M))
+
+
 def apply_vx_direct(phi: np.ndarray, X: np.ndarray, v_half: np.ndarray) -> np.ndarray:
     """Exact exchange on arbitrary functions, Eq. (vx): V_X x = -sum_j v_xj phi_j."""
     out = np.zeros_like(X)

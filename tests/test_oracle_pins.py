@@ -374,3 +374,75 @@ def test_p7_single_orbital_closed_form():
     v = oracle.coulomb_kernel(spec.N, spec.L, "erfc", 0.4)
     jj = spec.dV * np.sum(g[0] ** 2 * oracle.pair_potential(g[0], g[0], v))
     assert abs(r["ex"] + jj) < 1e-13 * jj
+
+
+# ----------------------------------------------------------------- P8
+
+def test_p8_apply_energy_is_trace_of_M(small_system):
+    """With the build's own orbitals and the full list, sum_i <phi_i|V_ACE|phi_i> = tr M
+    (V_ACE phi = W once M = Phi^T W dV is symmetric), for canonical and SCDM orbitals."""
+    o = small_system
+    s = o.spec
+    _, _, phi = oracle.scdm_localize(o.psi, s.dV)
+    for orbs in (o.psi, phi):
+        r = oracle.ace_build(orbs, _full_pairs(s.norb), s.N, s.L, "erfc", s.omega)
+        Y, e = oracle.ace_apply_energy(r["xi"], orbs, s.dV)
+        np.testing.assert_allclose(Y, r["W"], atol=1e-12 * np.abs(r["W"]).max())
+        assert abs(e - r["ex"]) < 1e-12 * abs(r["ex"])
+        assert abs(e - np.trace(r["M"])) < 1e-12 * abs(r["ex"])
+
+
+def test_p8_apply_energy_sign_and_mixing_invariance(small_system):
+    o = small_system
+    s = o.spec
+    r = oracle.ace_build(o.psi, _full_pairs(s.norb), s.N, s.L, "erfc", s.omega)
+    rng = np.random.default_rng(12)
+    X = rng.normal(size=(4,) + o.psi.shape[1:])
+    _, e = oracle.ace_apply_energy(r["xi"], X, s.dV)
+    assert e < 0
+    q, _ = np.linalg.qr(rng.normal(size=(4, 4)))
+    _, eq = oracle.ace_apply_energy(r["xi"], np.einsum("ab,bzyx->azyx", q, X), s.dV)
+    assert abs(eq - e) < 1e-12 * abs(e)
+    # each function's energy is its own quadratic form: scaling one by t scales its share by t^2
+    _, e0 = oracle.ace_apply_energy(r["xi"], X[:1], s.dV)
+    _, e0s = oracle.ace_apply_energy(r["xi"], 3.0 * X[:1], s.dV)
+    assert abs(e0s - 9.0 * e0) < 1e-12 * abs(e0s)
+
+
+# ----------------------------------------------------------------- P9
+
+def test_p9_exact_exchange_matches_pair_symmetric_build(small_system):
+    o = small_system
+    s = o.spec
+    W, M, ex = oracle.exact_exchange(o.psi, s.N, s.L, "erfc", s.omega)
+    r = oracle.ace_build(o.psi, _full_pairs(s.norb), s.N, s.L, "erfc", s.omega)
+    np.testing.assert_allclose(W, r["W"], atol=1e-12 * np.abs(W).max())
+    np.testing.assert_allclose(M, r["M"], atol=1e-13 * np.abs(M).max())
+    assert abs(ex - r["ex"]) < 1e-12 * abs(ex)
+    assert np.linalg.eigvalsh(M).max() < 0
+    np.testing.assert_allclose(M, M.T, atol=0)
+
+
+def test_p9_exact_exchange_rotation_invariance(small_system):
+    o = small_system
+    s = o.spec
+    _, M0, ex0 = oracle.exact_exchange(o.psi, s.N, s.L, "bare", 0.0)
+    q, _ = np.linalg.qr(np.random.default_rng(21).normal(size=(s.norb, s.norb)))
+    rot = np.einsum("ik,izyx->kzyx", q, o.psi)
+    W1, M1, ex1 = oracle.exact_exchange(rot, s.N, s.L, "bare", 0.0)
+    assert abs(ex1 - ex0) < 1e-12 * abs(ex0)
+    # M transforms as Q^T M Q
+    np.testing.assert_allclose(M1, q.T @ M0 @ q, atol=1e-12 * np.abs(M0).max())
+
+
+def test_p9_exact_exchange_single_orbital():
+    """One normalized Gaussian: W = -v_gg g and E_x = -dV sum g^2 v_gg, where
+    v_gg is pinned against the analytic erfc self-energy (P3)."""
+    spec = SystemSpec(n_mol=1, L=7.0, N=16, sigma=0.8, seed=5)
+    g = disjoint_gaussians(spec, [(3.0, 3.5, 2.0)])
+    W, M, ex = oracle.exact_exchange(g, spec.N, spec.L, "erfc", 0.4)
+    v = oracle.coulomb_kernel(spec.N, spec.L, "erfc", 0.4)
+    vgg = oracle.pair_potential(g[0], g[0], v)
+    np.testing.assert_allclose(W[0], -vgg * g[0], rtol=0, atol=1e-14 * np.abs(W).max())
+    jj = spec.dV * np.sum(g[0] ** 2 * vgg)
+    assert M.shape == (1, 1) and abs(ex + jj) < 1e-13 * jj
