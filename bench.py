@@ -148,6 +148,52 @@ def _timed(fn, reps=3, warm=True):
     return (time.perf_counter() - t0) * 1000.0 / reps, out
 
 
+def form_apply_energy(ctx, xi, x, grid, reps=10):
+    """Per-SCF-cycle application: V_ACE on every orbital fused with the energy.
+
+    Two FP64 products over the grid (c = dV xi x^T, y = -c^T xi): 4 norb nvec
+    N_G flops, (2 norb + 2 nvec) N_G 8 bytes of HBM traffic at the least."""
+    import torch
+
+    ctx.apply_energy(xi, x, grid)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        y, e = ctx.apply_energy(xi, x, grid)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / reps
+    norb, nvec, ng = xi.shape[0], x.shape[0], grid.size
+    tf = 4.0 * norb * nvec * ng / (ms / 1000.0) / 1e12
+    gbs = (2 * norb + 2 * nvec) * ng * 8 / (ms / 1000.0) / 1e9
+    return {"workload": f"V_ACE and E on all {nvec} orbitals, {norb} projectors, {round(ng ** (1 / 3))}^3",
+            "ms": round(ms, 3), "tflops": round(tf, 2), "bound": "mfma",
+            "frac_fp64_peak": round(tf / FP64_PEAK_TFLOPS, 4), "min_traffic_gbs": round(gbs, 1),
+            "e_hartree": float(e.item())}
+
+
+def form_exact_exchange(ctx, psi, grid, kind, omega, reps=3):
+    """Exact exchange on the canonical orbitals over every pair (W, M, E_x)."""
+    import torch
+
+    out = {"workload": f"canonical orbitals, all pairs, {psi.shape[0]} orbitals, {round(grid.size ** (1 / 3))}^3",
+           "pairs": psi.shape[0] * (psi.shape[0] + 1) // 2}
+    for p in ("fp64", "fp32"):
+        r = ctx.exact_exchange(psi, grid, kernel=kind, omega=omega, precision=p, want_M=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = ctx.exact_exchange(psi, grid, kernel=kind, omega=omega, precision=p, want_M=False,
+                                   out={"W": r["W"]})
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / reps
+        out[p] = {"ms": round(ms, 3), "pair_solves_per_s": round(out["pairs"] / (ms / 1000.0), 1),
+                  "ex": float(r["ex"].item())}
+        del r
+        torch.cuda.empty_cache()
+    out["ex_rel_err_fp32_vs_fp64"] = abs(out["fp32"]["ex"] - out["fp64"]["ex"]) / abs(out["fp64"]["ex"])
+    return out
+
+
 def form_precision(ctx, log):
     """64 waters (256 orbitals, 120^3): FP32 pair stage vs the plain FP64 path."""
     import torch
@@ -421,6 +467,9 @@ def main():
         r32 = ctx.build(phi, pairs, grid, kernel=kind, omega=omega, precision="fp32", want_M=False)
         forms["c2_screened_ex_rel_err_fp32_vs_fp64"] = abs(float(r32["ex"].item()) - ex) / abs(ex)
         del full, rf, r32
+        torch.cuda.empty_cache()
+        forms["apply_energy"] = form_apply_energy(ctx, r["xi"], phi, grid)
+        forms["exact_exchange"] = form_exact_exchange(ctx, psi, grid, kind, omega)
         torch.cuda.empty_cache()
         for name, fn in (("precision", lambda: form_precision(ctx, log)), ("batched", lambda: form_batched(ctx, log)),
                          ("learned", lambda: form_learned(ctx, log, args.screener))):

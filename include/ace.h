@@ -147,6 +147,37 @@ int ace_apply(ace_ctx* ctx, const ace_grid* grid, int norb, const double* xi, in
               double* y);
 
 /*
+ * ACE application fused with the exchange energy of the functions it is
+ * applied to (Appendix A, projector form; with x the occupied orbitals this is
+ * one SCF cycle's application and E_x).  Both results come from the same
+ * coefficients c_ka = <xi_k | x_a>:
+ *   y_a = -sum_k c_ka xi_k,   ex = sum_a <x_a | V_ACE x_a> = -sum_ka c_ka^2.
+ *   xi [norb][N_G], x [nvec][N_G] (inputs), y [nvec][N_G] (output),
+ *   ex [1] Hartree, device memory (output, required).
+ * Arguments and errors as ace_apply; the energy is summed in a fixed order.
+ */
+int ace_apply_energy(ace_ctx* ctx, const ace_grid* grid, int norb, const double* xi, int nvec, const double* x,
+                     double* y, double* ex);
+
+/*
+ * Exact exchange on the orbitals themselves (Eq. vx over every pair, no
+ * screening and no localization): the full-rank operator behind the exact
+ * force of the multiple-time-step force splitting (Sec. Theory).
+ *   W_i = V_X psi_i = -sum_j v_ij psi_j   (steps (c) of ace_build, all pairs)
+ *   M_kl = <psi_k | W_l>, symmetrized;  ex = tr M.
+ *   psi  [norb][N_G] orthonormal orbitals (input)
+ *   kernel, omega, prec as ace_build (prec sets the pair stage; W is returned
+ *        in FP64 either way)
+ *   W    [norb][N_G] (output, required)
+ *   M    [norb][norb] (output, nullable)
+ *   ex   [1] Hartree, device memory (output, nullable)
+ * The pair list i <= j is generated internally (norb (norb + 1) / 2 pairs).
+ * No Cholesky or projectors are formed.  Errors as ace_build.
+ */
+int ace_exact_exchange(ace_ctx* ctx, const ace_grid* grid, int norb, const double* psi, int kernel, double omega,
+                       int prec, double* W, double* M, double* ex);
+
+/*
  * Timing.  While enabled, every launch of the hot kernels and every stage of
  * the calls above is bracketed by HIP events on the context stream.
  * ace_profile_read synchronizes and returns, for class `cls`, the number of

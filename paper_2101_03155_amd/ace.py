@@ -110,6 +110,8 @@ def load(path: str = LIB_PATH):
         "ace_pairlist": ([P, GP, I, P, D, I64, P, P, C.POINTER(I64)], I),
         "ace_build": ([P, GP, I, P, P, I64, I, D, I, P, P, P, P, P], I),
         "ace_apply": ([P, GP, I, P, I, P, P], I),
+        "ace_apply_energy": ([P, GP, I, P, I, P, P, P], I),
+        "ace_exact_exchange": ([P, GP, I, P, I, D, I, P, P, P], I),
         "ace_profile_enable": ([P, I], I),
         "ace_profile_read": ([P, I, C.POINTER(I64), C.POINTER(D), C.POINTER(D), I], I),
         "ace_profile_classes": ([P, C.c_uint], I),
@@ -271,6 +273,46 @@ class Context:
         g = grid.c()
         self._check(self.lib.ace_apply(self.h, C.byref(g), xi.shape[0], _ptr(xi), x.shape[0], _ptr(x), _ptr(y)))
         return y
+
+    def apply_energy(self, xi, x, grid: Grid, out=None):
+        """(y, ex): y = V_ACE x and ex = sum_a <x_a|V_ACE x_a> (device scalar), one pass."""
+        import torch
+
+        _require(xi, torch.float64, "xi")
+        _require(x, torch.float64, "x")
+        o = out or {}
+        y = o.get("y")
+        if y is None:
+            y = torch.empty_like(x)
+        ex = o.get("ex")
+        if ex is None:
+            ex = torch.empty(1, dtype=torch.float64, device=x.device)
+        self._sync_stream()
+        g = grid.c()
+        self._check(self.lib.ace_apply_energy(self.h, C.byref(g), xi.shape[0], _ptr(xi), x.shape[0], _ptr(x),
+                                              _ptr(y), _ptr(ex)))
+        return y, ex
+
+    def exact_exchange(self, psi, grid: Grid, kernel: str = "erfc", omega: float = 0.106, precision: str = "fp64",
+                       want_M: bool = True, out=None):
+        """Exact V_X on every orbital over all pairs: returns dict(W, M, ex)."""
+        import torch
+
+        _require(psi, torch.float64, "psi")
+        norb = psi.shape[0]
+        o = out or {}
+        W = o.get("W")
+        if W is None:
+            W = torch.empty_like(psi)
+        M = torch.empty(norb, norb, dtype=torch.float64, device=psi.device) if want_M else None
+        ex = o.get("ex")
+        if ex is None:
+            ex = torch.empty(1, dtype=torch.float64, device=psi.device)
+        self._sync_stream()
+        g = grid.c()
+        self._check(self.lib.ace_exact_exchange(self.h, C.byref(g), norb, _ptr(psi), KERNELS[kernel], float(omega),
+                                                PRECISIONS[precision], _ptr(W), _ptr(M), _ptr(ex)))
+        return dict(W=W, M=M, ex=ex)
 
     # ------------------------------------------------------------ timing / tuning
     def profile(self, enable: bool):

@@ -121,6 +121,7 @@ hipError_t gemm_ls(int bprec, bool trans, bool lower, const double* S, int lds, 
 hipError_t refresh_bounds(const double* Q, int ldq, const double* Psi, int64_t ldp, int M, int K, int64_t R,
                           double* res, hipStream_t s);
 void launch_symmetrize(const double* M, int n, double* out, double* negM, double* ex, double* asym, hipStream_t s);
+void launch_neg_sumsq(const double* c, int64_t n, double* out, hipStream_t s);
 // Blocked Cholesky of the lower triangle of A (n <= 512) in place; info must
 // be zero on entry; tinv is 64 x 64 doubles of scratch.
 void launch_cholesky(double* A, int n, int* info, double* tinv, hipStream_t s);

@@ -782,8 +782,10 @@ static int build_impl(ace_ctx* c, const ace_grid* g, int norb, const double* phi
   double *epart = nullptr, *part, *Mraw, *Lb, *Li, *scal;
   void* vtab = nullptr;
   int* info;
-  if (xi) WS(c, "W", size_t(norb) * ng * es, W);
-  else W = nullptr;
+  // W lives in the workspace, or directly in the caller's FP64 output when no
+  // projectors follow (exact exchange)
+  if (xi || (Wout && prec == 1)) WS(c, "W", size_t(norb) * ng * es, W);
+  else W = Wout;
   if (owner) {
     WS(c, "spec", size_t(2 * onpk) * slot_bytes, spec);
     WS(c, "packs", size_t(onpk) * sizeof(Pack), dpk);
@@ -848,14 +850,14 @@ static int build_impl(ace_ctx* c, const ace_grid* g, int norb, const double* phi
     }
   }
   rec_end(R, ST_PAIRS, s);
-  if (!xi) {  // energies only
+  if (!xi && !Wout) {  // energies only
     rec_end(R, ST_BUILD, s);
     HIPCHK(c, hipGetLastError());
     return ACE_OK;
   }
 
   // W is an output of step (c) whatever the factorization below reports
-  if (Wout) {
+  if (Wout && W != Wout) {
     if (prec == 0)
       HIPCHK(c, hipMemcpyAsync(Wout, W, size_t(norb) * ng * sizeof(double), hipMemcpyDeviceToDevice, s));
     else
@@ -866,6 +868,12 @@ static int build_impl(ace_ctx* c, const ace_grid* g, int norb, const double* phi
   rec_begin(R, ST_TAIL, s);
   HIPCHK(c, gemm_nt(prec, 0, phiw, ng, W, ng, norb, norb, ng, dV, part, Mraw, s, R));
   launch_symmetrize(Mraw, norb, Mout, Lb, ex ? ex : scal, scal + 1, s);
+  if (!xi) {  // exact exchange: W, M and E_x only
+    rec_end(R, ST_TAIL, s);
+    rec_end(R, ST_BUILD, s);
+    HIPCHK(c, hipGetLastError());
+    return ACE_OK;
+  }
   launch_zero(info, sizeof(int), s);
   launch_cholesky(Lb, norb, info, tinv, s);
   int hinfo = 0;
@@ -882,8 +890,35 @@ static int build_impl(ace_ctx* c, const ace_grid* g, int norb, const double* phi
   return ACE_OK;
 }
 
+int ace_exact_exchange(ace_ctx* c, const ace_grid* g, int norb, const double* psi, int kernel, double omega,
+                       int prec, double* W, double* Mout, double* ex) {
+  if (!c) return ACE_E_ARG;
+  int rc = check_grid(c, g, norb);
+  if (rc) return rc;
+  if (!psi || !W) return fail(c, ACE_E_ARG, "psi and W must be non-NULL");
+  if (kernel != ACE_KERNEL_COULOMB && kernel != ACE_KERNEL_ERFC) return fail(c, ACE_E_ARG, "unknown kernel %d", kernel);
+  if (kernel == ACE_KERNEL_ERFC && !(omega > 0.0)) return fail(c, ACE_E_ARG, "omega must be > 0 for erfc");
+  if (prec != ACE_FP64 && prec != ACE_FP32) return fail(c, ACE_E_ARG, "unknown precision %d", prec);
+  // every pair i <= j, sorted by (i, j)
+  const int64_t np = int64_t(norb) * (norb + 1) / 2;
+  std::vector<int32_t> hp(size_t(2 * np));
+  size_t q = 0;
+  for (int i = 0; i < norb; ++i)
+    for (int j = i; j < norb; ++j) {
+      hp[q++] = i;
+      hp[q++] = j;
+    }
+  int32_t* dp;
+  WS(c, "allpairs", hp.size() * sizeof(int32_t), dp);
+  HIPCHK(c, hipMemcpyAsync(dp, hp.data(), hp.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return build_impl(c, g, norb, psi, dp, np, kernel, omega, prec, nullptr, Mout, W, ex, nullptr);
+}
+
 // ------------------------------------------------------------------ apply
-int ace_apply(ace_ctx* c, const ace_grid* g, int norb, const double* xi, int nvec, const double* x, double* y) {
+// y = V_ACE x from the coefficients cb = dV xi x^T; with ex, also -sum cb^2
+static int apply_impl(ace_ctx* c, const ace_grid* g, int norb, const double* xi, int nvec, const double* x, double* y,
+                      double* ex) {
   if (!c) return ACE_E_ARG;
   int rc = check_grid(c, g, norb);
   if (rc) return rc;
@@ -898,7 +933,19 @@ int ace_apply(ace_ctx* c, const ace_grid* g, int norb, const double* xi, int nve
   WS(c, "coef", size_t(norb) * nvec * sizeof(double), cb);
   HIPCHK(c, gemm_nt(0, 0, xi, ng, x, ng, norb, nvec, ng, grid_dv(g), part, cb, s, c->R()));
   HIPCHK(c, gemm_ls(0, true, false, cb, nvec, xi, ng, y, ng, nvec, norb, ng, -1.0, s, c->R()));
+  if (ex) launch_neg_sumsq(cb, int64_t(norb) * nvec, ex, s);
+  HIPCHK(c, hipGetLastError());
   return ACE_OK;
+}
+
+int ace_apply(ace_ctx* c, const ace_grid* g, int norb, const double* xi, int nvec, const double* x, double* y) {
+  return apply_impl(c, g, norb, xi, nvec, x, y, nullptr);
+}
+
+int ace_apply_energy(ace_ctx* c, const ace_grid* g, int norb, const double* xi, int nvec, const double* x, double* y,
+                     double* ex) {
+  if (c && !ex) return fail(c, ACE_E_ARG, "ex must be non-NULL");
+  return apply_impl(c, g, norb, xi, nvec, x, y, ex);
 }
 
 

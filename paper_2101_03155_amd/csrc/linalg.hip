@@ -1079,6 +1079,21 @@ __global__ void k_pair_energy(const double* __restrict__ epart, int npacks, int 
   e[pidx[2 * p]] = -(pk.ia == pk.ja ? 1.0 : 2.0) * dV * sa;
   if (pk.jb >= 0) e[pidx[2 * p + 1]] = -(pk.ib == pk.jb ? 1.0 : 2.0) * dV * sb;
 }
+// out[0] = -sum c^2 over n values: the summed exchange energy of a set of
+// functions from their projector coefficients c_ka = <xi_k | x_a>.  One block,
+// fixed summation order (deterministic).
+__global__ void k_neg_sumsq(const double* __restrict__ c, int64_t n, double* __restrict__ out) {
+  __shared__ double red[256];
+  double a = 0.0;
+  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) a = fma(c[e], c[e], a);
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = -red[0];
+}
 
 // ---------------------------------------------------------------- conversions
 __global__ void k_d2f(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
@@ -1102,6 +1117,9 @@ static int grid_for(int64_t n, int nt, int cap = 4096) {
   return int(g);
 }
 
+void launch_neg_sumsq(const double* c, int64_t n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_neg_sumsq, dim3(1), dim3(256), 0, s, c, n, out);
+}
 void launch_symmetrize(const double* M, int n, double* out, double* negM, double* ex, double* asym, hipStream_t s) {
   hipLaunchKernelGGL(k_symmetrize, dim3(1), dim3(256), 0, s, M, n, out, negM, ex, asym);
 }

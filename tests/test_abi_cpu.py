@@ -56,6 +56,16 @@ def test_argument_validation(ctx):
     n = C.c_int64()
     assert lib.ace_pairlist(h, C.byref(g), 4, fake, 1e-3, -1, fake, None, C.byref(n)) == -1
     assert lib.ace_apply(h, C.byref(g), 4, fake, 0, fake, fake) == -1
+    # fused application: energy output required, nvec >= 1
+    assert lib.ace_apply_energy(h, C.byref(g), 4, fake, 1, fake, fake, None) == -1
+    assert lib.ace_apply_energy(h, C.byref(g), 4, fake, 0, fake, fake, fake) == -1
+    # exact exchange: norb, NULL W, bad kernel, precision, erfc without omega, grid
+    assert lib.ace_exact_exchange(h, C.byref(g), 0, fake, 0, 0.1, 0, fake, None, None) == -1
+    assert lib.ace_exact_exchange(h, C.byref(g), 4, fake, 0, 0.1, 0, None, None, None) == -1
+    assert lib.ace_exact_exchange(h, C.byref(g), 4, fake, 7, 0.1, 0, fake, None, None) == -1
+    assert lib.ace_exact_exchange(h, C.byref(g), 4, fake, 0, 0.1, 5, fake, None, None) == -1
+    assert lib.ace_exact_exchange(h, C.byref(g), 4, fake, 1, 0.0, 0, fake, None, None) == -1
+    assert lib.ace_exact_exchange(h, C.byref(g7), 4, fake, 0, 0.1, 0, fake, None, None) == -7
     # non-positive box
     gb = ace.Grid.cubic(24, -1.0).c()
     assert lib.ace_apply(h, C.byref(gb), 4, fake, 1, fake, fake) == -1
