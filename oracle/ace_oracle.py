@@ -339,13 +339,31 @@ def scdm_localize(psi: np.ndarray, dV: float):
     Pinned by P5 (Phi invariant under psi -> psi Q, Phi Phi^T = Psi Psi^T,
     disjoint orbitals returned up to order and sign)."""
     n = psi.shape[0]
+    piv, _ = qrcp_pivots(psi.reshape(n, -1))
+    U, phi = lowdin_columns(psi, piv)
+    return piv, U, phi
+
+
+def lowdin_columns(psi: np.ndarray, piv):
+    """The Loewdin step of SCDM (Eq. unit) on given columns C = piv.
+
+    U = A_C (A_C^T A_C)^-1/2 with A_C = A[:, C], A[i, r] = psi_i(r), by a
+    symmetric eigendecomposition; phi_k = sum_i psi_i U_ik.  Any columns with
+    a nonsingular A_C give an orthogonal U, so the columns picked at one MD
+    step can serve the next.  Returns (U, phi).  Pinned by P5 (through
+    scdm_localize) and P10 (A_C = U H with H symmetric positive definite,
+    U orthogonal, Phi Phi^T = Psi Psi^T, ValueError on repeated or
+    out-of-range columns)."""
+    n = psi.shape[0]
     A = psi.reshape(n, -1)
-    piv, _ = qrcp_pivots(A)
+    piv = np.asarray(piv, dtype=np.int64)
+    if piv.shape != (n,) or piv.min() < 0 or piv.max() >= A.shape[1] or len(set(piv.tolist())) != n:
+        raise ValueError("need one distinct in-range grid column per orbital")
     AC = A[:, piv]
     w, V = np.linalg.eigh(AC.T @ AC)
     U = AC @ (V @ np.diag(w ** -0.5) @ V.T)
     phi = (U.T @ A).reshape(psi.shape)
-    return piv, U, phi
+    return U, phi
 
 
 # --------------------------------------------------------------------------

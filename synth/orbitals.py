@@ -19,7 +19,10 @@ locality:
 
 Random draws happen in a fixed order from ``numpy.random.default_rng(seed)``:
 centres, jitter, directions, mixing matrix (and, for the batched systems, the
-Coulomb-kernel choice).
+Coulomb-kernel choice).  Consecutive steps of an MD-like trajectory
+(``md_step``) move every Gaussian centre along a fixed seeded direction and
+keep the mixing matrix, so the orbitals of step t + 1 are a small
+displacement of those of step t.
 
 Grid layout: ``psi[orb, z, y, x]`` (x fastest), FP64, bohr^-3/2.
 """
@@ -54,6 +57,11 @@ class SystemSpec:
     kernel: str = "erfc"  # "bare" or "erfc"
     omega: float = 0.106
     lattice: Optional[tuple] = None
+    #: MD-like trajectory: at step t every Gaussian centre has moved by
+    #: t * md_disp bohr along its own seeded unit direction (drawn from a
+    #: generator of its own, so step 0 is the plain system)
+    md_step: int = 0
+    md_disp: float = 0.05
 
     @property
     def norb(self) -> int:
@@ -223,6 +231,10 @@ def make_orbitals(spec: SystemSpec, device=None) -> OrbitalSet:
     """
     rng = np.random.default_rng(spec.seed)
     mol_centres, gauss_centres = _draw_geometry(spec, rng)
+    if spec.md_step:
+        d = np.random.default_rng([spec.seed, 7919]).normal(size=gauss_centres.shape)
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        gauss_centres = np.mod(gauss_centres + (spec.md_step * spec.md_disp) * d, spec.L)
     q = _haar_orthogonal(rng, spec.norb)
     kernel = spec.kernel
     if spec.kernel == "mixed":

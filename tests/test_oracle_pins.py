@@ -446,3 +446,45 @@ def test_p9_exact_exchange_single_orbital():
     np.testing.assert_allclose(W[0], -vgg * g[0], rtol=0, atol=1e-14 * np.abs(W).max())
     jj = spec.dV * np.sum(g[0] ** 2 * vgg)
     assert M.shape == (1, 1) and abs(ex + jj) < 1e-13 * jj
+
+
+# ----------------------------------------------------------------- P10
+
+def test_p10_lowdin_on_reused_columns():
+    """Pivots of MD step 0 reused at step 1: U is the orthogonal polar factor of
+    A_C (A_C = U H, H symmetric positive definite), Phi is orthonormal and
+    spans the occupied space of step 1, and fresh pivots reproduce SCDM."""
+    s0 = config_spec("c1")
+    psi0 = make_orbitals(s0).psi
+    psi1 = make_orbitals(s0.replace(md_step=1)).psi
+    n = s0.norb
+    piv0, _ = oracle.qrcp_pivots(psi0.reshape(n, -1))
+    U, phi = oracle.lowdin_columns(psi1, piv0)
+    A1 = psi1.reshape(n, -1)
+    AC = A1[:, piv0]
+    H = U.T @ AC
+    np.testing.assert_allclose(U.T @ U, np.eye(n), atol=1e-13)
+    np.testing.assert_allclose(H, H.T, atol=1e-13 * np.abs(H).max())
+    assert np.linalg.eigvalsh(0.5 * (H + H.T)).min() > 0
+    P = phi.reshape(n, -1)
+    np.testing.assert_allclose(P @ P.T * s0.dV, np.eye(n), atol=1e-12)
+    np.testing.assert_allclose(P.T @ P, A1.T @ A1, atol=1e-12 * np.abs(A1.T @ A1).max())
+    # with the step's own pivots it is SCDM itself
+    piv1, U1, phi1 = oracle.scdm_localize(psi1, s0.dV)
+    U1b, phi1b = oracle.lowdin_columns(psi1, piv1)
+    np.testing.assert_array_equal(U1b, U1)
+    # the reused columns still localize: each orbital peaks at its own pivot
+    assert np.all(np.abs(P[np.arange(n), piv0]) >= np.abs(P[:, piv0]).max(axis=0) * (1 - 1e-12))
+
+
+def test_p10_lowdin_rejects_bad_columns():
+    s0 = config_spec("c1")
+    psi = make_orbitals(s0).psi
+    n = s0.norb
+    good = np.arange(n) * 37
+    with pytest.raises(ValueError):
+        oracle.lowdin_columns(psi, np.r_[good[:-1], good[0]])
+    with pytest.raises(ValueError):
+        oracle.lowdin_columns(psi, np.r_[good[:-1], s0.N ** 3])
+    with pytest.raises(ValueError):
+        oracle.lowdin_columns(psi, good[:-1])

@@ -43,3 +43,21 @@ def test_smooth_vectors_normalized():
     s = config_spec("c1")
     x = smooth_test_vectors(s, 4)
     np.testing.assert_allclose((x.reshape(4, -1) ** 2).sum(1) * s.dV, 1.0, rtol=1e-12)
+
+
+def test_md_steps_are_small_displacements():
+    s0 = config_spec("c1")
+    a = make_orbitals(s0)
+    assert make_orbitals(s0.replace(md_step=0)).psi.tobytes() == a.psi.tobytes()
+    b = make_orbitals(s0.replace(md_step=1))
+    c = make_orbitals(s0.replace(md_step=2))
+    n = s0.norb
+    Pa, Pb, Pc = (x.psi.reshape(n, -1) for x in (a, b, c))
+    np.testing.assert_allclose(Pb @ Pb.T * s0.dV, np.eye(n), atol=1e-12)
+    # same mixing matrix, centres moved by 0.05 bohr per step: the occupied
+    # spaces stay close and drift further with every step
+    def gap(P, Q):
+        return n - np.linalg.norm(P @ Q.T * s0.dV) ** 2
+    assert 0 < gap(Pa, Pb) < gap(Pa, Pc) < 0.05 * n
+    d = np.linalg.norm(b.gauss_centres - a.gauss_centres, axis=1)
+    np.testing.assert_allclose(np.minimum(d, s0.L - d), 0.05, rtol=1e-12)
