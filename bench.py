@@ -194,6 +194,38 @@ def form_exact_exchange(ctx, psi, grid, kind, omega, reps=3):
     return out
 
 
+def form_incremental(ctx, psi0, spec, grid, kind, omega, rho_cut, reps=5):
+    """The next MD step (every centre moved 0.05 bohr): fresh SCDM against the
+    Loewdin step on the previous step's columns, then the screened builds."""
+    import dataclasses
+
+    import torch
+
+    from synth import make_orbitals
+
+    _, piv0, _ = ctx.localize(psi0, grid)
+    psi1 = make_orbitals(dataclasses.replace(spec, md_step=1), device="cuda").psi
+    out = {"workload": f"MD step 1 of {spec.norb} orbitals, {spec.N}^3, centres moved {spec.md_disp} bohr"}
+    for name, fn in (("fresh", lambda: ctx.localize(psi1, grid)[0]),
+                     ("reused", lambda: ctx.localize_pivots(psi1, piv0, grid)[0])):
+        phi = fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            phi = fn()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / reps
+        pairs, _ = ctx.pairlist(phi, grid, rho_cut)
+        r = ctx.build(phi, pairs, grid, kernel=kind, omega=omega, want_M=False)
+        out[name] = {"localize_ms": round(ms, 3), "pairs": int(pairs.shape[0]), "ex": float(r["ex"].item())}
+        del phi, pairs, r
+    out["localize_speedup"] = round(out["fresh"]["localize_ms"] / out["reused"]["localize_ms"], 2)
+    out["ex_rel_diff_reused_vs_fresh"] = abs(out["reused"]["ex"] - out["fresh"]["ex"]) / abs(out["fresh"]["ex"])
+    del psi1
+    torch.cuda.empty_cache()
+    return out
+
+
 def form_precision(ctx, log):
     """64 waters (256 orbitals, 120^3): FP32 pair stage vs the plain FP64 path."""
     import torch
@@ -470,6 +502,7 @@ def main():
         torch.cuda.empty_cache()
         forms["apply_energy"] = form_apply_energy(ctx, r["xi"], phi, grid)
         forms["exact_exchange"] = form_exact_exchange(ctx, psi, grid, kind, omega)
+        forms["incremental"] = form_incremental(ctx, psi, spec, grid, kind, omega, args.rho_cut)
         torch.cuda.empty_cache()
         for name, fn in (("precision", lambda: form_precision(ctx, log)), ("batched", lambda: form_batched(ctx, log)),
                          ("learned", lambda: form_learned(ctx, log, args.screener))):

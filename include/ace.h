@@ -98,6 +98,24 @@ int ace_localize(ace_ctx* ctx, const ace_grid* grid, int norb, const double* psi
                  int32_t* pivots, double* U);
 
 /*
+ * (a) on given columns: the Loewdin step of SCDM (Eq. unit) only,
+ *   U = A_C (A_C^T A_C)^-1/2,  A_C = A[:, pivots],  phi_k = sum_i psi_i U_ik,
+ * with no pivot search.  For MD, where the ACE operator is rebuilt every step
+ * and the orbitals move little between steps, the columns ace_localize picked
+ * at the previous step can be reused: any columns with a nonsingular A_C give
+ * an orthonormal phi spanning the same occupied space.
+ *   psi    [norb][N_G] (input)
+ *   pivots [norb] int32 distinct grid indices in [0, N_G), device memory
+ *          (input; copied to the host and checked before any kernel runs)
+ *   phi    [norb][N_G] (output);  U [norb][norb] (output, nullable)
+ * Errors: ACE_E_ARG for a repeated or out-of-range column, ACE_E_NONFINITE
+ * when the polar iteration does not converge (A_C singular or nearly so:
+ * call ace_localize for fresh columns).
+ */
+int ace_localize_pivots(ace_ctx* ctx, const ace_grid* grid, int norb, const double* psi, const int32_t* pivots,
+                        double* phi, double* U);
+
+/*
  * (b) Pair screening (criterion in the SCDM paragraph of Sec. Theory): keep
  * (i, j), i <= j, when  O_ij = dV sum_r |phi_i(r)| |phi_j(r)|  >= rho_cut;
  * diagonal pairs are always kept.

@@ -110,6 +110,7 @@ def load(path: str = LIB_PATH):
         "ace_pairlist": ([P, GP, I, P, D, I64, P, P, C.POINTER(I64)], I),
         "ace_build": ([P, GP, I, P, P, I64, I, D, I, P, P, P, P, P], I),
         "ace_apply": ([P, GP, I, P, I, P, P], I),
+        "ace_localize_pivots": ([P, GP, I, P, P, P, P], I),
         "ace_apply_energy": ([P, GP, I, P, I, P, P, P], I),
         "ace_exact_exchange": ([P, GP, I, P, I, D, I, P, P, P], I),
         "ace_profile_enable": ([P, I], I),
@@ -213,6 +214,21 @@ class Context:
         g = grid.c()
         self._check(self.lib.ace_localize(self.h, C.byref(g), norb, _ptr(psi), _ptr(phi), _ptr(piv), _ptr(U)))
         return phi, piv, U
+
+    def localize_pivots(self, psi, pivots, grid: Grid):
+        """Loewdin step on given columns (e.g. the previous MD step's): returns (phi, U)."""
+        import torch
+
+        _require(psi, torch.float64, "psi")
+        _require(pivots, torch.int32, "pivots")
+        norb = psi.shape[0]
+        phi = torch.empty_like(psi)
+        U = torch.empty(norb, norb, dtype=torch.float64, device=psi.device)
+        self._sync_stream()
+        g = grid.c()
+        self._check(self.lib.ace_localize_pivots(self.h, C.byref(g), norb, _ptr(psi), _ptr(pivots), _ptr(phi),
+                                                 _ptr(U)))
+        return phi, U
 
     def pairlist(self, phi, grid: Grid, rho_cut: float, capacity: Optional[int] = None):
         """Screened pair list: returns (pairs[int32, n x 2], overlap[n])."""

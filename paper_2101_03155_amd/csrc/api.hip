@@ -486,6 +486,49 @@ int ace_get_pair_shape(ace_ctx* c, int prec, int n, int* fused, int* max_packs) 
 }
 
 // ------------------------------------------------------------------ (a) localize
+// Loewdin step on the columns `pivots`: U = A_C (A_C^T A_C)^-1/2 into U
+// (nullable) and phi_k = sum_i psi_i U_ik.  AC, X, G, Z are norb x norb
+// workspaces, dev one double.
+static int lowdin(ace_ctx* c, int norb, int64_t ng, const double* psi, const int32_t* pivots, double* AC, double* X,
+                  double* G, double* Z, double* dev, double* phi, double* U) {
+  hipStream_t s = c->stream;
+  // Loewdin rotation U = A_C (A_C^T A_C)^-1/2 = polar factor of A_C,
+  // by the Newton-Schulz iteration X <- X (3 I - X^T X) / 2 from X = A_C/|A_C|_F.
+  launch_gather_cols(psi, norb, ng, pivots, AC, s);
+  HIPCHK(c, hipMemcpyAsync(X, AC, size_t(norb) * norb * sizeof(double), hipMemcpyDeviceToDevice, s));
+  launch_scale_frob(X, int64_t(norb) * norb, s);
+  // Convergence is read back every 4 iterations; once max|X^T X - I| < 1e-11
+  // two more iterations take the quadratically converging iterate to rounding.
+  int converged_at = -1, it = 0;
+  while (it < 200) {
+    for (int j = 0; j < 4; ++j, ++it) {
+      HIPCHK(c, gemm_ls(0, true, false, X, norb, X, norb, G, norb, norb, norb, norb, 1.0, s, nullptr));
+      HIPCHK(c, gemm_ls(0, false, false, X, norb, G, norb, Z, norb, norb, norb, norb, 1.0, s, nullptr));
+      launch_ns_combine(X, Z, X, int64_t(norb) * norb, s);
+    }
+    HIPCHK(c, gemm_ls(0, true, false, X, norb, X, norb, G, norb, norb, norb, norb, 1.0, s, nullptr));
+    launch_dev_identity(G, norb, dev, s);
+    double h = 0.0;
+    HIPCHK(c, hipMemcpyAsync(&h, dev, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    if (!std::isfinite(h)) return fail(c, ACE_E_NONFINITE, "non-finite Loewdin iteration (singular A_C?)");
+    if (h < 1e-11) {
+      converged_at = it;
+      break;
+    }
+  }
+  if (converged_at < 0) return fail(c, ACE_E_NONFINITE, "Loewdin polar iteration did not converge");
+  for (int j = 0; j < 2; ++j) {
+    HIPCHK(c, gemm_ls(0, true, false, X, norb, X, norb, G, norb, norb, norb, norb, 1.0, s, nullptr));
+    HIPCHK(c, gemm_ls(0, false, false, X, norb, G, norb, Z, norb, norb, norb, norb, 1.0, s, nullptr));
+    launch_ns_combine(X, Z, X, int64_t(norb) * norb, s);
+  }
+  // phi_k = sum_i psi_i U_ik
+  HIPCHK(c, gemm_ls(0, true, false, X, norb, psi, ng, phi, ng, norb, norb, ng, 1.0, s, c->R()));
+  if (U) HIPCHK(c, hipMemcpyAsync(U, X, size_t(norb) * norb * sizeof(double), hipMemcpyDeviceToDevice, s));
+  return ACE_OK;
+}
+
 int ace_localize(ace_ctx* c, const ace_grid* g, int norb, const double* psi, double* phi, int32_t* pivots,
                  double* U) {
   if (!c) return ACE_E_ARG;
@@ -637,40 +680,41 @@ int ace_localize(ace_ctx* c, const ace_grid* g, int norb, const double* psi, dou
     k = hk[0];
   }
   HIPCHK(c, hipGetLastError());
-  // Loewdin rotation U = A_C (A_C^T A_C)^-1/2 = polar factor of A_C,
-  // by the Newton-Schulz iteration X <- X (3 I - X^T X) / 2 from X = A_C/|A_C|_F.
-  launch_gather_cols(psi, norb, ng, pivots, AC, s);
-  HIPCHK(c, hipMemcpyAsync(X, AC, size_t(norb) * norb * sizeof(double), hipMemcpyDeviceToDevice, s));
-  launch_scale_frob(X, int64_t(norb) * norb, s);
-  // Convergence is read back every 4 iterations; once max|X^T X - I| < 1e-11
-  // two more iterations take the quadratically converging iterate to rounding.
-  int converged_at = -1, it = 0;
-  while (it < 200) {
-    for (int j = 0; j < 4; ++j, ++it) {
-      HIPCHK(c, gemm_ls(0, true, false, X, norb, X, norb, G, norb, norb, norb, norb, 1.0, s, nullptr));
-      HIPCHK(c, gemm_ls(0, false, false, X, norb, G, norb, Z, norb, norb, norb, norb, 1.0, s, nullptr));
-      launch_ns_combine(X, Z, X, int64_t(norb) * norb, s);
-    }
-    HIPCHK(c, gemm_ls(0, true, false, X, norb, X, norb, G, norb, norb, norb, norb, 1.0, s, nullptr));
-    launch_dev_identity(G, norb, dev, s);
-    double h = 0.0;
-    HIPCHK(c, hipMemcpyAsync(&h, dev, sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
-    if (!std::isfinite(h)) return fail(c, ACE_E_NONFINITE, "non-finite Loewdin iteration (singular A_C?)");
-    if (h < 1e-11) {
-      converged_at = it;
-      break;
-    }
-  }
-  if (converged_at < 0) return fail(c, ACE_E_NONFINITE, "Loewdin polar iteration did not converge");
-  for (int j = 0; j < 2; ++j) {
-    HIPCHK(c, gemm_ls(0, true, false, X, norb, X, norb, G, norb, norb, norb, norb, 1.0, s, nullptr));
-    HIPCHK(c, gemm_ls(0, false, false, X, norb, G, norb, Z, norb, norb, norb, norb, 1.0, s, nullptr));
-    launch_ns_combine(X, Z, X, int64_t(norb) * norb, s);
-  }
-  // phi_k = sum_i psi_i U_ik
-  HIPCHK(c, gemm_ls(0, true, false, X, norb, psi, ng, phi, ng, norb, norb, ng, 1.0, s, c->R()));
-  if (U) HIPCHK(c, hipMemcpyAsync(U, X, size_t(norb) * norb * sizeof(double), hipMemcpyDeviceToDevice, s));
+  rc = lowdin(c, norb, ng, psi, pivots, AC, X, G, Z, dev, phi, U);
+  if (rc) return rc;
+  rec_end(c->R(), ST_LOCALIZE, s);
+  HIPCHK(c, hipGetLastError());
+  return ACE_OK;
+}
+
+int ace_localize_pivots(ace_ctx* c, const ace_grid* g, int norb, const double* psi, const int32_t* pivots,
+                        double* phi, double* U) {
+  if (!c) return ACE_E_ARG;
+  int rc = check_grid(c, g, norb);
+  if (rc) return rc;
+  if (!psi || !phi || !pivots) return fail(c, ACE_E_ARG, "psi, phi and pivots must be non-NULL");
+  const int64_t ng = grid_size(g);
+  if (ng < norb) return fail(c, ACE_E_ARG, "grid smaller than the number of orbitals");
+  hipStream_t s = c->stream;
+  // the columns are read by a gather kernel: check them on the host first
+  std::vector<int32_t> hp(static_cast<size_t>(norb));
+  HIPCHK(c, hipMemcpyAsync(hp.data(), pivots, size_t(norb) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  std::vector<int32_t> sorted(hp);
+  std::sort(sorted.begin(), sorted.end());
+  if (sorted.front() < 0 || int64_t(sorted.back()) >= ng)
+    return fail(c, ACE_E_ARG, "pivot outside [0, %lld)", (long long)ng);
+  if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+    return fail(c, ACE_E_ARG, "repeated pivot column");
+  rec_begin(c->R(), ST_LOCALIZE, s);
+  double *AC, *X, *G, *Z, *dev;
+  WS(c, "AC", size_t(norb) * norb * sizeof(double), AC);
+  WS(c, "X", size_t(norb) * norb * sizeof(double), X);
+  WS(c, "G", size_t(norb) * norb * sizeof(double), G);
+  WS(c, "Z", size_t(norb) * norb * sizeof(double), Z);
+  WS(c, "scal", 64 * sizeof(double), dev);
+  rc = lowdin(c, norb, ng, psi, pivots, AC, X, G, Z, dev, phi, U);
+  if (rc) return rc;
   rec_end(c->R(), ST_LOCALIZE, s);
   HIPCHK(c, hipGetLastError());
   return ACE_OK;

@@ -56,6 +56,11 @@ def test_argument_validation(ctx):
     n = C.c_int64()
     assert lib.ace_pairlist(h, C.byref(g), 4, fake, 1e-3, -1, fake, None, C.byref(n)) == -1
     assert lib.ace_apply(h, C.byref(g), 4, fake, 0, fake, fake) == -1
+    # localization on given columns: NULL arguments and bad grids fail before any device call
+    assert lib.ace_localize_pivots(h, C.byref(g), 4, fake, None, fake, None) == -1
+    assert lib.ace_localize_pivots(h, C.byref(g), 4, None, fake, fake, None) == -1
+    assert lib.ace_localize_pivots(h, C.byref(g), 0, fake, fake, fake, None) == -1
+    assert lib.ace_localize_pivots(h, C.byref(g7), 4, fake, fake, fake, None) == -7
     # fused application: energy output required, nvec >= 1
     assert lib.ace_apply_energy(h, C.byref(g), 4, fake, 1, fake, fake, None) == -1
     assert lib.ace_apply_energy(h, C.byref(g), 4, fake, 0, fake, fake, fake) == -1

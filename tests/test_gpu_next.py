@@ -130,3 +130,57 @@ def test_exact_exchange_full_size_sampled_rows(ctx):
     assert np.abs(M - M.T).max() == 0.0
     b = ctx.build(o.psi, _dev(full), g, kernel=s.kernel, omega=s.omega)
     assert abs(r["ex"].item() - b["ex"].item()) <= 1e-12 * abs(b["ex"].item())
+
+
+# ------------------------------------------------------------------ localization on reused columns
+
+def test_localize_pivots_reused_across_md_step(ctx):
+    """Columns of MD step 0 (picked by the oracle) reused at step 1, c1 system."""
+    s0 = config_spec("c1")
+    s1 = s0.replace(md_step=1)
+    psi0 = make_orbitals(s0).psi
+    psi1 = make_orbitals(s1).psi
+    piv0, _ = oracle.qrcp_pivots(psi0.reshape(s0.norb, -1))
+    _say("localize_pivots c1 md step 1")
+    g = _grid(s0.N, s0.L)
+    phi, U = ctx.localize_pivots(_dev(psi1), _dev(piv0.astype(np.int32)), g)
+    U_ref, phi_ref = oracle.lowdin_columns(psi1, piv0)
+    np.testing.assert_allclose(U.cpu().numpy(), U_ref, atol=1e-12)
+    assert _maxdiff(phi.cpu().numpy(), phi_ref) < 1e-12
+    # with the step's own columns it is the full localization
+    phi_f, piv_f, U_f = ctx.localize(_dev(psi1), g)
+    phi_p, U_p = ctx.localize_pivots(_dev(psi1), piv_f, g)
+    assert torch.equal(phi_p, phi_f) and torch.equal(U_p, U_f)
+
+
+def test_localize_pivots_rejects_bad_columns(ctx):
+    """Checked on the host before any kernel reads the columns."""
+    from paper_2101_03155_amd.ace import AceError
+
+    s0 = config_spec("c1")
+    psi_np = make_orbitals(s0).psi
+    psi = _dev(psi_np)
+    g = _grid(s0.N, s0.L)
+    good = oracle.qrcp_pivots(psi_np.reshape(s0.norb, -1))[0].astype(np.int32)
+    _say("localize_pivots bad columns")
+    for bad in (np.r_[good[:-1], good[0]], np.r_[good[:-1], s0.N ** 3], np.r_[good[:-1], -1]):
+        with pytest.raises(AceError):
+            ctx.localize_pivots(psi, _dev(bad.astype(np.int32)), g)
+    phi, _ = ctx.localize_pivots(psi, _dev(good), g)
+    assert torch.isfinite(phi).all()
+
+
+def test_localize_pivots_full_size(ctx):
+    """32 waters (128 orbitals, 96^3): step-0 columns reused at step 1, every element."""
+    s0 = config_spec("c2")
+    s1 = s0.replace(md_step=1)
+    psi0 = make_orbitals(s0).psi
+    piv0, _ = oracle.qrcp_pivots(psi0.reshape(s0.norb, -1))
+    del psi0
+    psi1 = make_orbitals(s1).psi
+    _say("localize_pivots full size md step 1")
+    g = _grid(s0.N, s0.L)
+    phi, U = ctx.localize_pivots(_dev(psi1), _dev(piv0.astype(np.int32)), g)
+    U_ref, phi_ref = oracle.lowdin_columns(psi1, piv0)
+    np.testing.assert_allclose(U.cpu().numpy(), U_ref, atol=1e-11)
+    assert _maxdiff(phi.cpu().numpy(), phi_ref) < 1e-10
