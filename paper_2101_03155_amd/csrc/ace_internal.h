@@ -155,7 +155,7 @@ void launch_pool_gather(const double* A, int n, int64_t ng, const int32_t* pool,
 void launch_refresh_res(const double* L, int k, int64_t rc, const double* norm0, double* res, hipStream_t s);
 void launch_retire(const int32_t* piv, int k, double* res, hipStream_t s);
 void launch_gather_cols(const double* A, int n, int64_t ng, const int32_t* piv, double* AC, hipStream_t s);
-void launch_scale_frob(double* X, int64_t cnt, hipStream_t s);
+void launch_scale_inf(double* X, const double* G, int n, hipStream_t s);
 void launch_ns_combine(const double* X, const double* Z, double* Y, int64_t cnt, hipStream_t s);
 void launch_dev_identity(const double* G, int n, double* out, hipStream_t s);
 void launch_compact_pairs(const double* O, int n, double rho_cut, int64_t cap, int32_t* pairs, double* ov,

@@ -492,34 +492,37 @@ int ace_get_pair_shape(ace_ctx* c, int prec, int n, int* fused, int* max_packs) 
 static int lowdin(ace_ctx* c, int norb, int64_t ng, const double* psi, const int32_t* pivots, double* AC, double* X,
                   double* G, double* Z, double* dev, double* phi, double* U) {
   hipStream_t s = c->stream;
-  // Loewdin rotation U = A_C (A_C^T A_C)^-1/2 = polar factor of A_C,
-  // by the Newton-Schulz iteration X <- X (3 I - X^T X) / 2 from X = A_C/|A_C|_F.
+  // Loewdin rotation U = A_C (A_C^T A_C)^-1/2 = polar factor of A_C, by the
+  // Newton-Schulz iteration X <- X (3 I - X^T X) / 2 from X = A_C scaled so
+  // that every singular value is at most 1 (max row sum of |A_C^T A_C|).
   launch_gather_cols(psi, norb, ng, pivots, AC, s);
   HIPCHK(c, hipMemcpyAsync(X, AC, size_t(norb) * norb * sizeof(double), hipMemcpyDeviceToDevice, s));
-  launch_scale_frob(X, int64_t(norb) * norb, s);
-  // Convergence is read back every 4 iterations; once max|X^T X - I| < 1e-11
-  // two more iterations take the quadratically converging iterate to rounding.
-  int converged_at = -1, it = 0;
-  while (it < 200) {
-    for (int j = 0; j < 4; ++j, ++it) {
-      HIPCHK(c, gemm_ls(0, true, false, X, norb, X, norb, G, norb, norb, norb, norb, 1.0, s, nullptr));
-      HIPCHK(c, gemm_ls(0, false, false, X, norb, G, norb, Z, norb, norb, norb, norb, 1.0, s, nullptr));
-      launch_ns_combine(X, Z, X, int64_t(norb) * norb, s);
-    }
+  HIPCHK(c, gemm_ls(0, true, false, X, norb, X, norb, G, norb, norb, norb, norb, 1.0, s, nullptr));
+  launch_scale_inf(X, G, norb, s);
+  // Each iteration forms G = X^T X, which also measures max|X^T X - I|; it is
+  // read back every second iteration from the fourth on.  Once below 1e-11,
+  // two more iterations (the first reusing that G) take the quadratically
+  // converging iterate to rounding.
+  int converged_at = -1;
+  for (int it = 0; it < 200; ++it) {
     HIPCHK(c, gemm_ls(0, true, false, X, norb, X, norb, G, norb, norb, norb, norb, 1.0, s, nullptr));
-    launch_dev_identity(G, norb, dev, s);
-    double h = 0.0;
-    HIPCHK(c, hipMemcpyAsync(&h, dev, sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
-    if (!std::isfinite(h)) return fail(c, ACE_E_NONFINITE, "non-finite Loewdin iteration (singular A_C?)");
-    if (h < 1e-11) {
-      converged_at = it;
-      break;
+    if (it >= 4 && it % 2 == 0) {
+      launch_dev_identity(G, norb, dev, s);
+      double h = 0.0;
+      HIPCHK(c, hipMemcpyAsync(&h, dev, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipStreamSynchronize(s));
+      if (!std::isfinite(h)) return fail(c, ACE_E_NONFINITE, "non-finite Loewdin iteration (singular A_C?)");
+      if (h < 1e-11) {
+        converged_at = it;
+        break;
+      }
     }
+    HIPCHK(c, gemm_ls(0, false, false, X, norb, G, norb, Z, norb, norb, norb, norb, 1.0, s, nullptr));
+    launch_ns_combine(X, Z, X, int64_t(norb) * norb, s);
   }
   if (converged_at < 0) return fail(c, ACE_E_NONFINITE, "Loewdin polar iteration did not converge");
   for (int j = 0; j < 2; ++j) {
-    HIPCHK(c, gemm_ls(0, true, false, X, norb, X, norb, G, norb, norb, norb, norb, 1.0, s, nullptr));
+    if (j > 0) HIPCHK(c, gemm_ls(0, true, false, X, norb, X, norb, G, norb, norb, norb, norb, 1.0, s, nullptr));
     HIPCHK(c, gemm_ls(0, false, false, X, norb, G, norb, Z, norb, norb, norb, norb, 1.0, s, nullptr));
     launch_ns_combine(X, Z, X, int64_t(norb) * norb, s);
   }

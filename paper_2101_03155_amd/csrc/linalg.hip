@@ -975,18 +975,26 @@ __global__ void k_gather_cols(const double* __restrict__ A, int n, int64_t ng, c
 
 // ---------------------------------------------------------------- Newton-Schulz helpers
 // X <- alpha * X (scale by 1/||X||_F computed in one workgroup)
-__global__ void k_scale_frob(double* __restrict__ X, int64_t cnt) {
+// X <- X / sqrt(max_i sum_j |G_ij|) with G = X^T X (n x n): the largest
+// absolute row sum of G bounds its largest eigenvalue, so every singular
+// value of the scaled X is at most 1 (the Newton-Schulz polar iteration then
+// converges from any nonsingular start).  One block.
+__global__ void k_scale_inf(double* __restrict__ X, const double* __restrict__ G, int n) {
   __shared__ double red[1024];
-  double s = 0.0;
-  for (int64_t e = threadIdx.x; e < cnt; e += blockDim.x) s += X[e] * X[e];
-  red[threadIdx.x] = s;
+  double m = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double r = 0.0;
+    for (int j = 0; j < n; ++j) r += fabs(G[int64_t(i) * n + j]);
+    m = fmax(m, r);
+  }
+  red[threadIdx.x] = m;
   __syncthreads();
   for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    if (threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
     __syncthreads();
   }
   const double inv = 1.0 / sqrt(red[0]);
-  for (int64_t e = threadIdx.x; e < cnt; e += blockDim.x) X[e] *= inv;
+  for (int64_t e = threadIdx.x; e < int64_t(n) * n; e += blockDim.x) X[e] *= inv;
 }
 
 // Y <- 1.5 X - 0.5 Z ; also dev = max |G - I| where G = X^T X (given)
@@ -1202,8 +1210,8 @@ void launch_retire(const int32_t* piv, int k, double* res, hipStream_t s) {
 void launch_gather_cols(const double* A, int n, int64_t ng, const int32_t* piv, double* AC, hipStream_t s) {
   hipLaunchKernelGGL(k_gather_cols, dim3(grid_for(int64_t(n) * n, 256)), dim3(256), 0, s, A, n, ng, piv, AC);
 }
-void launch_scale_frob(double* X, int64_t cnt, hipStream_t s) {
-  hipLaunchKernelGGL(k_scale_frob, dim3(1), dim3(1024), 0, s, X, cnt);
+void launch_scale_inf(double* X, const double* G, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_inf, dim3(1), dim3(1024), 0, s, X, G, n);
 }
 void launch_ns_combine(const double* X, const double* Z, double* Y, int64_t cnt, hipStream_t s) {
   hipLaunchKernelGGL(k_ns_combine, dim3(grid_for(cnt, 256)), dim3(256), 0, s, X, Z, Y, cnt);
