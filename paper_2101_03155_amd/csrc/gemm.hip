@@ -278,17 +278,20 @@ template <int NW> __host__ __device__ constexpr int tile_per() { return 2048 / t
 // four per SIMD (capped at 128 registers).
 template <int NW> __host__ __device__ constexpr int tile_waves() { return NW == 2 ? 2 : 4; }
 
-template <typename TX, bool KM, int OP, int NW = 2>
+// Loads stay in the operand's own type: the conversion to double and the
+// element map are applied by tile_store, after the current step's MFMAs, so
+// the next step's loads remain in flight meanwhile.
+template <typename TX, bool KM, int NW = 2>
 __device__ __forceinline__ void tile_load(const TX* __restrict__ X, int64_t ld, int r0, int rows, int64_t k0,
-                                          int64_t ke, int tid, double (&v)[tile_per<NW>()]) {
+                                          int64_t ke, int tid, TX (&v)[tile_per<NW>()]) {
 #pragma unroll
   for (int i = 0; i < tile_per<NW>(); ++i) {
     int r, k;
     tile_rk<KM>(tid + tile_threads<NW>() * i, r, k);
     const int64_t kk = k0 + k;
-    double x = 0.0;
-    if (r0 + r < rows && kk < ke) x = double(KM ? X[kk * ld + r0 + r] : X[int64_t(r0 + r) * ld + kk]);
-    v[i] = opmap<OP>(x);
+    TX x = TX(0);
+    if (r0 + r < rows && kk < ke) x = KM ? X[kk * ld + r0 + r] : X[int64_t(r0 + r) * ld + kk];
+    v[i] = x;
   }
 }
 
@@ -300,14 +303,14 @@ __device__ __forceinline__ void tile_load(const TX* __restrict__ X, int64_t ld, 
 constexpr int RP = KS + 1;
 static_assert(TT * RP <= KS * TP, "a row-major tile must fit a k-major tile's buffer");
 
-template <bool KM, int NW = 2>
-__device__ __forceinline__ void tile_store(double* S, int tid, const double (&v)[tile_per<NW>()]) {
+template <bool KM, int OP, int NW, typename TX>
+__device__ __forceinline__ void tile_store(double* S, int tid, const TX (&v)[tile_per<NW>()]) {
   if constexpr (!KM) {
 #pragma unroll
     for (int i = 0; i < tile_per<NW>(); ++i) {
       int r, k;
       tile_rk<false>(tid + tile_threads<NW>() * i, r, k);
-      S[r * RP + k] = v[i];
+      S[r * RP + k] = opmap<OP>(double(v[i]));
     }
     return;
   }
@@ -315,7 +318,7 @@ __device__ __forceinline__ void tile_store(double* S, int tid, const double (&v)
   for (int i = 0; i < tile_per<NW>(); ++i) {
     int r, k;
     tile_rk<KM>(tid + tile_threads<NW>() * i, r, k);
-    S[k * TP + r] = v[i];
+    S[k * TP + r] = opmap<OP>(double(v[i]));
   }
 }
 
@@ -336,20 +339,21 @@ __device__ __forceinline__ void tile_mma(const TA* __restrict__ A, int64_t lda, 
   // others stay zero, so their MFMAs are skipped; wave-uniform)
   const int ib = min(4, max(0, (M - m0 - wm * 64 + 15) / 16));
   const int jb = min(JB, max(0, (Nn - n0 - wn * WC + 15) / 16));
-  double va[PER], vb[PER];
+  TA va[PER];
+  TB vb[PER];
   int buf = 0;
   if (kb < ke) {
-    tile_load<TA, AK, OP, NW>(A, lda, m0, M, kb, ke, tid, va);
-    tile_load<TB, BK, OP, NW>(B, ldb, n0, Nn, kb, ke, tid, vb);
-    tile_store<AK, NW>(As, tid, va);
-    tile_store<BK, NW>(Bs, tid, vb);
+    tile_load<TA, AK, NW>(A, lda, m0, M, kb, ke, tid, va);
+    tile_load<TB, BK, NW>(B, ldb, n0, Nn, kb, ke, tid, vb);
+    tile_store<AK, OP, NW>(As, tid, va);
+    tile_store<BK, OP, NW>(Bs, tid, vb);
   }
   __syncthreads();
   for (int64_t k0 = kb; k0 < ke; k0 += KS) {
     const bool more = k0 + KS < ke;
     if (more) {
-      tile_load<TA, AK, OP, NW>(A, lda, m0, M, k0 + KS, ke, tid, va);
-      tile_load<TB, BK, OP, NW>(B, ldb, n0, Nn, k0 + KS, ke, tid, vb);
+      tile_load<TA, AK, NW>(A, lda, m0, M, k0 + KS, ke, tid, va);
+      tile_load<TB, BK, NW>(B, ldb, n0, Nn, k0 + KS, ke, tid, vb);
     }
     const double* as = As + buf * KS * TP;
     const double* bs = Bs + buf * KS * TP;
@@ -370,8 +374,8 @@ __device__ __forceinline__ void tile_mma(const TA* __restrict__ A, int64_t lda, 
     }
     if (more) {
       buf ^= 1;
-      tile_store<AK, NW>(As + buf * KS * TP, tid, va);
-      tile_store<BK, NW>(Bs + buf * KS * TP, tid, vb);
+      tile_store<AK, OP, NW>(As + buf * KS * TP, tid, va);
+      tile_store<BK, OP, NW>(Bs + buf * KS * TP, tid, vb);
     }
     __syncthreads();
   }
