@@ -322,6 +322,16 @@ __device__ __forceinline__ void tile_store(double* S, int tid, const TX (&v)[til
   }
 }
 
+// First row, within the 128-row tile, of 16-row block i of row wave wm.
+// With a lower-triangular left factor (IL) the two row waves take alternate
+// blocks (0, 2, 4, 6 and 1, 3, 5, 7): block b needs k < 16 (b + 1), and
+// alternating balances the two waves' MFMAs in every K step, where
+// contiguous halves leave the upper wave idle for the second half of K.
+template <bool IL>
+__device__ __forceinline__ int rowblk(int wm, int i) {
+  return IL ? (2 * i + wm) * 16 : wm * 64 + i * 16;
+}
+
 // Accumulate the tile over [kb, ke) into acc: each of the 2 x NW waves owns
 // 64 rows x (128 / NW) columns, JB = 8 / NW blocks of 16 columns.  With NW = 4
 // (512 threads) a wave holds half the accumulators, so four waves fit per
@@ -337,7 +347,6 @@ __device__ __forceinline__ void tile_mma(const TA* __restrict__ A, int64_t lda, 
   const int wm = wv / NW, wn = wv % NW;
   // 16 x 16 blocks of this wave that hold rows < M and columns < Nn (the
   // others stay zero, so their MFMAs are skipped; wave-uniform)
-  const int ib = min(4, max(0, (M - m0 - wm * 64 + 15) / 16));
   const int jb = min(JB, max(0, (Nn - n0 - wn * WC + 15) / 16));
   TA va[PER];
   TB vb[PER];
@@ -362,14 +371,15 @@ __device__ __forceinline__ void tile_mma(const TA* __restrict__ A, int64_t lda, 
       const int kq = kk + lane / 16, kr = kq * TP, li = lane % 16;
       double a[4], b[JB];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = AK ? as[kr + wm * 64 + i * 16 + li] : as[(wm * 64 + i * 16 + li) * RP + kq];
+      for (int i = 0; i < 4; ++i)
+        a[i] = AK ? as[kr + rowblk<LOWA>(wm, i) + li] : as[(rowblk<LOWA>(wm, i) + li) * RP + kq];
 #pragma unroll
       for (int j = 0; j < JB; ++j) b[j] = BK ? bs[kr + wn * WC + j * 16 + li] : bs[(wn * WC + j * 16 + li) * RP + kq];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < JB; ++j)
-          if (i < ib && j < jb && (!LOWA || k0 + kk < int64_t(m0) + wm * 64 + i * 16 + 16))
+          if (m0 + rowblk<LOWA>(wm, i) < M && j < jb && (!LOWA || k0 + kk < int64_t(m0) + rowblk<LOWA>(wm, i) + 16))
             acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     if (more) {
@@ -382,7 +392,7 @@ __device__ __forceinline__ void tile_mma(const TA* __restrict__ A, int64_t lda, 
 }
 
 // acc -> out[m][n] (ld) for rows < M, columns < Nn, times alpha
-template <int NW = 2>
+template <int NW = 2, bool IL = false>
 __device__ __forceinline__ void tile_write(const d4 (&acc)[4][8 / NW], int m0, int M, int64_t n0, int64_t Nn,
                                            double* __restrict__ out, int64_t ld, double alpha) {
   constexpr int JB = 8 / NW, WC = 128 / NW;
@@ -394,7 +404,7 @@ __device__ __forceinline__ void tile_write(const d4 (&acc)[4][8 / NW], int m0, i
     for (int j = 0; j < JB; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm * 64 + i * 16 + lane / 16 + 4 * r;
+        const int m = m0 + rowblk<IL>(wm, i) + lane / 16 + 4 * r;
         const int64_t n = n0 + wn * WC + j * 16 + lane % 16;
         if (m < M && n < Nn) out[int64_t(m) * ld + n] = alpha * acc[i][j][r];
       }
@@ -619,7 +629,7 @@ __global__ __launch_bounds__(tile_threads<NW>(), tile_waves<NW>()) void k_gemm_l
   const int64_t rrem = R - r0;
   tile_mma<double, TB, TRANS, true, 0, LOWER, NW>(S, lds, Bt, ldb, m0, M, 0, int(rrem < TT ? rrem : TT), 0, ke, As,
                                                  Bs, acc);
-  tile_write<NW>(acc, m0, M, 0, rrem < TT ? rrem : TT, C + r0, ldc, alpha);
+  tile_write<NW, LOWER>(acc, m0, M, 0, rrem < TT ? rrem : TT, C + r0, ldc, alpha);
 }
 
 // Bound refresh of the pivot search in one pass: for the 128 grid columns of
