@@ -184,3 +184,23 @@ def test_localize_pivots_full_size(ctx):
     U_ref, phi_ref = oracle.lowdin_columns(psi1, piv0)
     np.testing.assert_allclose(U.cpu().numpy(), U_ref, atol=1e-11)
     assert _maxdiff(phi.cpu().numpy(), phi_ref) < 1e-10
+
+
+def test_single_orbital_edge_cases(ctx):
+    """One orbital: exact exchange is its self-exchange (one pair), and the
+    Loewdin step on its single column returns it up to sign."""
+    from synth import disjoint_gaussians
+
+    spec = SystemSpec(n_mol=1, L=7.0, N=16, sigma=0.8, seed=5)
+    g1 = disjoint_gaussians(spec, [(3.0, 3.5, 2.0)])
+    grid = _grid(spec.N, spec.L)
+    _say("single orbital exact exchange and localize_pivots")
+    r = ctx.exact_exchange(_dev(g1), grid, kernel="erfc", omega=0.4)
+    W_ref, M_ref, ex_ref = oracle.exact_exchange(g1, spec.N, spec.L, "erfc", 0.4)
+    assert _maxdiff(r["W"].cpu().numpy(), W_ref) < 1e-10
+    assert abs(r["ex"].item() - ex_ref) <= 1e-10 * abs(ex_ref)
+    piv = np.array([int(np.argmax(np.abs(g1[0]).ravel()))], dtype=np.int32)
+    phi, U = ctx.localize_pivots(_dev(g1), _dev(piv), grid)
+    U_ref, phi_ref = oracle.lowdin_columns(g1, piv)
+    assert abs(U.item() - U_ref[0, 0]) <= 1e-15 and abs(U_ref[0, 0]) == 1.0
+    assert _maxdiff(phi.cpu().numpy(), phi_ref) < 1e-14
