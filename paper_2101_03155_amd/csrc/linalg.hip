@@ -57,38 +57,56 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ A, int n
                                                    double* __restrict__ Tinv, int* __restrict__ info) {
   __shared__ double D[CB][CB + 1];
   __shared__ double X[CB][CB + 1];
+  __shared__ double col[2][CB];
   if (*info) return;
   const int b = (n - k0 < CB) ? n - k0 : CB;
   const int tid = threadIdx.x;
-  // thread (tr, tc) owns rows 4 tr .. 4 tr + 3 and columns 4 tc .. 4 tc + 3
+  // thread (tr, tc) owns rows 4 tr .. 4 tr + 3 and columns 4 tc .. 4 tc + 3,
+  // kept in registers during the elimination
   const int r0 = (tid >> 4) * 4, c0 = (tid & 15) * 4;
+  double v[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = r0 + a, j = c0 + q;
-      D[i][j] = (i < b && j <= i) ? A[int64_t(k0 + i) * n + k0 + j] : 0.0;
+      v[a][q] = (i < b && j <= i) ? A[int64_t(k0 + i) * n + k0 + j] : 0.0;
     }
-  __syncthreads();
-  // a_ij -= a_ik a_jk / a_kk on unscaled columns: one barrier per column
+  // a_ij -= a_ik a_jk / a_kk on unscaled columns.  Column k is published by
+  // the threads that own it to an LDS vector (two alternating buffers, so one
+  // barrier per column suffices); every element sees the same updates in the
+  // same order as an in-place elimination.
   int bad = 0;
   for (int k = 0; k < b; ++k) {
-    const double d = D[k][k];
+    double* ck = col[k & 1];
+    if ((tid & 15) == (k >> 2)) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (q == (k & 3)) ck[r0 + a] = v[a][q];
+    }
+    __syncthreads();
+    const double d = ck[k];
     if (!isfinite(d)) { bad = -(k0 + k + 1); break; }
     if (!(d > 0.0)) { bad = k0 + k + 1; break; }
     const double inv = 1.0 / d;
     double li[4], lj[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) { li[a] = D[r0 + a][k] * inv; lj[a] = D[c0 + a][k]; }
+    for (int a = 0; a < 4; ++a) { li[a] = ck[r0 + a] * inv; lj[a] = ck[c0 + a]; }
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int i = r0 + a, j = c0 + q;
-        if (j > k && j <= i) D[i][j] -= li[a] * lj[q];
+        if (j > k && j <= i) v[a][q] -= li[a] * lj[q];
       }
-    __syncthreads();
   }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) D[r0 + a][c0 + q] = v[a][q];
+  __syncthreads();
   if (bad) {
     if (tid == 0) *info = bad;
     return;
@@ -108,9 +126,11 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ A, int n
     for (int q = 0; q < 4; ++q) D[r0 + a][c0 + q] = X[r0 + a][c0 + q];
   __syncthreads();
   // inverse by rows: X[i][c] = (delta_ic - sum_{c <= k < i} L[i][k] X[k][c]) / L[i][i],
-  // four lanes per column c, combined with shuffles
+  // four lanes per column c, combined with shuffles.  Only the panel below
+  // the block reads it, so the last block skips it (uniform over the block).
+  const bool last = k0 + b >= n;
   const int c = tid >> 2, part = tid & 3;
-  for (int i = 0; i < b; ++i) {
+  for (int i = 0; i < (last ? 0 : b); ++i) {
     double acc = 0.0;
     if (c < i)
       for (int k = c + part; k < i; k += 4) acc += D[i][k] * X[k][c];
@@ -122,7 +142,7 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ A, int n
   for (int e = tid; e < b * b; e += 256) {
     const int i = e / b, j = e % b;
     A[int64_t(k0 + i) * n + k0 + j] = D[i][j];
-    Tinv[i * CB + j] = X[i][j];
+    if (!last) Tinv[i * CB + j] = X[i][j];
   }
   // the strict upper triangle right of the block
   for (int e = tid; e < b * (n - k0 - b); e += 256) {
