@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--no-oracle-check", action="store_true")
     ap.add_argument("--screener", default=os.path.join(ROOT, "paper_2101_03155_amd", "models",
                                                        "screener_water_erfc.npz"))
-    ap.add_argument("--skip-forms", default="", help="comma list of precision,batched,learned")
+    ap.add_argument("--skip-forms", default="", help="comma list of precision,batched,learned,learned_batched")
     ap.add_argument("--shape", default="owner", choices=["auto", "default", "fused", "split", "r2c", "owner"],
                     help="pair-stage launch shape: autotuned, library default, or forced (default: owner, the "
                          "fastest measured for this workload, fixed so that profiles and the bench line agree)")
@@ -74,11 +74,11 @@ def pair_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, N, prec, units_per_launch):
-    """HBM bytes per launch from the committed counter summary: FETCH_SIZE and
-    WRITE_SIZE per dispatch, each scaled by what the counter reads for a plain
-    1 GiB copy, expressed per algorithmic byte and applied to this launch size.
-    None when no summary matches or the kernel source changed since."""
+def counter_row(kernel, N, prec):
+    """The committed counter summary's row for a kernel at this size and
+    precision: FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the
+    counter reads for a plain 1 GiB copy, per algorithmic byte.  (None, why)
+    when no row matches or the pair-stage sources changed since."""
     import re
 
     if not os.path.exists(COUNTERS_FILE):
@@ -86,14 +86,20 @@ def measured_traffic(kernel, N, prec, units_per_launch):
     m = re.search(r"```json\n(.*?)\n```", open(COUNTERS_FILE).read(), re.S)
     if not m:
         return None, "no counter summary"
-    rows = json.loads(m.group(1))
-    for r in rows:
+    for r in json.loads(m.group(1)):
         if r["kernel"] == kernel and r["N"] == N and r["precision"] == prec:
             if r["source_hash"] != pair_source_hash():
                 return None, "pair-stage sources changed since the counters were taken"
-            return r["traffic_per_algorithmic_byte"] * units_per_launch, "FETCH_SIZE x %.3g + WRITE_SIZE x %.3g" % (
-                r["fetch_scale"], r["write_scale"])
+            return r, "FETCH_SIZE x %.3g + WRITE_SIZE x %.3g" % (r["fetch_scale"], r["write_scale"])
     return None, "no counter row for this kernel"
+
+
+def measured_traffic(kernel, N, prec, units_per_launch):
+    """HBM bytes per launch from the counter summary, applied to this launch size."""
+    r, note = counter_row(kernel, N, prec)
+    if r is None:
+        return None, note
+    return r["traffic_per_algorithmic_byte"] * units_per_launch, note
 
 
 def copy_probe():
@@ -107,32 +113,67 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes": a.numel() * 8, "copies": 3, "source_hash": pair_source_hash()}), flush=True)
 
 
-def cpu_baseline(o, pairs_np, kind, omega, sample_pairs=1000):
-    """The FP64 oracle, single-threaded, on a bounded sample of the same step."""
-    import numpy as np
+def host_workers():
+    """Host threads the oracle may use: the cores this process may run on,
+    capped by OMP_NUM_THREADS when the environment sets it."""
+    n = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def cpu_baseline(o, kind, omega, rho_cut):
+    """The FP64 oracle on the host cores, the whole step of the bench: SCDM,
+    pair screening, every kept pair solve, M, Cholesky and the projectors.
+    Returns the baseline record and the oracle's results (for parity)."""
     from threadpoolctl import threadpool_limits
 
     import oracle
 
     s = o.spec
-    with threadpool_limits(limits=1):
+    workers = host_workers()
+    with threadpool_limits(limits=workers):
         t0 = time.perf_counter()
-        _, _, phi = oracle.scdm_localize(o.psi, s.dV)
+        piv, _, phi = oracle.scdm_localize(o.psi, s.dV)
         t1 = time.perf_counter()
-        oracle.pairlist(phi, s.dV, 1e-3)
+        pairs, _ = oracle.pairlist(phi, s.dV, rho_cut)
         t2 = time.perf_counter()
         v = oracle.coulomb_kernel(s.N, s.L, kind, omega)
-        sub = pairs_np[np.linspace(0, len(pairs_np) - 1, sample_pairs).astype(int)]
-        oracle.build_W(phi, sub, v, s.dV)
+        W, e = oracle.build_W(phi, pairs, v, s.dV, energies=True, workers=workers)
         t3 = time.perf_counter()
-    per_pair = (t3 - t2) / len(sub)
-    t_step = (t1 - t0) + (t2 - t1) + per_pair * len(pairs_np)
-    return {
-        "value": 1.0 / t_step, "unit": "builds/s", "cores": 1, "kind": "oracle",
-        "sample": (f"full SCDM + pair screening, then {len(sub)} of {len(pairs_np)} kept pair solves "
-                   f"(extrapolated; M/Cholesky tail omitted); oracle pair solves/s = {1.0 / per_pair:.2f}"),
-        "seconds": round(t3 - t0, 2),
+        M, _, xi, ex, _ = oracle.ace_from_W(phi, W, s.dV)
+        t4 = time.perf_counter()
+    rec = {
+        "value": 1.0 / (t4 - t0), "unit": "builds/s", "cores": workers, "kind": "oracle",
+        "sample": (f"one whole step (not a sample): SCDM of {s.norb} orbitals on {s.N}^3, screening at "
+                   f"rho_cut={rho_cut}, all {len(pairs)} kept pair solves on {workers} threads, M, Cholesky and xi"),
+        "seconds": round(t4 - t0, 2),
+        "stage_s": {"localize": round(t1 - t0, 3), "pairlist": round(t2 - t1, 3), "pair_stage": round(t3 - t2, 3),
+                    "tail": round(t4 - t3, 3)},
+        "pair_solves_per_s": round(len(pairs) / (t3 - t2), 2),
     }
+    return rec, dict(piv=piv, phi=phi, pairs=pairs, W=W, e=e, M=M, xi=xi, ex=ex)
+
+
+def parity_vs_oracle(ctx, grid, kind, omega, prec, gpu_piv, gpu_pairs, ref):
+    """The bench step's outputs against the oracle's whole step: pivots and
+    pair list exactly, then a build on the oracle's orbitals element by element."""
+    import numpy as np
+    import torch
+
+    out = {"pivots_equal": bool(np.array_equal(gpu_piv, ref["piv"])),
+           "pairs_equal": bool(np.array_equal(gpu_pairs, ref["pairs"]))}
+    phi = torch.as_tensor(ref["phi"], device="cuda")
+    pairs = torch.as_tensor(ref["pairs"].astype(np.int32), device="cuda")
+    r = ctx.build(phi, pairs, grid, kernel=kind, omega=omega, precision=prec, want_M=True, want_W=True)
+    W = r["W"].cpu().numpy()
+    out["ex_rel_err"] = abs(float(r["ex"].item()) - ref["ex"]) / abs(ref["ex"])
+    out["W_max_elem_err_rel"] = float(np.abs(W - ref["W"]).max() / np.abs(ref["W"]).max())
+    out["M_max_abs_err_ha"] = float(np.abs(r["M"].cpu().numpy() - ref["M"]).max())
+    xi = r["xi"].cpu().numpy()
+    out["xi_max_elem_err_rel"] = float(np.abs(xi - ref["xi"]).max() / np.abs(ref["xi"]).max())
+    return out
 
 
 def _timed(fn, reps=3, warm=True):
@@ -226,12 +267,16 @@ def form_incremental(ctx, psi0, spec, grid, kind, omega, rho_cut, reps=5):
     return out
 
 
-def form_precision(ctx, log):
-    """64 waters (256 orbitals, 120^3): FP32 pair stage vs the plain FP64 path."""
+def form_precision(ctx, log, with_oracle=True):
+    """64 waters (256 orbitals, 120^3): FP32 pair stage vs the plain FP64 path,
+    and both against the FP64 oracle's build of the screened list: E_x, every
+    element of W and M, and the ACE matrix elements over the orbitals and 16
+    smooth test vectors."""
+    import numpy as np
     import torch
 
     from paper_2101_03155_amd import Grid
-    from synth import config_spec, make_orbitals
+    from synth import config_spec, make_orbitals, smooth_test_vectors
 
     spec = config_spec("c3")
     o = make_orbitals(spec, device="cuda")
@@ -256,6 +301,39 @@ def form_precision(ctx, log):
                      "fp32_pair_solves_per_s": round(pl.shape[0] / ms32 * 1000, 1),
                      "ex_fp64": e64, "ex_rel_err_fp32_vs_fp64": abs(e32 - e64) / abs(e64)}
         log(f"precision form {name}: {out[name]}")
+        del r64, r32
+    del full
+    torch.cuda.empty_cache()
+    if with_oracle:
+        import oracle
+
+        t0 = time.perf_counter()
+        phi_np = phi.cpu().numpy()
+        pairs_np = pairs.cpu().numpy().astype(np.int64)
+        ref = oracle.ace_build(phi_np, pairs_np, spec.N, spec.L, "erfc", spec.omega, workers=host_workers())
+        vecs = np.concatenate([phi_np, smooth_test_vectors(spec, 16)])
+        A = vecs.reshape(len(vecs), -1)
+        mel_ref = spec.dV * A @ oracle.ace_apply(ref["xi"], vecs, spec.dV).reshape(len(A), -1).T
+        vd = torch.as_tensor(vecs, device="cuda")
+        err = {"reference": (f"FP64 oracle build of the screened list ({len(pairs_np)} pairs) on the same orbitals, "
+                             f"{host_workers()} host threads, {time.perf_counter() - t0:.1f} s"),
+               "ace_matrix_elements": "<a|V_ACE|b> over the 256 orbitals and 16 smooth test vectors"}
+        for p in ("fp64", "fp32"):
+            r = ctx.build(phi, pairs, g, kernel="erfc", omega=spec.omega, precision=p, want_M=True, want_W=True)
+            W = r["W"].cpu().numpy()
+            w_err = float(np.abs(W - ref["W"]).max() / np.abs(ref["W"]).max())
+            w_fro = float(np.linalg.norm(W - ref["W"]) / np.linalg.norm(ref["W"]))
+            del W
+            y = ctx.apply(r["xi"], vd, g)
+            mel = (vd.reshape(len(A), -1) @ y.reshape(len(A), -1).T).cpu().numpy() * spec.dV
+            err[p] = {"ex_rel_err": abs(r["ex"].item() - ref["ex"]) / abs(ref["ex"]),
+                      "M_max_abs_err_ha": float(np.abs(r["M"].cpu().numpy() - ref["M"]).max()),
+                      "ace_matrix_elements_max_abs_err_ha": float(np.abs(mel - mel_ref).max()),
+                      "W_max_elem_err_rel": w_err, "W_frobenius_rel_err": w_fro}
+            del r, y
+            torch.cuda.empty_cache()
+        out["vs_oracle_fp64"] = err
+        log(f"precision form vs oracle: {err}")
     return out
 
 
@@ -301,6 +379,75 @@ def form_batched(ctx, log):
     return out
 
 
+def form_learned_batched(ctx, log, model_path, mode="graph"):
+    """The learned-screened FP32 batched build against the plain FP64
+    full-pair builds of the same 16 systems (8-64 molecules, 48^3-96^3):
+    builds/s of each and the E_x error of every learned build against its
+    full-pair FP64 build, within the budget of 1e-5 Ha per molecule."""
+    import torch
+
+    from paper_2101_03155_amd import Grid
+    from paper_2101_03155_amd.screener import LearnedScreener
+    from synth import batched_specs, make_orbitals
+
+    if not os.path.exists(model_path):
+        return {"skipped": f"no screener checkpoint at {model_path}"}
+    scr = LearnedScreener.load(model_path)
+    specs = batched_specs()
+    systems, fulls, loc_ms, sel_ms, fallbacks = [], [], 0.0, 0.0, 0
+    for sp in specs:
+        o = make_orbitals(sp, device="cuda")
+        g = Grid.cubic(sp.N, sp.L)
+        ms, (phi, _, _) = _timed(lambda: ctx.localize(o.psi, g), 1)
+        loc_ms += ms
+        del o
+        ms, (pl, fb) = _timed(lambda: scr.select(ctx, phi, g, sp.n_mol), 1)
+        sel_ms += ms
+        fallbacks += int(fb)
+        n = phi.shape[0]
+        systems.append(dict(phi=phi, pairs=pl, grid=g, kernel=sp.kernel, omega=sp.omega,
+                            xi=torch.empty_like(phi), M=torch.empty(n, n, dtype=torch.float64, device="cuda"),
+                            ex=torch.empty(1, dtype=torch.float64, device="cuda")))
+        fulls.append(torch.tensor([(i, j) for i in range(n) for j in range(i, n)], dtype=torch.int32, device="cuda"))
+    torch.cuda.empty_cache()
+    ms_b, res = _timed(lambda: ctx.build_batched(systems, precision="fp32", mode=mode), 3)
+    ex_l = [float(r["ex"].item()) for r in res]
+
+    def full_builds():
+        out = []
+        for sy, fp in zip(systems, fulls):
+            r = ctx.build(sy["phi"], fp, sy["grid"], kernel=sy["kernel"], omega=sy["omega"], precision="fp64",
+                          want_M=False)
+            out.append(float(r["ex"].item()))
+            del r
+        return out
+
+    ms_full, ex_f = _timed(full_builds, 1)
+    errs = [abs(a - b) for a, b in zip(ex_l, ex_f)]
+    budgets = [1e-5 * sp.n_mol for sp in specs]
+    npairs = sum(int(sy["pairs"].shape[0]) for sy in systems)
+    nfull = sum(int(f.shape[0]) for f in fulls)
+    out = {"workload": "16 systems, 8-64 molecules, 48^3-96^3, mixed bare/erfc; learned screener, FP32 batched "
+                       f"build ({mode} mode) vs FP64 full-pair single builds",
+           "pairs_learned": npairs, "pairs_full": nfull, "used_fallback": fallbacks,
+           "learned_fp32_batched": {"ms": round(ms_b, 2), "builds_per_s": round(16 / ms_b * 1000, 2),
+                                    "builds_per_s_with_localize_and_selection":
+                                        round(16 / (ms_b + loc_ms + sel_ms) * 1000, 2),
+                                    "localize_ms": round(loc_ms, 2), "selection_ms": round(sel_ms, 2)},
+           "full_fp64": {"ms": round(ms_full, 2), "builds_per_s": round(16 / ms_full * 1000, 3),
+                         "builds_per_s_with_localize": round(16 / (ms_full + loc_ms) * 1000, 3)},
+           "max_abs_err_vs_full_fp64_ha": max(errs),
+           "all_within_budget": all(e <= b for e, b in zip(errs, budgets)),
+           "per_system": [{"n_mol": sp.n_mol, "N": sp.N, "kernel": sp.kernel, "pairs": int(sy["pairs"].shape[0]),
+                           "pairs_full": int(f.shape[0]), "abs_err_ha": e, "budget_ha": b}
+                          for sp, sy, f, e, b in zip(specs, systems, fulls, errs, budgets)]}
+    out["speedup_vs_full_fp64"] = round(ms_full / ms_b, 2)
+    log(f"learned batched: {ms_b:.1f} ms vs full fp64 {ms_full:.1f} ms, max |dE| {max(errs):.2e}")
+    del systems, fulls, res
+    torch.cuda.empty_cache()
+    return out
+
+
 def form_learned(ctx, log, model_path):
     """128 waters (512 orbitals, 160^3): learned vs threshold vs full-pair builds."""
     import torch
@@ -315,6 +462,7 @@ def form_learned(ctx, log, model_path):
     spec = config_spec("c5")
     o = make_orbitals(spec, device="cuda")
     g = Grid.cubic(spec.N, spec.L)
+    ctx.localize(o.psi, g)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     phi, _, _ = ctx.localize(o.psi, g)
@@ -336,12 +484,14 @@ def form_learned(ctx, log, model_path):
            "full_fp64": {"pairs": int(full.shape[0]), "build_ms": round(ms_full, 1),
                          "builds_per_s": round(1000 / ms_full, 4), "ex": ex_full},
            "screener_train": {k: v for k, v in scr.meta.items() if k != "loss_curve"}}
+    out["full_fp64"]["builds_per_s_with_localize"] = round(1000 / (ms_full + ms_loc), 4)
     for name, pl_, sel_ms in (("learned_fp32", pl, ms_sel), ("threshold_fp32", pt, ms_thr_sel)):
         ms_b, r = _timed(lambda: ctx.build(phi, pl_, g, kernel="erfc", omega=spec.omega, precision="fp32",
                                            want_M=False), 2)
         err = abs(r["ex"].item() - ex_full)
         out[name] = {"pairs": int(pl_.shape[0]), "select_ms": round(sel_ms, 2), "build_ms": round(ms_b, 1),
-                     "builds_per_s": round(1000 / (ms_b + sel_ms), 3), "ex": r["ex"].item(),
+                     "builds_per_s": round(1000 / (ms_loc + sel_ms + ms_b), 3),
+                     "builds_per_s_without_localize": round(1000 / (ms_b + sel_ms), 3), "ex": r["ex"].item(),
                      "abs_err_vs_full_fp64": err, "within_budget": err <= budget}
         log(f"learned form {name}: {out[name]}")
     return out
@@ -374,7 +524,7 @@ def main():
         phi, piv, _ = ctx.localize(psi, grid)
         pairs, _ = ctx.pairlist(phi, grid, args.rho_cut)
         r = ctx.build(phi, pairs, grid, kernel=kind, omega=omega, precision=prec, want_M=False)
-        return phi, pairs, r
+        return phi, piv, pairs, r
 
     tuned = None
     if args.shape == "auto":
@@ -402,7 +552,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        phi, pairs, r = step()
+        phi, piv, pairs, r = step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = {c: ctx.profile_read(c, reset=True) for c in range(15)}
@@ -443,6 +593,35 @@ def main():
                      else (None, "not an HBM-bound class"))
     roof["traffic"] = round(traffic) if traffic is not None else None
     roof["traffic_note"] = note
+    if traffic is not None:
+        roof["frac_counter"] = round(traffic / (ms_l / max(n_l, 1) / 1000.0) / 1e9 / peak, 4)
+    # the whole pair stage: the 12 N^3 s bytes per pair of the read-modify-write
+    # design (two FFT round trips, phi read twice, W read and written), and the
+    # counter bytes of its kernels, both over the stage's event time
+    s_bytes = 8 if prec == "fp64" else 4
+    st_ms = stage_ms["pair_stage"]
+    per_pair = 12 * spec.N ** 3 * s_bytes
+    stage = {"bytes_per_pair_12N3s": per_pair, "ms": round(st_ms, 3),
+             "achieved_12N3s": round(per_pair * npairs / (st_ms / 1000.0) / 1e9, 1)}
+    stage["frac_12N3s"] = round(stage["achieved_12N3s"] / HBM_PEAK_GBS, 4)
+    pair_classes = [c for c in range(7) if prof[c][0]]
+    t_bytes, missing = 0.0, []
+    for c in pair_classes:
+        kn = CLASS_KERNEL[c] + ("_r" if shape[0] in ("r2c", "owner") and c < 3 else "")
+        if shape[0] == "owner" and c == 2:
+            kn = "k_inv_owner_r"
+        row, why = counter_row(kn, spec.N, prec)
+        if row is None:
+            missing.append(f"{kn}: {why}")
+        else:
+            t_bytes += row["traffic_per_algorithmic_byte"] * prof[c][2] / args.steps
+    if not missing and pair_classes:
+        stage["counter_bytes_per_step"] = round(t_bytes)
+        stage["frac_counter"] = round(t_bytes / (st_ms / 1000.0) / 1e9 / HBM_PEAK_GBS, 4)
+    else:
+        stage["counter_bytes_per_step"] = None
+        stage["counter_note"] = "; ".join(missing)
+    roof["stage"] = stage
     kernels = {CLASS_NAMES[c]: {"steps": 2 if c in (7, 8, 9) else args.steps, "launches": prof[c][0],
                                 "ms": round(prof[c][1], 3),
                                 "rate": (round(prof[c][2] / (prof[c][1] / 1000.0) / (1e12 if c in (7, 8) else 1e9), 2)
@@ -467,13 +646,21 @@ def main():
     }
 
     pairs_np = pairs.cpu().numpy().astype(np.int64)
-    phi_np = None
-    if not args.no_oracle_check:
+    piv_np = piv.cpu().numpy()
+    oracle_ref = None
+    if not args.no_cpu_baseline:
+        # the oracle's whole step on the host cores (rank 0, one GPU): the CPU
+        # baseline, and the reference of the step's parity figures
+        out["cpu_baseline"], oracle_ref = cpu_baseline(o, kind, omega, args.rho_cut)
+        out["parity_vs_oracle"] = parity_vs_oracle(ctx, grid, kind, omega, prec, piv_np, pairs_np, oracle_ref)
+        out["ex_rel_err_vs_oracle_fp64"] = abs(ex - oracle_ref["ex"]) / abs(oracle_ref["ex"])
+        del oracle_ref
+    elif not args.no_oracle_check:
         import oracle
 
         phi_np = phi.cpu().numpy()
         v = oracle.coulomb_kernel(spec.N, spec.L, kind, omega)
-        e_ref = oracle.exchange_energy_pairs(phi_np, pairs_np, v, spec.dV)
+        e_ref = oracle.exchange_energy_pairs(phi_np, pairs_np, v, spec.dV, workers=host_workers())
         out["ex_rel_err_vs_oracle_fp64"] = abs(ex - e_ref.sum()) / abs(e_ref.sum())
 
     if not args.no_forms:
@@ -505,8 +692,10 @@ def main():
         forms["incremental"] = form_incremental(ctx, psi, spec, grid, kind, omega, args.rho_cut)
         torch.cuda.empty_cache()
         for name, fn in (("precision", lambda: form_precision(ctx, log)), ("batched", lambda: form_batched(ctx, log)),
-                         ("learned", lambda: form_learned(ctx, log, args.screener))):
-            if name in args.skip_forms:
+                         ("learned", lambda: form_learned(ctx, log, args.screener)),
+                         ("learned_batched", lambda: form_learned_batched(
+                             ctx, log, args.screener, forms.get("batched", {}).get("tuned", {}).get("mode", "graph")))):
+            if name in args.skip_forms.split(","):
                 continue
             ctx.release_workspace()  # each form starts from an empty device workspace
             torch.cuda.empty_cache()
@@ -517,8 +706,6 @@ def main():
             torch.cuda.empty_cache()
         out["forms"] = forms
 
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(o, pairs_np, kind, omega)
     print(json.dumps(out), flush=True)
 
 

@@ -38,6 +38,18 @@ def _rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
+def _elem_err(a, ref):
+    """max |a - ref| over every element, relative to max |ref|."""
+    a, ref = np.asarray(a), np.asarray(ref)
+    return float(np.abs(a - ref).max() / np.abs(ref).max())
+
+
+def _close(a, ref, tol, what=""):
+    err = _elem_err(a, ref)
+    print(f"  {what}: max elementwise err {err:.3e} (tol {tol:.0e})", flush=True)
+    assert err <= tol, f"{what}: {err:.3e} > {tol:.0e}"
+
+
 # ------------------------------------------------------------------ GEMMs via apply
 
 @pytest.mark.parametrize("norb,nvec,n", [(5, 3, 8), (70, 66, 12), (130, 1, 16)])
@@ -50,7 +62,7 @@ def test_apply_matches_oracle_ragged(ctx, norb, nvec, n):
     g = Grid.cubic(n, 6.0)
     y = ctx.apply(_dev(xi), _dev(x), g).cpu().numpy()
     ref = oracle.ace_apply(xi, x, g.dV)
-    assert _rel(y, ref) < 1e-13
+    _close(y, ref, 1e-13, "V_ACE x")
 
 
 # ------------------------------------------------------------------ c1 end to end
@@ -104,9 +116,9 @@ def test_build_c1_full_fp64(ctx, c1, which):
                   want_energies=True)
     ex = float(r["ex"].item())
     assert abs(ex - ref["ex"]) <= 1e-12 * abs(ref["ex"])
-    assert _rel(r["W"].cpu().numpy(), ref["W"]) < 1e-12
+    _close(r["W"].cpu().numpy(), ref["W"], 1e-12, "W")
     np.testing.assert_allclose(r["M"].cpu().numpy(), ref["M"], atol=1e-12 * np.abs(ref["M"]).max())
-    assert _rel(r["xi"].cpu().numpy(), ref["xi"]) < 1e-11
+    _close(r["xi"].cpu().numpy(), ref["xi"], 1e-11, "xi")
     np.testing.assert_allclose(r["e"].cpu().numpy(), ref["e"], atol=1e-13 * np.abs(ref["e"]).max())
 
 
@@ -125,7 +137,7 @@ def test_ace_matrix_elements_c1(ctx, c1):
     mref = s.dV * A @ yref.reshape(len(vecs), -1).T
     assert np.abs(mel - mref).max() <= 1e-10
     # V_ACE phi = W on the occupied space
-    assert _rel(y[: s.norb], ref["W"]) < 1e-11
+    _close(y[: s.norb], ref["W"], 1e-11, "V_ACE phi vs W")
 
 
 def test_split_path_matches_fused(ctx, c1):
@@ -139,7 +151,7 @@ def test_split_path_matches_fused(ctx, c1):
         b = ctx.build(_dev(phi), pairs, _grid(s), kernel="bare", want_W=True)
     finally:
         ctx.set_pair_shape("fp64", s.N, True, 64)
-    assert _rel(b["W"].cpu().numpy(), a["W"].cpu().numpy()) < 1e-13
+    _close(b["W"].cpu().numpy(), a["W"].cpu().numpy(), 1e-13, "split vs fused W")
     assert abs(b["ex"].item() - a["ex"].item()) < 1e-13 * abs(a["ex"].item())
 
 
@@ -162,8 +174,9 @@ def test_fp32_c1(ctx, c1):
     ref = oracle.ace_build(phi, pairs, s.N, s.L, "bare", 0.1)
     r = ctx.build(_dev(phi), _dev(pairs), _grid(s), kernel="bare", precision="fp32", want_W=True)
     assert abs(r["ex"].item() - ref["ex"]) <= 1e-6 * abs(ref["ex"])
-    assert _rel(r["W"].cpu().numpy(), ref["W"]) < 1e-5
+    _close(r["W"].cpu().numpy(), ref["W"], 2e-5, "fp32 W")
     np.testing.assert_allclose(r["M"].cpu().numpy(), ref["M"], atol=1e-5)
+    _close(r["xi"].cpu().numpy(), ref["xi"], 1e-4, "fp32 xi")
 
 
 def test_not_positive_definite_reported(ctx, c1):
@@ -193,49 +206,72 @@ def test_bad_pairs_rejected(ctx, c1):
 # ------------------------------------------------------------------ other grid sizes, ragged lists
 
 SIZE_CASES = [(8, "erfc", "fp64"), (12, "bare", "fp64"), (16, "erfc", "fp64"), (32, "erfc", "fp64"),
-              (48, "bare", "fp64"), (16, "erfc", "fp32"), (48, "erfc", "fp32")]
+              (48, "bare", "fp64"), (16, "erfc", "fp32"), (48, "erfc", "fp32"),
+              # the grids of the batched workload, the screener's training sets and the
+              # 64- and 128-water systems
+              (64, "erfc", "fp64"), (64, "bare", "fp32"), (80, "erfc", "fp64"), (80, "erfc", "fp32"),
+              (100, "erfc", "fp64"), (100, "erfc", "fp32"), (108, "erfc", "fp64"), (108, "erfc", "fp32"),
+              (120, "erfc", "fp64"), (120, "erfc", "fp32"), (160, "erfc", "fp64"), (160, "erfc", "fp32")]
+
+_SIZE_REF = {}
+
+
+def _size_case(n, kind):
+    """Inputs and oracle build of one size case (shared by paths and precisions)."""
+    if (n, kind) not in _SIZE_REF:
+        L = n * 0.3 if n <= 48 else 14.4 + 0.05 * n
+        spec = SystemSpec(n_mol=3 if n <= 48 else 2, L=L, N=n, sigma=0.7, offset=0.6, placement="uniform",
+                          seed=40 + n, kernel=kind, omega=0.4)
+        o = make_orbitals(spec)
+        rng = np.random.default_rng(n)
+        full = _full_pairs(spec.norb)
+        keep = (full[:, 0] == full[:, 1]) | (rng.random(len(full)) < 0.55)
+        pairs = full[keep]
+        if len(pairs) % 2 == 0:
+            pairs = pairs[:-1] if pairs[-1, 0] != pairs[-1, 1] else pairs
+        v = oracle.coulomb_kernel(n, L, kind, 0.4)
+        ref_W, ref_e = oracle.build_W(o.psi, pairs, v, spec.dV, energies=True, workers=8)
+        try:
+            ref_M, _, ref_xi, ref_ex, _ = oracle.ace_from_W(o.psi, ref_W, spec.dV)
+        except oracle.NotPositiveDefinite:
+            ref_M = ref_xi = ref_ex = None
+        _SIZE_REF.clear()  # keep one case resident (160^3 arrays are large)
+        _SIZE_REF[(n, kind)] = dict(spec=spec, psi=o.psi, pairs=pairs, W=ref_W, e=ref_e, M=ref_M, xi=ref_xi,
+                                    ex=ref_ex)
+    return _SIZE_REF[(n, kind)]
 
 
 @pytest.mark.parametrize("path", ["fused", "r2c", "split", "owner"])
 @pytest.mark.parametrize("n,kind,prec", SIZE_CASES)
 def test_sizes_and_screened_lists(ctx, n, kind, prec, path):
     _say(f"sizes N={n} {kind} {prec} path={path}")
-    L = n * 0.3
-    spec = SystemSpec(n_mol=3, L=L, N=n, sigma=0.7, offset=0.6, placement="uniform", seed=40 + n,
-                      kernel=kind, omega=0.4)
-    o = make_orbitals(spec)
-    rng = np.random.default_rng(n)
-    full = _full_pairs(spec.norb)
-    keep = (full[:, 0] == full[:, 1]) | (rng.random(len(full)) < 0.55)
-    pairs = full[keep]
-    if len(pairs) % 2 == 0:
-        pairs = pairs[:-1] if pairs[-1, 0] != pairs[-1, 1] else pairs
-    v = oracle.coulomb_kernel(n, L, kind, 0.4)
-    ref_W, ref_e = oracle.build_W(o.psi, pairs, v, spec.dV, energies=True)
-    try:
-        _, _, ref_xi, ref_ex, _ = oracle.ace_from_W(o.psi, ref_W, spec.dV)
-        pd = True
-    except oracle.NotPositiveDefinite:
-        pd = False
+    c = _size_case(n, kind)
+    spec, pairs = c["spec"], c["pairs"]
     from paper_2101_03155_amd import AceError
     saved = ctx.get_pair_shape(prec, n)
     ctx.set_pair_shape(prec, n, path, 3)
-    assert ctx.get_pair_shape(prec, n)[0] == path
+    ran = ctx.get_pair_shape(prec, n)[0]
     try:
-        if not pd:
+        if ran != path:
+            # the library runs the split passes where this path's plane does not fit in LDS
+            assert ran == "split"
+            pytest.skip(f"{path} does not fit at N={n} {prec}; the split path runs (tested on its own)")
+        if c["ex"] is None:
             with pytest.raises(AceError) as ei:
-                ctx.build(_dev(o.psi), _dev(pairs), _grid(spec), kernel=kind, omega=0.4, precision=prec)
+                ctx.build(_dev(c["psi"]), _dev(pairs), _grid(spec), kernel=kind, omega=0.4, precision=prec)
             assert ei.value.status == "ACE_E_NOT_PD"
             return
-        r = ctx.build(_dev(o.psi), _dev(pairs), _grid(spec), kernel=kind, omega=0.4, precision=prec,
+        r = ctx.build(_dev(c["psi"]), _dev(pairs), _grid(spec), kernel=kind, omega=0.4, precision=prec,
                       want_W=True, want_energies=True)
     finally:
         ctx.set_pair_shape(prec, n, *saved)
-    tol = 1e-12 if prec == "fp64" else 2e-5
-    assert _rel(r["W"].cpu().numpy(), ref_W) < tol
-    np.testing.assert_allclose(r["e"].cpu().numpy(), ref_e, atol=tol * np.abs(ref_e).max())
-    assert abs(r["ex"].item() - ref_ex) <= (1e-10 if prec == "fp64" else 1e-6) * abs(ref_ex)
-    assert _rel(r["xi"].cpu().numpy(), ref_xi) < (1e-10 if prec == "fp64" else 1e-4)
+    f64 = prec == "fp64"
+    _close(r["W"].cpu().numpy(), c["W"], 1e-12 if f64 else 2e-5, "W")
+    _close(r["e"].cpu().numpy(), c["e"], 1e-12 if f64 else 2e-5, "pair energies")
+    np.testing.assert_allclose(r["M"].cpu().numpy(), c["M"], rtol=0,
+                               atol=(1e-12 if f64 else 1e-6) * np.abs(c["M"]).max())
+    assert abs(r["ex"].item() - c["ex"]) <= (1e-10 if f64 else 1e-6) * abs(c["ex"])
+    _close(r["xi"].cpu().numpy(), c["xi"], 1e-10 if f64 else 1e-4, "xi")
 
 
 # ------------------------------------------------------------------ c2 (128 orbitals, 96^3)
@@ -262,12 +298,18 @@ def test_c2_localize_and_pairlist(ctx, c2):
     np.testing.assert_allclose(gov.cpu().numpy(), c2["ov"], rtol=1e-12)
 
 
+def _workers():
+    import os
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
 def _c2_screened_ref(c2):
-    if "e_ref" not in c2:
+    """The oracle's whole screened build (every row of W, M, L, xi, e)."""
+    if "ref" not in c2:
         s = c2["s"]
-        c2["e_ref"] = oracle.exchange_energy_pairs(c2["phi"], c2["pairs"], c2["v"], s.dV)
-        c2["W_rows"] = oracle.build_W_rows(c2["phi"], c2["pairs"], [5, 77], c2["v"])
-    return c2["e_ref"], c2["W_rows"]
+        _say(f"c2 oracle screened build, {len(c2['pairs'])} pairs on {_workers()} threads")
+        c2["ref"] = oracle.ace_build(c2["phi"], c2["pairs"], s.N, s.L, "erfc", s.omega, workers=_workers())
+    return c2["ref"]
 
 
 @pytest.mark.parametrize("path", ["split", "fused", "r2c", "owner"])
@@ -283,23 +325,27 @@ def test_c2_screened_build(ctx, c2, prec, path):
                       precision=prec, want_W=True, want_energies=True)
     finally:
         ctx.set_pair_shape(prec, s.N, *saved)
-    e_ref, Wref = _c2_screened_ref(c2)
-    ex_ref = e_ref.sum()
-    tol = 1e-10 if prec == "fp64" else 1e-6
-    assert abs(r["ex"].item() - ex_ref) <= tol * abs(ex_ref)
-    np.testing.assert_allclose(r["e"].cpu().numpy(), e_ref, atol=(1e-12 if prec == "fp64" else 1e-7))
-    rows = [5, 77]
-    Wg = r["W"][rows].cpu().numpy()
-    assert _rel(Wg, Wref) < (1e-12 if prec == "fp64" else 1e-5)
-    # M columns of the sampled rows: M_kl = dV <phi_k | W_l>
-    Mref = s.dV * phi.reshape(s.norb, -1) @ Wref.reshape(len(rows), -1).T
-    Mraw = r["M"].cpu().numpy()
-    # M is returned symmetrized; compare the symmetric part on sampled entries
-    for a, l in enumerate(rows):
-        for k in rows:
-            b = rows.index(k)
-            sym = 0.5 * (Mref[k, a] + Mref[l, b])
-            assert abs(Mraw[k, l] - sym) <= (1e-11 if prec == "fp64" else 1e-5)
+    ref = _c2_screened_ref(c2)
+    f64 = prec == "fp64"
+    assert abs(r["ex"].item() - ref["ex"]) <= (1e-10 if f64 else 1e-6) * abs(ref["ex"])
+    np.testing.assert_allclose(r["e"].cpu().numpy(), ref["e"], rtol=0, atol=(1e-12 if f64 else 1e-7))
+    # every element of W, M and xi against the oracle's build
+    _close(r["W"].cpu().numpy(), ref["W"], 1e-12 if f64 else 2e-5, "W (all rows)")
+    dM = np.abs(r["M"].cpu().numpy() - ref["M"]).max()
+    print(f"  M: max |dM| {dM:.3e} Ha", flush=True)
+    assert dM <= (1e-11 if f64 else 1e-5)
+    _close(r["xi"].cpu().numpy(), ref["xi"], 1e-10 if f64 else 1e-4, "xi (all rows)")
+    # ACE matrix elements <a|V_ACE|b> over {phi_i} and 16 smooth test vectors
+    if "vecs" not in c2:
+        c2["vecs"] = np.concatenate([phi, smooth_test_vectors(s, 16)])
+        A = c2["vecs"].reshape(len(c2["vecs"]), -1)
+        c2["mel_ref"] = s.dV * A @ oracle.ace_apply(ref["xi"], c2["vecs"], s.dV).reshape(len(A), -1).T
+    vecs = c2["vecs"]
+    y = ctx.apply(r["xi"], _dev(vecs), _grid(s)).cpu().numpy()
+    mel = s.dV * vecs.reshape(len(vecs), -1) @ y.reshape(len(vecs), -1).T
+    dmel = np.abs(mel - c2["mel_ref"]).max()
+    print(f"  ACE matrix elements: max |d<a|V|b>| {dmel:.3e} Ha", flush=True)
+    assert dmel <= (1e-10 if f64 else 1e-5)
 
 
 def test_c2_full_pair_energy(ctx, c2):
@@ -317,8 +363,8 @@ def test_c2_full_pair_energy(ctx, c2):
     assert abs((rs["ex"].item() - r["ex"].item()) + dropped) < 1e-9 * abs(e_ref.sum())
     # ACE matrix elements <phi_k|V_ACE|phi_l> for a sampled l against the oracle's
     # <phi_k|V_X|phi_l> = dV <phi_k|W_l> (full list: V_ACE = V_X on the occupied space)
-    rows = [31]
-    Wref = oracle.build_W_rows(phi, pairs, rows, c2["v"])
+    rows = [0, 31, 127]
+    Wref = oracle.build_W_rows(phi, pairs, rows, c2["v"], workers=_workers())
     mref = s.dV * phi.reshape(s.norb, -1) @ Wref.reshape(len(rows), -1).T
     y = ctx.apply(r["xi"], _dev(phi[rows]), _grid(s)).cpu().numpy()
     mel = s.dV * phi.reshape(s.norb, -1) @ y.reshape(len(rows), -1).T

@@ -147,6 +147,27 @@ def test_learned_screener_budget_and_gain(ctx):
     budget = 1e-5 * spec.n_mol
     pairs_l, fb = scr.select(ctx, phi, g, spec.n_mol)
     assert not fb
+    # the kept set is the oracle's budget rule applied to the GPU's own predictions
+    # (ties at the boundary aside, which a threshold keeps or drops together)
+    from oracle.screener_oracle import budget_selection
+    feats = ctx.pair_features(phi, g, stride=scr.stride)
+    pred = ctx.mlp_forward(scr.model, feats, clamp=True).cpu().numpy().astype(np.float64)
+    iu, ju = np.triu_indices(n)
+    off = iu != ju
+    sel_budget = budget / (1.0 + scr.margin)
+    keep_ref = np.ones(len(iu), bool)
+    keep_ref[off] = budget_selection(10.0 ** pred[off], sel_budget)
+    got = np.zeros(len(iu), bool)
+    pl = pairs_l.cpu().numpy()
+    got[pl[:, 0] * n - pl[:, 0] * (pl[:, 0] - 1) // 2 + (pl[:, 1] - pl[:, 0])] = True
+    diff = np.flatnonzero(got != keep_ref)
+    if len(diff):
+        tau = pred[off & got].min()
+        assert np.all(pred[diff] == tau), f"{len(diff)} pairs differ from the budget rule away from a tie"
+    dropped = 10.0 ** pred[off & ~got]
+    assert dropped.sum() <= sel_budget * (1 + 1e-9)
+    assert dropped.sum() + 10.0 ** pred[off & got].min() > sel_budget * (1 - 1e-9)
+    print(f"learned kept set: {got.sum()} pairs, {len(diff)} differ from the budget rule (ties)", flush=True)
     full = torch.as_tensor(np.array([(i, j) for i in range(n) for j in range(i, n)], dtype=np.int32), device="cuda")
     e_full = ctx.pair_energies(phi, full, g, kernel="erfc", omega=spec.omega).cpu().numpy()
     r_full = ctx.build(phi, full, g, kernel="erfc", omega=spec.omega, precision="fp64")

@@ -7,6 +7,8 @@ P4  ACE algebra (Appendix A)             -> M, Cholesky, projectors, application
 P5  SCDM                                 -> QRCP pivots (LAPACK dgeqp3), invariances
 P6  screening                            -> pair selection and the dropped-energy identity
 P7  one orbital                          -> closed-form projector
+P8-P10 application energy, exact exchange, reused columns
+P11 sampled helpers (rows of W, Parseval pair energies, threaded build) -> the serial build
 """
 import numpy as np
 import pytest
@@ -497,3 +499,72 @@ def test_p10_lowdin_rejects_bad_columns():
         oracle.lowdin_columns(psi, np.r_[good[:-1], s0.N ** 3])
     with pytest.raises(ValueError):
         oracle.lowdin_columns(psi, good[:-1])
+
+
+# ----------------------------------------------------------------- P11
+# The sampled helpers that serve as references at sizes where the whole
+# build is too slow for the oracle: each is pinned to the pinned serial build.
+
+def _ragged_list(n, seed):
+    rng = np.random.default_rng(seed)
+    full = _full_pairs(n)
+    keep = (full[:, 0] == full[:, 1]) | (rng.random(len(full)) < 0.45)
+    return full[keep]
+
+
+@pytest.mark.parametrize("which", ["full", "ragged"])
+def test_p11_build_W_rows_equals_rows_of_build_W(which):
+    o = make_orbitals(config_spec("c1"))
+    s = o.spec
+    _, _, phi = oracle.scdm_localize(o.psi, s.dV)
+    pairs = _full_pairs(s.norb) if which == "full" else _ragged_list(s.norb, 11)
+    v = oracle.coulomb_kernel(s.N, s.L, "erfc", 0.3)
+    W = oracle.build_W(phi, pairs, v, s.dV)
+    # every row, in a shuffled order, with a repeat: rows are independent of each other
+    rows = [5, 0, 7, 3, 3, 1, 6, 2, 4]
+    Wr = oracle.build_W_rows(phi, pairs, rows, v, workers=3)
+    assert Wr.shape == (len(rows),) + phi.shape[1:]
+    np.testing.assert_allclose(Wr, W[rows], rtol=0, atol=1e-14 * np.abs(W).max())
+    # an orbital whose only kept pair is its diagonal
+    lone = np.array([(0, 0), (1, 1), (1, 2), (2, 2)])
+    Wl = oracle.build_W_rows(phi, lone, [0, 1, 2], v, workers=2)
+    np.testing.assert_allclose(Wl[0], -oracle.pair_potential(phi[0], phi[0], v) * phi[0], rtol=0, atol=1e-300)
+    np.testing.assert_allclose(Wl, oracle.build_W(phi, lone, v, s.dV)[:3], rtol=0,
+                               atol=1e-14 * np.abs(Wl).max())
+
+
+@pytest.mark.parametrize("which", ["full", "ragged"])
+@pytest.mark.parametrize("kind", ["bare", "erfc"])
+def test_p11_exchange_energy_pairs_equals_build_energies_and_trace(which, kind):
+    """The Parseval route (forward transform only) against the real-space route
+    dV sum rho v of the full build, and their sum against tr M."""
+    o = make_orbitals(config_spec("c1"))
+    s = o.spec
+    _, _, phi = oracle.scdm_localize(o.psi, s.dV)
+    pairs = _full_pairs(s.norb) if which == "full" else _ragged_list(s.norb, 12)
+    v = oracle.coulomb_kernel(s.N, s.L, kind, 0.3)
+    e = oracle.exchange_energy_pairs(phi, pairs, v, s.dV, workers=3)
+    W, e_real = oracle.build_W(phi, pairs, v, s.dV, energies=True)
+    np.testing.assert_allclose(e, e_real, rtol=1e-13, atol=1e-15)
+    assert np.all(e < 0)
+    # tr M counts an off-diagonal pair once in row i and once in row j: this fixes
+    # the weights 1 (diagonal) and 2 (off-diagonal) of the pair energies
+    tr = float(np.trace(s.dV * phi.reshape(s.norb, -1) @ W.reshape(s.norb, -1).T))
+    assert abs(e.sum() - tr) < 1e-13 * abs(tr)
+    if which == "full":
+        r = oracle.ace_build(phi, pairs, s.N, s.L, kind, 0.3)
+        assert abs(e.sum() - r["ex"]) < 1e-13 * abs(r["ex"])
+
+
+def test_p11_threaded_build_W_is_bitwise_serial():
+    o = make_orbitals(config_spec("c1"))
+    s = o.spec
+    pairs = _ragged_list(s.norb, 13)
+    v = oracle.coulomb_kernel(s.N, s.L, "bare", 0.0)
+    W1, e1 = oracle.build_W(o.psi, pairs, v, s.dV, energies=True)
+    for workers in (2, 3, 5):
+        Wt, et = oracle.build_W(o.psi, pairs, v, s.dV, energies=True, workers=workers)
+        assert np.array_equal(Wt, W1) and np.array_equal(et, e1)
+    r1 = oracle.ace_build(o.psi, _full_pairs(s.norb), s.N, s.L, "erfc", 0.2)
+    r4 = oracle.ace_build(o.psi, _full_pairs(s.norb), s.N, s.L, "erfc", 0.2, workers=4)
+    assert np.array_equal(r1["xi"], r4["xi"]) and r1["ex"] == r4["ex"]
