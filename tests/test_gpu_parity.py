@@ -328,7 +328,10 @@ def test_c2_screened_build(ctx, c2, prec, path):
     ref = _c2_screened_ref(c2)
     f64 = prec == "fp64"
     assert abs(r["ex"].item() - ref["ex"]) <= (1e-10 if f64 else 1e-6) * abs(ref["ex"])
-    np.testing.assert_allclose(r["e"].cpu().numpy(), ref["e"], rtol=0, atol=(1e-12 if f64 else 1e-7))
+    # pair energies: FP64 to 1e-12 Ha; FP32 to the FP32 path's 1e-6 relative bound, per pair
+    # against the largest pair energy
+    np.testing.assert_allclose(r["e"].cpu().numpy(), ref["e"], rtol=0,
+                               atol=1e-12 if f64 else 1e-6 * np.abs(ref["e"]).max())
     # every element of W, M and xi against the oracle's build
     _close(r["W"].cpu().numpy(), ref["W"], 1e-12 if f64 else 2e-5, "W (all rows)")
     dM = np.abs(r["M"].cpu().numpy() - ref["M"]).max()
