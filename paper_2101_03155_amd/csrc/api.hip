@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -122,7 +123,10 @@ struct ace_ctx {
   std::map<int, Buf> twiddles;       // key: N*2 + prec
   std::map<int, PairShape> shapes;   // key: N*2 + prec
   std::map<int, int> max_packs;      // key: N*2 + prec
-  std::map<ScheduleKey, Schedule> schedules;
+  // Schedules are shared: a call holds its own references, so trimming the
+  // cache while a batched call builds the schedules of its other systems
+  // never frees one that is still in use.
+  std::map<ScheduleKey, std::shared_ptr<const Schedule>> schedules;
   EventRecorder rec;
   bool profiling = false;
   EventRecorder* R() { return profiling ? &rec : nullptr; }
@@ -348,7 +352,7 @@ static void make_owner_schedule(const std::vector<int32_t>& pr, int64_t npairs, 
 }
 
 static int schedule_for(ace_ctx* c, const std::vector<int32_t>& pr, int64_t npairs, int norb, int max_packs,
-                        const Schedule** out) {
+                        std::shared_ptr<const Schedule>* out) {
   uint64_t h = 1469598103934665603ull;
   std::vector<uint8_t> seen(size_t(norb) * norb, 0);
   for (int64_t p = 0; p < npairs; ++p) {
@@ -363,12 +367,12 @@ static int schedule_for(ace_ctx* c, const std::vector<int32_t>& pr, int64_t npai
   auto sit = c->schedules.find(key);
   if (sit == c->schedules.end()) {
     if (c->schedules.size() > 64) c->schedules.clear();
-    Schedule S;
-    make_schedule(pr, npairs, norb, max_packs, S);
-    make_owner_schedule(pr, npairs, norb, S);
+    auto S = std::make_shared<Schedule>();
+    make_schedule(pr, npairs, norb, max_packs, *S);
+    make_owner_schedule(pr, npairs, norb, *S);
     sit = c->schedules.emplace(key, std::move(S)).first;
   }
-  *out = &sit->second;
+  *out = sit->second;
   return ACE_OK;
 }
 
@@ -798,7 +802,7 @@ static int build_impl(ace_ctx* c, const ace_grid* g, int norb, const double* phi
   HIPCHK(c, hipMemcpyAsync(pr.data(), pairs, pr.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
   const int mp = max_packs_for(c, prec, N);
-  const Schedule* Sp = nullptr;
+  std::shared_ptr<const Schedule> Sp;
   rc = schedule_for(c, pr, npairs, norb, mp, &Sp);
   if (rc) return rc;
   const Schedule& S = *Sp;
@@ -1049,7 +1053,7 @@ int ace_build_batched(ace_ctx* c, int nsys, ace_system* sys, int prec, int mode)
                              us));
   }
   HIPCHK(c, hipStreamSynchronize(us));
-  std::vector<const Schedule*> sch(nsys);
+  std::vector<std::shared_ptr<const Schedule>> sch(static_cast<size_t>(nsys));
   uint64_t key = 1469598103934665603ull;
   auto mix = [&key](uint64_t v) { key = (key ^ v) * 1099511628211ull; };
   mix(uint64_t(prec)); mix(uint64_t(mode)); mix(uint64_t(c->b_txv)); mix(uint64_t(c->b_plan)); mix(uint64_t(c->b_bpc));

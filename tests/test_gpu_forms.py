@@ -278,3 +278,33 @@ def test_batched_c4_workload(ctx):
         print(f"  system {q}: max |dM| {dM:.3e} Ha", flush=True)
         assert dM <= 1e-5
         _close(res[q]["xi"].cpu().numpy(), ref["xi"], 1e-4, f"system {q} xi")
+
+
+def test_batched_after_many_schedules(lib):
+    """A batched call whose systems bring new pair lists into a context whose
+    schedule cache is nearly full: the cache is trimmed while the call still
+    uses the schedules of its earlier systems, which must stay valid."""
+    _say("batched build with the schedule cache full")
+    from paper_2101_03155_amd import Grid
+    from synth import SystemSpec
+    ctx = lib.Context()
+    spec = SystemSpec(n_mol=2, L=5.0, N=16, sigma=0.7, offset=0.6, placement="uniform", seed=321, kernel="erfc",
+                      omega=0.5)
+    phi = _dev(make_orbitals(spec).psi)
+    g = Grid.cubic(16, spec.L)
+    n = spec.norb
+    full = np.array([(i, j) for i in range(n) for j in range(i, n)], dtype=np.int32)
+    rng = np.random.default_rng(4)
+    lists = []
+    while len(lists) < 72:
+        keep = (full[:, 0] == full[:, 1]) | (rng.random(len(full)) < 0.6)
+        lists.append(full[keep])
+    for pl in lists[:60]:  # fill the cache with distinct lists
+        ctx.pair_energies(phi, _dev(pl), g, kernel="erfc", omega=0.5)
+    systems = [dict(phi=phi, pairs=_dev(pl), grid=g, kernel="erfc", omega=0.5) for pl in lists[60:]]
+    res = ctx.build_batched(systems, precision="fp64", mode="eager", raise_on_not_pd=False)
+    for q, sy in enumerate(systems):
+        if res[q]["status"] != "ACE_OK":
+            continue
+        r = ctx.build(phi, sy["pairs"], g, kernel="erfc", omega=0.5, precision="fp64")
+        assert abs(res[q]["ex"].item() - r["ex"].item()) <= 1e-12 * abs(r["ex"].item()), q
