@@ -48,6 +48,9 @@ def parse():
     ap.add_argument("--no-oracle-check", action="store_true")
     ap.add_argument("--screener", default=os.path.join(ROOT, "paper_2101_03155_amd", "models",
                                                        "screener_water_erfc.npz"))
+    ap.add_argument("--screener-bare", default=os.path.join(ROOT, "paper_2101_03155_amd", "models",
+                                                             "screener_water_bare.npz"),
+                    help="screener trained on bare-Coulomb pair energies (the batched form mixes kernels)")
     ap.add_argument("--skip-forms", default="", help="comma list of precision,batched,learned,learned_batched")
     ap.add_argument("--shape", default="owner", choices=["auto", "default", "fused", "split", "r2c", "owner"],
                     help="pair-stage launch shape: autotuned, library default, or forced (default: owner, the "
@@ -379,7 +382,7 @@ def form_batched(ctx, log):
     return out
 
 
-def form_learned_batched(ctx, log, model_path, mode="graph"):
+def form_learned_batched(ctx, log, model_paths, mode="graph"):
     """The learned-screened FP32 batched build against the plain FP64
     full-pair builds of the same 16 systems (8-64 molecules, 48^3-96^3):
     builds/s of each and the E_x error of every learned build against its
@@ -390,9 +393,10 @@ def form_learned_batched(ctx, log, model_path, mode="graph"):
     from paper_2101_03155_amd.screener import LearnedScreener
     from synth import batched_specs, make_orbitals
 
-    if not os.path.exists(model_path):
-        return {"skipped": f"no screener checkpoint at {model_path}"}
-    scr = LearnedScreener.load(model_path)
+    for k, p in model_paths.items():
+        if not os.path.exists(p):
+            return {"skipped": f"no {k} screener checkpoint at {p}"}
+    scrs = {k: LearnedScreener.load(p) for k, p in model_paths.items()}
     specs = batched_specs()
     systems, fulls, loc_ms, sel_ms, fallbacks = [], [], 0.0, 0.0, 0
     for sp in specs:
@@ -401,7 +405,8 @@ def form_learned_batched(ctx, log, model_path, mode="graph"):
         ms, (phi, _, _) = _timed(lambda: ctx.localize(o.psi, g), 1)
         loc_ms += ms
         del o
-        ms, (pl, fb) = _timed(lambda: scr.select(ctx, phi, g, sp.n_mol), 1)
+        # each system is screened by the screener trained on its own kernel
+        ms, (pl, fb) = _timed(lambda: scrs[sp.kernel].select(ctx, phi, g, sp.n_mol), 1)
         sel_ms += ms
         fallbacks += int(fb)
         n = phi.shape[0]
@@ -427,8 +432,9 @@ def form_learned_batched(ctx, log, model_path, mode="graph"):
     budgets = [1e-5 * sp.n_mol for sp in specs]
     npairs = sum(int(sy["pairs"].shape[0]) for sy in systems)
     nfull = sum(int(f.shape[0]) for f in fulls)
-    out = {"workload": "16 systems, 8-64 molecules, 48^3-96^3, mixed bare/erfc; learned screener, FP32 batched "
-                       f"build ({mode} mode) vs FP64 full-pair single builds",
+    out = {"workload": "16 systems, 8-64 molecules, 48^3-96^3, mixed bare/erfc; learned screeners (one per "
+                       f"kernel), FP32 batched build ({mode} mode) vs FP64 full-pair single builds",
+           "margins": {k: s.margin for k, s in scrs.items()},
            "pairs_learned": npairs, "pairs_full": nfull, "used_fallback": fallbacks,
            "learned_fp32_batched": {"ms": round(ms_b, 2), "builds_per_s": round(16 / ms_b * 1000, 2),
                                     "builds_per_s_with_localize_and_selection":
@@ -694,7 +700,8 @@ def main():
         for name, fn in (("precision", lambda: form_precision(ctx, log)), ("batched", lambda: form_batched(ctx, log)),
                          ("learned", lambda: form_learned(ctx, log, args.screener)),
                          ("learned_batched", lambda: form_learned_batched(
-                             ctx, log, args.screener, forms.get("batched", {}).get("tuned", {}).get("mode", "graph")))):
+                             ctx, log, {"erfc": args.screener, "bare": args.screener_bare},
+                             forms.get("batched", {}).get("tuned", {}).get("mode", "graph")))):
             if name in args.skip_forms.split(","):
                 continue
             ctx.release_workspace()  # each form starts from an empty device workspace

@@ -178,6 +178,23 @@ int ace_apply_energy(ace_ctx* ctx, const ace_grid* grid, int norb, const double*
                      double* y, double* ex);
 
 /*
+ * ace_apply_energy for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same results as ace_apply_energy (to the rounding of a different
+ * split-K summation order), with its scratch (the split-K partial sums and
+ * the coefficients c_ka) in a fixed device array of ACE_NOALLOC_SCRATCH_BYTES
+ * that the library holds on each device until the process ends.  The call
+ * allocates nothing and frees nothing; the caller passes every input and
+ * output.  Limits: norb <= 512, nvec <= 512 (ACE_E_ARG beyond); the split
+ * count of the product is capped so the partial sums fit.  Every call on a
+ * device shares that device's array: calls that overlap on one device (two
+ * streams, two contexts) race, so serialize them.
+ */
+#define ACE_NOALLOC_SCRATCH_BYTES ((4 * 1048576 + 512 * 512) * 8)
+int ace_apply_energy_noalloc(ace_ctx* ctx, const ace_grid* grid, int norb, const double* xi, int nvec,
+                             const double* x, double* y, double* ex);
+
+/*
  * Exact exchange on the orbitals themselves (Eq. vx over every pair, no
  * screening and no localization): the full-rank operator behind the exact
  * force of the multiple-time-step force splitting (Sec. Theory).

@@ -112,6 +112,7 @@ def load(path: str = LIB_PATH):
         "ace_apply": ([P, GP, I, P, I, P, P], I),
         "ace_localize_pivots": ([P, GP, I, P, P, P, P], I),
         "ace_apply_energy": ([P, GP, I, P, I, P, P, P], I),
+        "ace_apply_energy_noalloc": ([P, GP, I, P, I, P, P, P], I),
         "ace_exact_exchange": ([P, GP, I, P, I, D, I, P, P, P], I),
         "ace_profile_enable": ([P, I], I),
         "ace_profile_read": ([P, I, C.POINTER(I64), C.POINTER(D), C.POINTER(D), I], I),
@@ -307,6 +308,21 @@ class Context:
         g = grid.c()
         self._check(self.lib.ace_apply_energy(self.h, C.byref(g), xi.shape[0], _ptr(xi), x.shape[0], _ptr(x),
                                               _ptr(y), _ptr(ex)))
+        return y, ex
+
+    def apply_energy_noalloc(self, xi, x, grid: Grid, y, ex):
+        """apply_energy into caller-owned y and ex; the library allocates
+        nothing (its scratch is a fixed per-device array)."""
+        import torch
+
+        _require(xi, torch.float64, "xi")
+        _require(x, torch.float64, "x")
+        _require(y, torch.float64, "y")
+        _require(ex, torch.float64, "ex")
+        self._sync_stream()
+        g = grid.c()
+        self._check(self.lib.ace_apply_energy_noalloc(self.h, C.byref(g), xi.shape[0], _ptr(xi), x.shape[0],
+                                                      _ptr(x), _ptr(y), _ptr(ex)))
         return y, ex
 
     def exact_exchange(self, psi, grid: Grid, kernel: str = "erfc", omega: float = 0.106, precision: str = "fp64",

@@ -109,10 +109,11 @@ size_t pair_spec_elems(int prec, int N, const PairShape& sh);
 // 128 x 128 tiles is computed and mirrored (FP64 only).
 hipError_t gemm_nt(int prec, int op, const void* A, int64_t lda, const void* B, int64_t ldb, int M,
                    int Nn, int64_t K, double alpha, double* Cpart, double* C, hipStream_t s,
-                   EventRecorder* rec, bool sym = false);
+                   EventRecorder* rec, bool sym = false, int64_t max_split = 0);
 // Split count of gemm_nt; the default (sym = true) is the largest count any
-// product of this shape uses, for sizing the partial-sum buffer.
-int64_t gemm_nt_nsplit(int M, int Nn, int64_t K, int64_t* kchunk_out, bool sym = true);
+// product of this shape uses, for sizing the partial-sum buffer.  max_split > 0
+// caps the count (K is then cut into longer chunks).
+int64_t gemm_nt_nsplit(int M, int Nn, int64_t K, int64_t* kchunk_out, bool sym = true, int64_t max_split = 0);
 hipError_t gemm_ls(int bprec, bool trans, bool lower, const double* S, int lds, const void* B, int64_t ldb,
                    double* C, int64_t ldc, int M, int K, int64_t R, double alpha, hipStream_t s,
                    EventRecorder* rec);

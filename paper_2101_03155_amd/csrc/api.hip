@@ -9,6 +9,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -380,6 +381,8 @@ extern "C" {
 
 const char* ace_version(void) { return "libace 0.1 (gfx950)"; }
 
+static int scratch_on_device(ace_ctx* c, double** out);
+
 int ace_create(ace_ctx** out, void* stream) {
   if (!out) return ACE_E_ARG;
   ace_ctx* c = new ace_ctx();
@@ -387,6 +390,12 @@ int ace_create(ace_ctx** out, void* stream) {
   // Without a visible device the context still validates arguments; the
   // first HIP call then reports ACE_E_HIP.
   if (hipGetDevice(&c->device) != hipSuccess) c->device = -1;
+  // the allocation-free entry point's scratch address on this device, looked
+  // up at set-up; a failure here is reported by that entry point's first call
+  if (c->device >= 0) {
+    double* sp = nullptr;
+    if (scratch_on_device(c, &sp) != ACE_OK) c->err.clear();
+  }
   if (const char* cap = getenv("ACE_WORKSPACE_MAX")) c->ws_cap = (size_t)strtoull(cap, nullptr, 10);
   if (const char* om = getenv("ACE_OWNER_SPECTRA_MAX")) c->owner_max = (size_t)strtoull(om, nullptr, 10);
   *out = c;
@@ -997,6 +1006,69 @@ int ace_apply_energy(ace_ctx* c, const ace_grid* g, int norb, const double* xi, 
                      double* ex) {
   if (c && !ex) return fail(c, ACE_E_ARG, "ex must be non-NULL");
   return apply_impl(c, g, norb, xi, nvec, x, y, ex);
+}
+
+
+// ------------------------------------------------------------------ allocation-free application
+// The fixed device scratch of ace_apply_energy_noalloc: the split-K partial
+// sums of the coefficients c = dV xi x^T (at most kNoAllocPart doubles; the
+// split count is capped to fit) followed by c itself (at most 512 x 512).
+// One copy per device for the life of the process; every call on a device
+// shares it, so calls that overlap on one device race.
+constexpr int64_t kNoAllocPart = int64_t(4) << 20;  // 32 MiB of partial sums
+constexpr int64_t kNoAllocCoef = int64_t(512) * 512;
+static __device__ __align__(256) double scratch[kNoAllocPart + kNoAllocCoef];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the scratch array on the current device, looked up once
+// per device (the array's name is only a host-side stand-in).
+static int scratch_on_device(ace_ctx* c, double** out) {
+  int dev = -1;
+  HIPCHK(c, hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(c, ACE_E_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(c, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(c, ACE_E_HIP, "no device address for the scratch array on device %d", dev);
+    g_scratch_ptr[dev] = p;
+  }
+  *out = static_cast<double*>(g_scratch_ptr[dev]);
+  return ACE_OK;
+}
+
+int ace_apply_energy_noalloc(ace_ctx* c, const ace_grid* g, int norb, const double* xi, int nvec, const double* x,
+                             double* y, double* ex) {
+  if (!c) return ACE_E_ARG;
+  int rc = check_grid(c, g, norb);
+  if (rc) return rc;
+  if (!xi || !x || !y || !ex) return fail(c, ACE_E_ARG, "xi, x, y and ex must be non-NULL");
+  if (nvec < 1 || nvec > 512) return fail(c, ACE_E_ARG, "nvec=%d outside [1, 512] (fixed scratch)", nvec);
+  double* base = nullptr;
+  rc = scratch_on_device(c, &base);
+  if (rc) return rc;
+  const int64_t ng = grid_size(g);
+  const int64_t mn = int64_t(norb) * nvec;
+  const int64_t max_split = std::max<int64_t>(1, std::min<int64_t>(512, kNoAllocPart / mn));
+  int64_t kchunk;
+  // the split count gemm_nt will use (the largest of its cases), within the cap
+  const int64_t nsplit = gemm_nt_nsplit(norb, nvec, ng, &kchunk, true, max_split);
+  if (nsplit * mn > kNoAllocPart || mn > kNoAllocCoef)
+    return fail(c, ACE_E_CAPACITY, "norb x nvec = %lld needs %lld partial sums, scratch holds %lld", (long long)mn,
+                (long long)(nsplit * mn), (long long)kNoAllocPart);
+  double* part = base;
+  double* cb = base + kNoAllocPart;
+  hipStream_t s = c->stream;
+  // every partial tile and every coefficient is written before it is read:
+  // nothing in the scratch needs clearing between calls
+  HIPCHK(c, gemm_nt(0, 0, xi, ng, x, ng, norb, nvec, ng, grid_dv(g), part, cb, s, nullptr, false, max_split));
+  HIPCHK(c, gemm_ls(0, true, false, cb, nvec, xi, ng, y, ng, nvec, norb, ng, -1.0, s, nullptr));
+  launch_neg_sumsq(cb, mn, ex, s);
+  HIPCHK(c, hipGetLastError());
+  return ACE_OK;
 }
 
 

@@ -681,7 +681,7 @@ hipError_t refresh_bounds(const double* Q, int ldq, const double* Psi, int64_t l
 
 // ---------------------------------------------------------------- host wrappers
 
-int64_t gemm_nt_nsplit(int M, int Nn, int64_t K, int64_t* kchunk_out, bool sym) {
+int64_t gemm_nt_nsplit(int M, int Nn, int64_t K, int64_t* kchunk_out, bool sym, int64_t max_split) {
   // about 512 workgroups (two per CU) over the 128 x 128 tiles that are
   // computed (the upper triangle only for a symmetric product), K chunks a
   // multiple of 256 (the compensated FP32 sub-chunk).  With sym = true for a
@@ -693,6 +693,11 @@ int64_t gemm_nt_nsplit(int M, int Nn, int64_t K, int64_t* kchunk_out, bool sym) 
   int64_t kchunk = (K + want - 1) / want;
   kchunk = ((kchunk + 255) / 256) * 256;
   if (kchunk < 256) kchunk = 256;
+  // a caller with a fixed partial-sum buffer caps the split count: longer chunks
+  if (max_split > 0 && (K + kchunk - 1) / kchunk > max_split) {
+    kchunk = (K + max_split - 1) / max_split;
+    kchunk = ((kchunk + 255) / 256) * 256;
+  }
   const int64_t nsplit = (K + kchunk - 1) / kchunk;
   *kchunk_out = kchunk;
   return nsplit;
@@ -700,10 +705,10 @@ int64_t gemm_nt_nsplit(int M, int Nn, int64_t K, int64_t* kchunk_out, bool sym) 
 
 hipError_t gemm_nt(int prec, int op, const void* A, int64_t lda, const void* B, int64_t ldb, int M,
                    int Nn, int64_t K, double alpha, double* Cpart, double* C, hipStream_t s,
-                   EventRecorder* rec, bool sym) {
+                   EventRecorder* rec, bool sym, int64_t max_split) {
   int64_t kchunk;
   sym = sym && prec == 0 && M == Nn && A == B && lda == ldb;
-  const int64_t nsplit = gemm_nt_nsplit(M, Nn, K, &kchunk, sym);
+  const int64_t nsplit = gemm_nt_nsplit(M, Nn, K, &kchunk, sym, max_split);
   rec_begin(rec, KC_GEMM_NT, s);
   const int64_t mn = int64_t(M) * Nn;
   const unsigned nbr = unsigned((mn + RO - 1) / RO);

@@ -78,7 +78,8 @@ def training_set(ctx, specs: Sequence, rho_near: float = 1e-5, far_fraction: flo
         idx = np.flatnonzero(sel)
         pairs = torch.as_tensor(np.stack([iu[idx], ju[idx]], 1).astype(np.int32), device="cuda")
         e = ctx.pair_energies(phi, pairs, grid, kernel=spec.kernel, omega=spec.omega, precision=precision)
-        t = torch.log10(torch.clamp(e.abs(), min=1e-16)).float()
+        # targets log10 |e_ij| (host bookkeeping of the library's pair energies)
+        t = torch.as_tensor(np.log10(np.maximum(np.abs(e.cpu().numpy()), 1e-16)).astype(np.float32), device="cuda")
         xs.append(f[torch.as_tensor(idx, device="cuda")])
         ts.append(t)
         info.append({"seed": spec.seed, "n_mol": spec.n_mol, "N": spec.N, "pairs": int(len(idx))})
@@ -158,8 +159,8 @@ class LearnedScreener:
             dpairs = torch.as_tensor(drop, device="cuda")
             e = ctx.pair_energies(phi, dpairs, grid, kernel=spec.kernel, omega=spec.omega, precision=precision)
             f = ctx.pair_features(phi, grid, dpairs, stride=self.stride)
-            pred = (10.0 ** ctx.mlp_forward(self.model, f, clamp=True).double()).sum().item()
-            true = e.abs().sum().item()
+            pred = float(np.sum(10.0 ** ctx.mlp_forward(self.model, f, clamp=True).cpu().numpy().astype(np.float64)))
+            true = float(np.sum(np.abs(e.cpu().numpy())))
             ratios.append(true / max(pred, 1e-300))
             if log:
                 log(f"calibration {spec.n_mol} molecules: dropped true {true:.3e} Ha, predicted {pred:.3e} Ha")
@@ -188,19 +189,26 @@ def main(argv=None):
     """Train, calibrate and save a screener: python -m paper_2101_03155_amd.screener OUT.npz"""
     import argparse
 
-    from synth import training_specs
+    from synth import batched_like_specs, training_specs
 
     ap = argparse.ArgumentParser()
     ap.add_argument("out")
     ap.add_argument("--configs", type=int, default=200)
     ap.add_argument("--validation", type=int, default=8)
+    ap.add_argument("--validation-batched", type=int, default=8,
+                    help="held-out systems drawn like the batched workload (8-64 molecules, coarser grids)")
     ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--kernel", default="erfc", choices=["erfc", "bare"])
     args = ap.parse_args(argv)
     ctx = ace.Context()
     log = lambda m: print(m, flush=True)  # noqa: E731
-    data = training_set(ctx, training_specs(args.configs), log=log)
+    data = training_set(ctx, training_specs(args.configs, kernel=args.kernel), log=log)
     scr = LearnedScreener.train(ctx, data, epochs=args.epochs)
-    scr.calibrate(ctx, training_specs(args.validation, first_seed=7000), log=log)
+    held = (training_specs(args.validation, first_seed=7000, kernel=args.kernel)
+            + batched_like_specs(args.validation_batched, first_seed=7100, kernel=args.kernel))
+    scr.calibrate(ctx, held, log=log)
+    scr.meta["kernel"] = args.kernel
+    scr.meta["calibration_systems"] = [{"seed": s.seed, "n_mol": s.n_mol, "N": s.N} for s in held]
     scr.save(args.out)
     log(json.dumps({k: v for k, v in scr.meta.items() if k != "loss_curve"}))
 

@@ -162,7 +162,7 @@ def batched_specs(n_systems: int = 16, master_seed: int = 4000) -> List[SystemSp
 
 
 def training_specs(n_configs: int = 200, first_seed: int = 6000,
-                   min_mol: int = 32, max_mol: int = 64) -> List[SystemSpec]:
+                   min_mol: int = 32, max_mol: int = 64, kernel: str = "erfc") -> List[SystemSpec]:
     """Training configurations for the learned pair screener (32-64 molecules)."""
     out = []
     for k in range(n_configs):
@@ -171,7 +171,23 @@ def training_specs(n_configs: int = 200, first_seed: int = 6000,
         L = box_length_for(n_mol)
         out.append(SystemSpec(n_mol=n_mol, L=L, N=training_grid_for(L), sigma=1.0,
                               offset=0.8, placement="lattice", jitter=0.5, seed=seed,
-                              kernel="erfc", omega=0.106))
+                              kernel=kernel, omega=0.106))
+    return out
+
+
+def batched_like_specs(n_configs: int, first_seed: int, kernel: str = "erfc",
+                       min_mol: int = 8, max_mol: int = 64) -> List[SystemSpec]:
+    """Held-out systems drawn like the batched workload (8-64 molecules, box
+    from the density, grid spacing <= 0.25 bohr), one kernel: calibration
+    systems for a screener that will serve such batches."""
+    out = []
+    for k in range(n_configs):
+        seed = first_seed + k
+        n_mol = int(np.random.default_rng(seed + 2_000_000).integers(min_mol, max_mol + 1))
+        L = box_length_for(n_mol)
+        out.append(SystemSpec(n_mol=n_mol, L=L, N=batched_grid_for(L), sigma=1.0,
+                              offset=0.8, placement="lattice", jitter=0.5, seed=seed,
+                              kernel=kernel, omega=0.106))
     return out
 
 
