@@ -429,6 +429,14 @@ def form_learned_batched(ctx, log, model_paths, mode="graph"):
 
     ms_full, ex_f = _timed(full_builds, 1)
     errs = [abs(a - b) for a, b in zip(ex_l, ex_f)]
+    # the screening part of the error: FP64 builds of the learned lists
+    ex_l64 = []
+    for sy in systems:
+        r = ctx.build(sy["phi"], sy["pairs"], sy["grid"], kernel=sy["kernel"], omega=sy["omega"], precision="fp64",
+                      want_M=False)
+        ex_l64.append(float(r["ex"].item()))
+        del r
+    scr_errs = [abs(a - b) for a, b in zip(ex_l64, ex_f)]
     budgets = [1e-5 * sp.n_mol for sp in specs]
     npairs = sum(int(sy["pairs"].shape[0]) for sy in systems)
     nfull = sum(int(f.shape[0]) for f in fulls)
@@ -443,10 +451,14 @@ def form_learned_batched(ctx, log, model_paths, mode="graph"):
            "full_fp64": {"ms": round(ms_full, 2), "builds_per_s": round(16 / ms_full * 1000, 3),
                          "builds_per_s_with_localize": round(16 / (ms_full + loc_ms) * 1000, 3)},
            "max_abs_err_vs_full_fp64_ha": max(errs),
-           "all_within_budget": all(e <= b for e, b in zip(errs, budgets)),
+           "max_screening_err_ha": max(scr_errs),
+           "screening_within_budget": all(e <= b for e, b in zip(scr_errs, budgets)),
+           "note": ("abs_err_ha: the FP32 learned batched build against the FP64 full-pair build (screening plus "
+                    "FP32 rounding); screening_err_ha: the FP64 build of the learned list against the same "
+                    "(the part the budget of 1e-5 Ha per molecule bounds)"),
            "per_system": [{"n_mol": sp.n_mol, "N": sp.N, "kernel": sp.kernel, "pairs": int(sy["pairs"].shape[0]),
-                           "pairs_full": int(f.shape[0]), "abs_err_ha": e, "budget_ha": b}
-                          for sp, sy, f, e, b in zip(specs, systems, fulls, errs, budgets)]}
+                           "pairs_full": int(f.shape[0]), "abs_err_ha": e, "screening_err_ha": se, "budget_ha": b}
+                          for sp, sy, f, e, se, b in zip(specs, systems, fulls, errs, scr_errs, budgets)]}
     out["speedup_vs_full_fp64"] = round(ms_full / ms_b, 2)
     log(f"learned batched: {ms_b:.1f} ms vs full fp64 {ms_full:.1f} ms, max |dE| {max(errs):.2e}")
     del systems, fulls, res
