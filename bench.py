@@ -238,34 +238,40 @@ def form_exact_exchange(ctx, psi, grid, kind, omega, reps=3):
     return out
 
 
-def form_incremental(ctx, psi0, spec, grid, kind, omega, rho_cut, reps=5):
-    """The next MD step (every centre moved 0.05 bohr): fresh SCDM against the
-    Loewdin step on the previous step's columns, then the screened builds."""
+def form_incremental(ctx, psi0, spec, grid, kind, omega, rho_cut, cond_max=2.0, reps=5):
+    """MD steps 1-3 (every centre moved 0.05 bohr per step): the previous
+    step's columns kept while their quality ratio stays below cond_max
+    (Loewdin only) and the re-screen against the previous list, against a
+    fresh SCDM and screening at the same step; then the builds."""
     import dataclasses
 
     import torch
 
     from synth import make_orbitals
 
-    _, piv0, _ = ctx.localize(psi0, grid)
-    psi1 = make_orbitals(dataclasses.replace(spec, md_step=1), device="cuda").psi
-    out = {"workload": f"MD step 1 of {spec.norb} orbitals, {spec.N}^3, centres moved {spec.md_disp} bohr"}
-    for name, fn in (("fresh", lambda: ctx.localize(psi1, grid)[0]),
-                     ("reused", lambda: ctx.localize_pivots(psi1, piv0, grid)[0])):
-        phi = fn()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            phi = fn()
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1000.0 / reps
-        pairs, _ = ctx.pairlist(phi, grid, rho_cut)
-        r = ctx.build(phi, pairs, grid, kernel=kind, omega=omega, want_M=False)
-        out[name] = {"localize_ms": round(ms, 3), "pairs": int(pairs.shape[0]), "ex": float(r["ex"].item())}
-        del phi, pairs, r
-    out["localize_speedup"] = round(out["fresh"]["localize_ms"] / out["reused"]["localize_ms"], 2)
-    out["ex_rel_diff_reused_vs_fresh"] = abs(out["reused"]["ex"] - out["fresh"]["ex"]) / abs(out["fresh"]["ex"])
-    del psi1
+    phi, piv, _ = ctx.localize(psi0, grid)
+    pairs, _ = ctx.pairlist(phi, grid, rho_cut)
+    out = {"workload": f"MD steps 1-3 of {spec.norb} orbitals, {spec.N}^3, centres moved {spec.md_disp} bohr "
+                       f"per step, columns kept while (max R_kk / min R_kk)^2 <= {cond_max}", "steps": []}
+    for t in (1, 2, 3):
+        psi = make_orbitals(dataclasses.replace(spec, md_step=t), device="cuda").psi
+        ms_f, (phi_f, _, _) = _timed(lambda: ctx.localize(psi, grid), reps)
+        ms_fp, (pairs_f, _) = _timed(lambda: ctx.pairlist(phi_f, grid, rho_cut), reps)
+        ms_k, (phi_k, piv_k, _, info) = _timed(lambda: ctx.localize_step(psi, piv, grid, cond_max), reps)
+        ms_kp, (pairs_k, _, pinfo) = _timed(lambda: ctx.pairlist_step(phi_k, grid, rho_cut, pairs), reps)
+        rf = ctx.build(phi_f, pairs_f, grid, kernel=kind, omega=omega, want_M=False)
+        rk = ctx.build(phi_k, pairs_k, grid, kernel=kind, omega=omega, want_M=False)
+        ef, ek = float(rf["ex"].item()), float(rk["ex"].item())
+        out["steps"].append({"step": t, "reused_columns": info["reused_columns"], "quality": round(info["gram_cond"], 4),
+                             "pairs": int(pairs_k.shape[0]), "pairs_added": pinfo["pairs_added"],
+                             "pairs_removed": pinfo["pairs_removed"], "pairs_fresh": int(pairs_f.shape[0]),
+                             "localize_ms_kept": round(ms_k, 3), "localize_ms_fresh": round(ms_f, 3),
+                             "pairlist_ms_step": round(ms_kp, 3), "pairlist_ms_fresh": round(ms_fp, 3),
+                             "ex_rel_diff_kept_vs_fresh": abs(ek - ef) / abs(ef)})
+        piv, pairs = piv_k, pairs_k
+        del psi, phi_f, phi_k, rf, rk
+    st = out["steps"]
+    out["localize_speedup"] = round(sum(s["localize_ms_fresh"] for s in st) / sum(s["localize_ms_kept"] for s in st), 2)
     torch.cuda.empty_cache()
     return out
 

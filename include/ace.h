@@ -116,6 +116,43 @@ int ace_localize_pivots(ace_ctx* ctx, const ace_grid* grid, int norb, const doub
                         double* phi, double* U);
 
 /*
+ * (a) at the next MD step, with the previous step's columns as the warm start
+ * (the ACE operator is rebuilt at least once per MD step, Sec. Theory).
+ *   pivots  [norb] int32, device (in: the previous step's columns; out: the
+ *           columns used at this step)
+ *   cond_max >= 1: the previous columns are kept when (max_k R_kk / min_k R_kk)^2,
+ *           with A_C = Q R the QR factorization of this step's A[:, pivots] in
+ *           pivot order (read from the Cholesky factor of A_C^T A_C), is at most
+ *           cond_max; then only the Loewdin step of Eq. (unit) runs, as in
+ *           ace_localize_pivots.  Otherwise (or when the polar iteration fails)
+ *           a fresh SCDM (ace_localize) picks new columns.
+ *   phi, U  as ace_localize;  info (HOST): reused_columns, gram_cond.
+ * Greedy pivoting keeps that ratio small, so the fresh columns' ratio is the
+ * natural reference for cond_max.  Errors as ace_localize_pivots.
+ */
+typedef struct {
+  int32_t reused_columns; /* 1: previous columns kept (Loewdin only); 0: fresh SCDM      */
+  double gram_cond;       /* (max R_kk / min R_kk)^2 of the previous columns (inf if singular) */
+  int64_t pairs_added;    /* ace_pairlist_step: kept now, not in the previous list        */
+  int64_t pairs_removed;  /* ace_pairlist_step: in the previous list, not kept now        */
+} ace_step_info;
+
+int ace_localize_step(ace_ctx* ctx, const ace_grid* grid, int norb, const double* psi, int32_t* pivots,
+                      double cond_max, double* phi, double* U, ace_step_info* info);
+
+/*
+ * (b) at the next MD step: ace_pairlist on this step's orbitals, compared
+ * pair by pair with the previous step's list (meaningful when the columns
+ * were kept, so orbital k continues orbital k): info->pairs_added and
+ * info->pairs_removed count the pairs whose overlap crossed rho_cut upward
+ * and downward.  prev_pairs [nprev][2] int32 device, sorted by (i, j) (as
+ * ace_pairlist writes them); the other arguments and errors as ace_pairlist.
+ */
+int ace_pairlist_step(ace_ctx* ctx, const ace_grid* grid, int norb, const double* phi, double rho_cut,
+                      const int32_t* prev_pairs, int64_t nprev, int64_t capacity, int32_t* pairs, double* overlap,
+                      int64_t* npairs, ace_step_info* info);
+
+/*
  * (b) Pair screening (criterion in the SCDM paragraph of Sec. Theory): keep
  * (i, j), i <= j, when  O_ij = dV sum_r |phi_i(r)| |phi_j(r)|  >= rho_cut;
  * diagonal pairs are always kept.

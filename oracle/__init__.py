@@ -23,5 +23,5 @@ from .ace_oracle import (  # noqa: F401
     grid_G2, coulomb_kernel, pair_potential, pair_energy_forward, build_W,
     ace_from_W, ace_build, ace_apply, scdm_localize, qrcp_pivots, pairlist,
     overlap_abs, exchange_energy_pairs, NotPositiveDefinite, apply_vx_direct, build_W_rows,
-    ace_apply_energy, exact_exchange, lowdin_columns,
+    ace_apply_energy, exact_exchange, lowdin_columns, column_quality, localize_step, pairlist_step,
 )

@@ -400,6 +400,35 @@ def lowdin_columns(psi: np.ndarray, piv):
     return U, phi
 
 
+def column_quality(psi: np.ndarray, piv) -> float:
+    """(max_k |R_kk| / min_k |R_kk|)^2 of the QR factorization A[:, piv] = Q R,
+    columns in pivot order (A[i, r] = psi_i(r)); inf when A[:, piv] is
+    singular.  Greedy pivoting keeps this ratio small; it is a lower bound on
+    the condition number of A_C^T A_C.  Pinned by P12 (R_kk are the residual
+    norms greedy QRCP picks its columns with; the bound; diagonal cases)."""
+    n = psi.shape[0]
+    A = psi.reshape(n, -1)[:, np.asarray(piv, dtype=np.int64)]
+    d = np.abs(np.diag(np.linalg.qr(A, mode="r")))
+    if d.min() == 0.0 or not np.all(np.isfinite(d)):
+        return float("inf")
+    return float((d.max() / d.min()) ** 2)
+
+
+def localize_step(psi: np.ndarray, prev_piv, dV: float, cond_max: float):
+    """SCDM at the next MD step with the previous step's columns as the warm
+    start (the ACE operator is rebuilt at least once per MD step, Sec. Theory):
+    the columns are kept, and only the Loewdin step of Eq. (unit) runs, when
+    their column_quality on this step's orbitals is at most cond_max;
+    otherwise SCDM picks fresh columns.  Returns (piv, U, phi, reused, quality).
+    Pinned by P12."""
+    q = column_quality(psi, prev_piv)
+    if q <= cond_max:
+        U, phi = lowdin_columns(psi, prev_piv)
+        return np.asarray(prev_piv, dtype=np.int64), U, phi, True, q
+    piv, U, phi = scdm_localize(psi, dV)
+    return piv, U, phi, False, q
+
+
 # --------------------------------------------------------------------------
 # Pair screening (criterion of Sec. Theory)
 # --------------------------------------------------------------------------
@@ -423,3 +452,14 @@ def pairlist(phi: np.ndarray, dV: float, rho_cut: float):
     keep = (O[iu, ju] >= rho_cut) | (iu == ju)
     pairs = np.stack([iu[keep], ju[keep]], axis=1)
     return pairs, O[iu[keep], ju[keep]]
+
+
+def pairlist_step(phi: np.ndarray, dV: float, rho_cut: float, prev_pairs):
+    """The screening criterion at the next MD step, compared with the previous
+    step's list: returns (pairs, O_kept, added, removed) with added the kept
+    pairs absent from prev_pairs and removed the previous pairs no longer
+    kept.  Pinned by P12 (brute-force set differences)."""
+    pairs, O = pairlist(phi, dV, rho_cut)
+    new = {(int(i), int(j)) for i, j in pairs}
+    old = {(int(i), int(j)) for i, j in np.asarray(prev_pairs).reshape(-1, 2)}
+    return pairs, O, len(new - old), len(old - new)

@@ -55,6 +55,11 @@ MLP_NPARAM = 4609
 MLP_NMODEL = 4631
 
 
+class ace_step_info(C.Structure):
+    _fields_ = [("reused_columns", C.c_int32), ("gram_cond", C.c_double), ("pairs_added", C.c_int64),
+                ("pairs_removed", C.c_int64)]
+
+
 class ace_mlp_hparams(C.Structure):
     _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
                 ("batch", C.c_int32), ("epochs", C.c_int32), ("step0", C.c_int32), ("seed", C.c_uint64)]
@@ -108,6 +113,8 @@ def load(path: str = LIB_PATH):
         "ace_set_stream": ([P, P], I),
         "ace_localize": ([P, GP, I, P, P, P, P], I),
         "ace_pairlist": ([P, GP, I, P, D, I64, P, P, C.POINTER(I64)], I),
+        "ace_localize_step": ([P, GP, I, P, P, D, P, P, C.POINTER(ace_step_info)], I),
+        "ace_pairlist_step": ([P, GP, I, P, D, P, I64, I64, P, P, C.POINTER(I64), C.POINTER(ace_step_info)], I),
         "ace_build": ([P, GP, I, P, P, I64, I, D, I, P, P, P, P, P], I),
         "ace_apply": ([P, GP, I, P, I, P, P], I),
         "ace_localize_pivots": ([P, GP, I, P, P, P, P], I),
@@ -230,6 +237,45 @@ class Context:
         self._check(self.lib.ace_localize_pivots(self.h, C.byref(g), norb, _ptr(psi), _ptr(pivots), _ptr(phi),
                                                  _ptr(U)))
         return phi, U
+
+    def localize_step(self, psi, pivots, grid: Grid, cond_max: float):
+        """Next MD step: keep the previous columns (Loewdin only) when their
+        diagonal ratio (max R_kk / min R_kk)^2 is <= cond_max, else fresh SCDM.
+        Returns (phi, pivots used [new tensor], U, info dict)."""
+        import torch
+
+        _require(psi, torch.float64, "psi")
+        _require(pivots, torch.int32, "pivots")
+        norb = psi.shape[0]
+        piv = pivots.clone()
+        phi = torch.empty_like(psi)
+        U = torch.empty(norb, norb, dtype=torch.float64, device=psi.device)
+        info = ace_step_info()
+        self._sync_stream()
+        g = grid.c()
+        self._check(self.lib.ace_localize_step(self.h, C.byref(g), norb, _ptr(psi), _ptr(piv), float(cond_max),
+                                               _ptr(phi), _ptr(U), C.byref(info)))
+        return phi, piv, U, {"reused_columns": bool(info.reused_columns), "gram_cond": info.gram_cond}
+
+    def pairlist_step(self, phi, grid: Grid, rho_cut: float, prev_pairs):
+        """Re-screen against the previous step's list: (pairs, overlap, info)
+        with info = pairs_added / pairs_removed relative to prev_pairs."""
+        import torch
+
+        _require(phi, torch.float64, "phi")
+        _require(prev_pairs, torch.int32, "prev_pairs")
+        norb = phi.shape[0]
+        cap = norb * (norb + 1) // 2
+        pairs = torch.empty(cap, 2, dtype=torch.int32, device=phi.device)
+        ov = torch.empty(cap, dtype=torch.float64, device=phi.device)
+        n = C.c_int64()
+        info = ace_step_info()
+        self._sync_stream()
+        g = grid.c()
+        self._check(self.lib.ace_pairlist_step(self.h, C.byref(g), norb, _ptr(phi), float(rho_cut), _ptr(prev_pairs),
+                                               prev_pairs.shape[0], cap, _ptr(pairs), _ptr(ov), C.byref(n),
+                                               C.byref(info)))
+        return pairs[: n.value], ov[: n.value], {"pairs_added": info.pairs_added, "pairs_removed": info.pairs_removed}
 
     def pairlist(self, phi, grid: Grid, rho_cut: float, capacity: Optional[int] = None):
         """Screened pair list: returns (pairs[int32, n x 2], overlap[n])."""

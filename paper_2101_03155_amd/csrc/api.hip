@@ -736,6 +736,68 @@ int ace_localize_pivots(ace_ctx* c, const ace_grid* g, int norb, const double* p
   return ACE_OK;
 }
 
+// ------------------------------------------------------------------ (a) across MD steps
+int ace_localize_step(ace_ctx* c, const ace_grid* g, int norb, const double* psi, int32_t* pivots, double cond_max,
+                      double* phi, double* U, ace_step_info* info) {
+  if (!c) return ACE_E_ARG;
+  int rc = check_grid(c, g, norb);
+  if (rc) return rc;
+  if (!psi || !phi || !pivots || !info) return fail(c, ACE_E_ARG, "psi, pivots, phi and info must be non-NULL");
+  if (!(cond_max >= 1.0)) return fail(c, ACE_E_ARG, "cond_max must be >= 1");
+  const int64_t ng = grid_size(g);
+  if (ng < norb) return fail(c, ACE_E_ARG, "grid smaller than the number of orbitals");
+  hipStream_t s = c->stream;
+  std::vector<int32_t> hp(static_cast<size_t>(norb));
+  HIPCHK(c, hipMemcpyAsync(hp.data(), pivots, size_t(norb) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  std::vector<int32_t> sorted(hp);
+  std::sort(sorted.begin(), sorted.end());
+  if (sorted.front() < 0 || int64_t(sorted.back()) >= ng)
+    return fail(c, ACE_E_ARG, "pivot outside [0, %lld)", (long long)ng);
+  if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+    return fail(c, ACE_E_ARG, "repeated pivot column");
+  // Quality of the previous columns on this step's orbitals: the Cholesky
+  // factor of A_C^T A_C taken in pivot order is R^T of the QR factorization
+  // of A_C, so (max_k R_kk / min_k R_kk)^2 is the diagonal ratio greedy
+  // pivoting keeps small, and a lower bound on the condition number.
+  double *AC, *G, *tinv;
+  int* dinfo;
+  WS(c, "AC", size_t(norb) * norb * sizeof(double), AC);
+  WS(c, "G", size_t(norb) * norb * sizeof(double), G);
+  WS(c, "tinv", 64 * 64 * sizeof(double), tinv);
+  WS(c, "info", 64, dinfo);
+  launch_gather_cols(psi, norb, ng, pivots, AC, s);
+  HIPCHK(c, gemm_ls(0, true, false, AC, norb, AC, norb, G, norb, norb, norb, norb, 1.0, s, nullptr));
+  launch_zero(dinfo, sizeof(int), s);
+  launch_cholesky(G, norb, dinfo, tinv, s);
+  std::vector<double> hg(size_t(norb) * norb);
+  int hinfo = 0;
+  HIPCHK(c, hipMemcpyAsync(hg.data(), G, hg.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(&hinfo, dinfo, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  double dmax = 0.0, dmin = INFINITY;
+  for (int k = 0; k < norb; ++k) {
+    const double d = hg[size_t(k) * norb + k];
+    dmax = std::max(dmax, d);
+    dmin = std::min(dmin, d);
+  }
+  const double cond = (hinfo == 0 && dmin > 0.0 && std::isfinite(dmax)) ? (dmax / dmin) * (dmax / dmin) : INFINITY;
+  info->gram_cond = cond;
+  info->pairs_added = info->pairs_removed = 0;
+  if (cond <= cond_max) {
+    info->reused_columns = 1;
+    double *X, *Z, *dev;
+    WS(c, "X", size_t(norb) * norb * sizeof(double), X);
+    WS(c, "Z", size_t(norb) * norb * sizeof(double), Z);
+    WS(c, "scal", 64 * sizeof(double), dev);
+    rc = lowdin(c, norb, ng, psi, pivots, AC, X, G, Z, dev, phi, U);
+    if (rc != ACE_E_NONFINITE) return rc;
+    c->err.clear();  // the polar iteration failed on these columns: fresh SCDM below
+  }
+  info->reused_columns = 0;
+  return ace_localize(c, g, norb, psi, phi, pivots, U);
+}
+
 // ------------------------------------------------------------------ (b) pairlist
 int ace_pairlist(ace_ctx* c, const ace_grid* g, int norb, const double* phi, double rho_cut, int64_t capacity,
                  int32_t* pairs, double* overlap, int64_t* npairs) {
@@ -764,6 +826,57 @@ int ace_pairlist(ace_ctx* c, const ace_grid* g, int norb, const double* phi, dou
   *npairs = h;
   if (h > capacity) return fail(c, ACE_E_CAPACITY, "%lld pairs kept but capacity is %lld", (long long)h,
                                 (long long)capacity);
+  return ACE_OK;
+}
+
+// Re-screening at the next MD step against the previous step's list.  With
+// the previous step's columns kept (ace_localize_step), orbital k of this
+// step continues orbital k of the last one, so the two lists compare pair by
+// pair: the call reports how many pairs crossed rho_cut in each direction.
+// An unchanged list is bitwise the previous one, and the build then finds
+// the list's schedule in the context's cache.
+int ace_pairlist_step(ace_ctx* c, const ace_grid* g, int norb, const double* phi, double rho_cut,
+                      const int32_t* prev_pairs, int64_t nprev, int64_t capacity, int32_t* pairs, double* overlap,
+                      int64_t* npairs, ace_step_info* info) {
+  if (!c) return ACE_E_ARG;
+  if (!info || (nprev > 0 && !prev_pairs) || nprev < 0)
+    return fail(c, ACE_E_ARG, "info must be non-NULL and prev_pairs hold nprev >= 0 pairs");
+  if (nprev > int64_t(norb) * (norb + 1) / 2) return fail(c, ACE_E_ARG, "nprev above norb (norb + 1) / 2");
+  hipStream_t s = c->stream;
+  std::vector<int32_t> hprev(size_t(2 * nprev));
+  if (nprev > 0) {
+    HIPCHK(c, hipMemcpyAsync(hprev.data(), prev_pairs, hprev.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+  }
+  for (int64_t t = 0; t < nprev; ++t) {
+    const int32_t i = hprev[size_t(2 * t)], j = hprev[size_t(2 * t + 1)];
+    if (i < 0 || j < i || j >= norb) return fail(c, ACE_E_ARG, "previous pair %lld = (%d, %d) out of range",
+                                                 (long long)t, i, j);
+    if (t > 0) {
+      const int32_t pi = hprev[size_t(2 * t - 2)], pj = hprev[size_t(2 * t - 1)];
+      if (i < pi || (i == pi && j <= pj)) return fail(c, ACE_E_ARG, "previous pairs not sorted by (i, j)");
+    }
+  }
+  int rc = ace_pairlist(c, g, norb, phi, rho_cut, capacity, pairs, overlap, npairs);
+  if (rc) return rc;
+  const int64_t n = *npairs;
+  std::vector<int32_t> hnew(size_t(2 * n));
+  if (n > 0) {
+    HIPCHK(c, hipMemcpyAsync(hnew.data(), pairs, hnew.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+  }
+  // merge of two lists sorted by (i, j)
+  int64_t a = 0, b = 0, added = 0, removed = 0;
+  auto key = [](const std::vector<int32_t>& v, int64_t t) {
+    return (int64_t(v[size_t(2 * t)]) << 32) | uint32_t(v[size_t(2 * t + 1)]);
+  };
+  while (a < nprev || b < n) {
+    if (b >= n || (a < nprev && key(hprev, a) < key(hnew, b))) { ++removed; ++a; }
+    else if (a >= nprev || key(hnew, b) < key(hprev, a)) { ++added; ++b; }
+    else { ++a; ++b; }
+  }
+  info->pairs_added = added;
+  info->pairs_removed = removed;
   return ACE_OK;
 }
 

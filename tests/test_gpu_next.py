@@ -204,3 +204,51 @@ def test_single_orbital_edge_cases(ctx):
     U_ref, phi_ref = oracle.lowdin_columns(g1, piv)
     assert abs(U.item() - U_ref[0, 0]) <= 1e-15 and abs(U_ref[0, 0]) == 1.0
     assert _maxdiff(phi.cpu().numpy(), phi_ref) < 1e-14
+
+
+# ------------------------------------------------------------------ MD steps 1-3: kept columns, re-screen
+
+@pytest.mark.parametrize("cfg,rho_cut", [("c1", 0.05), ("c2", 1e-3)])
+def test_md_steps_kept_columns_and_rescreen(ctx, cfg, rho_cut):
+    """A short MD chain: fresh SCDM at step 0, then at steps 1-3 the previous
+    columns kept while their quality ratio stays below 2 (ace_localize_step),
+    the re-screen against the previous list (ace_pairlist_step) and the build,
+    each against the oracle's chain on the same inputs; then a forced refresh."""
+    s0 = config_spec(cfg)
+    g = _grid(s0.N, s0.L)
+    kind = "bare" if cfg == "c1" else "erfc"
+    v = oracle.coulomb_kernel(s0.N, s0.L, kind, s0.omega)
+    psi = make_orbitals(s0).psi
+    _say(f"md chain {cfg} step 0")
+    piv_o, _, phi_o = oracle.scdm_localize(psi, s0.dV)
+    pairs_o, _ = oracle.pairlist(phi_o, s0.dV, rho_cut)
+    phi_g, piv_g, _ = ctx.localize(_dev(psi), g)
+    pairs_g, _ = ctx.pairlist(phi_g, g, rho_cut)
+    np.testing.assert_array_equal(piv_g.cpu().numpy(), piv_o)
+    np.testing.assert_array_equal(pairs_g.cpu().numpy(), pairs_o)
+    for t in (1, 2, 3):
+        _say(f"md chain {cfg} step {t}")
+        psi = make_orbitals(s0.replace(md_step=t)).psi
+        piv_o, _, phi_o, reused_o, q_o = oracle.localize_step(psi, piv_o, s0.dV, 2.0)
+        pairs_prev_o = pairs_o
+        pairs_o, _, add_o, rem_o = oracle.pairlist_step(phi_o, s0.dV, rho_cut, pairs_prev_o)
+        psi_d = _dev(psi)
+        phi_g, piv_g, _, info = ctx.localize_step(psi_d, piv_g, g, 2.0)
+        assert info["reused_columns"] == reused_o and reused_o
+        assert abs(info["gram_cond"] - q_o) <= 1e-10 * q_o
+        np.testing.assert_array_equal(piv_g.cpu().numpy(), piv_o)
+        assert _maxdiff(phi_g.cpu().numpy(), phi_o) < 1e-10
+        prev_g = pairs_g
+        pairs_g, _, pinfo = ctx.pairlist_step(phi_g, g, rho_cut, prev_g)
+        np.testing.assert_array_equal(pairs_g.cpu().numpy(), pairs_o)
+        assert (pinfo["pairs_added"], pinfo["pairs_removed"]) == (add_o, rem_o)
+        print(f"  step {t}: quality {q_o:.4f}, {len(pairs_o)} pairs (+{add_o} -{rem_o})", flush=True)
+        r = ctx.build(_dev(phi_o), _dev(pairs_o.astype(np.int32)), g, kernel=kind, omega=s0.omega)
+        e = oracle.exchange_energy_pairs(phi_o, pairs_o, v, s0.dV)
+        assert abs(r["ex"].item() - e.sum()) <= 1e-10 * abs(e.sum())
+    # a ratio no column set reaches forces fresh SCDM, equal to ace_localize
+    phi_g2, piv_g2, _, info = ctx.localize_step(psi_d, piv_g, g, 1.0)
+    assert not info["reused_columns"]
+    phi_f, piv_f, _ = ctx.localize(psi_d, g)
+    assert torch.equal(piv_g2, piv_f) and torch.equal(phi_g2, phi_f)
+    np.testing.assert_array_equal(piv_f.cpu().numpy(), oracle.qrcp_pivots(psi.reshape(s0.norb, -1))[0])

@@ -9,6 +9,7 @@ P6  screening                            -> pair selection and the dropped-energ
 P7  one orbital                          -> closed-form projector
 P8-P10 application energy, exact exchange, reused columns
 P11 sampled helpers (rows of W, Parseval pair energies, threaded build) -> the serial build
+P12 the next MD step: kept columns and their quality measure, the re-screen against the previous list
 """
 import numpy as np
 import pytest
@@ -568,3 +569,96 @@ def test_p11_threaded_build_W_is_bitwise_serial():
     r1 = oracle.ace_build(o.psi, _full_pairs(s.norb), s.N, s.L, "erfc", 0.2)
     r4 = oracle.ace_build(o.psi, _full_pairs(s.norb), s.N, s.L, "erfc", 0.2, workers=4)
     assert np.array_equal(r1["xi"], r4["xi"]) and r1["ex"] == r4["ex"]
+
+
+# ----------------------------------------------------------------- P12
+# The next MD step: the previous columns as the warm start, the re-screen
+# against the previous list.
+
+def test_p12_column_quality_is_the_qrcp_residual_ratio():
+    """On fresh SCDM columns the R diagonal of A_C = Q R holds the residual
+    norms greedy QRCP picked its columns with (q_k . a_{p_k})."""
+    o = make_orbitals(config_spec("c1"))
+    n = o.spec.norb
+    A = o.psi.reshape(n, -1)
+    piv, Q = oracle.qrcp_pivots(A)
+    r = np.abs(np.einsum("ik,ik->k", Q, A[:, piv]))
+    assert abs(oracle.column_quality(o.psi, piv) - (r.max() / r.min()) ** 2) < 1e-12 * (r.max() / r.min()) ** 2
+    # greedy pivoting: the picked residual norms never increase
+    assert np.all(np.diff(r) <= 1e-12 * r[0])
+
+
+def test_p12_column_quality_bounds_and_diagonal_case():
+    s0 = config_spec("c1")
+    psi = make_orbitals(s0.replace(md_step=2)).psi
+    n = s0.norb
+    piv0, _ = oracle.qrcp_pivots(make_orbitals(s0).psi.reshape(n, -1))
+    q = oracle.column_quality(psi, piv0)
+    AC = psi.reshape(n, -1)[:, piv0]
+    w = np.linalg.eigvalsh(AC.T @ AC)
+    assert 1.0 <= q <= w.max() / w.min() * (1 + 1e-12)
+    # disjoint Gaussians sampled at their own centres: A_C is diagonal up to
+    # the tiny tails, and the ratio is that of the squared peak values
+    spec = SystemSpec(n_mol=1, L=12.0, N=24, sigma=0.6, seed=9)
+    cen = [(2.0, 2.0, 2.0), (8.0, 2.0, 2.0), (2.0, 8.0, 8.0), (8.0, 8.0, 5.0)]
+    g = disjoint_gaussians(spec, cen)
+    g[1] *= 0.5
+    h = spec.L / spec.N
+    idx = [int(round(z / h)) * spec.N ** 2 + int(round(y / h)) * spec.N + int(round(x / h)) for x, y, z in cen]
+    peaks = np.array([g[k].reshape(-1)[idx[k]] for k in range(4)])
+    assert abs(oracle.column_quality(g, idx) - (peaks.max() / peaks.min()) ** 2) < 1e-8 * (peaks.max() / peaks.min()) ** 2
+    assert oracle.column_quality(g, [idx[0], idx[0] + 1, idx[0] + 2, idx[0] + 3]) > 1e3
+
+
+def test_p12_localize_step_keeps_or_refreshes_columns():
+    s0 = config_spec("c1")
+    psi0 = make_orbitals(s0).psi
+    psi1 = make_orbitals(s0.replace(md_step=1)).psi
+    n = s0.norb
+    piv0, _, _ = oracle.scdm_localize(psi0, s0.dV)
+    piv, U, phi, reused, q = oracle.localize_step(psi1, piv0, s0.dV, 2.0)
+    assert reused and np.array_equal(piv, piv0) and 1.0 < q < 2.0
+    U_ref, phi_ref = oracle.lowdin_columns(psi1, piv0)
+    assert np.array_equal(U, U_ref) and np.array_equal(phi, phi_ref)
+    # a ratio no real column set reaches: fresh SCDM, exactly
+    piv, U, phi, reused, _ = oracle.localize_step(psi1, piv0, s0.dV, 1.0)
+    pf, Uf, phif = oracle.scdm_localize(psi1, s0.dV)
+    assert not reused and np.array_equal(piv, pf) and np.array_equal(phi, phif)
+
+
+def test_p12_pairlist_step_counts_crossings():
+    s0 = config_spec("c1")
+    n = s0.norb
+    piv0, _, phi0 = oracle.scdm_localize(make_orbitals(s0).psi, s0.dV)
+    prev, _ = oracle.pairlist(phi0, s0.dV, 0.05)
+    for t in (1, 2, 3):
+        psi = make_orbitals(s0.replace(md_step=t)).psi
+        _, _, phi, _, _ = oracle.localize_step(psi, piv0, s0.dV, 2.0)
+        pairs, O, added, removed = oracle.pairlist_step(phi, s0.dV, 0.05, prev)
+        np.testing.assert_array_equal(pairs, oracle.pairlist(phi, s0.dV, 0.05)[0])
+        # brute force over every pair of orbitals
+        Ofull = np.array([[s0.dV * np.sum(np.abs(phi[i] * phi[j])) for j in range(n)] for i in range(n)])
+        was = {tuple(p) for p in prev.tolist()}
+        a = sum(1 for i in range(n) for j in range(i, n) if (i == j or Ofull[i, j] >= 0.05) and (i, j) not in was)
+        r = sum(1 for (i, j) in was if not (i == j or Ofull[i, j] >= 0.05))
+        assert (added, removed) == (a, r)
+        assert len(pairs) == len(prev) + added - removed
+        prev = pairs
+    assert oracle.pairlist_step(phi, s0.dV, 0.05, prev)[2:] == (0, 0)
+
+
+def test_p12_full_list_energy_is_the_same_for_kept_and_fresh_columns():
+    """With every pair the exchange energy does not depend on which columns
+    localized the orbitals (rotation invariance), at each MD step."""
+    s0 = config_spec("c1")
+    n = s0.norb
+    piv0, _, _ = oracle.scdm_localize(make_orbitals(s0).psi, s0.dV)
+    full = _full_pairs(n)
+    for t in (1, 2, 3):
+        psi = make_orbitals(s0.replace(md_step=t)).psi
+        _, _, phi_r, reused, _ = oracle.localize_step(psi, piv0, s0.dV, 2.0)
+        _, _, phi_f, fresh, _ = oracle.localize_step(psi, piv0, s0.dV, 1.0)
+        assert reused and not fresh
+        er = oracle.ace_build(phi_r, full, s0.N, s0.L, "bare", 0.1)["ex"]
+        ef = oracle.ace_build(phi_f, full, s0.N, s0.L, "bare", 0.1)["ex"]
+        assert abs(er - ef) < 1e-12 * abs(ef)
