@@ -250,6 +250,46 @@ int ace_exact_exchange(ace_ctx* ctx, const ace_grid* grid, int norb, const doubl
                        int prec, double* W, double* M, double* ex);
 
 /*
+ * Complex orbitals with k-points (the screening criterion of Sec. Theory is
+ * written with phi_j*; Eq. (vx) and Appendix A with conjugates).  The
+ * orbitals are Bloch functions psi_a(r) = exp(i k_a.r) u_a(r) on an N_k-point
+ * sampling of the Brillouin zone, given by their cell-periodic parts u.
+ * Complex arrays are interleaved (re, im) FP64 pairs.
+ *
+ *   norb    bands per k-point;  nk  k-points (nk * norb <= 2048)
+ *   kvec    HOST [nk][3] k-point coordinates kx, ky, kz (bohr^-1)
+ *   u       [nk * norb][N_G] complex: u_a, a = q * norb + m (k-point q, band m);
+ *           orthonormal within each k-point: dV sum_r conj(u_a) u_b = d_ab
+ *   pairs   [npairs][2] int32 over a: 0 <= a <= b < nk * norb, no duplicates
+ *   xi      [nk * norb][N_G] complex projectors (output)
+ *   M       [nk][norb][norb] complex, each Hermitian (output, nullable)
+ *   W       [nk * norb][N_G] complex (output, nullable)
+ *   ex      [1] E_x = (1/N_k) sum_k tr M_k, Hartree (output, nullable)
+ *
+ * For a pair (a, b), d = k_b - k_a and
+ *   V = IFFT( v(|G + d|) FFT(conj(u_a) u_b) )   (Eq. e:vij with the Bloch phase),
+ *   w_b -= V u_a / N_k  and, if a != b,  w_a -= conj(V) u_b / N_k,
+ * i.e. W = V_X psi on the periodic parts, with the Brillouin-zone average.
+ * The operator is block-diagonal in k: per k-point M = dV U^H W made
+ * Hermitian, -M = L L^H, and P = W L^-H (Appendix A), returned by rows as
+ * xi = conj(L)^-1 W, so that V_ACE x = -sum_j xi_j <xi_j|x> dV.  FP64 only.
+ * Errors as ace_build; ACE_E_NOT_PD names the k-point and the column.
+ */
+int ace_build_kpoints(ace_ctx* ctx, const ace_grid* grid, int norb, int nk, const double* kvec, const double* u,
+                      const int32_t* pairs, int64_t npairs, int kernel, double omega, double* xi, double* M,
+                      double* W, double* ex);
+
+/*
+ * Screening of Bloch orbitals (criterion of Sec. Theory with phi_j*): keep
+ * (a, b), a <= b, when  dV sum_r |u_a| |u_b|  (= the integral of |psi_a psi_b*|,
+ * |exp(i k.r)| = 1)  >= rho_cut; diagonal pairs always kept.  u as for
+ * ace_build_kpoints with ntot = nk * norb rows; the other arguments and the
+ * errors as ace_pairlist.
+ */
+int ace_pairlist_kpoints(ace_ctx* ctx, const ace_grid* grid, int ntot, const double* u, double rho_cut,
+                         int64_t capacity, int32_t* pairs, double* overlap, int64_t* npairs);
+
+/*
  * Timing.  While enabled, every launch of the hot kernels and every stage of
  * the calls above is bracketed by HIP events on the context stream.
  * ace_profile_read synchronizes and returns, for class `cls`, the number of

@@ -121,6 +121,8 @@ def load(path: str = LIB_PATH):
         "ace_apply_energy": ([P, GP, I, P, I, P, P, P], I),
         "ace_apply_energy_noalloc": ([P, GP, I, P, I, P, P, P], I),
         "ace_exact_exchange": ([P, GP, I, P, I, D, I, P, P, P], I),
+        "ace_build_kpoints": ([P, GP, I, I, C.POINTER(D), P, P, I64, I, D, P, P, P, P], I),
+        "ace_pairlist_kpoints": ([P, GP, I, P, D, I64, P, P, C.POINTER(I64)], I),
         "ace_profile_enable": ([P, I], I),
         "ace_profile_read": ([P, I, C.POINTER(I64), C.POINTER(D), C.POINTER(D), I], I),
         "ace_profile_classes": ([P, C.c_uint], I),
@@ -391,6 +393,43 @@ class Context:
         self._check(self.lib.ace_exact_exchange(self.h, C.byref(g), norb, _ptr(psi), KERNELS[kernel], float(omega),
                                                 PRECISIONS[precision], _ptr(W), _ptr(M), _ptr(ex)))
         return dict(W=W, M=M, ex=ex)
+
+    # ------------------------------------------------------------ complex orbitals, k-points
+    def build_kpoints(self, u, kvec, norb: int, pairs, grid: Grid, kernel: str = "erfc", omega: float = 0.106,
+                      want_M: bool = True, want_W: bool = False):
+        """ACE build of Bloch orbitals: u complex128 [nk * norb, ...grid] (cell-periodic
+        parts), kvec [nk][3] (bohr^-1, host sequence).  Returns dict(xi, M, W, ex)."""
+        import torch
+
+        _require(u, torch.complex128, "u")
+        _require(pairs, torch.int32, "pairs")
+        nk = len(kvec)
+        kv = (C.c_double * (3 * nk))(*[float(x) for k in kvec for x in k])
+        xi = torch.empty_like(u)
+        M = torch.empty(nk, norb, norb, dtype=torch.complex128, device=u.device) if want_M else None
+        W = torch.empty_like(u) if want_W else None
+        ex = torch.empty(1, dtype=torch.float64, device=u.device)
+        self._sync_stream()
+        g = grid.c()
+        self._check(self.lib.ace_build_kpoints(self.h, C.byref(g), norb, nk, kv, _ptr(u), _ptr(pairs), pairs.shape[0],
+                                               KERNELS[kernel], float(omega), _ptr(xi), _ptr(M), _ptr(W), _ptr(ex)))
+        return dict(xi=xi, M=M, W=W, ex=ex)
+
+    def pairlist_kpoints(self, u, grid: Grid, rho_cut: float):
+        """Screened pairs of Bloch orbitals: (pairs[int32, n x 2], overlap[n])."""
+        import torch
+
+        _require(u, torch.complex128, "u")
+        ntot = u.shape[0]
+        cap = ntot * (ntot + 1) // 2
+        pairs = torch.empty(cap, 2, dtype=torch.int32, device=u.device)
+        ov = torch.empty(cap, dtype=torch.float64, device=u.device)
+        n = C.c_int64()
+        self._sync_stream()
+        g = grid.c()
+        self._check(self.lib.ace_pairlist_kpoints(self.h, C.byref(g), ntot, _ptr(u), float(rho_cut), cap, _ptr(pairs),
+                                                  _ptr(ov), C.byref(n)))
+        return pairs[: n.value], ov[: n.value]
 
     # ------------------------------------------------------------ timing / tuning
     def profile(self, enable: bool):

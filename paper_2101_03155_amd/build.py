@@ -10,7 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libace.so")
-SOURCES = ["api.hip", "pair.hip", "gemm.hip", "linalg.hip", "batched.hip", "screener.hip"]
+SOURCES = ["api.hip", "pair.hip", "gemm.hip", "linalg.hip", "batched.hip", "screener.hip", "kpoint.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # no packed FP32 instructions in any generated code

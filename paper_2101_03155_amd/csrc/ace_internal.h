@@ -12,6 +12,13 @@ struct Pack {
   int ia, ja, ib, jb;
 };
 
+// One pair slot of the k-point pair stage: Bloch orbitals a <= b and the
+// shift d = k_b - k_a (bohr^-1) of the kernel; b < 0 marks an empty slot.
+struct KPair {
+  int a, b;
+  double d[3];
+};
+
 // Interaction kernel in reciprocal space: v(G) for the bare Coulomb 1/r
 // (kind 0, v(0)=0) or erfc(omega r)/r (kind 1, v(0)=pi/omega^2).
 struct KernelParams {
@@ -207,5 +214,15 @@ void launch_select(const float* pred, const float* feats, int64_t np, int norb, 
                    const double* O, double rho_cut, float ood_tol, int* ood, double* tau, uint8_t* keep, int64_t cap,
                    int32_t* pairs, int64_t* count, float* q, double* w, hipStream_t s);
 PairShape pair_default_shape(int prec, int N);
+
+// k-point build (kpoint.hip): complex fields as interleaved (re, im) doubles.
+hipError_t kpair_round(int N, const void* u, void* spec, const KPair* slots, int nslots, void* W, const void* tw,
+                       const KernelParams& kp, double c, hipStream_t s);
+void launch_times_minus_i(const void* W, void* Wm, int64_t n, hipStream_t s);
+void launch_hermitize(const double* Re, const double* Im, int n, int nk, void* Mout, void* negM, hipStream_t s);
+void launch_trace_avg(const double* Re, int n, int nk, double* ex, hipStream_t s);
+void launch_chol_c(void* A, int n, int nk, int* info, hipStream_t s);
+void launch_trinv_c(const void* L, int n, int nk, double* Xr, double* Xi, hipStream_t s);
+void launch_cabs(const void* u, double* a, int64_t n, hipStream_t s);
 
 }  // namespace ace

@@ -799,11 +799,20 @@ int ace_localize_step(ace_ctx* c, const ace_grid* g, int norb, const double* psi
 }
 
 // ------------------------------------------------------------------ (b) pairlist
+static int pairlist_core(ace_ctx* c, const ace_grid* g, int norb, const double* phi, double rho_cut,
+                         int64_t capacity, int32_t* pairs, double* overlap, int64_t* npairs);
+
 int ace_pairlist(ace_ctx* c, const ace_grid* g, int norb, const double* phi, double rho_cut, int64_t capacity,
                  int32_t* pairs, double* overlap, int64_t* npairs) {
   if (!c) return ACE_E_ARG;
   int rc = check_grid(c, g, norb);
   if (rc) return rc;
+  return pairlist_core(c, g, norb, phi, rho_cut, capacity, pairs, overlap, npairs);
+}
+
+// O = dV |A| |A|^T over the rows of A (norb of them), compacted at rho_cut.
+static int pairlist_core(ace_ctx* c, const ace_grid* g, int norb, const double* phi, double rho_cut,
+                         int64_t capacity, int32_t* pairs, double* overlap, int64_t* npairs) {
   if (!phi || !pairs || !npairs) return fail(c, ACE_E_ARG, "phi, pairs and npairs must be non-NULL");
   if (capacity < 0) return fail(c, ACE_E_ARG, "negative capacity");
   if (!std::isfinite(rho_cut)) return fail(c, ACE_E_ARG, "rho_cut must be finite");
@@ -1182,6 +1191,131 @@ int ace_apply_energy_noalloc(ace_ctx* c, const ace_grid* g, int norb, const doub
   launch_neg_sumsq(cb, mn, ex, s);
   HIPCHK(c, hipGetLastError());
   return ACE_OK;
+}
+
+
+// ------------------------------------------------------------------ complex orbitals, k-points
+int ace_build_kpoints(ace_ctx* c, const ace_grid* g, int norb, int nk, const double* kvec, const double* u,
+                      const int32_t* pairs, int64_t npairs, int kernel, double omega, double* xi, double* Mout,
+                      double* Wout, double* ex) {
+  if (!c) return ACE_E_ARG;
+  int rc = check_grid(c, g, norb);
+  if (rc) return rc;
+  if (nk < 1 || int64_t(nk) * norb > 2048) return fail(c, ACE_E_ARG, "nk=%d: need 1 <= nk and nk * norb <= 2048", nk);
+  if (!kvec || !u || !pairs || !xi) return fail(c, ACE_E_ARG, "kvec, u, pairs and xi must be non-NULL");
+  for (int q = 0; q < 3 * nk; ++q)
+    if (!std::isfinite(kvec[q])) return fail(c, ACE_E_ARG, "non-finite k-point coordinate");
+  if (kernel != ACE_KERNEL_COULOMB && kernel != ACE_KERNEL_ERFC) return fail(c, ACE_E_ARG, "unknown kernel %d", kernel);
+  if (kernel == ACE_KERNEL_ERFC && !(omega > 0.0)) return fail(c, ACE_E_ARG, "omega must be > 0 for erfc");
+  const int ntot = nk * norb;
+  const int64_t maxp = int64_t(ntot) * (ntot + 1) / 2;
+  if (npairs < 1 || npairs > maxp) return fail(c, ACE_E_ARG, "npairs=%lld outside [1, %lld]", (long long)npairs,
+                                               (long long)maxp);
+  const int N = g->n[0];
+  const int64_t ng = grid_size(g);
+  const double dV = grid_dv(g);
+  hipStream_t s = c->stream;
+  std::vector<int32_t> pr(size_t(2 * npairs));
+  HIPCHK(c, hipMemcpyAsync(pr.data(), pairs, pr.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  std::shared_ptr<const Schedule> Sp;
+  rc = schedule_for(c, pr, npairs, ntot, 16, &Sp);
+  if (rc) return rc;
+  const Schedule& S = *Sp;
+  // one slot per pair of every pack, launches in the schedule's order
+  std::vector<KPair> slots(2 * S.packs.size());
+  for (size_t p = 0; p < S.packs.size(); ++p) {
+    const Pack& pk = S.packs[p];
+    for (int h = 0; h < 2; ++h) {
+      KPair& kq = slots[2 * p + h];
+      kq.a = h ? pk.ib : pk.ia;
+      kq.b = h ? pk.jb : pk.ja;
+      for (int d = 0; d < 3; ++d)
+        kq.d[d] = kq.b < 0 ? 0.0 : kvec[3 * (kq.b / norb) + d] - kvec[3 * (kq.a / norb) + d];
+    }
+  }
+  const void* tw;
+  rc = twiddles(c, N, 0, &tw);
+  if (rc) return rc;
+  const size_t cbytes = size_t(ntot) * ng * 2 * sizeof(double);  // one complex array of every orbital
+  KPair* dslots;
+  double *spec, *W, *Wm, *Mre, *Mim, *part, *negM, *Lr, *Li, *X2;
+  int* info;
+  int64_t kchunk;
+  const int64_t nsplit = gemm_nt_nsplit(norb, norb, 2 * ng, &kchunk);
+  WS(c, "kslots", slots.size() * sizeof(KPair), dslots);
+  WS(c, "kspec", size_t(2 * S.max_launch) * ng * 2 * sizeof(double), spec);
+  if (Wout) W = Wout; else WS(c, "kW", cbytes, W);
+  WS(c, "kWm", cbytes, Wm);
+  WS(c, "kMre", size_t(nk) * norb * norb * sizeof(double), Mre);
+  WS(c, "kMim", size_t(nk) * norb * norb * sizeof(double), Mim);
+  WS(c, "mpart", size_t(nsplit) * norb * norb * sizeof(double), part);
+  WS(c, "knegM", size_t(nk) * norb * norb * 2 * sizeof(double), negM);
+  WS(c, "kLr", size_t(nk) * norb * norb * sizeof(double), Lr);
+  WS(c, "kLi", size_t(nk) * norb * norb * sizeof(double), Li);
+  WS(c, "kX2", size_t(norb) * ng * 2 * sizeof(double), X2);
+  WS(c, "kinfo", size_t(nk) * sizeof(int) + 64, info);
+  HIPCHK(c, hipMemcpyAsync(dslots, slots.data(), slots.size() * sizeof(KPair), hipMemcpyHostToDevice, s));
+  launch_zero(W, cbytes, s);
+  KernelParams kp;
+  kp.kind = kernel;
+  kp.omega = omega;
+  kp.inv_ng = 1.0 / double(ng);
+  for (int d = 0; d < 3; ++d) kp.g[d] = 2.0 * 3.141592653589793238462643383279502884 / g->L[d];
+  // (c) pair potentials and W, launch by launch (each conflict-free)
+  for (const Schedule::Launch& l : S.launches)
+    HIPCHK(c, kpair_round(N, u, spec, dslots + 2 * size_t(l.first), 2 * l.second, W, tw, kp, 1.0 / nk, s));
+  // (d) per k-point M = dV U^H W from real products over the interleaved rows
+  launch_times_minus_i(W, Wm, int64_t(ntot) * ng, s);
+  for (int q = 0; q < nk; ++q) {
+    const size_t ro = size_t(q) * norb * ng * 2;
+    const size_t mo = size_t(q) * norb * norb;
+    HIPCHK(c, gemm_nt(0, 0, u + ro, 2 * ng, W + ro, 2 * ng, norb, norb, 2 * ng, dV, part, Mre + mo, s, nullptr));
+    HIPCHK(c, gemm_nt(0, 0, u + ro, 2 * ng, Wm + ro, 2 * ng, norb, norb, 2 * ng, dV, part, Mim + mo, s, nullptr));
+  }
+  launch_hermitize(Mre, Mim, norb, nk, Mout, negM, s);
+  if (ex) launch_trace_avg(Mre, norb, nk, ex, s);
+  // -M = L L^H per k-point
+  launch_zero(info, size_t(nk) * sizeof(int), s);
+  launch_chol_c(negM, norb, nk, info, s);
+  std::vector<int> hinfo(static_cast<size_t>(nk));
+  HIPCHK(c, hipMemcpyAsync(hinfo.data(), info, size_t(nk) * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  for (int q = 0; q < nk; ++q) {
+    if (hinfo[size_t(q)] > 0)
+      return fail(c, ACE_E_NOT_PD, "-M of k-point %d is not positive definite (Cholesky column %d)", q,
+                  hinfo[size_t(q)] - 1);
+    if (hinfo[size_t(q)] < 0)
+      return fail(c, ACE_E_NONFINITE, "non-finite value in M of k-point %d (column %d)", q, -hinfo[size_t(q)] - 1);
+  }
+  // (e) xi = conj(L)^-1 W = Re(L^-1) W + Im(L^-1) (-i W), per k-point
+  launch_trinv_c(negM, norb, nk, Lr, Li, s);
+  for (int q = 0; q < nk; ++q) {
+    const size_t ro = size_t(q) * norb * ng * 2;
+    const size_t mo = size_t(q) * norb * norb;
+    HIPCHK(c, gemm_ls(0, false, true, Lr + mo, norb, W + ro, 2 * ng, xi + ro, 2 * ng, norb, norb, 2 * ng, 1.0, s,
+                      nullptr));
+    HIPCHK(c, gemm_ls(0, false, true, Li + mo, norb, Wm + ro, 2 * ng, X2, 2 * ng, norb, norb, 2 * ng, 1.0, s,
+                      nullptr));
+    launch_add_inplace(xi + ro, X2, int64_t(norb) * ng * 2, s);
+  }
+  HIPCHK(c, hipGetLastError());
+  return ACE_OK;
+}
+
+int ace_pairlist_kpoints(ace_ctx* c, const ace_grid* g, int ntot, const double* u, double rho_cut, int64_t capacity,
+                         int32_t* pairs, double* overlap, int64_t* npairs) {
+  if (!c) return ACE_E_ARG;
+  if (!g) return fail(c, ACE_E_ARG, "grid is NULL");
+  if (ntot < 1 || ntot > 2048) return fail(c, ACE_E_ARG, "ntot=%d outside [1, 2048]", ntot);
+  if (!u) return fail(c, ACE_E_ARG, "u must be non-NULL");
+  int rc = check_grid(c, g, 1);
+  if (rc) return rc;
+  const int64_t ng = grid_size(g);
+  double* mag;
+  WS(c, "kabs", size_t(ntot) * ng * sizeof(double), mag);
+  launch_cabs(u, mag, int64_t(ntot) * ng, c->stream);
+  return pairlist_core(c, g, ntot, mag, rho_cut, capacity, pairs, overlap, npairs);
 }
 
 

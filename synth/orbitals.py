@@ -314,3 +314,43 @@ def disjoint_gaussians(spec: SystemSpec, centres: Sequence) -> np.ndarray:
     g = (f[:, 2, :, None, None] * f[:, 1, None, :, None]) * f[:, 0, None, None, :]
     g /= np.sqrt((g * g).sum(axis=(1, 2, 3)) * spec.dV)[:, None, None, None]
     return g
+
+
+def _haar_unitary(rng: np.random.Generator, n: int) -> np.ndarray:
+    z = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+    q, r = np.linalg.qr(z)
+    d = np.diag(r)
+    return q * (d / np.abs(d))[None, :]
+
+
+def make_bloch_orbitals(spec: SystemSpec, kfrac: Sequence) -> tuple:
+    """Complex Bloch orbitals on a k-point sampling, by their cell-periodic parts.
+
+    The molecules and Gaussians are drawn as by make_orbitals.  For each
+    k-point k = 2 pi kfrac / L each Gaussian g becomes the Bloch sum
+    sum_R exp(i k.R) g(r - R) over the 27 nearest images, whose cell-periodic
+    part is exp(-i k.r) times it; the norb sums of each k-point are mixed by a
+    seeded Haar-random unitary matrix and Loewdin-orthonormalized on the grid.
+    Returns (u complex [n_k * norb][N][N][N], a = q * norb + m;
+    kvec [n_k][3] in bohr^-1)."""
+    rng = np.random.default_rng(spec.seed)
+    _, gauss_centres = _draw_geometry(spec, rng)
+    L, N, s = spec.L, spec.N, spec.sigma
+    x = np.arange(N) * (L / N)
+    kf = np.asarray(kfrac, dtype=np.float64).reshape(-1, 3)
+    kvec = 2.0 * np.pi * kf / L
+    out = np.empty((len(kf) * spec.norb, N, N, N), dtype=np.complex128)
+    for q, k in enumerate(kvec):
+        prof = np.zeros((spec.norb, 3, N), dtype=np.complex128)
+        for n in (-1, 0, 1):
+            diff = x[None, None, :] - gauss_centres[:, :, None] - n * L
+            prof += np.exp(1j * k[None, :, None] * n * L) * np.exp(-(diff * diff) / (2.0 * s * s))
+        prof *= np.exp(-1j * k[None, :, None] * x[None, None, :])
+        ov = np.einsum("adx,bdx->abd", np.conj(prof), prof)
+        S = spec.dV * np.prod(ov, axis=2)
+        U = _haar_unitary(rng, spec.norb)
+        w, V = np.linalg.eigh(U.conj().T @ S @ U)
+        C = U @ (V @ np.diag(w ** -0.5) @ V.conj().T)
+        g = (prof[:, 2, :, None, None] * prof[:, 1, None, :, None]) * prof[:, 0, None, None, :]
+        out[q * spec.norb:(q + 1) * spec.norb] = (C.T @ g.reshape(spec.norb, -1)).reshape(spec.norb, N, N, N)
+    return out, kvec
