@@ -105,8 +105,9 @@ hipError_t pair_owner(int prec, int N, const void* phi, void* spec, const Pack* 
                       const int32_t* adj_ptr, const int32_t* adj, int norb, int64_t nadj, void* W, double* epart,
                       const void* tw, const KernelParams& kp, const void* vt, int chunk, hipStream_t s,
                       EventRecorder* rec);
-// v(G) / N^3 of every half-spectrum point, [z][y][kx] (N * N * (N/2 + 1)
-// values in the pair-stage precision).
+// v(G) / N^3 over the folded frequencies, [zq][yq][kx] with zq, yq, kx in
+// [0, N/2] ((N/2 + 1)^3 values in the pair-stage precision): v depends on
+// ky and kz only through their squares.
 hipError_t launch_vtable(int prec, int N, const KernelParams& kp, void* vt, hipStream_t s);
 size_t pair_spec_elems(int prec, int N, const PairShape& sh);
 

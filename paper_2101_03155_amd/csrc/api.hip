@@ -975,7 +975,7 @@ static int build_impl(ace_ctx* c, const ace_grid* g, int norb, const double* phi
     WS(c, "adjp", S.adj_ptr.size() * sizeof(int32_t), dadjp);
     WS(c, "adj", std::max<size_t>(S.adj.size(), 2) * sizeof(int32_t), dadj);
     if (pair_energy) WS(c, "epart", size_t(onpk) * nblk * 2 * sizeof(double), epart);
-    WS(c, "vtab", size_t(N) * N * (N / 2 + 1) * es, vtab);
+    WS(c, "vtab", size_t(N / 2 + 1) * (N / 2 + 1) * (N / 2 + 1) * es, vtab);
   } else {
     WS(c, "spec", size_t(S.max_launch) * pair_spec_elems(prec, N, sh) * 2 * es, spec);
     WS(c, "packs", size_t(npk) * sizeof(Pack), dpk);
@@ -1557,7 +1557,7 @@ int ace_build_batched(ace_ctx* c, int nsys, ace_system* sys, int prec, int mode)
       const int n = sys[q].grid.n[0];
       if (n != sizes[a]) continue;
       vt_off[q] = vt_total;
-      vt_total += (int64_t(n) * n * (n / 2 + 1) * int64_t(es) + 255) / 256 * 256;
+      vt_total += (int64_t(n / 2 + 1) * (n / 2 + 1) * (n / 2 + 1) * int64_t(es) + 255) / 256 * 256;
     }
   }
   char* bvt = nullptr;

@@ -441,16 +441,16 @@ hipError_t pair_owner(int prec, int N, const void* phi, void* spec, const Pack* 
 // same values the z pass would evaluate per element (kernel_value).
 template <typename T, int N>
 __global__ void k_vtable(KernelParams kp, T* __restrict__ vt) {
-  constexpr int XS = r2c_xs<N>();
-  constexpr int64_t TOT = int64_t(N) * N * XS;
+  constexpr int XS = r2c_xs<N>(), H = vt_half<N>();
+  constexpr int64_t TOT = int64_t(H) * H * XS;
   for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < TOT; e += int64_t(gridDim.x) * blockDim.x) {
-    const int kx = int(e % XS), y = int((e / XS) % N), z = int(e / (int64_t(XS) * N));
+    const int kx = int(e % XS), y = int((e / XS) % H), z = int(e / (int64_t(XS) * H));
     vt[e] = kernel_value<T, N>(kp, kx, y, z);
   }
 }
 
 hipError_t launch_vtable(int prec, int N, const KernelParams& kp, void* vt, hipStream_t s) {
-  const int64_t tot = int64_t(N) * N * (N / 2 + 1);
+  const int64_t tot = int64_t(N / 2 + 1) * (N / 2 + 1) * (N / 2 + 1);
   const unsigned g = unsigned(std::min<int64_t>((tot + 255) / 256, 2048));
   switch (N) {
 #define X(n)                                                                                                   \

@@ -198,6 +198,11 @@ __device__ __forceinline__ void body_inv_x(const T* __restrict__ phi, const cplx
 // tiles of consecutive (y, kx) columns of the flattened planes.
 
 template <int N> __host__ __device__ constexpr int r2c_xs() { return N / 2 + 1; }
+// v(G) depends on ky and kz through ky^2 and kz^2 only, so its table holds the
+// folded frequencies min(k, N - k) of y and z: [zq][yq][kx], each of y and z
+// N/2 + 1 values, an eighth of the spectrum plane set, which stays in L2.
+template <int N> __host__ __device__ constexpr int vt_half() { return N / 2 + 1; }
+template <int N> __device__ __forceinline__ int vt_fold(int k) { return k <= N / 2 ? k : N - k; }
 template <int N> __host__ __device__ constexpr int r2c_tx() {
   return (N * r2c_xs<N>()) % 16 == 0 ? 16 : (N * r2c_xs<N>()) % 8 == 0 ? 8 : (N * r2c_xs<N>()) % 4 == 0 ? 4 : 2;
 }
@@ -266,9 +271,9 @@ __device__ __forceinline__ void body_fwd_xy_r(const T* __restrict__ pi_, const T
 // With eslot != nullptr the tile's share of sum_r rho v_ij is formed on the
 // way (Parseval: sum_r rho v = sum_G (v(G)/N^3) |rho^(G)|^2, the half spectrum
 // weighted 2 except at kx = 0 and N/2) and written to eslot[0]; red holds
-// NT / 64 doubles.  vt (nullable): the kernel values v(G) of the whole half
-// spectrum, [z][y][kx] as the spectrum, read (before the forward transform,
-// so the loads overlap it) instead of evaluated per element.
+// NT / 64 doubles.  vt (nullable): the kernel values v(G) of launch_vtable,
+// [zq][yq][kx] over the folded z and y frequencies, read (before the forward
+// transform, so the loads overlap it) instead of evaluated per element.
 template <typename T, int N, int TX, int NT, int V = 0>
 __device__ __forceinline__ void body_conv_z_r(cplx<T>* spec_p, int f0, const KernelParams& kp, cplx<T>* buf,
                                               const cplx<T>* tw, int tid, bool active = true,
@@ -286,7 +291,10 @@ __device__ __forceinline__ void body_conv_z_r(cplx<T>* spec_p, int f0, const Ker
 #pragma unroll
     for (int q = 0; q < LV; ++q) {
       const int e = tid + q * NT;
-      if ((E % NT == 0 || e < E) && (PL % TX == 0 || e % TX < ncol)) vv[q] = vt[size_t(e / TX) * PL + f0 + e % TX];
+      if ((E % NT == 0 || e < E) && (PL % TX == 0 || e % TX < ncol)) {
+        const int f = f0 + e % TX;
+        vv[q] = vt[(size_t(vt_fold<N>(e / TX)) * vt_half<N>() + vt_fold<N>(f / XS)) * XS + f % XS];
+      }
     }
   }
   // forward z transforms, the first pass reading the tile from global memory

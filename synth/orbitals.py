@@ -323,14 +323,16 @@ def _haar_unitary(rng: np.random.Generator, n: int) -> np.ndarray:
     return q * (d / np.abs(d))[None, :]
 
 
-def make_bloch_orbitals(spec: SystemSpec, kfrac: Sequence) -> tuple:
+def make_bloch_orbitals(spec: SystemSpec, kfrac: Sequence, mix: bool = True) -> tuple:
     """Complex Bloch orbitals on a k-point sampling, by their cell-periodic parts.
 
     The molecules and Gaussians are drawn as by make_orbitals.  For each
     k-point k = 2 pi kfrac / L each Gaussian g becomes the Bloch sum
     sum_R exp(i k.R) g(r - R) over the 27 nearest images, whose cell-periodic
     part is exp(-i k.r) times it; the norb sums of each k-point are mixed by a
-    seeded Haar-random unitary matrix and Loewdin-orthonormalized on the grid.
+    seeded Haar-random unitary matrix (mix=True; the draw happens either way)
+    and Loewdin-orthonormalized on the grid.  Unmixed, the orbitals stay
+    localized, as localized orbitals are for the screening criterion.
     Returns (u complex [n_k * norb][N][N][N], a = q * norb + m;
     kvec [n_k][3] in bohr^-1)."""
     rng = np.random.default_rng(spec.seed)
@@ -349,6 +351,8 @@ def make_bloch_orbitals(spec: SystemSpec, kfrac: Sequence) -> tuple:
         ov = np.einsum("adx,bdx->abd", np.conj(prof), prof)
         S = spec.dV * np.prod(ov, axis=2)
         U = _haar_unitary(rng, spec.norb)
+        if not mix:
+            U = np.eye(spec.norb)
         w, V = np.linalg.eigh(U.conj().T @ S @ U)
         C = U @ (V @ np.diag(w ** -0.5) @ V.conj().T)
         g = (prof[:, 2, :, None, None] * prof[:, 1, None, :, None]) * prof[:, 0, None, None, :]

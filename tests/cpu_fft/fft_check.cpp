@@ -114,8 +114,10 @@ void check_z(double tol) {
       ref[z * PL + f] = cplx<T>{T(acc.real()), T(acc.imag())};
     }
   }
-  std::vector<T> vt(N * PL);
-  for (int e = 0; e < N * PL; ++e) vt[e] = kernel_value<T, N>(kp, e % XS, (e / XS) % N, e / PL);
+  // the library's table: folded y and z frequencies, [zq][yq][kx]
+  constexpr int H = N / 2 + 1;
+  std::vector<T> vt(H * H * XS);
+  for (int e = 0; e < H * H * XS; ++e) vt[e] = kernel_value<T, N>(kp, e % XS, (e / XS) % H, e / (XS * H));
   std::vector<cplx<T>> buf(N * TX), tw = twiddles<T, N>();
   double es = 0, red[4];
   for (int t = 0; t < NT; ++t) {

@@ -53,12 +53,14 @@ def test_gamma_real_orbitals_match_real_build(ctx):
 
 
 KCASES = [
-    # (grid, molecules, k-points (fractional), kernel, rho_cut)
+    # (grid, molecules, k-points (fractional), kernel, rho_cut); screened cases use
+    # unmixed (localized) Bloch sums, which the criterion can tell apart
     (12, 1, [(0, 0, 0), (0.5, 0, 0)], "bare", 0.0),
     (16, 2, [(0, 0, 0), (0.5, 0, 0), (0, 0.5, 0.5)], "erfc", 0.0),
     (24, 2, [(0, 0, 0), (0.5, 0.5, 0.5)], "erfc", 0.02),
     (32, 3, [(0, 0, 0), (0.25, 0, 0), (0.5, 0, 0), (0.75, 0, 0)], "bare", 0.02),
     (48, 4, [(0, 0, 0), (0.5, 0, 0), (0, 0.5, 0), (0.5, 0.5, 0)], "erfc", 5e-3),
+    (64, 6, [(0, 0, 0), (0.5, 0.5, 0.5)], "erfc", 1e-3),
 ]
 
 
@@ -67,7 +69,7 @@ def test_kpoint_build_matches_oracle(ctx, n, nmol, kf, kind, rho_cut):
     _say(f"k-points N={n} molecules={nmol} nk={len(kf)} {kind} rho_cut={rho_cut}")
     spec = SystemSpec(n_mol=nmol, L=0.45 * n, N=n, sigma=0.8, offset=0.7, placement="uniform", seed=600 + n,
                       kernel=kind, omega=0.5)
-    u, kv = make_bloch_orbitals(spec, kf)
+    u, kv = make_bloch_orbitals(spec, kf, mix=rho_cut == 0.0)
     norb = spec.norb
     g = _grid(n, spec.L)
     ud = torch.as_tensor(u, device="cuda")
@@ -78,7 +80,10 @@ def test_kpoint_build_matches_oracle(ctx, n, nmol, kf, kind, rho_cut):
     ref = ko.ace_build_k(u, kv, norb, pairs_ref, n, spec.L, kind, 0.5)
     r = ctx.build_kpoints(ud, [tuple(k) for k in kv], norb, pg, g, kernel=kind, omega=0.5, want_W=True)
     ex = r["ex"].item()
-    print(f"  {len(pairs_ref)} pairs of {u.shape[0]} Bloch orbitals; E_x {ex:.12f} oracle {ref['ex']:.12f}", flush=True)
+    print(f"  {len(pairs_ref)} of {u.shape[0] * (u.shape[0] + 1) // 2} pairs of {u.shape[0]} Bloch orbitals; "
+          f"E_x {ex:.12f} oracle {ref['ex']:.12f}", flush=True)
+    if rho_cut > 0.0:
+        assert len(pairs_ref) < u.shape[0] * (u.shape[0] + 1) // 2  # the criterion drops pairs here
     assert abs(ex - ref["ex"]) <= 1e-10 * abs(ref["ex"])
     _close(r["W"].cpu().numpy(), ref["W"], 1e-12, "W")
     _close(r["M"].cpu().numpy(), ref["M"], 1e-12, "M")
