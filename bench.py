@@ -538,8 +538,10 @@ def main():
 
     spec = config_spec(args.config)
     kind, omega = spec.kernel, spec.omega
-    o = make_orbitals(spec)
-    psi = torch.as_tensor(o.psi, device="cuda")
+    # the oracle baseline needs the orbitals on the host; otherwise they are
+    # assembled on the device (the large systems)
+    o = make_orbitals(spec, device=None if not args.no_cpu_baseline else "cuda")
+    psi = o.psi if args.no_cpu_baseline else torch.as_tensor(o.psi, device="cuda")
     grid = Grid.cubic(spec.N, spec.L)
     ctx = Context()
     prec = args.precision
