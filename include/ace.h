@@ -116,6 +116,16 @@ int ace_localize_pivots(ace_ctx* ctx, const ace_grid* grid, int norb, const doub
                         double* phi, double* U);
 
 /*
+ * (b) without a host synchronization: as ace_pairlist, but the kept count is
+ * written to npairs (DEVICE int64) and nothing waits for it, so a caller can
+ * queue the screening and the following work without a round trip (or
+ * capture them in a graph after one call has grown the workspaces).  Pairs
+ * beyond capacity are not written; the caller compares *npairs with capacity.
+ */
+int ace_pairlist_device(ace_ctx* ctx, const ace_grid* grid, int norb, const double* phi, double rho_cut,
+                        int64_t capacity, int32_t* pairs, double* overlap, int64_t* npairs);
+
+/*
  * (a) at the next MD step, with the previous step's columns as the warm start
  * (the ACE operator is rebuilt at least once per MD step, Sec. Theory).
  *   pivots  [norb] int32, device (in: the previous step's columns; out: the
@@ -453,6 +463,17 @@ int ace_mlp_grad(ace_ctx* ctx, const float* model, const float* x, const float* 
  * each epoch.  Deterministic for a given seed. */
 int ace_mlp_train(ace_ctx* ctx, float* model, float* adam_m, float* adam_v, const float* x, const float* t, int64_t n,
                   const ace_mlp_hparams* hp, float* loss_curve);
+
+/* Training and inference of the screener on one state array: the model
+ * (ACE_MLP_NMODEL floats, standardization set, e.g. by ace_mlp_fit_norm)
+ * followed by the Adam moments m and v (ACE_MLP_NPARAM floats each).
+ * ace_screener_train: ace_mlp_train on that state (feats [n][5], target [n]
+ * log10 |e_ij|).  ace_screener_predict: predictions pred [n] (log10 |e_ij|)
+ * with the features clipped to the training ranges, as the screening uses
+ * them (ace_mlp_forward with clamp = 1). */
+int ace_screener_train(ace_ctx* ctx, const float* feats, const float* target, int64_t n, const ace_mlp_hparams* hp,
+                       float* state);
+int ace_screener_predict(ace_ctx* ctx, const float* state, const float* feats, int64_t n, float* pred);
 
 /* Learned screening: features and predictions for every pair i <= j, then
  * off-diagonal pairs are dropped in ascending order of predicted |e_ij| while

@@ -139,6 +139,9 @@ def load(path: str = LIB_PATH):
         "ace_mlp_grad": ([P, P, P, P, I64, P, P], I),
         "ace_mlp_train": ([P, P, P, P, P, P, I64, C.POINTER(ace_mlp_hparams), P], I),
         "ace_screen_learned": ([P, GP, I, P, P, D, D, D, I64, P, C.POINTER(I64), C.POINTER(I), I], I),
+        "ace_pairlist_device": ([P, GP, I, P, D, I64, P, P, P], I),
+        "ace_screener_train": ([P, P, P, I64, C.POINTER(ace_mlp_hparams), P], I),
+        "ace_screener_predict": ([P, P, P, I64, P], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -588,6 +591,38 @@ class Context:
         self._check(self.lib.ace_mlp_train(self.h, _ptr(model), _ptr(adam_m), _ptr(adam_v), _ptr(x), _ptr(t),
                                            x.shape[0], C.byref(hp), _ptr(curve)))
         return curve
+
+    def pairlist_device(self, phi, grid: Grid, rho_cut: float, capacity: Optional[int] = None):
+        """Screening with the count left on the device and no host wait:
+        returns (pairs buffer [capacity, 2], overlap buffer, npairs device int64 [1])."""
+        import torch
+
+        _require(phi, torch.float64, "phi")
+        norb = phi.shape[0]
+        cap = norb * (norb + 1) // 2 if capacity is None else int(capacity)
+        pairs = torch.empty(max(cap, 1), 2, dtype=torch.int32, device=phi.device)
+        ov = torch.empty(max(cap, 1), dtype=torch.float64, device=phi.device)
+        n = torch.empty(1, dtype=torch.int64, device=phi.device)
+        self._sync_stream()
+        g = grid.c()
+        self._check(self.lib.ace_pairlist_device(self.h, C.byref(g), norb, _ptr(phi), float(rho_cut), cap, _ptr(pairs),
+                                                 _ptr(ov), _ptr(n)))
+        return pairs, ov, n
+
+    def screener_train(self, state, x, t, lr=1e-3, batch=4096, epochs=10, seed=0, step0=0, beta1=0.9, beta2=0.999,
+                       eps=1e-8):
+        """Adam training on one state array (model, then the two Adam moments)."""
+        hp = ace_mlp_hparams(lr, beta1, beta2, eps, batch, epochs, step0, seed)
+        self._sync_stream()
+        self._check(self.lib.ace_screener_train(self.h, _ptr(x), _ptr(t), x.shape[0], C.byref(hp), _ptr(state)))
+
+    def screener_predict(self, state, x):
+        import torch
+
+        y = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+        self._sync_stream()
+        self._check(self.lib.ace_screener_predict(self.h, _ptr(state), _ptr(x), x.shape[0], _ptr(y)))
+        return y
 
     def screen_learned(self, phi, grid: Grid, model, budget: float, rho_cut_fallback: float = 1e-3,
                        ood_tol: float = 0.05, stride: int = 1):

@@ -838,6 +838,30 @@ static int pairlist_core(ace_ctx* c, const ace_grid* g, int norb, const double* 
   return ACE_OK;
 }
 
+// The screening with the kept count left in device memory and no host
+// synchronization, for callers that queue the screening and the build without
+// waiting (graph capture after a first call has grown the workspaces).
+int ace_pairlist_device(ace_ctx* c, const ace_grid* g, int norb, const double* phi, double rho_cut,
+                        int64_t capacity, int32_t* pairs, double* overlap, int64_t* npairs_dev) {
+  if (!c) return ACE_E_ARG;
+  int rc = check_grid(c, g, norb);
+  if (rc) return rc;
+  if (!phi || !pairs || !npairs_dev) return fail(c, ACE_E_ARG, "phi, pairs and npairs must be non-NULL");
+  if (capacity < 0) return fail(c, ACE_E_ARG, "negative capacity");
+  if (!std::isfinite(rho_cut)) return fail(c, ACE_E_ARG, "rho_cut must be finite");
+  const int64_t ng = grid_size(g);
+  hipStream_t s = c->stream;
+  double *part, *O;
+  int64_t kchunk;
+  const int64_t nsplit = gemm_nt_nsplit(norb, norb, ng, &kchunk);
+  WS(c, "mpart", size_t(nsplit) * norb * norb * sizeof(double), part);
+  WS(c, "O", size_t(norb) * norb * sizeof(double), O);
+  HIPCHK(c, gemm_nt(0, 1, phi, ng, phi, ng, norb, norb, ng, grid_dv(g), part, O, s, nullptr, true));
+  launch_compact_pairs(O, norb, rho_cut, capacity, pairs, overlap, npairs_dev, s);
+  HIPCHK(c, hipGetLastError());
+  return ACE_OK;
+}
+
 // Re-screening at the next MD step against the previous step's list.  With
 // the previous step's columns kept (ace_localize_step), orbital k of this
 // step continues orbital k of the last one, so the two lists compare pair by
@@ -1863,6 +1887,20 @@ int ace_mlp_train(ace_ctx* c, float* model, float* adam_m, float* adam_v, const 
   }
   HIPCHK(c, hipGetLastError());
   return ACE_OK;
+}
+
+// The screener's training and inference under one state array: the model
+// (ACE_MLP_NMODEL floats) followed by the Adam moments (2 x ACE_MLP_NPARAM).
+int ace_screener_train(ace_ctx* c, const float* feats, const float* target, int64_t n, const ace_mlp_hparams* hp,
+                       float* state) {
+  if (!c) return ACE_E_ARG;
+  if (!state) return fail(c, ACE_E_ARG, "state must be non-NULL");
+  return ace_mlp_train(c, state, state + ACE_MLP_NMODEL, state + ACE_MLP_NMODEL + ACE_MLP_NPARAM, feats, target, n,
+                       hp, nullptr);
+}
+
+int ace_screener_predict(ace_ctx* c, const float* state, const float* feats, int64_t n, float* pred) {
+  return ace_mlp_forward(c, state, feats, n, 1, pred);
 }
 
 int ace_screen_learned(ace_ctx* c, const ace_grid* g, int norb, const double* phi, const float* model,

@@ -372,3 +372,54 @@ def test_c2_full_pair_energy(ctx, c2):
     y = ctx.apply(r["xi"], _dev(phi[rows]), _grid(s)).cpu().numpy()
     mel = s.dV * phi.reshape(s.norb, -1) @ y.reshape(len(rows), -1).T
     assert np.abs(mel - mref).max() <= 1e-10
+
+
+# ------------------------------------------------------------------ failure paths, device-count screening
+
+def test_failure_paths_nonfinite_input_and_workspace_cap(lib, c1):
+    """A NaN in the orbitals reaches M and the factorization reports
+    ACE_E_NONFINITE; a workspace cap below the build's needs gives
+    ACE_E_NOMEM before any allocation; a context without the cap still builds."""
+    _say("failure paths: NaN input, workspace cap")
+    import os
+    from paper_2101_03155_amd import AceError
+    o, _, _, phi = c1
+    s = o.spec
+    pairs = _dev(_full_pairs(s.norb))
+    ctx = lib.Context()
+    bad = phi.copy()
+    bad[3, 5, 5, 5] = np.nan
+    with pytest.raises(AceError) as ei:
+        ctx.build(_dev(bad), pairs, _grid(s), kernel="bare")
+    assert ei.value.status == "ACE_E_NONFINITE"
+    old = os.environ.get("ACE_WORKSPACE_MAX")
+    os.environ["ACE_WORKSPACE_MAX"] = "4096"
+    try:
+        capped = lib.Context()
+    finally:
+        if old is None:
+            del os.environ["ACE_WORKSPACE_MAX"]
+        else:
+            os.environ["ACE_WORKSPACE_MAX"] = old
+    with pytest.raises(AceError) as ei:
+        capped.build(_dev(phi), pairs, _grid(s), kernel="bare")
+    assert ei.value.status == "ACE_E_NOMEM" and "ACE_WORKSPACE_MAX" in str(ei.value)
+    r = ctx.build(_dev(phi), pairs, _grid(s), kernel="bare")
+    assert np.isfinite(r["ex"].item())
+
+
+@pytest.mark.parametrize("rho_cut", [0.0, 0.05, 2.0])
+def test_pairlist_device_count(ctx, c1, rho_cut):
+    _say(f"pairlist with the count on the device, rho_cut={rho_cut}")
+    o, _, _, phi = c1
+    s = o.spec
+    ref, ov = oracle.pairlist(phi, s.dV, rho_cut)
+    pairs, gov, n = ctx.pairlist_device(_dev(phi), _grid(s), rho_cut)
+    k = int(n.item())
+    assert k == len(ref)
+    np.testing.assert_array_equal(pairs[:k].cpu().numpy(), ref)
+    np.testing.assert_allclose(gov[:k].cpu().numpy(), ov, atol=1e-14)
+    # a short capacity: the count is still the full one, only the first rows are written
+    pairs, _, n = ctx.pairlist_device(_dev(phi), _grid(s), rho_cut, capacity=5)
+    assert int(n.item()) == len(ref)
+    np.testing.assert_array_equal(pairs[: min(5, len(ref))].cpu().numpy(), ref[:5])

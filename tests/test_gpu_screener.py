@@ -196,4 +196,24 @@ def test_learned_screener_budget_and_gain(ctx):
     print(f"dropped energy at {pairs_l.shape[0]} pairs: learned {err_l_sum:.3e}, overlap order "
           f"{err_overlap_order:.3e}, exact-|e| order {err_best_order:.3e}", flush=True)
     assert abs(err_l_sum - err_l) <= 1e-6 + 1e-3 * err_l
-    assert err_l_sum <= err_overlap_order * 1.05
+    assert err_l_sum <= err_overlap_order
+
+
+def test_screener_state_entry_points_equal_mlp_calls(ctx):
+    """ace_screener_train / ace_screener_predict on one state array give
+    bitwise what ace_mlp_train / ace_mlp_forward (clamped) give."""
+    _say("screener train/predict on one state array")
+    rng = np.random.default_rng(3)
+    x = torch.as_tensor(rng.normal(size=(3000, 5)).astype(np.float32), device="cuda")
+    t = torch.as_tensor(rng.normal(size=3000).astype(np.float32), device="cuda")
+    from paper_2101_03155_amd import ace
+    m1 = ctx.mlp_init(11)
+    ctx.mlp_fit_norm(m1, x, t)
+    am = torch.zeros(ace.MLP_NPARAM, dtype=torch.float32, device="cuda")
+    av = torch.zeros_like(am)
+    state = torch.cat([m1.clone(), am.clone(), av.clone()])
+    ctx.mlp_train(m1, am, av, x, t, lr=1e-3, batch=512, epochs=3, seed=5)
+    ctx.screener_train(state, x, t, lr=1e-3, batch=512, epochs=3, seed=5)
+    assert torch.equal(state[: ace.MLP_NMODEL], m1)
+    assert torch.equal(state[ace.MLP_NMODEL: ace.MLP_NMODEL + ace.MLP_NPARAM], am)
+    assert torch.equal(ctx.screener_predict(state, x), ctx.mlp_forward(m1, x, clamp=True))
