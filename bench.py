@@ -79,9 +79,10 @@ def pair_source_hash():
 
 def counter_row(kernel, N, prec):
     """The committed counter summary's row for a kernel at this size and
-    precision: FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the
-    counter reads for a plain 1 GiB copy, per algorithmic byte.  (None, why)
-    when no row matches or the pair-stage sources changed since."""
+    precision: HBM bytes (read bytes from the per-size read-request counters,
+    WRITE_SIZE for the writes, both checked on a plain 1 GiB copy) per
+    algorithmic byte.  (None, why) when no row matches or the pair-stage
+    sources changed since."""
     import re
 
     if not os.path.exists(COUNTERS_FILE):
@@ -93,7 +94,8 @@ def counter_row(kernel, N, prec):
         if r["kernel"] == kernel and r["N"] == N and r["precision"] == prec:
             if r["source_hash"] != pair_source_hash():
                 return None, "pair-stage sources changed since the counters were taken"
-            return r, "FETCH_SIZE x %.3g + WRITE_SIZE x %.3g" % (r["fetch_scale"], r["write_scale"])
+            return r, ("reads 128 n128 + 64 n64 + 32 n32 from the request-size counters, writes WRITE_SIZE; "
+                       "counters of the %s workload" % r.get("workload", "?"))
     return None, "no counter row for this kernel"
 
 
