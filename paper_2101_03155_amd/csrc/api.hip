@@ -130,6 +130,7 @@ struct ace_ctx {
   std::map<ScheduleKey, std::shared_ptr<const Schedule>> schedules;
   EventRecorder rec;
   bool profiling = false;
+  bool qrcp_coop = true;  // pool steps in one cooperative launch (ACE_QRCP_COOP=0: one launch per step)
   EventRecorder* R() { return profiling ? &rec : nullptr; }
   // batched form
   hipStream_t bstream = nullptr;
@@ -398,6 +399,7 @@ int ace_create(ace_ctx** out, void* stream) {
   }
   if (const char* cap = getenv("ACE_WORKSPACE_MAX")) c->ws_cap = (size_t)strtoull(cap, nullptr, 10);
   if (const char* om = getenv("ACE_OWNER_SPECTRA_MAX")) c->owner_max = (size_t)strtoull(om, nullptr, 10);
+  if (const char* qc = getenv("ACE_QRCP_COOP")) c->qrcp_coop = std::atoi(qc) != 0;
   *out = c;
   return ACE_OK;
 }
@@ -644,13 +646,31 @@ int ace_localize(ace_ctx* c, const ace_grid* g, int norb, const double* psi, dou
           launch_add_inplace(Apool, Tpool, int64_t(norb) * np, s);
         }
       launch_qrcp_update_r(Apool, norb, np, nullptr, pres, pv, pi, iv + 1, s);
+      const int nbp = qrcp_pool_blocks(np);
+      // all the pool's steps in one cooperative launch (a grid barrier between
+      // steps), then the last pick; where the device cannot hold the grid at
+      // once, one launch per step as below
+      bool steps_done = false;
+      if (c->qrcp_coop && k + 1 < norb) {
+        const int nsteps = norb - 1 - k;
+        hipError_t e = launch_qrcp_steps_coop(Apool, norb, np, iv, pv, pi, pv + nbp, pi + nbp, Q, pres, pivots, pool,
+                                              tvals + 1, iv + 1, nsteps, s);
+        if (e == hipSuccess) {
+          const int par = nsteps & 1;
+          launch_qrcp_select_r(Apool, norb, np, iv, pv + size_t(par) * nbp, pi + size_t(par) * nbp, Q, pres, pivots,
+                               q, pool, tvals + 1, iv + 1, s);
+          steps_done = true;
+        } else {
+          (void)hipGetLastError();
+          c->qrcp_coop = false;
+        }
+      }
       // one launch per step (selection repeated in every block, then the
       // update), the block candidates alternating between two halves of pv/pi;
       // steps are queued in batches, and since a batch after a certification
       // failure would only hold no-op launches the flag is checked between them
-      const int nbp = qrcp_pool_blocks(np);
       int par = 0;
-      for (int kk = k; kk < norb;) {
+      for (int kk = k; kk < norb && !steps_done;) {
         const int kend = std::min(norb, kk + 24);
         for (; kk < kend; ++kk) {
           double* pvi = pv + size_t(par) * nbp;

@@ -5,10 +5,13 @@
 //   * Newton-Schulz polar iteration for the Loewdin rotation;
 //   * screening-pair compaction; pair-energy reduction; conversions.
 #include <hip/hip_runtime.h>
+#include <hip/hip_cooperative_groups.h>
 #include <cstdint>
 #include "ace_internal.h"
 
 namespace ace {
+
+namespace cg = cooperative_groups;
 
 // ---------------------------------------------------------------- M handling
 // Msym = (M + M^T)/2 -> out (nullable); negM = -Msym; ex = trace(M).
@@ -670,14 +673,13 @@ __global__ __launch_bounds__(NT) void k_qrcp_select_r(const double* __restrict__
 // racing with its owner.  A failed certification or an exhausted pool
 // raises the stop flag (block 0), and every block returns.
 template <int NT, int CW>
-__global__ __launch_bounds__(NT) void k_qrcp_step_r(double* __restrict__ R, int n, int P, int* __restrict__ kdev,
+__device__ __forceinline__ bool qrcp_step_dev(double* __restrict__ R, int n, int P, int* __restrict__ kdev,
                                                     const double* __restrict__ pv_in,
                                                     const int64_t* __restrict__ pi_in, int nblk,
                                                     double* __restrict__ Q, double* __restrict__ res,
                                                     int32_t* __restrict__ piv, const int32_t* __restrict__ pool,
                                                     const double* __restrict__ t_out, int* __restrict__ stop,
                                                     double* __restrict__ pv_out, int64_t* __restrict__ pi_out) {
-  if (*stop) return;
   constexpr int RG = NT / CW;
   __shared__ double qs[1024];
   __shared__ double red[RG][CW];
@@ -695,7 +697,7 @@ __global__ __launch_bounds__(NT) void k_qrcp_step_r(double* __restrict__ R, int 
   const int64_t b = bi;
   if (b < 0 || b >= P) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *stop = 1;
-    return;
+    return false;
   }
   {
     double v = 0.0;
@@ -712,7 +714,7 @@ __global__ __launch_bounds__(NT) void k_qrcp_step_r(double* __restrict__ R, int 
   const bool ok = r2 > 0.0 && (t_out == nullptr || r2 >= *t_out);
   if (!ok) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *stop = 1;
-    return;
+    return false;
   }
   const double inv = 1.0 / sqrt(r2);
   for (int i = threadIdx.x; i < n; i += NT) qs[i] = R[int64_t(i) * P + b] * inv;
@@ -789,6 +791,46 @@ __global__ __launch_bounds__(NT) void k_qrcp_step_r(double* __restrict__ R, int 
   if (threadIdx.x == 0) {
     pv_out[blockIdx.x] = bv;
     pi_out[blockIdx.x] = bi;
+  }
+  return true;
+}
+
+
+template <int NT, int CW>
+__global__ __launch_bounds__(NT) void k_qrcp_step_r(double* __restrict__ R, int n, int P, int* __restrict__ kdev,
+                                                    const double* __restrict__ pv_in,
+                                                    const int64_t* __restrict__ pi_in, int nblk,
+                                                    double* __restrict__ Q, double* __restrict__ res,
+                                                    int32_t* __restrict__ piv, const int32_t* __restrict__ pool,
+                                                    const double* __restrict__ t_out, int* __restrict__ stop,
+                                                    double* __restrict__ pv_out, int64_t* __restrict__ pi_out) {
+  if (*stop) return;
+  (void)qrcp_step_dev<NT, CW>(R, n, P, kdev, pv_in, pi_in, nblk, Q, res, piv, pool, t_out, stop, pv_out, pi_out);
+}
+
+// Steps k .. k + nsteps - 1 of the pool search in one cooperative launch: the
+// step body above, then a grid barrier, so the next step's selection reads
+// every block's candidates and the updated winner column.  Every block takes
+// the same selection and certification from the same data in the same
+// reduction order, so all blocks leave the loop at the same step (certified
+// to the end, or stopped with the flag set for the host).
+template <int NT, int CW>
+__global__ __launch_bounds__(NT) void k_qrcp_steps_coop(double* __restrict__ R, int n, int P, int* __restrict__ kdev,
+                                                        double* __restrict__ pv0, int64_t* __restrict__ pi0,
+                                                        double* __restrict__ pv1, int64_t* __restrict__ pi1,
+                                                        int nblk, double* __restrict__ Q, double* __restrict__ res,
+                                                        int32_t* __restrict__ piv, const int32_t* __restrict__ pool,
+                                                        const double* __restrict__ t_out, int* __restrict__ stop,
+                                                        int nsteps) {
+  cg::grid_group grid = cg::this_grid();
+  if (*stop) return;
+  int par = 0;
+  for (int s = 0; s < nsteps; ++s) {
+    const bool go = qrcp_step_dev<NT, CW>(R, n, P, kdev, par ? pv1 : pv0, par ? pi1 : pi0, nblk, Q, res, piv, pool,
+                                          t_out, stop, par ? pv0 : pv1, par ? pi0 : pi1);
+    if (!go) break;
+    grid.sync();
+    par ^= 1;
   }
 }
 
@@ -1196,6 +1238,18 @@ void launch_qrcp_step_r(double* R, int n, int P, int* kdev, const double* pv_in,
                         double* pv_out, int64_t* pi_out, hipStream_t s) {
   hipLaunchKernelGGL((k_qrcp_step_r<256, QCW>), dim3(qrcp_pool_blocks(P)), dim3(256), 0, s, R, n, P, kdev, pv_in,
                      pi_in, qrcp_pool_blocks(P), Q, res, piv, pool, t_out, stop, pv_out, pi_out);
+}
+// The steps of one pool in one cooperative launch; hipErrorCooperativeLaunchTooLarge
+// (or another launch error) leaves the caller to queue the steps one by one.
+// The candidates start in (pv0, pi0) and alternate; after nsteps steps they
+// are in buffer nsteps % 2.
+hipError_t launch_qrcp_steps_coop(double* R, int n, int P, int* kdev, double* pv0, int64_t* pi0, double* pv1,
+                                  int64_t* pi1, double* Q, double* res, int32_t* piv, const int32_t* pool,
+                                  const double* t_out, int* stop, int nsteps, hipStream_t s) {
+  int nblk = qrcp_pool_blocks(P);
+  void* args[] = {&R, &n, &P, &kdev, &pv0, &pi0, &pv1, &pi1, &nblk, &Q, &res, &piv, &pool, &t_out, &stop, &nsteps};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_qrcp_steps_coop<256, QCW>), dim3(nblk), dim3(256),
+                                    args, 0, s);
 }
 void launch_add_inplace(double* a, const double* b, int64_t cnt, hipStream_t s) {
   hipLaunchKernelGGL(k_add_inplace, dim3(grid_for(cnt, 256)), dim3(256), 0, s, a, b, cnt);
