@@ -645,20 +645,20 @@ int ace_localize(ace_ctx* c, const ace_grid* g, int norb, const double* psi, dou
           HIPCHK(c, gemm_ls(0, true, false, Q, norb, Lc, np, Tpool, np, norb, k, np, -1.0, s, nullptr));
           launch_add_inplace(Apool, Tpool, int64_t(norb) * np, s);
         }
-      launch_qrcp_update_r(Apool, norb, np, nullptr, pres, pv, pi, iv + 1, s);
       const int nbp = qrcp_pool_blocks(np);
-      // all the pool's steps in one cooperative launch (a grid barrier between
-      // steps), then the last pick; where the device cannot hold the grid at
-      // once, one launch per step as below
+      // the whole pool search in one cooperative launch, the pool's columns
+      // resident in LDS (a grid barrier between picks); where the device
+      // cannot hold the grid at once, one launch per step as below
       bool steps_done = false;
-      if (c->qrcp_coop && k + 1 < norb) {
-        const int nsteps = norb - 1 - k;
-        hipError_t e = launch_qrcp_steps_coop(Apool, norb, np, iv, pv, pi, pv + nbp, pi + nbp, Q, pres, pivots, pool,
-                                              tvals + 1, iv + 1, nsteps, s);
+      if (c->qrcp_coop && k < norb) {
+        const int nbl = qrcp_lds_blocks(norb, np);
+        double *cv, *cc;
+        int64_t* ci;
+        WS(c, "qcv", size_t(2 * nbl) * sizeof(double), cv);
+        WS(c, "qci", size_t(2 * nbl) * sizeof(int64_t), ci);
+        WS(c, "qcc", size_t(2 * nbl) * norb * sizeof(double), cc);
+        hipError_t e = launch_qrcp_pool_lds(Apool, norb, np, k, cv, ci, cc, Q, pivots, pool, tvals + 1, iv, iv + 1, s);
         if (e == hipSuccess) {
-          const int par = nsteps & 1;
-          launch_qrcp_select_r(Apool, norb, np, iv, pv + size_t(par) * nbp, pi + size_t(par) * nbp, Q, pres, pivots,
-                               q, pool, tvals + 1, iv + 1, s);
           steps_done = true;
         } else {
           (void)hipGetLastError();
@@ -669,6 +669,7 @@ int ace_localize(ace_ctx* c, const ace_grid* g, int norb, const double* psi, dou
       // update), the block candidates alternating between two halves of pv/pi;
       // steps are queued in batches, and since a batch after a certification
       // failure would only hold no-op launches the flag is checked between them
+      if (!steps_done) launch_qrcp_update_r(Apool, norb, np, nullptr, pres, pv, pi, iv + 1, s);
       int par = 0;
       for (int kk = k; kk < norb && !steps_done;) {
         const int kend = std::min(norb, kk + 24);
