@@ -151,11 +151,6 @@ void launch_qrcp_step_r(double* R, int n, int P, int* kdev, const double* pv_in,
                         double* res, int32_t* piv, const int32_t* pool, const double* t_out, int* stop,
                         double* pv_out, int64_t* pi_out, hipStream_t s);
 void launch_add_inplace(double* a, const double* b, int64_t cnt, hipStream_t s);
-int qrcp_lds_cols(int n);
-int qrcp_lds_blocks(int n, int P);
-hipError_t launch_qrcp_pool_lds(const double* R, int n, int P, int k0, double* cv, int64_t* ci, double* cc, double* Q,
-                                int32_t* piv, const int32_t* pool, const double* t_out, int* kdev, int* stop,
-                                hipStream_t s);
 void launch_qrcp_select(const double* A, int n, int64_t ng, int* kdev, const double* pv, const int64_t* pi,
                         int nblk, double* Q, double* res, int32_t* piv, double* qout, const int32_t* pool,
                         const double* t_out, int* stop, hipStream_t s);

@@ -130,7 +130,6 @@ struct ace_ctx {
   std::map<ScheduleKey, std::shared_ptr<const Schedule>> schedules;
   EventRecorder rec;
   bool profiling = false;
-  bool qrcp_coop = true;  // pool steps in one cooperative launch (ACE_QRCP_COOP=0: one launch per step)
   EventRecorder* R() { return profiling ? &rec : nullptr; }
   // batched form
   hipStream_t bstream = nullptr;
@@ -399,7 +398,6 @@ int ace_create(ace_ctx** out, void* stream) {
   }
   if (const char* cap = getenv("ACE_WORKSPACE_MAX")) c->ws_cap = (size_t)strtoull(cap, nullptr, 10);
   if (const char* om = getenv("ACE_OWNER_SPECTRA_MAX")) c->owner_max = (size_t)strtoull(om, nullptr, 10);
-  if (const char* qc = getenv("ACE_QRCP_COOP")) c->qrcp_coop = std::atoi(qc) != 0;
   *out = c;
   return ACE_OK;
 }
@@ -645,33 +643,14 @@ int ace_localize(ace_ctx* c, const ace_grid* g, int norb, const double* psi, dou
           HIPCHK(c, gemm_ls(0, true, false, Q, norb, Lc, np, Tpool, np, norb, k, np, -1.0, s, nullptr));
           launch_add_inplace(Apool, Tpool, int64_t(norb) * np, s);
         }
-      const int nbp = qrcp_pool_blocks(np);
-      // the whole pool search in one cooperative launch, the pool's columns
-      // resident in LDS (a grid barrier between picks); where the device
-      // cannot hold the grid at once, one launch per step as below
-      bool steps_done = false;
-      if (c->qrcp_coop && k < norb) {
-        const int nbl = qrcp_lds_blocks(norb, np);
-        double *cv, *cc;
-        int64_t* ci;
-        WS(c, "qcv", size_t(2 * nbl) * sizeof(double), cv);
-        WS(c, "qci", size_t(2 * nbl) * sizeof(int64_t), ci);
-        WS(c, "qcc", size_t(2 * nbl) * norb * sizeof(double), cc);
-        hipError_t e = launch_qrcp_pool_lds(Apool, norb, np, k, cv, ci, cc, Q, pivots, pool, tvals + 1, iv, iv + 1, s);
-        if (e == hipSuccess) {
-          steps_done = true;
-        } else {
-          (void)hipGetLastError();
-          c->qrcp_coop = false;
-        }
-      }
+      launch_qrcp_update_r(Apool, norb, np, nullptr, pres, pv, pi, iv + 1, s);
       // one launch per step (selection repeated in every block, then the
       // update), the block candidates alternating between two halves of pv/pi;
       // steps are queued in batches, and since a batch after a certification
       // failure would only hold no-op launches the flag is checked between them
-      if (!steps_done) launch_qrcp_update_r(Apool, norb, np, nullptr, pres, pv, pi, iv + 1, s);
+      const int nbp = qrcp_pool_blocks(np);
       int par = 0;
-      for (int kk = k; kk < norb && !steps_done;) {
+      for (int kk = k; kk < norb;) {
         const int kend = std::min(norb, kk + 24);
         for (; kk < kend; ++kk) {
           double* pvi = pv + size_t(par) * nbp;

@@ -5,13 +5,10 @@
 //   * Newton-Schulz polar iteration for the Loewdin rotation;
 //   * screening-pair compaction; pair-energy reduction; conversions.
 #include <hip/hip_runtime.h>
-#include <hip/hip_cooperative_groups.h>
 #include <cstdint>
 #include "ace_internal.h"
 
 namespace ace {
-
-namespace cg = cooperative_groups;
 
 // ---------------------------------------------------------------- M handling
 // Msym = (M + M^T)/2 -> out (nullable); negM = -Msym; ex = trace(M).
@@ -673,13 +670,14 @@ __global__ __launch_bounds__(NT) void k_qrcp_select_r(const double* __restrict__
 // racing with its owner.  A failed certification or an exhausted pool
 // raises the stop flag (block 0), and every block returns.
 template <int NT, int CW>
-__device__ __forceinline__ bool qrcp_step_dev(double* __restrict__ R, int n, int P, int* __restrict__ kdev,
+__global__ __launch_bounds__(NT) void k_qrcp_step_r(double* __restrict__ R, int n, int P, int* __restrict__ kdev,
                                                     const double* __restrict__ pv_in,
                                                     const int64_t* __restrict__ pi_in, int nblk,
                                                     double* __restrict__ Q, double* __restrict__ res,
                                                     int32_t* __restrict__ piv, const int32_t* __restrict__ pool,
                                                     const double* __restrict__ t_out, int* __restrict__ stop,
                                                     double* __restrict__ pv_out, int64_t* __restrict__ pi_out) {
+  if (*stop) return;
   constexpr int RG = NT / CW;
   __shared__ double qs[1024];
   __shared__ double red[RG][CW];
@@ -697,7 +695,7 @@ __device__ __forceinline__ bool qrcp_step_dev(double* __restrict__ R, int n, int
   const int64_t b = bi;
   if (b < 0 || b >= P) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *stop = 1;
-    return false;
+    return;
   }
   {
     double v = 0.0;
@@ -714,7 +712,7 @@ __device__ __forceinline__ bool qrcp_step_dev(double* __restrict__ R, int n, int
   const bool ok = r2 > 0.0 && (t_out == nullptr || r2 >= *t_out);
   if (!ok) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *stop = 1;
-    return false;
+    return;
   }
   const double inv = 1.0 / sqrt(r2);
   for (int i = threadIdx.x; i < n; i += NT) qs[i] = R[int64_t(i) * P + b] * inv;
@@ -791,161 +789,6 @@ __device__ __forceinline__ bool qrcp_step_dev(double* __restrict__ R, int n, int
   if (threadIdx.x == 0) {
     pv_out[blockIdx.x] = bv;
     pi_out[blockIdx.x] = bi;
-  }
-  return true;
-}
-
-
-template <int NT, int CW>
-__global__ __launch_bounds__(NT) void k_qrcp_step_r(double* __restrict__ R, int n, int P, int* __restrict__ kdev,
-                                                    const double* __restrict__ pv_in,
-                                                    const int64_t* __restrict__ pi_in, int nblk,
-                                                    double* __restrict__ Q, double* __restrict__ res,
-                                                    int32_t* __restrict__ piv, const int32_t* __restrict__ pool,
-                                                    const double* __restrict__ t_out, int* __restrict__ stop,
-                                                    double* __restrict__ pv_out, int64_t* __restrict__ pi_out) {
-  if (*stop) return;
-  (void)qrcp_step_dev<NT, CW>(R, n, P, kdev, pv_in, pi_in, nblk, Q, res, piv, pool, t_out, stop, pv_out, pi_out);
-}
-
-// The whole search of one candidate pool in one cooperative launch, with
-// the pool's residual columns resident in LDS.  A grid barrier's cost grows
-// with the number of workgroups (measured on this device: about 4 us at 24
-// workgroups, 19 us at 192), so each workgroup holds CWL pool columns
-// (n * CWL doubles, up to 128 KB) and there are few of them.  Per pick:
-//  - every workgroup reads all workgroups' best candidates (value, pool
-//    index) of the previous step and the published column of the winner,
-//    takes the same winner (largest norm, ties to the smaller index),
-//    recomputes its norm from the published values and certifies it against
-//    t_out (the largest bound outside the pool); all workgroups compute the
-//    same result from the same data in the same order, so they agree on
-//    stopping;
-//  - workgroup 0 appends q to Q, records the pivot and advances the count;
-//  - every workgroup projects q out of its live columns, recomputes their
-//    exact norms, and publishes its best column (value, index and its n
-//    values) for the next pick; then the grid barrier.
-// Nothing of R is written back: the host redraws a pool from Psi and Q.
-template <int NT>
-__global__ __launch_bounds__(NT) void k_qrcp_pool_lds(const double* __restrict__ Rg, int n, int P, int CWL, int k0,
-                                                      double* __restrict__ cv, int64_t* __restrict__ ci,
-                                                      double* __restrict__ cc, double* __restrict__ Q,
-                                                      int32_t* __restrict__ piv, const int32_t* __restrict__ pool,
-                                                      const double* __restrict__ t_out, int* __restrict__ kdev,
-                                                      int* __restrict__ stop) {
-  cg::grid_group grid = cg::this_grid();
-  extern __shared__ double lds[];
-  double* Rs = lds;              // [n][CWL]
-  double* qs = lds + size_t(n) * CWL;  // [n]
-  double* nrm = qs + n;          // [CWL] exact squared norms, -1 when retired
-  __shared__ double red[NT];
-  __shared__ double bv;
-  __shared__ int64_t bi;
-  const int NB = gridDim.x, blk = blockIdx.x, tid = threadIdx.x;
-  const int c0 = blk * CWL;
-  const int ncol = (P - c0 < CWL) ? (P - c0 > 0 ? P - c0 : 0) : CWL;
-  const int RG = NT / CWL;  // row groups (CWL divides NT)
-  const int cl = tid % CWL, g = tid / CWL;
-  // load the columns, zero beyond the pool
-  for (int e = tid; e < n * CWL; e += NT) {
-    const int i = e / CWL, c = e % CWL;
-    Rs[e] = (c < ncol) ? Rg[int64_t(i) * P + c0 + c] : 0.0;
-  }
-  __syncthreads();
-  // initial norms and the block's best column
-  auto publish = [&](int par) {
-    double v = 0.0;
-    for (int i = g; i < n; i += RG) {
-      const double x = Rs[i * CWL + cl];
-      v += x * x;
-    }
-    red[tid] = v;
-    __syncthreads();
-    double cand = -INFINITY;
-    int64_t cidx = INT64_MAX;
-    if (g == 0) {
-      double s = 0.0;
-      for (int h = 0; h < RG; ++h) s += red[h * CWL + cl];
-      if (cl < ncol && nrm[cl] > -0.5) {
-        nrm[cl] = s;
-        cand = s;
-        cidx = c0 + cl;
-      }
-    }
-    block_top1<NT>(cand, cidx, &bv, &bi);
-    const int64_t b = bi;
-    if (tid == 0) {
-      cv[par * NB + blk] = bv;
-      ci[par * NB + blk] = b;
-    }
-    double* out = cc + (size_t(par) * NB + blk) * n;
-    const int bl = (b >= c0 && b < c0 + CWL) ? int(b - c0) : -1;
-    for (int i = tid; i < n; i += NT) out[i] = bl >= 0 ? Rs[i * CWL + bl] : 0.0;
-  };
-  for (int c = tid; c < CWL; c += NT) nrm[c] = 0.0;
-  __syncthreads();
-  int par = 0;
-  publish(par);
-  grid.sync();
-  for (int k = k0; k < n; ++k) {
-    // selection: the best of the workgroups' candidates
-    {
-      double v = -INFINITY;
-      int64_t idx = INT64_MAX;
-      for (int e = tid; e < NB; e += NT)
-        if (ranks_before(cv[par * NB + e], ci[par * NB + e], v, idx)) { v = cv[par * NB + e]; idx = ci[par * NB + e]; }
-      block_top1<NT>(v, idx, &bv, &bi);
-    }
-    const int64_t b = bi;
-    if (b < 0 || b >= P) {
-      if (blk == 0 && tid == 0) *stop = 1;
-      return;
-    }
-    const double* wc = cc + (size_t(par) * NB + b / CWL) * n;
-    double v = 0.0;
-    for (int i = tid; i < n; i += NT) {
-      const double x = wc[i];
-      qs[i] = x;
-      v += x * x;
-    }
-    red[tid] = v;
-    __syncthreads();
-    if (tid == 0) {
-      double s = 0.0;
-      for (int h = 0; h < NT; ++h) s += red[h];
-      bv = s;
-    }
-    __syncthreads();
-    const double r2 = bv;
-    if (!(r2 > 0.0) || (t_out != nullptr && !(r2 >= *t_out))) {
-      if (blk == 0 && tid == 0) *stop = 1;
-      return;
-    }
-    const double inv = 1.0 / sqrt(r2);
-    for (int i = tid; i < n; i += NT) qs[i] *= inv;
-    if (b >= c0 && b < c0 + CWL && tid == 0) nrm[b - c0] = -1.0;  // retire the pivot column
-    __syncthreads();
-    if (blk == 0) {
-      for (int i = tid; i < n; i += NT) Q[int64_t(k) * n + i] = qs[i];
-      if (tid == 0) {
-        piv[k] = pool[b];
-        *kdev = k + 1;
-      }
-    }
-    if (k + 1 >= n) break;
-    // update: l = q . R[:, c], R[:, c] -= q l for the live columns
-    double l = 0.0;
-    for (int i = g; i < n; i += RG) l += qs[i] * Rs[i * CWL + cl];
-    red[tid] = l;
-    __syncthreads();
-    l = 0.0;
-    for (int h = 0; h < RG; ++h) l += red[h * CWL + cl];
-    const bool live = cl < ncol && nrm[cl] > -0.5;
-    if (live)
-      for (int i = g; i < n; i += RG) Rs[i * CWL + cl] -= qs[i] * l;
-    __syncthreads();
-    par ^= 1;
-    publish(par);
-    grid.sync();
   }
 }
 
@@ -1353,34 +1196,6 @@ void launch_qrcp_step_r(double* R, int n, int P, int* kdev, const double* pv_in,
                         double* pv_out, int64_t* pi_out, hipStream_t s) {
   hipLaunchKernelGGL((k_qrcp_step_r<256, QCW>), dim3(qrcp_pool_blocks(P)), dim3(256), 0, s, R, n, P, kdev, pv_in,
                      pi_in, qrcp_pool_blocks(P), Q, res, piv, pool, t_out, stop, pv_out, pi_out);
-}
-// The search of one pool in one cooperative launch (k_qrcp_pool_lds);
-// returns the launch error (the caller then queues the steps one by one).
-// cv, ci hold 2 * nblocks candidates and cc 2 * nblocks * n values.
-int qrcp_lds_cols(int n) {
-  int c = 16384 / (n > 0 ? n : 1);
-  c = c > 128 ? 128 : c;
-  int p = 16;
-  while (p * 2 <= c) p *= 2;  // a power of two dividing the 256 threads
-  return c >= 16 ? p : 0;
-}
-int qrcp_lds_blocks(int n, int P) {
-  const int c = qrcp_lds_cols(n);
-  return c ? (P + c - 1) / c : 0;
-}
-hipError_t launch_qrcp_pool_lds(const double* R, int n, int P, int k0, double* cv, int64_t* ci, double* cc, double* Q,
-                                int32_t* piv, const int32_t* pool, const double* t_out, int* kdev, int* stop,
-                                hipStream_t s) {
-  int cwl = qrcp_lds_cols(n);
-  if (!cwl) return hipErrorInvalidValue;
-  const int nblk = (P + cwl - 1) / cwl;
-  const size_t lds = (size_t(n) * cwl + n + cwl) * sizeof(double);
-  void* args[] = {&R, &n, &P, &cwl, &k0, &cv, &ci, &cc, &Q, &piv, &pool, &t_out, &kdev, &stop};
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_qrcp_pool_lds<256>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-  if (e != hipSuccess) return e;
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_qrcp_pool_lds<256>), dim3(nblk), dim3(256), args,
-                                    lds, s);
 }
 void launch_add_inplace(double* a, const double* b, int64_t cnt, hipStream_t s) {
   hipLaunchKernelGGL(k_add_inplace, dim3(grid_for(cnt, 256)), dim3(256), 0, s, a, b, cnt);
