@@ -490,6 +490,28 @@ int ace_screen_learned(ace_ctx* ctx, const ace_grid* grid, int norb, const doubl
                        double budget, double rho_cut_fallback, double ood_tol, int64_t capacity, int32_t* pairs,
                        int64_t* npairs, int* used_fallback, int stride);
 
+/*
+ * Both screening rules behind one record (the screening criterion of Sec.
+ * Theory, or its learned replacement):
+ *   mode 0: the overlap rule at rho_cut (ace_pairlist; overlap nullable);
+ *   mode 1: the learned rule under ex_budget (Hartree) with model, ood_tol and
+ *           the feature stride, and the overlap rule at rho_cut as the
+ *           fallback (ace_screen_learned; overlap must be NULL).
+ * pairs, capacity and *npairs (HOST) as for ace_pairlist; *used_fallback
+ * (nullable) is set when the learned rule fell back.
+ */
+typedef struct {
+  int32_t mode;
+  double rho_cut;
+  double ex_budget;
+  const float* model;
+  double ood_tol;
+  int32_t stride;
+} ace_screen_spec;
+
+int ace_screen(ace_ctx* ctx, const ace_grid* grid, int norb, const double* phi, const ace_screen_spec* screen,
+               int64_t capacity, int32_t* pairs, double* overlap, int64_t* npairs, int* used_fallback);
+
 #ifdef __cplusplus
 }
 #endif

@@ -60,6 +60,11 @@ class ace_step_info(C.Structure):
                 ("pairs_removed", C.c_int64)]
 
 
+class ace_screen_spec(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("rho_cut", C.c_double), ("ex_budget", C.c_double), ("model", C.c_void_p),
+                ("ood_tol", C.c_double), ("stride", C.c_int32)]
+
+
 class ace_mlp_hparams(C.Structure):
     _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
                 ("batch", C.c_int32), ("epochs", C.c_int32), ("step0", C.c_int32), ("seed", C.c_uint64)]
@@ -140,6 +145,7 @@ def load(path: str = LIB_PATH):
         "ace_mlp_train": ([P, P, P, P, P, P, I64, C.POINTER(ace_mlp_hparams), P], I),
         "ace_screen_learned": ([P, GP, I, P, P, D, D, D, I64, P, C.POINTER(I64), C.POINTER(I), I], I),
         "ace_pairlist_device": ([P, GP, I, P, D, I64, P, P, P], I),
+        "ace_screen": ([P, GP, I, P, C.POINTER(ace_screen_spec), I64, P, P, C.POINTER(I64), C.POINTER(I)], I),
         "ace_screener_train": ([P, P, P, I64, C.POINTER(ace_mlp_hparams), P], I),
         "ace_screener_predict": ([P, P, P, I64, P], I),
     }
@@ -608,6 +614,26 @@ class Context:
         self._check(self.lib.ace_pairlist_device(self.h, C.byref(g), norb, _ptr(phi), float(rho_cut), cap, _ptr(pairs),
                                                  _ptr(ov), _ptr(n)))
         return pairs, ov, n
+
+    def screen(self, phi, grid: Grid, rho_cut: float = 1e-3, model=None, budget: float = 0.0, ood_tol: float = 0.05,
+               stride: int = 1):
+        """One call for both rules: the overlap rule (model None) or the learned
+        rule with the overlap rule as fallback.  Returns (pairs, used_fallback)."""
+        import torch
+
+        _require(phi, torch.float64, "phi")
+        norb = phi.shape[0]
+        cap = norb * (norb + 1) // 2
+        pairs = torch.empty(cap, 2, dtype=torch.int32, device=phi.device)
+        sc = ace_screen_spec(0 if model is None else 1, float(rho_cut), float(budget), _ptr(model), float(ood_tol),
+                             int(stride))
+        n = C.c_int64()
+        fb = C.c_int()
+        self._sync_stream()
+        g = grid.c()
+        self._check(self.lib.ace_screen(self.h, C.byref(g), norb, _ptr(phi), C.byref(sc), cap, _ptr(pairs), None,
+                                        C.byref(n), C.byref(fb)))
+        return pairs[: n.value], bool(fb.value)
 
     def screener_train(self, state, x, t, lr=1e-3, batch=4096, epochs=10, seed=0, step0=0, beta1=0.9, beta2=0.999,
                        eps=1e-8):

@@ -1952,4 +1952,17 @@ int ace_screen_learned(ace_ctx* c, const ace_grid* g, int norb, const double* ph
   return ACE_OK;
 }
 
+// One screening call for both rules, selected by the record.
+int ace_screen(ace_ctx* c, const ace_grid* g, int norb, const double* phi, const ace_screen_spec* sc, int64_t capacity,
+               int32_t* pairs, double* overlap, int64_t* npairs, int* used_fallback) {
+  if (!c) return ACE_E_ARG;
+  if (!sc) return fail(c, ACE_E_ARG, "screen record is NULL");
+  if (used_fallback) *used_fallback = 0;
+  if (sc->mode == 0) return ace_pairlist(c, g, norb, phi, sc->rho_cut, capacity, pairs, overlap, npairs);
+  if (sc->mode != 1) return fail(c, ACE_E_ARG, "unknown screening mode %d", sc->mode);
+  if (overlap) return fail(c, ACE_E_ARG, "the learned rule returns no overlaps (pass NULL)");
+  return ace_screen_learned(c, g, norb, phi, sc->model, sc->ex_budget, sc->rho_cut, sc->ood_tol, capacity, pairs,
+                            npairs, used_fallback, sc->stride);
+}
+
 }  // extern "C"

@@ -147,6 +147,12 @@ def test_learned_screener_budget_and_gain(ctx):
     budget = 1e-5 * spec.n_mol
     pairs_l, fb = scr.select(ctx, phi, g, spec.n_mol)
     assert not fb
+    # the same selection and the overlap rule through the one screening record
+    budget_sel = budget / (1.0 + scr.margin)
+    pr, fr = ctx.screen(phi, g, 1e-3, model=scr.model, budget=budget_sel, ood_tol=0.05, stride=scr.stride)
+    assert not fr and torch.equal(pr, pairs_l)
+    po, _ = ctx.screen(phi, g, 1e-3)
+    assert torch.equal(po, ctx.pairlist(phi, g, 1e-3)[0])
     # the kept set is the oracle's budget rule applied to the GPU's own predictions
     # (ties at the boundary aside, which a threshold keeps or drops together)
     from oracle.screener_oracle import budget_selection
