@@ -98,11 +98,13 @@ int pair_energy_blocks(int N, const PairShape& sh);
 bool pair_supported(int N);
 bool pair_r2c_fits(int prec, int N);
 int pair_owner_ntile(int prec, int N);  // z-pass tiles per pair slot of the owner path
-// Owner-computes W over all pairs (spectra of every pair resident); W may be
+// Owner-computes W over all pairs (spectra of every pair resident); operm
+// (nullable) is the order the owners are dispatched in; W may be
 // null (energies only); epart: per (pack, tile) partial energies or null; vt:
 // the table of launch_vtable or null (v(G) evaluated per element).
 hipError_t pair_owner(int prec, int N, const void* phi, void* spec, const Pack* packs, int npacks, int npairs,
-                      const int32_t* adj_ptr, const int32_t* adj, int norb, int64_t nadj, void* W, double* epart,
+                      const int32_t* adj_ptr, const int32_t* adj, const int32_t* operm, int norb, int64_t nadj,
+                      void* W, double* epart,
                       const void* tw, const KernelParams& kp, const void* vt, int chunk, hipStream_t s,
                       EventRecorder* rec);
 // v(G) / N^3 over the folded frequencies, [zq][yq][kx] with zq, yq, kx in

@@ -112,6 +112,10 @@ struct Schedule {
   std::vector<Pack> opacks;
   std::vector<int64_t> opidx;
   std::vector<int32_t> adj_ptr, adj;
+  // the order the owners run in: a reverse Cuthill-McKee order of the pair
+  // graph, so that the owners in flight together are neighbours and read the
+  // same partner rows and spectra; each owner's entries follow it too
+  std::vector<int32_t> operm;
 };
 
 struct ace_ctx {
@@ -130,6 +134,7 @@ struct ace_ctx {
   std::map<ScheduleKey, std::shared_ptr<const Schedule>> schedules;
   EventRecorder rec;
   bool profiling = false;
+  bool owner_order = true;  // owners dispatched in the schedule's order (ACE_OWNER_ORDER=0: index order)
   EventRecorder* R() { return profiling ? &rec : nullptr; }
   // batched form
   hipStream_t bstream = nullptr;
@@ -312,6 +317,45 @@ static void make_schedule(const std::vector<int32_t>& pr, int64_t npairs, int no
 }
 
 // Validate a host copy of a pair list and return its (cached) schedule.
+// Reverse Cuthill-McKee order of the orbitals over the pair graph: breadth
+// first from a vertex of least degree, neighbours in order of increasing
+// degree (then index), each component in turn, the whole order reversed.
+static std::vector<int32_t> rcm_order(int n, const std::vector<int32_t>& adj_ptr, const std::vector<int32_t>& adj) {
+  std::vector<int> deg(size_t(n), 0);
+  for (int k = 0; k < n; ++k)
+    for (int a = adj_ptr[size_t(k)]; a < adj_ptr[size_t(k) + 1]; ++a)
+      if (adj[size_t(2 * a + 1)] != k) ++deg[size_t(k)];
+  std::vector<char> seen(size_t(n), 0);
+  std::vector<int32_t> order;
+  order.reserve(size_t(n));
+  std::vector<int32_t> nb;
+  while (int(order.size()) < n) {
+    int s = -1;
+    for (int k = 0; k < n; ++k)
+      if (!seen[size_t(k)] && (s < 0 || deg[size_t(k)] < deg[size_t(s)])) s = k;
+    seen[size_t(s)] = 1;
+    size_t head = order.size();
+    order.push_back(s);
+    while (head < order.size()) {
+      const int v = order[head++];
+      nb.clear();
+      for (int a = adj_ptr[size_t(v)]; a < adj_ptr[size_t(v) + 1]; ++a) {
+        const int j = adj[size_t(2 * a + 1)];
+        if (!seen[size_t(j)]) {
+          seen[size_t(j)] = 1;
+          nb.push_back(j);
+        }
+      }
+      std::sort(nb.begin(), nb.end(), [&](int x, int y) {
+        return deg[size_t(x)] != deg[size_t(y)] ? deg[size_t(x)] < deg[size_t(y)] : x < y;
+      });
+      order.insert(order.end(), nb.begin(), nb.end());
+    }
+  }
+  std::reverse(order.begin(), order.end());
+  return order;
+}
+
 static void make_owner_schedule(const std::vector<int32_t>& pr, int64_t npairs, int norb, Schedule& S) {
   const int64_t npk = (npairs + 1) / 2;
   S.opacks.resize(size_t(npk));
@@ -350,7 +394,26 @@ static void make_owner_schedule(const std::vector<int32_t>& pr, int64_t npairs, 
       S.adj[size_t(2 * a + 1)] = i;
     }
   }
+  // the owners' order, and each owner's entries by their partner's place in it
+  S.operm = rcm_order(norb, S.adj_ptr, S.adj);
+  std::vector<int32_t> rank(static_cast<size_t>(norb));
+  for (int p = 0; p < norb; ++p) rank[size_t(S.operm[size_t(p)])] = p;
+  std::vector<std::pair<int32_t, int32_t>> ent;
+  for (int k = 0; k < norb; ++k) {
+    const int a0 = S.adj_ptr[size_t(k)], a1 = S.adj_ptr[size_t(k) + 1];
+    ent.clear();
+    for (int a = a0; a < a1; ++a) ent.emplace_back(S.adj[size_t(2 * a)], S.adj[size_t(2 * a + 1)]);
+    std::stable_sort(ent.begin(), ent.end(), [&](const std::pair<int32_t, int32_t>& x,
+                                                 const std::pair<int32_t, int32_t>& y) {
+      return rank[size_t(x.second)] < rank[size_t(y.second)];
+    });
+    for (int a = a0; a < a1; ++a) {
+      S.adj[size_t(2 * a)] = ent[size_t(a - a0)].first;
+      S.adj[size_t(2 * a + 1)] = ent[size_t(a - a0)].second;
+    }
+  }
 }
+
 
 static int schedule_for(ace_ctx* c, const std::vector<int32_t>& pr, int64_t npairs, int norb, int max_packs,
                         std::shared_ptr<const Schedule>* out) {
@@ -398,6 +461,7 @@ int ace_create(ace_ctx** out, void* stream) {
   }
   if (const char* cap = getenv("ACE_WORKSPACE_MAX")) c->ws_cap = (size_t)strtoull(cap, nullptr, 10);
   if (const char* om = getenv("ACE_OWNER_SPECTRA_MAX")) c->owner_max = (size_t)strtoull(om, nullptr, 10);
+  if (const char* oo = getenv("ACE_OWNER_ORDER")) c->owner_order = std::atoi(oo) != 0;
   *out = c;
   return ACE_OK;
 }
@@ -984,7 +1048,7 @@ static int build_impl(ace_ctx* c, const ace_grid* g, int norb, const double* phi
   void *W, *spec, *phiw;
   Pack* dpk;
   int64_t* dpidx;
-  int32_t *dadjp = nullptr, *dadj = nullptr;
+  int32_t *dadjp = nullptr, *dadj = nullptr, *doperm = nullptr;
   double *epart = nullptr, *part, *Mraw, *Lb, *Li, *scal;
   void* vtab = nullptr;
   int* info;
@@ -998,6 +1062,7 @@ static int build_impl(ace_ctx* c, const ace_grid* g, int norb, const double* phi
     WS(c, "pidx", size_t(onpk) * 2 * sizeof(int64_t), dpidx);
     WS(c, "adjp", S.adj_ptr.size() * sizeof(int32_t), dadjp);
     WS(c, "adj", std::max<size_t>(S.adj.size(), 2) * sizeof(int32_t), dadj);
+    WS(c, "operm", size_t(norb) * sizeof(int32_t), doperm);
     if (pair_energy) WS(c, "epart", size_t(onpk) * nblk * 2 * sizeof(double), epart);
     WS(c, "vtab", size_t(N / 2 + 1) * (N / 2 + 1) * (N / 2 + 1) * es, vtab);
   } else {
@@ -1028,6 +1093,7 @@ static int build_impl(ace_ctx* c, const ace_grid* g, int norb, const double* phi
     HIPCHK(c, hipMemcpyAsync(dadjp, S.adj_ptr.data(), S.adj_ptr.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     if (!S.adj.empty())
       HIPCHK(c, hipMemcpyAsync(dadj, S.adj.data(), S.adj.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(doperm, S.operm.data(), size_t(norb) * sizeof(int32_t), hipMemcpyHostToDevice, s));
   } else {
     HIPCHK(c, hipMemcpyAsync(dpk, S.packs.data(), size_t(npk) * sizeof(Pack), hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(dpidx, S.pidx.data(), size_t(npk) * 2 * sizeof(int64_t), hipMemcpyHostToDevice, s));
@@ -1045,8 +1111,8 @@ static int build_impl(ace_ctx* c, const ace_grid* g, int norb, const double* phi
   rec_begin(R, ST_PAIRS, s);
   if (owner) {
     HIPCHK(c, launch_vtable(prec, N, kp, vtab, s));
-    HIPCHK(c, pair_owner(prec, N, phiw, spec, dpk, int(onpk), int(npairs), dadjp, dadj, norb,
-                         int64_t(S.adj.size() / 2), W, epart, tw, kp, vtab, 1 << 30, s, R));
+    HIPCHK(c, pair_owner(prec, N, phiw, spec, dpk, int(onpk), int(npairs), dadjp, dadj, c->owner_order ? doperm : nullptr,
+                         norb, int64_t(S.adj.size() / 2), W, epart, tw, kp, vtab, 1 << 30, s, R));
     if (pair_energy) launch_pair_energy(epart, int(onpk), nblk, dpk, dpidx, dV, pair_energy, s);
   } else {
     for (const auto& L : S.launches) {

@@ -218,7 +218,8 @@ __global__ __launch_bounds__(NT) void k_conv_z_r(cplx<T>* __restrict__ spec, con
 template <typename T, int N, int NT, bool XCD = false>
 __global__ __launch_bounds__(NT, 4) void k_inv_owner_r(const T* __restrict__ phi, const cplx<T>* __restrict__ spec,
                                                     const int32_t* __restrict__ adj_ptr,
-                                                    const int32_t* __restrict__ adj, T* __restrict__ W,
+                                                    const int32_t* __restrict__ adj,
+                                                    const int32_t* __restrict__ operm, T* __restrict__ W,
                                                     const cplx<T>* __restrict__ twg) {
   constexpr size_t NG = size_t(N) * N * N;
   __shared__ cplx<T> buf[N * r2c_xs<N>()];
@@ -233,6 +234,7 @@ __global__ __launch_bounds__(NT, 4) void k_inv_owner_r(const T* __restrict__ phi
     z = (l / norb) * 8 + (i & 7);
     k = l % norb;
   }
+  if (operm) k = operm[k];
   for (int t = threadIdx.x; t < N; t += NT) tw[t] = twg[t];
   const size_t zo = size_t(z) * N * N;
   body_inv_owner_r<T, N, NT>(phi, spec, adj, adj_ptr[k], adj_ptr[k + 1], zo,
@@ -354,7 +356,8 @@ static hipError_t pair_round_t(const PairShape& sh, const void* phi_, void* spec
 // off-diagonal pair, 1 per diagonal one) and writes each W row once.
 template <typename T, int N>
 static hipError_t pair_owner_t(const void* phi_, void* spec_, const Pack* packs, int npacks, int npairs,
-                               const int32_t* adj_ptr, const int32_t* adj, int norb, int64_t nadj, void* W_,
+                               const int32_t* adj_ptr, const int32_t* adj, const int32_t* operm, int norb,
+                               int64_t nadj, void* W_,
                                double* epart, const void* tw_, const KernelParams& kp, const void* vt_, int chunk,
                                hipStream_t s, EventRecorder* rec) {
   if constexpr (!r2c_fits_t<T, N>()) {
@@ -399,9 +402,10 @@ static hipError_t pair_owner_t(const void* phi_, void* spec_, const Pack* packs,
       rec_begin(rec, KC_INV_XY, s);
       if (N % 8 == 0)
         hipLaunchKernelGGL((k_inv_owner_r<T, N, NTR, true>), dim3(N * norb), dim3(NTR), 0, s, phi, spec, adj_ptr, adj,
-                           W, tw);
+                           operm, W, tw);
       else
-        hipLaunchKernelGGL((k_inv_owner_r<T, N, NTR>), dim3(N, norb), dim3(NTR), 0, s, phi, spec, adj_ptr, adj, W, tw);
+        hipLaunchKernelGGL((k_inv_owner_r<T, N, NTR>), dim3(N, norb), dim3(NTR), 0, s, phi, spec, adj_ptr, adj, operm,
+                           W, tw);
       rec_end(rec, KC_INV_XY, s, double(nadj) * (2.0 * SLOT * sizeof(T) + u3) + double(norb) * u3);
     }
     return hipGetLastError();
@@ -420,16 +424,16 @@ bool pair_supported(int N) {
 }
 
 hipError_t pair_owner(int prec, int N, const void* phi, void* spec, const Pack* packs, int npacks, int npairs,
-                      const int32_t* adj_ptr, const int32_t* adj, int norb, int64_t nadj, void* W, double* epart,
-                      const void* tw, const KernelParams& kp, const void* vt, int chunk, hipStream_t s,
-                      EventRecorder* rec) {
+                      const int32_t* adj_ptr, const int32_t* adj, const int32_t* operm, int norb, int64_t nadj,
+                      void* W, double* epart, const void* tw, const KernelParams& kp, const void* vt, int chunk,
+                      hipStream_t s, EventRecorder* rec) {
   switch (N) {
 #define X(n)                                                                                                       \
   case n:                                                                                                          \
-    return prec == 0 ? pair_owner_t<double, n>(phi, spec, packs, npacks, npairs, adj_ptr, adj, norb, nadj, W,      \
-                                               epart, tw, kp, vt, chunk, s, rec)                                   \
-                     : pair_owner_t<float, n>(phi, spec, packs, npacks, npairs, adj_ptr, adj, norb, nadj, W, epart, \
-                                              tw, kp, vt, chunk, s, rec);
+    return prec == 0 ? pair_owner_t<double, n>(phi, spec, packs, npacks, npairs, adj_ptr, adj, operm, norb, nadj, \
+                                               W, epart, tw, kp, vt, chunk, s, rec)                                \
+                     : pair_owner_t<float, n>(phi, spec, packs, npacks, npairs, adj_ptr, adj, operm, norb, nadj, W, \
+                                              epart, tw, kp, vt, chunk, s, rec);
     ACE_PAIR_SIZES(X)
 #undef X
     default:
