@@ -195,6 +195,9 @@ __global__ __launch_bounds__(NT) void k_conv_z_r(cplx<T>* __restrict__ spec, con
   __shared__ cplx<T> tw[N];
   __shared__ double red[NT / 64];
   for (int t = threadIdx.x; t < N; t += NT) tw[t] = twg[t];
+  // the tile's kernel values serve every slot of the workgroup
+  T vv[conv_lv<T, N, TX, NT>()];
+  if (vt) load_vtile<T, N, TX, NT>(vt, blockIdx.x * TX, threadIdx.x, vv);
   for (int q = 0; q < SPW; ++q) {
     const int slot = blockIdx.y * SPW + q;
     if (slot >= nslots) break;
@@ -202,8 +205,8 @@ __global__ __launch_bounds__(NT) void k_conv_z_r(cplx<T>* __restrict__ spec, con
     double* es = epart ? epart + 2 * (size_t(slot >> 1) * gridDim.x + blockIdx.x) + (slot & 1) : nullptr;
     // (each body's first barrier orders the previous body's reads of buf,
     // tw and red before its writes)
-    body_conv_z_r<T, N, TX, NT>(spec + size_t(slot) * N * PL, blockIdx.x * TX, kp, buf, tw, threadIdx.x, true, es,
-                                red, vt);
+    body_conv_z_r_v<T, N, TX, NT>(spec + size_t(slot) * N * PL, blockIdx.x * TX, kp, buf, tw, threadIdx.x, true, es,
+                                  red, vt != nullptr, vv);
   }
 }
 

@@ -275,29 +275,36 @@ __device__ __forceinline__ void body_fwd_xy_r(const T* __restrict__ pi_, const T
 // NT / 64 doubles.  vt (nullable): the kernel values v(G) of launch_vtable,
 // [zq][yq][kx] over the folded z and y frequencies, read (before the forward
 // transform, so the loads overlap it) instead of evaluated per element.
+template <typename T, int N, int TX, int NT> __host__ __device__ constexpr int conv_lv() { return (N * TX + NT - 1) / NT; }
+
+// The kernel values of the TX columns starting at f0 for the elements this
+// thread multiplies in body_conv_z_r_v, from the folded table vt.
+template <typename T, int N, int TX, int NT>
+__device__ __forceinline__ void load_vtile(const T* __restrict__ vt, int f0, int tid, T (&vv)[conv_lv<T, N, TX, NT>()]) {
+  constexpr int XS = r2c_xs<N>(), PL = N * XS, E = N * TX, LV = conv_lv<T, N, TX, NT>();
+  const int ncol = PL - f0 < TX ? PL - f0 : TX;
+#pragma unroll
+  for (int q = 0; q < LV; ++q) {
+    const int e = tid + q * NT;
+    if ((E % NT == 0 || e < E) && (PL % TX == 0 || e % TX < ncol)) {
+      const int f = f0 + e % TX;
+      vv[q] = vt[(size_t(vt_fold<N>(e / TX)) * vt_half<N>() + vt_fold<N>(f / XS)) * XS + f % XS];
+    }
+  }
+}
+
+// body_conv_z_r with the tile's kernel values already in registers (usev) or
+// evaluated per element (kp).
 template <typename T, int N, int TX, int NT, int V = 0>
-__device__ __forceinline__ void body_conv_z_r(cplx<T>* spec_p, int f0, const KernelParams& kp, cplx<T>* buf,
-                                              const cplx<T>* tw, int tid, bool active = true,
-                                              double* eslot = nullptr, double* red = nullptr,
-                                              const T* __restrict__ vt = nullptr) {
+__device__ __forceinline__ void body_conv_z_r_v(cplx<T>* spec_p, int f0, const KernelParams& kp, cplx<T>* buf,
+                                                const cplx<T>* tw, int tid, bool active, double* eslot,
+                                                double* red, bool usev, const T (&vv)[conv_lv<T, N, TX, NT>()]) {
   using C = cplx<T>;
-  constexpr int XS = r2c_xs<N>(), PL = N * XS, E = N * TX;
+  constexpr int XS = r2c_xs<N>(), PL = N * XS, LV = conv_lv<T, N, TX, NT>(), E = N * TX;
   C* base = spec_p + f0;
   // columns of this tile inside the plane (fewer than TX in a ragged last
   // tile, whose other columns are transformed as zeros and not stored)
   const int ncol = PL - f0 < TX ? PL - f0 : TX;
-  constexpr int LV = (E + NT - 1) / NT;
-  T vv[LV];
-  if (vt) {
-#pragma unroll
-    for (int q = 0; q < LV; ++q) {
-      const int e = tid + q * NT;
-      if ((E % NT == 0 || e < E) && (PL % TX == 0 || e % TX < ncol)) {
-        const int f = f0 + e % TX;
-        vv[q] = vt[(size_t(vt_fold<N>(e / TX)) * vt_half<N>() + vt_fold<N>(f / XS)) * XS + f % XS];
-      }
-    }
-  }
   // forward z transforms, the first pass reading the tile from global memory
   fft_lines_load<T, N, TX, 1, TX, NT, -1, false, V>(buf, tw, tid, [=](int l, int p) {
     if (active && (PL % TX == 0 || l < ncol)) return base[size_t(p) * PL + l];
@@ -314,7 +321,7 @@ __device__ __forceinline__ void body_conv_z_r(cplx<T>* spec_p, int f0, const Ker
     if (PL % TX != 0 && e % TX >= ncol) continue;
     const int f = f0 + e % TX;
     const int kx = f % XS;
-    const T v = vt ? vv[q] : kernel_value<T, N>(kp, kx, f / XS, e / TX);
+    const T v = usev ? vv[q] : kernel_value<T, N>(kp, kx, f / XS, e / TX);
     C c = buf[e];
     if (eslot) es += double((kx == 0 || kx == N / 2) ? 1 : 2) * double(v) * (double(c.x) * c.x + double(c.y) * c.y);
     c.x *= v;
@@ -335,6 +342,17 @@ __device__ __forceinline__ void body_conv_z_r(cplx<T>* spec_p, int f0, const Ker
   fft_lines_to<T, N, 0, TX, 1, TX, NT, +1, false, V>(buf, tw, tid, [=](int l, int p, C x) {
     if (active && (PL % TX == 0 || l < ncol)) base[size_t(p) * PL + l] = x;
   });
+}
+
+template <typename T, int N, int TX, int NT, int V = 0>
+__device__ __forceinline__ void body_conv_z_r(cplx<T>* spec_p, int f0, const KernelParams& kp, cplx<T>* buf,
+                                              const cplx<T>* tw, int tid, bool active = true,
+                                              double* eslot = nullptr, double* red = nullptr,
+                                              const T* __restrict__ vt = nullptr) {
+  T vv[conv_lv<T, N, TX, NT>()];
+  // the table loads are issued before the forward transform, so they overlap it
+  if (vt) load_vtile<T, N, TX, NT>(vt, f0, tid, vv);
+  body_conv_z_r_v<T, N, TX, NT, V>(spec_p, f0, kp, buf, tw, tid, active, eslot, red, vt != nullptr, vv);
 }
 
 // Half spectrum of plane z -> the real potential of the plane, left in buf as
