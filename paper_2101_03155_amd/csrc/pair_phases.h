@@ -203,6 +203,16 @@ template <int N> __host__ __device__ constexpr int r2c_xs() { return N / 2 + 1; 
 // N/2 + 1 values, an eighth of the spectrum plane set, which stays in L2.
 template <int N> __host__ __device__ constexpr int vt_half() { return N / 2 + 1; }
 template <int N> __device__ __forceinline__ int vt_fold(int k) { return k <= N / 2 ? k : N - k; }
+// LDS stride of the packed x lines of the in-plane transforms: one complex
+// value of padding per line, so that consecutive lines start in different
+// banks.  The passes that read their inputs from LDS give consecutive threads
+// the same butterfly of consecutive lines, which then hit distinct banks.
+// With unpadded lines and consecutive butterflies of one line per thread
+// group, the Stockham writes of a line fall on a few banks: bank conflicts
+// took over half of the LDS cycles of the owner pass and the forward at 96^3.
+template <int N> __host__ __device__ constexpr int xls() { return N + 1; }
+// position in buf of element e = l * N + x of the packed potential lines
+template <int N> __device__ __forceinline__ int xpos(int e) { return e + e / N * (xls<N>() - N); }
 template <int N> __host__ __device__ constexpr int r2c_tx() {
   return (N * r2c_xs<N>()) % 16 == 0 ? 16 : (N * r2c_xs<N>()) % 8 == 0 ? 8 : (N * r2c_xs<N>()) % 4 == 0 ? 4 : 2;
 }
@@ -234,22 +244,42 @@ __device__ __forceinline__ void body_fwd_xy_r(const T* __restrict__ pi_, const T
     v.y = pi_[(l + H) * N + p] * pj_[(l + H) * N + p];
     return v;
   };
-  if constexpr (H * (N / plan_radix_v(N, 0, V)) >= NT) {
-    fft_lines_load<T, N, H, N, 1, NT, -1, true, V>(buf, tw, tid, prod);
+  // The lines sit at stride xls<N>() in LDS; the passes that read LDS give
+  // consecutive threads the same butterfly of consecutive lines (distinct
+  // banks), a first pass reading global memory consecutive butterflies of
+  // one line (coalesced loads).  With 512 threads the radix order is
+  // reversed: at 96^3 the larger first radix leaves fewer butterflies than
+  // threads, so the products are staged and every pass reads LDS (8% faster;
+  // slower with 1024 threads).
+  constexpr int XL = xls<N>(), VX = NT <= 512 ? (V ^ 1) : V;
+  if constexpr (H * (N / plan_radix_v(N, 0, VX)) >= NT) {
+    fft_pass_l<T, N, 0, H, XL, 1, NT, -1, true, VX>(buf, tw, tid, prod);
+    fft_lines_from<T, N, 1, H, XL, 1, NT, -1, false, VX>(buf, tw, tid);
   } else {
-    stage_in<C, H * N, NT>(buf, [&](int e) { return prod(e / N, e % N); }, tid);
+    constexpr int E = H * N, LP = (E + NT - 1) / NT;
+    C r[LP];
+#pragma unroll
+    for (int q = 0; q < LP; ++q) {
+      const int e = tid + q * NT;
+      if (E % NT == 0 || e < E) r[q] = prod(e / N, e % N);
+    }
+#pragma unroll
+    for (int q = 0; q < LP; ++q) {
+      const int e = tid + q * NT;
+      if (E % NT == 0 || e < E) buf[xpos<N>(e)] = r[q];
+    }
     __syncthreads();
-    fft_lines<T, N, H, N, 1, NT, -1, true, V>(buf, tw, tid);
+    fft_lines<T, N, H, XL, 1, NT, -1, false, VX>(buf, tw, tid);
   }
   // The y transforms of the half spectra, whose first pass separates the two
   // rows of each packed line on the way in: row y < H of column k is
   // X1 = (Z[k] + conj Z[N-k]) / 2 of line y, row y >= H is
   // X2 = (Z[k] - conj Z[N-k]) / 2i of line y - H (Z = line after the x
-  // transform, still in the packed layout [l][N] of buf); the last pass
+  // transform, still in the packed layout of buf); the last pass
   // stores the spectrum ([y][kx]) to global memory.
   auto sep = [buf](int k, int y) {
     const int l = y < H ? y : y - H;
-    const C a = buf[l * N + k], b = buf[l * N + (k == 0 ? 0 : N - k)];
+    const C a = buf[l * XL + k], b = buf[l * XL + (k == 0 ? 0 : N - k)];
     C x;
     if (y < H) {
       x.x = T(0.5) * (a.x + b.x);
@@ -356,7 +386,8 @@ __device__ __forceinline__ void body_conv_z_r(cplx<T>* spec_p, int f0, const Ker
 }
 
 // Half spectrum of plane z -> the real potential of the plane, left in buf as
-// H complex lines: line l holds row l in .x and row l + N/2 in .y.
+// H complex lines of stride xls<N>(): line l holds row l in .x and row
+// l + N/2 in .y.
 // body_inv_xy_t: the same on a plane already staged in buf (and synchronized).
 template <typename T, int N, int NT, int V = 0>
 __device__ __forceinline__ void body_inv_xy_t(cplx<T>* buf, const cplx<T>* tw, int tid);
@@ -397,8 +428,11 @@ __device__ __forceinline__ void inv_x_repacked(cplx<T>* buf, const cplx<T>* tw, 
   // l on the way in: Z[k] = X1[k] + i X2[k] and Z[N-k] = conj X1[k] +
   // i conj X2[k] for k <= H (X1, X2 = rows l, l + H of the [y][kx] layout);
   // the zero and Nyquist bins of a real row are real, as a c2r transform
-  // takes them.
-  fft_lines_load<T, N, H, N, 1, NT, +1, true, V>(buf, tw, tid, [buf](int l, int p) {
+  // takes them.  This pass keeps consecutive butterflies of one line on
+  // consecutive threads (with consecutive lines its re-pack spills registers
+  // in FP64), with the radix order reversed: the larger first radix spreads
+  // its writes over more banks.  The later passes take consecutive lines.
+  fft_pass_l<T, N, 0, H, xls<N>(), 1, NT, +1, true, V ^ 1>(buf, tw, tid, [buf](int l, int p) {
     const bool lowk = p <= H;
     const int k = lowk ? p : N - p;
     C x1 = buf[l * XS + k], x2 = buf[(l + H) * XS + k];
@@ -416,6 +450,7 @@ __device__ __forceinline__ void inv_x_repacked(cplx<T>* buf, const cplx<T>* tw, 
     }
     return z;
   });
+  fft_lines_from<T, N, 1, H, xls<N>(), 1, NT, +1, false, V ^ 1>(buf, tw, tid);
 }
 
 // W_i -= v phi_j and (i != j) W_j -= v phi_i over plane z for one pair, with
@@ -445,7 +480,7 @@ __device__ __forceinline__ void accumulate_w_r(const T* __restrict__ pi_, const 
       for (int u = 0; u < U; ++u) {
         const int e = tid + (q0 + u) * NT;
         if (q0 + u < LP && (HN % NT == 0 || e < HN)) {
-          const cplx<T> v = buf[e];
+          const cplx<T> v = buf[xpos<N>(e)];
           wi[e] = w0[u] - v.x * fj0[u];
           wi[e + HN] = w1[u] - v.y * fj1[u];
           if (off) {
@@ -458,7 +493,7 @@ __device__ __forceinline__ void accumulate_w_r(const T* __restrict__ pi_, const 
     }
   } else if (EN) {
     for (int e = tid; e < HN; e += NT) {
-      const cplx<T> v = buf[e];
+      const cplx<T> v = buf[xpos<N>(e)];
       ea += v.x * pi_[e] * pj_[e] + v.y * pi_[e + HN] * pj_[e + HN];
     }
   }
@@ -516,7 +551,7 @@ __device__ __forceinline__ void body_inv_owner_r(const T* __restrict__ phi, cons
       for (int u = 0; u < U; ++u) {
         const int e = t + (q0 + u) * NT;
         if (q0 + u < LP && (HN % NT == 0 || e < HN)) {
-          const cplx<T> v = buf[e];
+          const cplx<T> v = buf[xpos<N>(e)];
           acc0[q0 + u] += v.x * f0[u];
           acc1[q0 + u] += v.y * f1[u];
         }

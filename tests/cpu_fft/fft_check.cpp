@@ -82,7 +82,8 @@ void check_plane(double tol) {
     for (int x = 0; x < N; ++x) {
       const double r0 = double(pi[l * N + x]) * pj[l * N + x] * N * N;
       const double r1 = double(pi[(l + H) * N + x]) * pj[(l + H) * N + x] * N * N;
-      e2 = std::max(e2, std::max(std::abs(buf[l * N + x].x - r0), std::abs(buf[l * N + x].y - r1)));
+      const auto v = buf[l * xls<N>() + x];
+      e2 = std::max(e2, std::max(std::abs(v.x - r0), std::abs(v.y - r1)));
       m2 = std::max(m2, std::max(std::abs(r0), std::abs(r1)));
     }
   report(sizeof(T) == 8 ? "inverse in-plane round trip, fp64" : "inverse in-plane round trip, fp32", N, e2 / m2, tol);
