@@ -58,6 +58,7 @@ struct BOwner {
   int norb;
   int64_t orb0;              // offset of the system's orbitals among those of the segment
   const int32_t* adj_ptr;    // [norb + 1] absolute offsets into the entry table
+  const int32_t* operm;      // [norb] dispatch order of the owners (nullable: index order)
 };
 
 // Kernel launch shape of the pair stage, chosen by the tuner.

@@ -1529,7 +1529,7 @@ int ace_build_batched(ace_ctx* c, int nsys, ace_system* sys, int prec, int mode)
   std::vector<OwnerSeg> osegs;
   std::vector<BOwner> hown;
   std::vector<int64_t> own_adjp_off;     // offset of each system's adjacency offsets in the table
-  std::vector<int32_t> hadjp, hadj;
+  std::vector<int32_t> hadjp, hadj, hoperm;
   size_t owner_off = 0;
   for (size_t a = 0; a < sizes.size(); ++a) {
     if (!size_owner[a]) continue;
@@ -1554,6 +1554,7 @@ int ace_build_batched(ace_ctx* c, int nsys, ace_system* sys, int prec, int mode)
       o.norb = sys[q].norb;
       o.orb0 = os.items / n;
       own_adjp_off.push_back(int64_t(hadjp.size()));
+      hoperm.insert(hoperm.end(), S.operm.begin(), S.operm.end());
       const int32_t e0 = int32_t(hadj.size() / 2);
       for (int32_t v : S.adj_ptr) hadjp.push_back(v + e0);
       for (size_t e = 0; e < S.adj.size(); e += 2) {
@@ -1653,12 +1654,17 @@ int ace_build_batched(ace_ctx* c, int nsys, ace_system* sys, int prec, int mode)
   char* bvt = nullptr;
   if (vt_total > 0) WS(c, "bvtab", size_t(vt_total), bvt);
   BOwner* dbown = nullptr;
-  int32_t *dbadjp = nullptr, *dbadj = nullptr;
+  int32_t *dbadjp = nullptr, *dbadj = nullptr, *dboperm = nullptr;
   if (!osegs.empty()) {
     WS(c, "bown", std::max<size_t>(hown.size(), 1) * sizeof(BOwner), dbown);
     WS(c, "badjp", std::max<size_t>(hadjp.size(), 1) * sizeof(int32_t), dbadjp);
     WS(c, "badj", std::max<size_t>(hadj.size(), 2) * sizeof(int32_t), dbadj);
-    for (size_t q = 0; q < hown.size(); ++q) hown[q].adj_ptr = dbadjp + own_adjp_off[q];
+    WS(c, "boperm", std::max<size_t>(hoperm.size(), 1) * sizeof(int32_t), dboperm);
+    // the owners of each system run in its schedule's order, as in the single build
+    for (size_t q = 0, off = 0; q < hown.size(); off += size_t(hown[q].norb), ++q) {
+      hown[q].adj_ptr = dbadjp + own_adjp_off[q];
+      hown[q].operm = c->owner_order ? dboperm + off : nullptr;
+    }
   }
   // per-branch scratch of the tails (the branches run concurrently)
   constexpr int NBR = ace_ctx::kTailBranches;
@@ -1709,6 +1715,8 @@ int ace_build_batched(ace_ctx* c, int nsys, ace_system* sys, int prec, int mode)
     HIPCHK(c, hipMemcpyAsync(dbadjp, hadjp.data(), hadjp.size() * sizeof(int32_t), hipMemcpyHostToDevice, us));
     if (!hadj.empty())
       HIPCHK(c, hipMemcpyAsync(dbadj, hadj.data(), hadj.size() * sizeof(int32_t), hipMemcpyHostToDevice, us));
+    if (!hoperm.empty())
+      HIPCHK(c, hipMemcpyAsync(dboperm, hoperm.data(), hoperm.size() * sizeof(int32_t), hipMemcpyHostToDevice, us));
   }
   HIPCHK(c, hipStreamSynchronize(us));
 

@@ -391,7 +391,7 @@ __global__ __launch_bounds__(BNTR, 4) void k_batched_owner_r(int nown, const BOw
   }
   const BOwner o = own[lo];
   const BSys& sy = sys[o.sys];
-  const int k = int(j - o.orb0);
+  const int k = o.operm ? o.operm[j - o.orb0] : int(j - o.orb0);
   const cplx<T>* twg = static_cast<const cplx<T>*>(sy.tw);
   for (int t = threadIdx.x; t < N; t += BNTR) tw[t] = twg[t];
   const size_t zo = size_t(z) * N * N;
