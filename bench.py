@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--screener-bare", default=os.path.join(ROOT, "paper_2101_03155_amd", "models",
                                                              "screener_water_bare.npz"),
                     help="screener trained on bare-Coulomb pair energies (the batched form mixes kernels)")
-    ap.add_argument("--skip-forms", default="", help="comma list of precision,batched,learned,learned_batched")
+    ap.add_argument("--skip-forms", default="", help="comma list of precision,batched,kpoints,learned,learned_batched")
     ap.add_argument("--shape", default="owner", choices=["auto", "default", "fused", "split", "r2c", "owner"],
                     help="pair-stage launch shape: autotuned, library default, or forced (default: owner, the "
                          "fastest measured for this workload, fixed so that profiles and the bench line agree)")
@@ -390,6 +390,58 @@ def form_batched(ctx, log):
     return out
 
 
+def form_kpoints(ctx, log, with_oracle=True):
+    """Complex Bloch orbitals on a 2x2x2 k-point mesh: 8 waters per cell (the
+    32-water cell's density and grid spacing, L = 9.3 bohr on 48^3), 32 bands
+    per k-point, localized Bloch sums screened at rho_cut = 1e-3, erfc kernel.
+    Times the screening and the FP64 build; the split complex passes move
+    16 N^3 16 bytes per pair.  With with_oracle, W rows 0 and n-1 against the
+    k-point oracle over the kept pairs that touch them, and the pair list
+    against the oracle's."""
+    import numpy as np
+    import torch
+
+    from paper_2101_03155_amd import Grid
+    from synth import SystemSpec, make_bloch_orbitals
+
+    spec = SystemSpec(n_mol=8, L=9.3, N=48, sigma=1.0, offset=0.8, placement="lattice", jitter=0.5, seed=7001,
+                      kernel="erfc", omega=0.106)
+    kf = [(a, b, c) for a in (0.0, 0.5) for b in (0.0, 0.5) for c in (0.0, 0.5)]
+    u, kv = make_bloch_orbitals(spec, kf, mix=False)
+    g = Grid.cubic(spec.N, spec.L)
+    ud = torch.as_tensor(u, device="cuda")
+    rho_cut = 1e-3
+    ms_pl, (pairs, _) = _timed(lambda: ctx.pairlist_kpoints(ud, g, rho_cut), 3)
+    ms_b, r = _timed(lambda: ctx.build_kpoints(ud, kv, spec.norb, pairs, g, kernel=spec.kernel, omega=spec.omega,
+                                               want_W=True), 3)
+    npairs = int(pairs.shape[0])
+    ntot = u.shape[0]
+    per_pair = 16 * spec.N ** 3 * 16
+    tbs = per_pair * npairs / (ms_b / 1000.0) / 1e9
+    out = {"workload": f"8 waters per cell, 2x2x2 k-points, {spec.norb} bands per k-point ({ntot} in all), "
+                       f"{spec.N}^3, L={spec.L}, erfc omega={spec.omega}, rho_cut={rho_cut}",
+           "pairs": npairs, "pairs_full": ntot * (ntot + 1) // 2, "pairlist_ms": round(ms_pl, 3),
+           "build_ms": round(ms_b, 3), "pair_solves_per_s": round(npairs / ms_b * 1000, 1),
+           "bytes_per_pair_16N3x16": per_pair, "achieved_gbs": round(tbs, 1),
+           "frac_hbm_peak": round(tbs / HBM_PEAK_GBS, 4), "ex": float(r["ex"].item())}
+    if with_oracle:
+        from oracle import kpoint_oracle as ko
+
+        pl = pairs.cpu().numpy()
+        ref_pairs, _ = ko.pairlist_k(u, spec.dV, rho_cut)
+        out["pairs_equal_oracle"] = bool(np.array_equal(pl, ref_pairs))
+        rows = [0, ntot - 1]
+        touch = pl[np.isin(pl[:, 0], rows) | np.isin(pl[:, 1], rows)]
+        t0 = time.perf_counter()
+        Wref, _ = ko.build_W_k(u, kv, spec.norb, touch, spec.N, spec.L, spec.kernel, spec.omega)
+        Wg = r["W"].cpu().numpy()
+        errs = [float(np.abs(Wg[q] - Wref[q]).max() / np.abs(Wref[q]).max()) for q in rows]
+        out["vs_oracle"] = {"rows": rows, "pairs_touching": int(touch.shape[0]),
+                            "W_max_elem_err_rel": max(errs), "oracle_s": round(time.perf_counter() - t0, 2)}
+    log(f"k-point form: {npairs} pairs, {out['build_ms']} ms, {out['achieved_gbs']} GB/s")
+    return out
+
+
 def form_learned_batched(ctx, log, model_paths, mode="graph"):
     """The learned-screened FP32 batched build against the plain FP64
     full-pair builds of the same 16 systems (8-64 molecules, 48^3-96^3):
@@ -720,6 +772,7 @@ def main():
         forms["incremental"] = form_incremental(ctx, psi, spec, grid, kind, omega, args.rho_cut)
         torch.cuda.empty_cache()
         for name, fn in (("precision", lambda: form_precision(ctx, log)), ("batched", lambda: form_batched(ctx, log)),
+                         ("kpoints", lambda: form_kpoints(ctx, log)),
                          ("learned", lambda: form_learned(ctx, log, args.screener)),
                          ("learned_batched", lambda: form_learned_batched(
                              ctx, log, {"erfc": args.screener, "bare": args.screener_bare},
