@@ -669,7 +669,7 @@ __global__ __launch_bounds__(NT) void k_qrcp_select_r(const double* __restrict__
 // pivot column itself is left untouched, so the blocks that read it are not
 // racing with its owner.  A failed certification or an exhausted pool
 // raises the stop flag (block 0), and every block returns.
-template <int NT, int CW>
+template <int NT, int CW, int MP>
 __global__ __launch_bounds__(NT) void k_qrcp_step_r(double* __restrict__ R, int n, int P, int* __restrict__ kdev,
                                                     const double* __restrict__ pv_in,
                                                     const int64_t* __restrict__ pi_in, int nblk,
@@ -677,13 +677,25 @@ __global__ __launch_bounds__(NT) void k_qrcp_step_r(double* __restrict__ R, int 
                                                     int32_t* __restrict__ piv, const int32_t* __restrict__ pool,
                                                     const double* __restrict__ t_out, int* __restrict__ stop,
                                                     double* __restrict__ pv_out, int64_t* __restrict__ pi_out) {
-  if (*stop) return;
   constexpr int RG = NT / CW;
   __shared__ double qs[1024];
   __shared__ double red[RG][CW];
   __shared__ double r2s[NT / 64];
   __shared__ double bv;
   __shared__ int64_t bi;
+  // The block's residual tile (its CW columns, rows g + m RG) and their
+  // bounds are loaded first: no block writes them before this block does,
+  // so the loads stay in flight through the selection.
+  const int lane = threadIdx.x % CW, g = threadIdx.x / CW;
+  const int c = blockIdx.x * CW + lane;
+  const bool inb = c < P;
+  const int nm = g < n ? (n - g + RG - 1) / RG : 0;  // rows of this thread
+  double xr[MP];
+#pragma unroll
+  for (int m = 0; m < MP; ++m)
+    if (inb && m < nm) xr[m] = R[int64_t(g + m * RG) * P + c];
+  const double rc = inb ? res[c] : -1.0;
+  if (*stop) return;
   // selection, as k_qrcp_select_r
   {
     double v = -INFINITY;
@@ -726,22 +738,25 @@ __global__ __launch_bounds__(NT) void k_qrcp_step_r(double* __restrict__ R, int 
       *kdev = k + 1;
     }
   }
-  // update, as k_qrcp_update_r with q
-  const int lane = threadIdx.x % CW, g = threadIdx.x / CW;
-  const int c = blockIdx.x * CW + lane;
-  const bool live = c < P && c != b && res[c] > -0.5;
+  // update, as k_qrcp_update_r with q (the same sums in the same order)
+  const bool live = inb && c != b && rc > -0.5;
   double* col = R + c;
   double l = 0.0;
   if (live) {
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int i = g;
-    for (; i + 3 * RG < n; i += 4 * RG) {
-      a0 += qs[i] * col[int64_t(i) * P];
-      a1 += qs[i + RG] * col[int64_t(i + RG) * P];
-      a2 += qs[i + 2 * RG] * col[int64_t(i + 2 * RG) * P];
-      a3 += qs[i + 3 * RG] * col[int64_t(i + 3 * RG) * P];
-    }
-    for (; i < n; i += RG) a0 += qs[i] * col[int64_t(i) * P];
+    int m0 = 0;
+#pragma unroll
+    for (int m = 0; m + 3 < MP; m += 4)
+      if (m + 3 < nm) {
+        a0 += qs[g + m * RG] * xr[m];
+        a1 += qs[g + (m + 1) * RG] * xr[m + 1];
+        a2 += qs[g + (m + 2) * RG] * xr[m + 2];
+        a3 += qs[g + (m + 3) * RG] * xr[m + 3];
+        m0 = m + 4;
+      }
+#pragma unroll
+    for (int m = 0; m < MP; ++m)
+      if (m >= m0 && m < nm) a0 += qs[g + m * RG] * xr[m];
     l = (a0 + a1) + (a2 + a3);
   }
   red[g][lane] = l;
@@ -753,22 +768,27 @@ __global__ __launch_bounds__(NT) void k_qrcp_step_r(double* __restrict__ R, int 
   double v = 0.0;
   if (live) {
     double v0 = 0.0, v1 = 0.0;
-    int i = g;
-    for (; i + RG < n; i += 2 * RG) {
-      double x0 = col[int64_t(i) * P], x1 = col[int64_t(i + RG) * P];
-      x0 -= qs[i] * l;
-      x1 -= qs[i + RG] * l;
-      col[int64_t(i) * P] = x0;
-      col[int64_t(i + RG) * P] = x1;
-      v0 += x0 * x0;
-      v1 += x1 * x1;
-    }
-    for (; i < n; i += RG) {
-      double x = col[int64_t(i) * P];
-      x -= qs[i] * l;
-      col[int64_t(i) * P] = x;
-      v0 += x * x;
-    }
+    int m0 = 0;
+#pragma unroll
+    for (int m = 0; m + 1 < MP; m += 2)
+      if (m + 1 < nm) {
+        double x0 = xr[m], x1 = xr[m + 1];
+        x0 -= qs[g + m * RG] * l;
+        x1 -= qs[g + (m + 1) * RG] * l;
+        col[int64_t(g + m * RG) * P] = x0;
+        col[int64_t(g + (m + 1) * RG) * P] = x1;
+        v0 += x0 * x0;
+        v1 += x1 * x1;
+        m0 = m + 2;
+      }
+#pragma unroll
+    for (int m = 0; m < MP; ++m)
+      if (m >= m0 && m < nm) {
+        double x = xr[m];
+        x -= qs[g + m * RG] * l;
+        col[int64_t(g + m * RG) * P] = x;
+        v0 += x * x;
+      }
     v = v0 + v1;
   }
   red[g][lane] = v;
@@ -1194,8 +1214,16 @@ void launch_qrcp_select_r(const double* R, int n, int P, int* kdev, const double
 void launch_qrcp_step_r(double* R, int n, int P, int* kdev, const double* pv_in, const int64_t* pi_in, double* Q,
                         double* res, int32_t* piv, const int32_t* pool, const double* t_out, int* stop,
                         double* pv_out, int64_t* pi_out, hipStream_t s) {
-  hipLaunchKernelGGL((k_qrcp_step_r<256, QCW>), dim3(qrcp_pool_blocks(P)), dim3(256), 0, s, R, n, P, kdev, pv_in,
-                     pi_in, qrcp_pool_blocks(P), Q, res, piv, pool, t_out, stop, pv_out, pi_out);
+  // rows per thread of the block's tile: n / (256 / QCW), held in registers
+#define QSTEP(MPV)                                                                                                 \
+  hipLaunchKernelGGL((k_qrcp_step_r<256, QCW, MPV>), dim3(qrcp_pool_blocks(P)), dim3(256), 0, s, R, n, P, kdev,   \
+                     pv_in, pi_in, qrcp_pool_blocks(P), Q, res, piv, pool, t_out, stop, pv_out, pi_out)
+  constexpr int RG = 256 / QCW;
+  if (n <= 8 * RG) QSTEP(8);
+  else if (n <= 16 * RG) QSTEP(16);
+  else if (n <= 32 * RG) QSTEP(32);
+  else QSTEP(64);
+#undef QSTEP
 }
 void launch_add_inplace(double* a, const double* b, int64_t cnt, hipStream_t s) {
   hipLaunchKernelGGL(k_add_inplace, dim3(grid_for(cnt, 256)), dim3(256), 0, s, a, b, cnt);
