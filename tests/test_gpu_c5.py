@@ -3,8 +3,10 @@ learned-screen form.  The oracle cannot run a whole build at this size in a
 test, so it checks sampled pair energies one by one, and the rest is held to
 properties that hold at any size: orthonormality of the localized orbitals,
 invariance of the occupied projector at sampled grid points, the first SCDM
-pivot, and E_x = sum of the pair energies of the kept pairs (Sec. Theory,
-Appendix A)."""
+pivot, the greedy choice of the pivots at sampled steps (the column picked at
+step k has the largest residual norm once the first k pivot columns are
+projected out, the definition of column-pivoted QR), and E_x = sum of the
+pair energies of the kept pairs (Sec. Theory, Appendix A)."""
 import numpy as np
 import pytest
 
@@ -38,10 +40,35 @@ def c5(ctx):
     pts = torch.as_tensor(np.sort(rng.choice(spec.N ** 3, size=96, replace=False)), device="cuda")
     first = int(torch.argmax((psi * psi).sum(0)).item())
     psi_pts = psi[:, pts].clone()
+    greedy = _greedy_steps(psi, piv.long(), [1, 2, 16, 128, 384, spec.norb - 1])
     del o, psi
     torch.cuda.empty_cache()
     pairs, _ = ctx.pairlist(phi, grid, 1e-3)
-    return dict(spec=spec, grid=grid, phi=phi, piv=piv, pts=pts, psi_pts=psi_pts, first=first, pairs=pairs)
+    return dict(spec=spec, grid=grid, phi=phi, piv=piv, pts=pts, psi_pts=psi_pts, first=first, pairs=pairs,
+                greedy=greedy)
+
+
+def _greedy_steps(A, piv, steps, chunk=1 << 20):
+    """For each step k: the residual norms of all grid columns of A (norb x N_G,
+    on the GPU) after projecting out the columns piv[:k] (an orthonormal basis
+    from a QR of those columns, the projection applied explicitly), returned
+    as (k, residual of piv[k], largest residual, its column)."""
+    out = []
+    for k in steps:
+        Q, _ = torch.linalg.qr(A[:, piv[:k]])
+        best, arg = -1.0, -1
+        for c0 in range(0, A.shape[1], chunk):
+            blk = A[:, c0:c0 + chunk]
+            r = blk - Q @ (Q.T @ blk)
+            r2 = (r * r).sum(0)
+            r2[torch.isin(torch.arange(c0, c0 + blk.shape[1], device=A.device), piv[:k])] = -1.0
+            v, i = torch.max(r2, 0)
+            if float(v) > best:
+                best, arg = float(v), c0 + int(i)
+        col = A[:, piv[k]]
+        rk = col - Q @ (Q.T @ col)
+        out.append((k, float((rk * rk).sum()), best, arg))
+    return out
 
 
 def test_c5_localize_invariants(c5):
@@ -54,6 +81,15 @@ def test_c5_localize_invariants(c5):
     np.testing.assert_allclose((a.T @ a).cpu().numpy(), (b.T @ b).cpu().numpy(), atol=1e-12)
     assert len(set(piv.tolist())) == s.norb
     assert piv[0] == c5["first"]
+
+
+def test_c5_pivots_greedy_at_sampled_steps(c5):
+    _say("c5 localize: greedy pivot choice at sampled steps")
+    piv = c5["piv"].cpu().numpy()
+    for k, rk, best, arg in c5["greedy"]:
+        print(f"  step {k}: pivot {piv[k]} residual {rk:.6e}, largest {best:.6e} at {arg}", flush=True)
+        # the pick is the largest residual; a different column may tie to rounding
+        assert rk >= best * (1.0 - 1e-9), k
 
 
 def _sample_pairs(spec, pairs_np):
