@@ -337,7 +337,10 @@ int ace_profile_classes(ace_ctx* ctx, unsigned mask);
  *   fused = 3  real-to-complex with the half spectra of all pairs resident and
  *              W formed per owner row: one workgroup per (z-plane, orbital k)
  *              sums v_kj phi_j over k's pairs and writes W_k once (about
- *              9 N^3 s per pair; no conflict-free rounds).  When the spectra
+ *              9 N^3 s per pair; no conflict-free rounds).  The owners run in
+ *              a reverse Cuthill-McKee order of the pair graph (in index
+ *              order when the environment sets ACE_OWNER_ORDER=0 before
+ *              ace_create; results agree to rounding).  When the spectra
  *              exceed ACE_OWNER_SPECTRA_MAX bytes (default 96 GiB) the build
  *              uses fused = 2 instead.  The default where two real-to-complex
  *              planes fit in one CU's LDS.
