@@ -423,3 +423,32 @@ def test_pairlist_device_count(ctx, c1, rho_cut):
     pairs, _, n = ctx.pairlist_device(_dev(phi), _grid(s), rho_cut, capacity=5)
     assert int(n.item()) == len(ref)
     np.testing.assert_array_equal(pairs[: min(5, len(ref))].cpu().numpy(), ref[:5])
+
+
+def test_owner_order_switch_gives_identical_build(lib):
+    """The owners' dispatch order (reverse Cuthill-McKee by default, index
+    order with ACE_OWNER_ORDER=0 at context creation) changes only which
+    workgroups run together: each owner still sums its entries in the same
+    order, so W, M, xi and E_x are bitwise equal."""
+    _say("owner order: default vs ACE_OWNER_ORDER=0 on the 32^3 size case")
+    import os
+    c = _size_case(32, "erfc")
+    spec, pairs = c["spec"], c["pairs"]
+    old = os.environ.get("ACE_OWNER_ORDER")
+    os.environ["ACE_OWNER_ORDER"] = "0"
+    try:
+        plain = lib.Context()
+    finally:
+        if old is None:
+            del os.environ["ACE_OWNER_ORDER"]
+        else:
+            os.environ["ACE_OWNER_ORDER"] = old
+    ordered = lib.Context()
+    out = []
+    for cx in (ordered, plain):
+        cx.set_pair_shape("fp64", 32, "owner", 3)
+        assert cx.get_pair_shape("fp64", 32)[0] == "owner"
+        out.append(cx.build(_dev(c["psi"]), _dev(pairs), _grid(spec), kernel="erfc", omega=0.4, want_W=True))
+    for key in ("W", "M", "xi", "ex"):
+        assert torch.equal(out[0][key], out[1][key]), key
+    _close(out[0]["W"].cpu().numpy(), c["W"], 1e-12, "W")
