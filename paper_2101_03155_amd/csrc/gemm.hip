@@ -338,16 +338,22 @@ __device__ __forceinline__ int rowblk(int wm, int i) {
 // SIMD instead of two.
 // LOWA: A(m, k) = 0 for k > m (lower-triangular left factor, global row and
 // k indices): a 16-row block skips the MFMAs of the k beyond its last row.
-template <typename TA, typename TB, bool AK, bool BK, int OP, bool LOWA = false, int NW = 2>
+// MIR (NW = 4): wave column wn takes the 16-column blocks wn and 7 - wn of
+// the tile (else 2 wn and 2 wn + 1); with upper (a tile on the diagonal of a
+// symmetric product) the blocks below the diagonal are skipped, and the two
+// waves of every SIMD then share nine of its sixteen blocks.
+template <int NW, bool MIR>
+__device__ __forceinline__ int colblk(int wn, int j) {
+  return MIR ? (j == 0 ? wn : 2 * NW - 1 - wn) : wn * (8 / NW) + j;
+}
+template <typename TA, typename TB, bool AK, bool BK, int OP, bool LOWA = false, int NW = 2, bool MIR = false>
 __device__ __forceinline__ void tile_mma(const TA* __restrict__ A, int64_t lda, const TB* __restrict__ B,
                                          int64_t ldb, int m0, int M, int n0, int Nn, int64_t kb, int64_t ke,
-                                         double* As, double* Bs, d4 (&acc)[4][8 / NW]) {
-  constexpr int JB = 8 / NW, WC = 128 / NW, PER = tile_per<NW>();
+                                         double* As, double* Bs, d4 (&acc)[4][8 / NW], bool upper = false) {
+  constexpr int JB = 8 / NW, PER = tile_per<NW>();
+  static_assert(!MIR || NW == 4, "mirrored column blocks need four wave columns");
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wm = wv / NW, wn = wv % NW;
-  // 16 x 16 blocks of this wave that hold rows < M and columns < Nn (the
-  // others stay zero, so their MFMAs are skipped; wave-uniform)
-  const int jb = min(JB, max(0, (Nn - n0 - wn * WC + 15) / 16));
   TA va[PER];
   TB vb[PER];
   int buf = 0;
@@ -374,12 +380,19 @@ __device__ __forceinline__ void tile_mma(const TA* __restrict__ A, int64_t lda, 
       for (int i = 0; i < 4; ++i)
         a[i] = AK ? as[kr + rowblk<LOWA>(wm, i) + li] : as[(rowblk<LOWA>(wm, i) + li) * RP + kq];
 #pragma unroll
-      for (int j = 0; j < JB; ++j) b[j] = BK ? bs[kr + wn * WC + j * 16 + li] : bs[(wn * WC + j * 16 + li) * RP + kq];
+      for (int j = 0; j < JB; ++j) {
+        const int cb = colblk<NW, MIR>(wn, j) * 16;
+        b[j] = BK ? bs[kr + cb + li] : bs[(cb + li) * RP + kq];
+      }
+      // blocks with rows < M and columns < Nn (the others stay zero, so their
+      // MFMAs are skipped; wave-uniform)
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < JB; ++j)
-          if (m0 + rowblk<LOWA>(wm, i) < M && j < jb && (!LOWA || k0 + kk < int64_t(m0) + rowblk<LOWA>(wm, i) + 16))
+          if (m0 + rowblk<LOWA>(wm, i) < M && n0 + colblk<NW, MIR>(wn, j) * 16 < Nn &&
+              (!upper || rowblk<LOWA>(wm, i) <= colblk<NW, MIR>(wn, j) * 16) &&
+              (!LOWA || k0 + kk < int64_t(m0) + rowblk<LOWA>(wm, i) + 16))
             acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     if (more) {
@@ -392,10 +405,10 @@ __device__ __forceinline__ void tile_mma(const TA* __restrict__ A, int64_t lda, 
 }
 
 // acc -> out[m][n] (ld) for rows < M, columns < Nn, times alpha
-template <int NW = 2, bool IL = false>
+template <int NW = 2, bool IL = false, bool MIR = false>
 __device__ __forceinline__ void tile_write(const d4 (&acc)[4][8 / NW], int m0, int M, int64_t n0, int64_t Nn,
                                            double* __restrict__ out, int64_t ld, double alpha) {
-  constexpr int JB = 8 / NW, WC = 128 / NW;
+  constexpr int JB = 8 / NW;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int wm = wv / NW, wn = wv % NW;
 #pragma unroll
@@ -405,7 +418,7 @@ __device__ __forceinline__ void tile_write(const d4 (&acc)[4][8 / NW], int m0, i
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int m = m0 + rowblk<IL>(wm, i) + lane / 16 + 4 * r;
-        const int64_t n = n0 + wn * WC + j * 16 + lane % 16;
+        const int64_t n = n0 + colblk<NW, MIR>(wn, j) * 16 + lane % 16;
         if (m < M && n < Nn) out[int64_t(m) * ld + n] = alpha * acc[i][j][r];
       }
 }
@@ -438,8 +451,11 @@ __global__ __launch_bounds__(tile_threads<NW>(), tile_waves<NW>()) void k_gemm_n
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 8 / NW; ++j) acc[i][j] = d4{0, 0, 0, 0};
-  tile_mma<double, double, false, false, OP, false, NW>(A, lda, B, ldb, m0, M, n0, Nn, kb, ke, As, Bs, acc);
-  tile_write<NW>(acc, m0, M, n0, Nn, Cpart + int64_t(blockIdx.y) * M * Nn, Nn, 1.0);
+  // a symmetric product forms the upper triangle only (tiles tm <= tn and,
+  // on the diagonal, 16 x 16 blocks on or above it); the reduction mirrors
+  tile_mma<double, double, false, false, OP, false, NW, SYM>(A, lda, B, ldb, m0, M, n0, Nn, kb, ke, As, Bs, acc,
+                                                             SYM && tm == tn);
+  tile_write<NW, false, SYM>(acc, m0, M, n0, Nn, Cpart + int64_t(blockIdx.y) * M * Nn, Nn, 1.0);
 }
 
 // ---------------------------------------------------------------- 128 x 64 FP32 compensated tiles
@@ -584,8 +600,9 @@ __global__ __launch_bounds__(256) void k_reduce_parts_t(const double* __restrict
   if (e < mn) {
     int64_t src = e;
     if (SYM) {
+      // only blocks on or above the diagonal (16 x 16) were formed
       const int i = int(e / Nn), j = int(e % Nn);
-      if (i / TT > j / TT) src = int64_t(j) * Nn + i;
+      if (i / 16 > j / 16) src = int64_t(j) * Nn + i;
     }
     int p = g;
     for (; p + 3 * RGR < nsplit; p += 4 * RGR) {
