@@ -138,6 +138,9 @@ void launch_neg_sumsq(const double* c, int64_t n, double* out, hipStream_t s);
 // be zero on entry; tinv is 64 x 64 doubles of scratch.
 void launch_cholesky(double* A, int n, int* info, double* tinv, hipStream_t s);
 void launch_trinv(const double* L, int n, double* X, hipStream_t s);
+// -A = L L^T and X = L^-1 (zeros above the diagonal); info zero on entry, set
+// as by launch_cholesky.  A holds L afterwards only where n > 128.
+void launch_chol_inv(double* A, int n, int* info, double* X, double* tinv, hipStream_t s);
 void launch_colnorm(const double* A, int n, int64_t ng, double* res, hipStream_t s);
 int qrcp_blocks(int64_t ng);
 void launch_qrcp_update(const double* A, int n, int64_t ng, const double* q, double* res, double* pv, int64_t* pi,

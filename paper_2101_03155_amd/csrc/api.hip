@@ -1147,17 +1147,17 @@ static int build_impl(ace_ctx* c, const ace_grid* g, int norb, const double* phi
     return ACE_OK;
   }
   launch_zero(info, sizeof(int), s);
-  launch_cholesky(Lb, norb, info, tinv, s);
+  launch_chol_inv(Lb, norb, info, Li, tinv, s);
+  // (e) xi = L^-1 W; the factorization's status is read once, after it (on
+  // failure the outputs are unspecified)
+  HIPCHK(c, gemm_ls(prec, false, true, Li, norb, W, ng, xi, ng, norb, norb, ng, 1.0, s, R));
+  rec_end(R, ST_TAIL, s);
+  rec_end(R, ST_BUILD, s);
   int hinfo = 0;
   HIPCHK(c, hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
   if (hinfo > 0) return fail(c, ACE_E_NOT_PD, "-M is not positive definite (Cholesky column %d)", hinfo - 1);
   if (hinfo < 0) return fail(c, ACE_E_NONFINITE, "non-finite value in M (Cholesky column %d)", -hinfo - 1);
-  // (e) xi = L^-1 W
-  launch_trinv(Lb, norb, Li, s);
-  HIPCHK(c, gemm_ls(prec, false, true, Li, norb, W, ng, xi, ng, norb, norb, ng, 1.0, s, R));
-  rec_end(R, ST_TAIL, s);
-  rec_end(R, ST_BUILD, s);
   HIPCHK(c, hipGetLastError());
   return ACE_OK;
 }
@@ -1775,8 +1775,7 @@ int ace_build_batched(ace_ctx* c, int nsys, ace_system* sys, int prec, int mode)
       hipError_t e = gemm_nt(prec, 0, ph, ng, W, ng, n, n, ng, grid_dv(&y.grid), bpart, bM, sb, nullptr);
       if (e != hipSuccess) return fail(c, ACE_E_HIP, "batched M launch failed: %s", hipGetErrorString(e));
       launch_symmetrize(bM, n, y.M, bL, y.ex ? y.ex : exs + 2 * q, exs + 2 * q + 1, sb);
-      launch_cholesky(bL, n, infos + q, btv, sb);
-      launch_trinv(bL, n, bLi, sb);
+      launch_chol_inv(bL, n, infos + q, bLi, btv, sb);
       e = gemm_ls(prec, false, true, bLi, n, W, ng, y.xi, ng, n, n, ng, 1.0, sb, nullptr);
       if (e != hipSuccess) return fail(c, ACE_E_HIP, "batched projector launch failed: %s", hipGetErrorString(e));
     }

@@ -205,6 +205,142 @@ __global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ A, int
   }
 }
 
+// -A = ... : for n <= 128 the factorization and the inverse in one workgroup
+// with the matrix resident in LDS.  A (n x n, lower triangle read) = L L^T,
+// X = L^-1 (lower triangular, zeros above the diagonal).  Right-looking over
+// panels of 16 columns: wave 0 factors a panel in registers (lane l holds
+// panel rows k0 + l and k0 + l + 64, the pivot column broadcast by
+// shuffles), then all threads apply the panel to the trailing lower
+// triangle in 4 x 4 blocks.  The inverse runs column-parallel: 8 threads per
+// column c solve L x = e_c by forward substitution, each summing every
+// eighth term, combined by shuffles.  Both triangles sit packed in LDS (row
+// i at i (i + 1) / 2).  info as the blocked factorization: k + 1 for a
+// non-positive pivot in column k, -(k + 1) for a non-finite one.
+constexpr int SMALL_N = 128;
+__device__ __forceinline__ int pk(int i, int j) { return i * (i + 1) / 2 + j; }
+
+__global__ __launch_bounds__(1024) void k_chol_inv_small(const double* __restrict__ A, int n, int* __restrict__ info,
+                                                         double* __restrict__ X) {
+  constexpr int PB = 16, NP = SMALL_N * (SMALL_N + 1) / 2;
+  __shared__ double S[NP];
+  __shared__ double XP[NP];
+  __shared__ int sbad;
+  const int tid = threadIdx.x, lane = tid & 63;
+  if (tid == 0) sbad = 0;
+  for (int e = tid; e < n * (n + 1) / 2; e += 1024) {
+    // row i of the packed triangle holds elements i (i + 1) / 2 .. + i
+    int i = int((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+    while (i * (i + 1) / 2 > e) --i;
+    while ((i + 1) * (i + 2) / 2 <= e) ++i;
+    const int j = e - i * (i + 1) / 2;
+    S[e] = A[int64_t(i) * n + j];
+  }
+  __syncthreads();
+  for (int k0 = 0; k0 < n; k0 += PB) {
+    const int kb = n - k0 < PB ? n - k0 : PB;
+    if (tid < 64) {
+      const int r0 = k0 + lane, r1 = k0 + lane + 64;
+      double v0[PB], v1[PB];
+#pragma unroll
+      for (int jj = 0; jj < PB; ++jj) {
+        v0[jj] = (jj < kb && r0 < n && k0 + jj <= r0) ? S[pk(r0, k0 + jj)] : 0.0;
+        v1[jj] = (jj < kb && r1 < n && k0 + jj <= r1) ? S[pk(r1, k0 + jj)] : 0.0;
+      }
+      int bad = 0;
+#pragma unroll
+      for (int kk = 0; kk < PB; ++kk) {
+        if (kk < kb && !bad) {
+          const int k = k0 + kk;
+          const double d = __shfl(v0[kk], kk, 64);
+          if (!isfinite(d)) bad = -(k + 1);
+          else if (!(d > 0.0)) bad = k + 1;
+          if (!bad) {
+            const double r = sqrt(d), inv = 1.0 / r;
+            if (r0 > k) v0[kk] *= inv;
+            else if (r0 == k) v0[kk] = r;
+            if (r1 < n) v1[kk] *= inv;  // r1 >= k0 + 64 > k
+#pragma unroll
+            for (int jj = kk + 1; jj < PB; ++jj) {
+              if (jj < kb) {
+                const double lj = __shfl(v0[kk], jj, 64);  // L[k0 + jj][k]
+                if (r0 >= k0 + jj) v0[jj] -= v0[kk] * lj;
+                if (r1 < n) v1[jj] -= v1[kk] * lj;
+              }
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int jj = 0; jj < PB; ++jj) {
+        if (jj < kb && r0 < n && k0 + jj <= r0) S[pk(r0, k0 + jj)] = v0[jj];
+        if (jj < kb && r1 < n) S[pk(r1, k0 + jj)] = v1[jj];
+      }
+      if (lane == 0 && bad) sbad = bad;
+    }
+    __syncthreads();
+    if (sbad) break;
+    // trailing update S[i][j] -= sum_kk L[i][k0 + kk] L[j][k0 + kk], k0 + kb <= j <= i < n
+    const int t0 = k0 + kb, nt = (n - t0 + 3) / 4;
+    for (int b = tid; b < nt * (nt + 1) / 2; b += 1024) {
+      int bi = int((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+      while (bi * (bi + 1) / 2 > b) --bi;
+      while ((bi + 1) * (bi + 2) / 2 <= b) ++bi;
+      const int bj = b - bi * (bi + 1) / 2;
+      const int i0 = t0 + 4 * bi, j0 = t0 + 4 * bj;
+      double acc[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[a][q] = 0.0;
+      for (int kk = 0; kk < kb; ++kk) {
+        double li[4], lj[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          li[a] = i0 + a < n ? S[pk(i0 + a, k0 + kk)] : 0.0;
+          lj[a] = j0 + a < n ? S[pk(j0 + a, k0 + kk)] : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[a][q] += li[a] * lj[q];
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = i0 + a, j = j0 + q;
+          if (i < n && j <= i) S[pk(i, j)] -= acc[a][q];
+        }
+    }
+    __syncthreads();
+  }
+  if (sbad) {
+    if (tid == 0) *info = sbad;
+    return;
+  }
+  // X = L^-1 by columns: group of 8 threads per column c
+  const int c = tid >> 3, sub = tid & 7;
+  if (c < n) {
+    for (int i = c; i < n; ++i) {
+      double sacc = 0.0;
+      for (int k = c + sub; k < i; k += 8) sacc += S[pk(i, k)] * XP[pk(k, c)];
+      sacc += __shfl_xor(sacc, 1, 64);
+      sacc += __shfl_xor(sacc, 2, 64);
+      sacc += __shfl_xor(sacc, 4, 64);
+      const double x = ((i == c ? 1.0 : 0.0) - sacc) / S[pk(i, i)];
+      if (sub == 0) XP[pk(i, c)] = x;
+      // the group's later steps read x from LDS: the write is ordered
+      // before them within the wave
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < n * n; e += 1024) {
+    const int i = e / n, j = e % n;
+    X[e] = j <= i ? XP[pk(i, j)] : 0.0;
+  }
+}
+
 // Inverse of a lower-triangular L (n x n, n <= 512): one 64-lane wave per
 // column c solves L x = e_c by forward substitution, each step a wave-wide
 // dot product; x lives in LDS.  X is lower triangular.
@@ -1184,6 +1320,14 @@ void launch_cholesky(double* A, int n, int* info, double* tinv, hipStream_t s) {
 }
 void launch_trinv(const double* L, int n, double* X, hipStream_t s) {
   hipLaunchKernelGGL(k_trinv_lower, dim3(n), dim3(64), 0, s, L, n, X);
+}
+void launch_chol_inv(double* A, int n, int* info, double* X, double* tinv, hipStream_t s) {
+  if (n <= SMALL_N) {
+    hipLaunchKernelGGL(k_chol_inv_small, dim3(1), dim3(1024), 0, s, A, n, info, X);
+  } else {
+    launch_cholesky(A, n, info, tinv, s);
+    launch_trinv(A, n, X, s);
+  }
 }
 void launch_colnorm(const double* A, int n, int64_t ng, double* res, hipStream_t s) {
   hipLaunchKernelGGL(k_colnorm, dim3(grid_for(ng, 256)), dim3(256), 0, s, A, n, ng, res);
