@@ -205,16 +205,16 @@ __global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ A, int
   }
 }
 
-// -A = ... : for n <= 128 the factorization and the inverse in one workgroup
-// with the matrix resident in LDS.  A (n x n, lower triangle read) = L L^T,
-// X = L^-1 (lower triangular, zeros above the diagonal).  Right-looking over
-// panels of 16 columns: wave 0 factors a panel in registers (lane l holds
-// panel rows k0 + l and k0 + l + 64, the pivot column broadcast by
-// shuffles), then all threads apply the panel to the trailing lower
-// triangle in 4 x 4 blocks.  The inverse runs column-parallel: 8 threads per
-// column c solve L x = e_c by forward substitution, each summing every
-// eighth term, combined by shuffles.  Both triangles sit packed in LDS (row
-// i at i (i + 1) / 2).  info as the blocked factorization: k + 1 for a
+// For n <= 128 the factorization and the inverse in one workgroup with the
+// matrix resident in LDS.  A (n x n, lower triangle read) = L L^T, X = L^-1
+// (lower triangular, zeros above the diagonal).  Right-looking over panels
+// of 16 columns: wave 0 factors a panel in registers (lane l holds panel
+// rows k0 + l and k0 + l + 64, the pivot column passed through LDS), then
+// all threads apply the panel to the trailing lower triangle in 4 x 4
+// blocks.  The inverse runs by 16-row block rows: the diagonal blocks'
+// inverses by substitution, one thread per column, then each block row from
+// the ones above it (all its blocks at once).  Both triangles sit packed in
+// LDS (row i at i (i + 1) / 2).  info as the blocked factorization: k + 1 for a
 // non-positive pivot in column k, -(k + 1) for a non-finite one.
 constexpr int SMALL_N = 128;
 __device__ __forceinline__ int pk(int i, int j) { return i * (i + 1) / 2 + j; }
@@ -224,6 +224,8 @@ __global__ __launch_bounds__(1024) void k_chol_inv_small(const double* __restric
   constexpr int PB = 16, NP = SMALL_N * (SMALL_N + 1) / 2;
   __shared__ double S[NP];
   __shared__ double XP[NP];
+  __shared__ double T[(SMALL_N / 16 - 1) * 256];
+  __shared__ double pc[17];
   __shared__ int sbad;
   const int tid = threadIdx.x, lane = tid & 63;
   if (tid == 0) sbad = 0;
@@ -246,12 +248,16 @@ __global__ __launch_bounds__(1024) void k_chol_inv_small(const double* __restric
         v0[jj] = (jj < kb && r0 < n && k0 + jj <= r0) ? S[pk(r0, k0 + jj)] : 0.0;
         v1[jj] = (jj < kb && r1 < n && k0 + jj <= r1) ? S[pk(r1, k0 + jj)] : 0.0;
       }
+      // the pivot and the scaled pivot column inside the panel reach the
+      // other lanes through pc[] (one wave: its LDS accesses run in order)
       int bad = 0;
 #pragma unroll
       for (int kk = 0; kk < PB; ++kk) {
         if (kk < kb && !bad) {
           const int k = k0 + kk;
-          const double d = __shfl(v0[kk], kk, 64);
+          if (lane == kk) pc[0] = v0[kk];
+          __builtin_amdgcn_wave_barrier();
+          const double d = pc[0];
           if (!isfinite(d)) bad = -(k + 1);
           else if (!(d > 0.0)) bad = k + 1;
           if (!bad) {
@@ -259,15 +265,18 @@ __global__ __launch_bounds__(1024) void k_chol_inv_small(const double* __restric
             if (r0 > k) v0[kk] *= inv;
             else if (r0 == k) v0[kk] = r;
             if (r1 < n) v1[kk] *= inv;  // r1 >= k0 + 64 > k
+            if (lane > kk && lane < PB) pc[1 + lane] = v0[kk];  // L[k0 + lane][k]
+            __builtin_amdgcn_wave_barrier();
 #pragma unroll
             for (int jj = kk + 1; jj < PB; ++jj) {
               if (jj < kb) {
-                const double lj = __shfl(v0[kk], jj, 64);  // L[k0 + jj][k]
+                const double lj = pc[1 + jj];
                 if (r0 >= k0 + jj) v0[jj] -= v0[kk] * lj;
                 if (r1 < n) v1[jj] -= v1[kk] * lj;
               }
             }
           }
+          __builtin_amdgcn_wave_barrier();
         }
       }
 #pragma unroll
@@ -318,23 +327,51 @@ __global__ __launch_bounds__(1024) void k_chol_inv_small(const double* __restric
     if (tid == 0) *info = sbad;
     return;
   }
-  // X = L^-1 by columns: group of 8 threads per column c
-  const int c = tid >> 3, sub = tid & 7;
-  if (c < n) {
-    for (int i = c; i < n; ++i) {
-      double sacc = 0.0;
-      for (int k = c + sub; k < i; k += 8) sacc += S[pk(i, k)] * XP[pk(k, c)];
-      sacc += __shfl_xor(sacc, 1, 64);
-      sacc += __shfl_xor(sacc, 2, 64);
-      sacc += __shfl_xor(sacc, 4, 64);
-      const double x = ((i == c ? 1.0 : 0.0) - sacc) / S[pk(i, i)];
-      if (sub == 0) XP[pk(i, c)] = x;
-      // the group's later steps read x from LDS: the write is ordered
-      // before them within the wave
-      __builtin_amdgcn_wave_barrier();
+  // X = L^-1 by 16-row block rows.  First the inverses of the diagonal
+  // blocks, one thread per column (forward substitution within the block),
+  // into X's diagonal blocks; then for each block row I: T_IJ = sum over
+  // K = J .. I-1 of L_IK X_KJ for every J < I, and X_IJ = -X_II T_IJ.
+  {
+    const int b = tid >> 4, lc = tid & 15, r0 = b * 16;
+    if (tid < n) {
+      const int m = n - r0 < 16 ? n - r0 : 16;  // rows of this diagonal block
+      double x[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        double v = 0.0;
+        if (r >= lc && r < m) {
+          double acc = r == lc ? 1.0 : 0.0;
+#pragma unroll
+          for (int t = 0; t < 16; ++t)
+            if (t >= lc && t < r) acc -= S[pk(r0 + r, r0 + t)] * x[t];
+          v = acc / S[pk(r0 + r, r0 + r)];
+          XP[pk(r0 + r, r0 + lc)] = v;
+        }
+        x[r] = v;
+      }
     }
   }
   __syncthreads();
+  for (int I = 1; I * 16 < n; ++I) {
+    const int i0 = I * 16, m = n - i0 < 16 ? n - i0 : 16;
+    for (int f = tid; f < I * 256; f += 1024) {
+      const int J = f >> 8, r = (f >> 4) & 15, q = f & 15, col = J * 16 + q;
+      double acc = 0.0;
+      if (r < m)
+        for (int k = col; k < i0; ++k) acc += S[pk(i0 + r, k)] * XP[pk(k, col)];
+      T[f] = acc;
+    }
+    __syncthreads();
+    for (int f = tid; f < I * 256; f += 1024) {
+      const int J = f >> 8, r = (f >> 4) & 15, q = f & 15;
+      if (r < m) {
+        double acc = 0.0;
+        for (int t = 0; t <= r; ++t) acc += XP[pk(i0 + r, i0 + t)] * T[(J << 8) + (t << 4) + q];
+        XP[pk(i0 + r, J * 16 + q)] = -acc;
+      }
+    }
+    __syncthreads();
+  }
   for (int e = tid; e < n * n; e += 1024) {
     const int i = e / n, j = e % n;
     X[e] = j <= i ? XP[pk(i, j)] : 0.0;
