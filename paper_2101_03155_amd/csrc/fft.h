@@ -356,30 +356,44 @@ __device__ __forceinline__ void fft_lines(cplx<T>* buf, const cplx<T>* tw, int t
   fft_lines_from<T, N, 0, LINES, LS, PS, NT, S, JFAST, V>(buf, tw, tid);
 }
 
-// Passes P .. plan_len(N) - 2 in place, then the last pass through the storer.
-template <typename T, int N, int P, int LINES, int LS, int PS, int NT, int S, bool JFAST, int V, typename St>
+// Passes P .. plan_len(N) - 2 in place, then the last pass through the storer
+// (followed by a barrier if ES, for a storer that writes LDS).
+template <typename T, int N, int P, int LINES, int LS, int PS, int NT, int S, bool JFAST, int V, bool ES = false,
+          typename St>
 __device__ __forceinline__ void fft_lines_to(cplx<T>* buf, const cplx<T>* tw, int tid, St store) {
   if constexpr (P + 1 < plan_len(N)) {
     fft_pass<T, N, P, LINES, LS, PS, NT, S, JFAST, V>(buf, tw, tid);
-    fft_lines_to<T, N, P + 1, LINES, LS, PS, NT, S, JFAST, V>(buf, tw, tid, store);
+    fft_lines_to<T, N, P + 1, LINES, LS, PS, NT, S, JFAST, V, ES>(buf, tw, tid, store);
   } else {
-    fft_pass_ls<T, N, P, LINES, LS, PS, NT, S, JFAST, V, false>(
+    fft_pass_ls<T, N, P, LINES, LS, PS, NT, S, JFAST, V, ES>(
         buf, tw, tid, [buf](int l, int p) { return buf[l * LS + p * PS]; }, store);
   }
 }
 
 // Full transform with the first pass reading through load(l, p) and the last
-// writing through store(l, p, value) (to global memory: no closing barrier).
-// Expects nothing of buf (the first pass fills it after a barrier); ends
-// unsynchronized.
-template <typename T, int N, int LINES, int LS, int PS, int NT, int S, bool JFAST, int V, typename L, typename St>
+// writing through store(l, p, value) (to global memory: no closing barrier,
+// unless ES).  Expects nothing of buf (the first pass fills it after a
+// barrier); ends unsynchronized unless ES.
+template <typename T, int N, int LINES, int LS, int PS, int NT, int S, bool JFAST, int V, bool ES = false,
+          typename L, typename St>
 __device__ __forceinline__ void fft_lines_ls(cplx<T>* buf, const cplx<T>* tw, int tid, L load, St store) {
   static_assert(smooth235(N), "FFT length must be 2^a 3^b 5^c");
   if constexpr (plan_len(N) == 1) {
-    fft_pass_ls<T, N, 0, LINES, LS, PS, NT, S, JFAST, V, false>(buf, tw, tid, load, store);
+    fft_pass_ls<T, N, 0, LINES, LS, PS, NT, S, JFAST, V, ES>(buf, tw, tid, load, store);
   } else {
     fft_pass_l<T, N, 0, LINES, LS, PS, NT, S, JFAST, V>(buf, tw, tid, load);
-    fft_lines_to<T, N, 1, LINES, LS, PS, NT, S, JFAST, V>(buf, tw, tid, store);
+    fft_lines_to<T, N, 1, LINES, LS, PS, NT, S, JFAST, V, ES>(buf, tw, tid, store);
+  }
+}
+
+// Passes P .. plan_len(N) - 1 in place, element p of line l at buf[addr(l, p)].
+template <typename T, int N, int P, int LINES, int NT, int S, bool JFAST, int V, typename A>
+__device__ __forceinline__ void fft_lines_from_at(cplx<T>* buf, const cplx<T>* tw, int tid, A addr) {
+  if constexpr (P < plan_len(N)) {
+    fft_pass_ls<T, N, P, LINES, 0, 0, NT, S, JFAST, V, true>(
+        buf, tw, tid, [buf, addr](int l, int p) { return buf[addr(l, p)]; },
+        [buf, addr](int l, int p, cplx<T> x) { buf[addr(l, p)] = x; });
+    fft_lines_from_at<T, N, P + 1, LINES, NT, S, JFAST, V>(buf, tw, tid, addr);
   }
 }
 

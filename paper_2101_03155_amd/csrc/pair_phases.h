@@ -213,6 +213,36 @@ template <int N> __device__ __forceinline__ int vt_fold(int k) { return k <= N /
 template <int N> __host__ __device__ constexpr int xls() { return N + 1; }
 // position in buf of element e = l * N + x of the packed potential lines
 template <int N> __device__ __forceinline__ int xpos(int e) { return e + e / N * (xls<N>() - N); }
+// LDS layout of the inverse in-plane transforms (V: the y passes' plan order;
+// the x passes take the other).  The y-transformed plane is [y][kx] at row
+// stride XS, and the x passes' first pass re-packs rows l and l + N/2 into x
+// line l with eight threads per line.  Where it has eight threads per line
+// and N is a multiple of 32, the last y pass writes row y to row ysig(y),
+// which interleaves each block of 32 rows so that the rows read by the
+// neighbouring 8-thread groups of one LDS cycle start in disjoint bank ranges
+// (adjacent rows start one FP64 value apart, and their 8-value ranges
+// overlapped).  In FP64 with a radix-12 first x pass, the x lines also take 2
+// values of padding after each 48: the pass writes element 12 j + r of a
+// line from thread j, which without it hits each bank twice.  Line stride XL
+// stays odd, for the later x passes (consecutive lines on consecutive
+// threads).
+template <typename T, int N, int V> struct InvLayout {
+  static constexpr int XS = r2c_xs<N>();
+  static constexpr int R0 = plan_radix_v(N, 0, V ^ 1);
+  static constexpr bool SIG = N % 32 == 0 && N / R0 == 8;
+  static constexpr int PG = (sizeof(T) == 8 && SIG && R0 == 12) ? 4 * R0 : N;
+  static constexpr int PW = PG < N ? 2 : 0;
+  static constexpr int XL = N + PW * ((N - 1) / PG) + 1;
+  // LDS elements of the plane buffer: the larger of the two layouts
+  static constexpr int BUF = N * XS > (N / 2) * XL ? N * XS : (N / 2) * XL;
+  static_assert(XL % 2 == 1, "x line stride must be odd");
+  static __host__ __device__ __forceinline__ int ysig(int y) {
+    return SIG ? (y & ~31) | ((y & 3) << 3) | ((y & 31) >> 2) : y;
+  }
+  static __host__ __device__ __forceinline__ int xq(int l, int p) { return l * XL + p + PW * (p / PG); }
+  // element e = l * N + x of the packed potential lines
+  static __host__ __device__ __forceinline__ int xe(int e) { return xq(e / N, e % N); }
+};
 template <int N> __host__ __device__ constexpr int r2c_tx() {
   return (N * r2c_xs<N>()) % 16 == 0 ? 16 : (N * r2c_xs<N>()) % 8 == 0 ? 8 : (N * r2c_xs<N>()) % 4 == 0 ? 4 : 2;
 }
@@ -386,8 +416,8 @@ __device__ __forceinline__ void body_conv_z_r(cplx<T>* spec_p, int f0, const Ker
 }
 
 // Half spectrum of plane z -> the real potential of the plane, left in buf as
-// H complex lines of stride xls<N>(): line l holds row l in .x and row
-// l + N/2 in .y.
+// H complex lines, element x of line l at buf[InvLayout<T, N, V>::xq(l, x)]:
+// line l holds row l in .x and row l + N/2 in .y.
 // body_inv_xy_t: the same on a plane already staged in buf (and synchronized).
 template <typename T, int N, int NT, int V = 0>
 __device__ __forceinline__ void body_inv_xy_t(cplx<T>* buf, const cplx<T>* tw, int tid);
@@ -405,7 +435,11 @@ __device__ __forceinline__ void inv_x_repacked(cplx<T>* buf, const cplx<T>* tw, 
 
 template <typename T, int N, int NT, int V>
 __device__ __forceinline__ void body_inv_xy_t(cplx<T>* buf, const cplx<T>* tw, int tid) {
-  fft_lines<T, N, r2c_xs<N>(), 1, r2c_xs<N>(), NT, +1, false, V>(buf, tw, tid);
+  using Lay = InvLayout<T, N, V>;
+  constexpr int XS = r2c_xs<N>();
+  fft_lines_ls<T, N, XS, 1, XS, NT, +1, false, V, true>(
+      buf, tw, tid, [buf](int l, int p) { return buf[l + p * XS]; },
+      [buf](int l, int p, cplx<T> x) { buf[l + Lay::ysig(p) * XS] = x; });
   inv_x_repacked<T, N, NT, V>(buf, tw, tid);
 }
 
@@ -415,8 +449,11 @@ __device__ __forceinline__ void body_inv_xy_t(cplx<T>* buf, const cplx<T>* tw, i
 template <typename T, int N, int NT, int V = 0>
 __device__ __forceinline__ void body_inv_xy_g(const cplx<T>* __restrict__ in, cplx<T>* buf, const cplx<T>* tw,
                                               int tid) {
+  using Lay = InvLayout<T, N, V>;
   constexpr int XS = r2c_xs<N>();
-  fft_lines_load<T, N, XS, 1, XS, NT, +1, false, V>(buf, tw, tid, [in](int l, int p) { return in[p * XS + l]; });
+  fft_lines_ls<T, N, XS, 1, XS, NT, +1, false, V, true>(
+      buf, tw, tid, [in](int l, int p) { return in[p * XS + l]; },
+      [buf](int l, int p, cplx<T> x) { buf[l + Lay::ysig(p) * XS] = x; });
   inv_x_repacked<T, N, NT, V>(buf, tw, tid);
 }
 
@@ -432,10 +469,11 @@ __device__ __forceinline__ void inv_x_repacked(cplx<T>* buf, const cplx<T>* tw, 
   // consecutive threads (with consecutive lines its re-pack spills registers
   // in FP64), with the radix order reversed: the larger first radix spreads
   // its writes over more banks.  The later passes take consecutive lines.
-  fft_pass_l<T, N, 0, H, xls<N>(), 1, NT, +1, true, V ^ 1>(buf, tw, tid, [buf](int l, int p) {
+  using Lay = InvLayout<T, N, V>;
+  fft_pass_ls<T, N, 0, H, 0, 0, NT, +1, true, V ^ 1, true>(buf, tw, tid, [buf](int l, int p) {
     const bool lowk = p <= H;
     const int k = lowk ? p : N - p;
-    C x1 = buf[l * XS + k], x2 = buf[(l + H) * XS + k];
+    C x1 = buf[Lay::ysig(l) * XS + k], x2 = buf[Lay::ysig(l + H) * XS + k];
     if (k == 0 || k == H) {
       x1.y = T(0);
       x2.y = T(0);
@@ -449,13 +487,13 @@ __device__ __forceinline__ void inv_x_repacked(cplx<T>* buf, const cplx<T>* tw, 
       z.y = x2.x - x1.y;
     }
     return z;
-  });
-  fft_lines_from<T, N, 1, H, xls<N>(), 1, NT, +1, false, V ^ 1>(buf, tw, tid);
+  }, [buf](int l, int p, C x) { buf[Lay::xq(l, p)] = x; });
+  fft_lines_from_at<T, N, 1, H, NT, +1, false, V ^ 1>(buf, tw, tid, [](int l, int p) { return Lay::xq(l, p); });
 }
 
 // W_i -= v phi_j and (i != j) W_j -= v phi_i over plane z for one pair, with
 // v from the packed lines of body_inv_xy_r; optional partial sum of v rho.
-template <typename T, int N, int NT, bool EN>
+template <typename T, int N, int NT, bool EN, int V = 0>
 __device__ __forceinline__ void accumulate_w_r(const T* __restrict__ pi_, const T* __restrict__ pj_, T* wi, T* wj,
                                                bool off, double* eslot, const cplx<T>* buf, double* red, int tid) {
   constexpr int HN = (N / 2) * N;
@@ -480,7 +518,7 @@ __device__ __forceinline__ void accumulate_w_r(const T* __restrict__ pi_, const 
       for (int u = 0; u < U; ++u) {
         const int e = tid + (q0 + u) * NT;
         if (q0 + u < LP && (HN % NT == 0 || e < HN)) {
-          const cplx<T> v = buf[xpos<N>(e)];
+          const cplx<T> v = buf[InvLayout<T, N, V>::xe(e)];
           wi[e] = w0[u] - v.x * fj0[u];
           wi[e + HN] = w1[u] - v.y * fj1[u];
           if (off) {
@@ -493,7 +531,7 @@ __device__ __forceinline__ void accumulate_w_r(const T* __restrict__ pi_, const 
     }
   } else if (EN) {
     for (int e = tid; e < HN; e += NT) {
-      const cplx<T> v = buf[xpos<N>(e)];
+      const cplx<T> v = buf[InvLayout<T, N, V>::xe(e)];
       ea += v.x * pi_[e] * pj_[e] + v.y * pi_[e + HN] * pj_[e + HN];
     }
   }
@@ -551,7 +589,7 @@ __device__ __forceinline__ void body_inv_owner_r(const T* __restrict__ phi, cons
       for (int u = 0; u < U; ++u) {
         const int e = t + (q0 + u) * NT;
         if (q0 + u < LP && (HN % NT == 0 || e < HN)) {
-          const cplx<T> v = buf[xpos<N>(e)];
+          const cplx<T> v = buf[InvLayout<T, N, V>::xe(e)];
           acc0[q0 + u] += v.x * f0[u];
           acc1[q0 + u] += v.y * f1[u];
         }
