@@ -129,16 +129,12 @@ __global__ __launch_bounds__(BNT) void k_batched_persistent(int nseg, const BRou
 // one or two pair slots, each with its own N * N * (N/2 + 1) half spectrum.
 constexpr int BNTR = 512;
 
-// LDS buffer of the three phases: the in-plane bodies use the larger of the
-// forward's N * XS values and the inverse layout, the z pass two tiles of
-// N * TX (TX can exceed XS on small grids, e.g. 16 > 9 at N = 16).
-template <typename T, int N, int V>
+// LDS buffer of the three phases: the in-plane bodies use N * XS values, the
+// z pass two tiles of N * TX (TX can exceed XS on small grids, e.g. 16 > 9 at
+// N = 16).
+template <int N>
 __host__ __device__ constexpr int r2c_buf_elems() {
-  return 2 * N * r2c_tx<N>() > InvLayout<T, N, V>::BUF ? 2 * N * r2c_tx<N>() : InvLayout<T, N, V>::BUF;
-}
-template <typename T, int N>
-constexpr int r2c_buf_elems_any() {
-  return r2c_buf_elems<T, N, 0>() > r2c_buf_elems<T, N, 1>() ? r2c_buf_elems<T, N, 0>() : r2c_buf_elems<T, N, 1>();
+  return 2 * N * r2c_tx<N>() > N * r2c_xs<N>() ? 2 * N * r2c_tx<N>() : N * r2c_xs<N>();
 }
 
 // Items per pair slot: one per z-plane in phases 0 and 2; in phase 1 one per
@@ -207,7 +203,7 @@ __device__ __forceinline__ void run_item_r(int p, int64_t j, int q, const BRound
     const size_t zo = size_t(sub) * N * N;
     body_inv_xy_r<T, N, BNTR, V>(spec + size_t(sub) * PL, buf, tw, tid);
     T* W = static_cast<T*>(sy.W);
-    accumulate_w_r<T, N, BNTR, false, V>(phi + size_t(oi) * NG + zo, phi + size_t(oj) * NG + zo,
+    accumulate_w_r<T, N, BNTR, false>(phi + size_t(oi) * NG + zo, phi + size_t(oj) * NG + zo,
                                       W + size_t(oi) * NG + zo, W + size_t(oj) * NG + zo, oi != oj, nullptr, buf,
                                       red, tid);
   }
@@ -244,7 +240,7 @@ template <typename T, int N, int V, int P>
 __global__ __launch_bounds__(BNTR, 4) void k_batched_phase_r(BRound sg, const BSys* __restrict__ sys,
                                                           const BPack* __restrict__ packs,
                                                           const int64_t* __restrict__ starts) {
-  __shared__ cplx<T> buf[InvLayout<T, N, V>::BUF];
+  __shared__ cplx<T> buf[N * r2c_xs<N>()];
   __shared__ cplx<T> tw[N];
   __shared__ double red[BNTR / 64];
   int tw_sys = -1;
@@ -268,7 +264,7 @@ __global__ __launch_bounds__(BNTR, 4) void k_batched_persistent_r(int nseg, cons
                                                                const BSys* __restrict__ sys,
                                                                const BPack* __restrict__ packs,
                                                                const int64_t* __restrict__ starts) {
-  __shared__ cplx<T> buf[r2c_buf_elems<T, N, V>()];
+  __shared__ cplx<T> buf[r2c_buf_elems<N>()];
   __shared__ cplx<T> tw[N];
   __shared__ double red[BNTR / 64];
   cg::grid_group grid = cg::this_grid();
@@ -382,7 +378,7 @@ __global__ __launch_bounds__(BNTR, 4) void k_batched_owner_r(int nown, const BOw
                                                           const int32_t* __restrict__ adj,
                                                           const cplx<T>* __restrict__ spec) {
   constexpr size_t NG = size_t(N) * N * N;
-  __shared__ cplx<T> buf[InvLayout<T, N, V>::BUF];
+  __shared__ cplx<T> buf[N * r2c_xs<N>()];
   __shared__ cplx<T> tw[N];
   const int64_t g = blockIdx.x, l = g >> 3;
   const int64_t norb_all = int64_t(gridDim.x) / N;
@@ -439,10 +435,7 @@ hipError_t batched_owner(int prec, int n, int plan_v, int nslots, int nown, int6
 
 bool batched_r2c_fits(int prec, int n) {
   switch (n) {
-#define X(nn)                                                                                    \
-  case nn:                                                                                         \
-    return prec == 0 ? (size_t(r2c_buf_elems_any<double, nn>()) + nn) * 16 + 1024 <= 163840       \
-                     : (size_t(r2c_buf_elems_any<float, nn>()) + nn) * 8 + 1024 <= 163840;
+#define X(nn) case nn: return (size_t(r2c_buf_elems<nn>()) + nn) * (prec == 0 ? 16 : 8) + 1024 <= 163840;
     X(16) X(24) X(32) X(48) X(64) X(80) X(96)
 #undef X
     default: return false;

@@ -386,17 +386,6 @@ __device__ __forceinline__ void fft_lines_ls(cplx<T>* buf, const cplx<T>* tw, in
   }
 }
 
-// Passes P .. plan_len(N) - 1 in place, element p of line l at buf[addr(l, p)].
-template <typename T, int N, int P, int LINES, int NT, int S, bool JFAST, int V, typename A>
-__device__ __forceinline__ void fft_lines_from_at(cplx<T>* buf, const cplx<T>* tw, int tid, A addr) {
-  if constexpr (P < plan_len(N)) {
-    fft_pass_ls<T, N, P, LINES, 0, 0, NT, S, JFAST, V, true>(
-        buf, tw, tid, [buf, addr](int l, int p) { return buf[addr(l, p)]; },
-        [buf, addr](int l, int p, cplx<T> x) { buf[addr(l, p)] = x; });
-    fft_lines_from_at<T, N, P + 1, LINES, NT, S, JFAST, V>(buf, tw, tid, addr);
-  }
-}
-
 // The same, with the first pass reading its inputs through load(l, p) (an
 // element-wise step fused into the transform's first LDS read).
 template <typename T, int N, int LINES, int LS, int PS, int NT, int S, bool JFAST, int V, typename L>

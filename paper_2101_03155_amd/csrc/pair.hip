@@ -154,7 +154,7 @@ __global__ __launch_bounds__(NT) void k_inv_x(const T* __restrict__ phi, const c
 
 template <typename T, int N>
 constexpr bool r2c_fits_t() {
-  return (size_t(InvLayout<T, N, 0>::BUF) + N) * sizeof(cplx<T>) + 1024 <= 163840;
+  return (size_t(N) * r2c_xs<N>() + N) * sizeof(cplx<T>) + 1024 <= 163840;
 }
 
 // ZFAST: blockIdx.x = z-plane, blockIdx.y = pair slot; otherwise the slot
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(NT, 4) void k_inv_owner_r(const T* __restrict__ phi
                                                     const int32_t* __restrict__ operm, T* __restrict__ W,
                                                     const cplx<T>* __restrict__ twg) {
   constexpr size_t NG = size_t(N) * N * N;
-  __shared__ cplx<T> buf[InvLayout<T, N, 0>::BUF];
+  __shared__ cplx<T> buf[N * r2c_xs<N>()];
   __shared__ cplx<T> tw[N];
   int z, k;
   if (!XCD) {
@@ -252,7 +252,7 @@ __global__ __launch_bounds__(NT) void k_inv_xy_r(const T* __restrict__ phi, cons
   using C = cplx<T>;
   constexpr int XS = r2c_xs<N>();
   constexpr size_t NG = size_t(N) * N * N, PL = size_t(N) * XS;
-  __shared__ C buf[InvLayout<T, N, 0>::BUF];
+  __shared__ C buf[N * XS];
   __shared__ C tw[N];
   __shared__ double red[NT / 64];
   const int tid = threadIdx.x, z = blockIdx.x, slot = blockIdx.y;
@@ -373,7 +373,7 @@ static hipError_t pair_owner_t(const void* phi_, void* spec_, const Pack* packs,
     const C* tw = static_cast<const C*>(tw_);
     // planes too large for two workgroups per CU take 1024 threads, so that
     // one workgroup still runs four waves per SIMD
-    constexpr int NTR = size_t(InvLayout<T, N, 0>::BUF) * sizeof(C) > 81920 ? 1024 : 512;
+    constexpr int NTR = size_t(N) * r2c_xs<N>() * sizeof(C) > 81920 ? 1024 : 512;
     constexpr int NTL = 256, TXR = own_tx<T, N>();
     constexpr int NTILE = own_ntile<T, N>();
     constexpr size_t SLOT = size_t(N) * N * r2c_xs<N>();  // complex values per pair slot

@@ -216,32 +216,22 @@ template <int N> __device__ __forceinline__ int xpos(int e) { return e + e / N *
 // LDS layout of the inverse in-plane transforms (V: the y passes' plan order;
 // the x passes take the other).  The y-transformed plane is [y][kx] at row
 // stride XS, and the x passes' first pass re-packs rows l and l + N/2 into x
-// line l with eight threads per line.  Where it has eight threads per line
-// and N is a multiple of 32, the last y pass writes row y to row ysig(y),
-// which interleaves each block of 32 rows so that the rows read by the
-// neighbouring 8-thread groups of one LDS cycle start in disjoint bank ranges
-// (adjacent rows start one FP64 value apart, and their 8-value ranges
-// overlapped).  In FP64 with a radix-12 first x pass, the x lines also take 2
-// values of padding after each 48: the pass writes element 12 j + r of a
-// line from thread j, which without it hits each bank twice.  Line stride XL
-// stays odd, for the later x passes (consecutive lines on consecutive
-// threads).
+// line l (stride N + 1).  Where that pass has eight threads per line and N is
+// a multiple of 32, the last y pass writes row y to row ysig(y), which
+// interleaves each block of 32 rows so that the rows read by the 8-thread
+// groups served in one LDS cycle start in disjoint bank ranges (rows l and
+// l + 1 start one FP64 value apart, and their 8-value ranges overlapped).
+// Padding the x lines as well, against the 2-way conflicts of that pass's
+// writes, made the FP64 owner kernel spill registers.
 template <typename T, int N, int V> struct InvLayout {
   static constexpr int XS = r2c_xs<N>();
   static constexpr int R0 = plan_radix_v(N, 0, V ^ 1);
   static constexpr bool SIG = N % 32 == 0 && N / R0 == 8;
-  static constexpr int PG = (sizeof(T) == 8 && SIG && R0 == 12) ? 4 * R0 : N;
-  static constexpr int PW = PG < N ? 2 : 0;
-  static constexpr int XL = N + PW * ((N - 1) / PG) + 1;
-  // LDS elements of the plane buffer: the larger of the two layouts
-  static constexpr int BUF = N * XS > (N / 2) * XL ? N * XS : (N / 2) * XL;
-  static_assert(XL % 2 == 1, "x line stride must be odd");
+  static constexpr int XL = xls<N>();
   static __host__ __device__ __forceinline__ int ysig(int y) {
     return SIG ? (y & ~31) | ((y & 3) << 3) | ((y & 31) >> 2) : y;
   }
-  static __host__ __device__ __forceinline__ int xq(int l, int p) { return l * XL + p + PW * (p / PG); }
-  // element e = l * N + x of the packed potential lines
-  static __host__ __device__ __forceinline__ int xe(int e) { return xq(e / N, e % N); }
+  static __host__ __device__ __forceinline__ int xq(int l, int p) { return l * XL + p; }
 };
 template <int N> __host__ __device__ constexpr int r2c_tx() {
   return (N * r2c_xs<N>()) % 16 == 0 ? 16 : (N * r2c_xs<N>()) % 8 == 0 ? 8 : (N * r2c_xs<N>()) % 4 == 0 ? 4 : 2;
@@ -470,7 +460,7 @@ __device__ __forceinline__ void inv_x_repacked(cplx<T>* buf, const cplx<T>* tw, 
   // in FP64), with the radix order reversed: the larger first radix spreads
   // its writes over more banks.  The later passes take consecutive lines.
   using Lay = InvLayout<T, N, V>;
-  fft_pass_ls<T, N, 0, H, 0, 0, NT, +1, true, V ^ 1, true>(buf, tw, tid, [buf](int l, int p) {
+  fft_pass_l<T, N, 0, H, Lay::XL, 1, NT, +1, true, V ^ 1>(buf, tw, tid, [buf](int l, int p) {
     const bool lowk = p <= H;
     const int k = lowk ? p : N - p;
     C x1 = buf[Lay::ysig(l) * XS + k], x2 = buf[Lay::ysig(l + H) * XS + k];
@@ -487,13 +477,13 @@ __device__ __forceinline__ void inv_x_repacked(cplx<T>* buf, const cplx<T>* tw, 
       z.y = x2.x - x1.y;
     }
     return z;
-  }, [buf](int l, int p, C x) { buf[Lay::xq(l, p)] = x; });
-  fft_lines_from_at<T, N, 1, H, NT, +1, false, V ^ 1>(buf, tw, tid, [](int l, int p) { return Lay::xq(l, p); });
+  });
+  fft_lines_from<T, N, 1, H, Lay::XL, 1, NT, +1, false, V ^ 1>(buf, tw, tid);
 }
 
 // W_i -= v phi_j and (i != j) W_j -= v phi_i over plane z for one pair, with
 // v from the packed lines of body_inv_xy_r; optional partial sum of v rho.
-template <typename T, int N, int NT, bool EN, int V = 0>
+template <typename T, int N, int NT, bool EN>
 __device__ __forceinline__ void accumulate_w_r(const T* __restrict__ pi_, const T* __restrict__ pj_, T* wi, T* wj,
                                                bool off, double* eslot, const cplx<T>* buf, double* red, int tid) {
   constexpr int HN = (N / 2) * N;
@@ -518,7 +508,7 @@ __device__ __forceinline__ void accumulate_w_r(const T* __restrict__ pi_, const 
       for (int u = 0; u < U; ++u) {
         const int e = tid + (q0 + u) * NT;
         if (q0 + u < LP && (HN % NT == 0 || e < HN)) {
-          const cplx<T> v = buf[InvLayout<T, N, V>::xe(e)];
+          const cplx<T> v = buf[xpos<N>(e)];
           wi[e] = w0[u] - v.x * fj0[u];
           wi[e + HN] = w1[u] - v.y * fj1[u];
           if (off) {
@@ -531,7 +521,7 @@ __device__ __forceinline__ void accumulate_w_r(const T* __restrict__ pi_, const 
     }
   } else if (EN) {
     for (int e = tid; e < HN; e += NT) {
-      const cplx<T> v = buf[InvLayout<T, N, V>::xe(e)];
+      const cplx<T> v = buf[xpos<N>(e)];
       ea += v.x * pi_[e] * pj_[e] + v.y * pi_[e + HN] * pj_[e + HN];
     }
   }
@@ -589,7 +579,7 @@ __device__ __forceinline__ void body_inv_owner_r(const T* __restrict__ phi, cons
       for (int u = 0; u < U; ++u) {
         const int e = t + (q0 + u) * NT;
         if (q0 + u < LP && (HN % NT == 0 || e < HN)) {
-          const cplx<T> v = buf[InvLayout<T, N, V>::xe(e)];
+          const cplx<T> v = buf[xpos<N>(e)];
           acc0[q0 + u] += v.x * f0[u];
           acc1[q0 + u] += v.y * f1[u];
         }

@@ -61,7 +61,7 @@ double inverse_err(const std::vector<T>& pi, const std::vector<T>& pj, const std
                    const std::vector<cplx<T>>& tw, bool global) {
   constexpr int H = N / 2;
   using Lay = InvLayout<T, N, V>;
-  std::vector<cplx<T>> buf(Lay::BUF);
+  std::vector<cplx<T>> buf(N * (N / 2 + 1));
   for (auto& c : buf) { c.x = T(1e30); c.y = T(-1e30); }
   if (global) body_inv_xy_g<T, N, 1, V>(out.data(), buf.data(), tw.data(), 0);
   else body_inv_xy_r<T, N, 1, V>(out.data(), buf.data(), tw.data(), 0);
@@ -71,7 +71,6 @@ double inverse_err(const std::vector<T>& pi, const std::vector<T>& pj, const std
       const double r0 = double(pi[l * N + x]) * pj[l * N + x] * N * N;
       const double r1 = double(pi[(l + H) * N + x]) * pj[(l + H) * N + x] * N * N;
       const auto v = buf[Lay::xq(l, x)];
-      if (Lay::xe(l * N + x) != Lay::xq(l, x)) return 1.0;
       e2 = std::max(e2, std::max(std::abs(v.x - r0), std::abs(v.y - r1)));
       m2 = std::max(m2, std::max(std::abs(r0), std::abs(r1)));
     }
