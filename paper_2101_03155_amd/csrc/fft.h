@@ -279,13 +279,17 @@ template <int S, typename C> struct Dft<16, S, C> {
 // followed by a barrier unless END_SYNC is false (a last pass storing to
 // global memory; the barrier between reads and writes stays, so the buffer's
 // previous contents are read by all threads before a first pass writes it).
+// WROT: threads whose butterfly index j has bit 2 set store their R outputs
+// in an order rotated by WROT (same values, same places, other instructions),
+// which moves their writes to other banks than those of threads j - 4.
 template <typename T, int N, int P, int LINES, int LS, int PS, int NT, int S, bool JFAST, int V, bool END_SYNC,
-          typename L, typename St>
+          int WROT = 0, typename L, typename St>
 __device__ __forceinline__ void fft_pass_ls(cplx<T>* buf, const cplx<T>* tw, int tid, L load, St store);
 
-template <typename T, int N, int P, int LINES, int LS, int PS, int NT, int S, bool JFAST, int V, typename L>
+template <typename T, int N, int P, int LINES, int LS, int PS, int NT, int S, bool JFAST, int V, int WROT = 0,
+          typename L>
 __device__ __forceinline__ void fft_pass_l(cplx<T>* buf, const cplx<T>* tw, int tid, L load) {
-  fft_pass_ls<T, N, P, LINES, LS, PS, NT, S, JFAST, V, true>(
+  fft_pass_ls<T, N, P, LINES, LS, PS, NT, S, JFAST, V, true, WROT>(
       buf, tw, tid, load, [buf](int l, int p, cplx<T> x) { buf[l * LS + p * PS] = x; });
 }
 
@@ -296,7 +300,7 @@ __device__ __forceinline__ void fft_pass(cplx<T>* buf, const cplx<T>* tw, int ti
 }
 
 template <typename T, int N, int P, int LINES, int LS, int PS, int NT, int S, bool JFAST, int V, bool END_SYNC,
-          typename L, typename St>
+          int WROT, typename L, typename St>
 __device__ __forceinline__ void fft_pass_ls(cplx<T>* buf, const cplx<T>* tw, int tid, L load, St store) {
   using C = cplx<T>;
   constexpr int R = plan_radix_v(N, P, V);
@@ -333,8 +337,24 @@ __device__ __forceinline__ void fft_pass_ls(cplx<T>* buf, const cplx<T>* tw, int
       }
       Dft<R, S, C>::run(v[s]);
       const int o = (j / NS) * NS * R + k;
+      const bool rot = WROT != 0 && (j & 4) != 0;
 #pragma unroll
-      for (int r = 0; r < R; ++r) store(l, o + r * NS, v[s][r]);
+      for (int r = 0; r < R; ++r) {
+        if constexpr (WROT == 0) {
+          store(l, o + r * NS, v[s][r]);
+        } else {
+          const int r2 = (r + WROT) % R;
+          // (the empty asm keeps the two values in registers: a select of
+          // the array elements themselves becomes an indexed load, which
+          // moves the whole array to scratch memory)
+          C a = v[s][r], b = v[s][r2];
+          asm("" : "+v"(a.x), "+v"(a.y), "+v"(b.x), "+v"(b.y));
+          C x;
+          x.x = rot ? b.x : a.x;
+          x.y = rot ? b.y : a.y;
+          store(l, o + (rot ? r2 : r) * NS, x);
+        }
+      }
     }
   }
   if (END_SYNC) __syncthreads();

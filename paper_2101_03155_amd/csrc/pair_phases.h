@@ -221,12 +221,16 @@ template <int N> __device__ __forceinline__ int xpos(int e) { return e + e / N *
 // interleaves each block of 32 rows so that the rows read by the 8-thread
 // groups served in one LDS cycle start in disjoint bank ranges (rows l and
 // l + 1 start one FP64 value apart, and their 8-value ranges overlapped).
-// Padding the x lines as well, against the 2-way conflicts of that pass's
-// writes, made the FP64 owner kernel spill registers.
+// Its writes (element 12 j + r of a line from thread j, radix 12) hit each
+// FP64 bank group twice, threads j and j + 4 alike; threads j >= 4 store in
+// an order rotated by 2 (WROT), which puts them on the other half of the
+// bank groups.  (Padding the x lines instead made the FP64 owner kernel
+// spill registers.)  FP32 writes are conflict-free without the rotation.
 template <typename T, int N, int V> struct InvLayout {
   static constexpr int XS = r2c_xs<N>();
   static constexpr int R0 = plan_radix_v(N, 0, V ^ 1);
   static constexpr bool SIG = N % 32 == 0 && N / R0 == 8;
+  static constexpr int WROT = sizeof(T) == 8 && SIG && R0 == 12 ? 2 : 0;
   static constexpr int XL = xls<N>();
   static __host__ __device__ __forceinline__ int ysig(int y) {
     return SIG ? (y & ~31) | ((y & 3) << 3) | ((y & 31) >> 2) : y;
@@ -460,7 +464,7 @@ __device__ __forceinline__ void inv_x_repacked(cplx<T>* buf, const cplx<T>* tw, 
   // in FP64), with the radix order reversed: the larger first radix spreads
   // its writes over more banks.  The later passes take consecutive lines.
   using Lay = InvLayout<T, N, V>;
-  fft_pass_l<T, N, 0, H, Lay::XL, 1, NT, +1, true, V ^ 1>(buf, tw, tid, [buf](int l, int p) {
+  fft_pass_l<T, N, 0, H, Lay::XL, 1, NT, +1, true, V ^ 1, Lay::WROT>(buf, tw, tid, [buf](int l, int p) {
     const bool lowk = p <= H;
     const int k = lowk ? p : N - p;
     C x1 = buf[Lay::ysig(l) * XS + k], x2 = buf[Lay::ysig(l + H) * XS + k];
